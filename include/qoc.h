@@ -1,0 +1,201 @@
+/*
+ * qoc.h - C ABI of the symmetry-reduced GRAPE hot path for AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Wang, Okyay, Kumar & Wong, "Accelerating Quantum Optimal
+ * Control of Multi-Qubit Systems with Symmetry-Based Hamiltonian Transformations"
+ * (AVS Quantum Sci. 2023):
+ *   - Schroedinger dynamics with a static H0 and controls H_c(t) = sum_k u_k(t) H_k
+ *     (Sec. II A, Eqs. (1)-(2); Eq. (6) for the global x/y controls);
+ *   - piecewise-constant slice propagators U_j = exp(-i dt (H0 + sum_k u[j,k] H_k))
+ *     (Eq. (3));
+ *   - the state-transfer objective |<psi_f|psi_N>|^2 (Eq. (4)) and its gradient with
+ *     respect to every slice sample (App. B, Eq. (B2), here taken exactly);
+ *   - the block diagonalisation of ring-symmetric (D_n) and permutation-symmetric (S_n)
+ *     Hamiltonians by group-algebra projections (Sec. II A, Table I; App. A,
+ *     Eqs. (A1)-(A2)).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Qubits q = 1..n; qubit q is bit position p = n - q of a basis index (qubit 1 is the
+ * most significant bit, the Kronecker order of Sec. II A).  Bit value 0 is spin up.
+ * The group acts on bit positions: rotation rho: p -> p + stride (mod n) and, for the
+ * dihedral group, the site-centred reflection phi: p -> -p (mod n).  L = n / stride.
+ *
+ * Blocks (irreps) are ordered A1, A2, B1, B2 (B only for even L), E_1 .. E_{ceil(L/2)-1}
+ * for the dihedral group; k_0 .. k_{L-1} (momentum 2 pi m / L) for the cyclic group;
+ * J = n/2, n/2 - 1, ... for the symmetric group.  B1 has character -1 on rho and +1 on
+ * phi.  Inside a block the basis states are ordered by ascending orbit representative
+ * (the minimum integer of the orbit).  For a one-dimensional irrep chi and
+ * representative a (allowed when chi is trivial on the stabiliser of a) the basis
+ * state is |a,chi> = |O_a|^{-1/2} sum_{y in O_a} conj(chi(g_y)) |y>, g_y a = y.  For
+ * E_m the first copy is the momentum state |c,k> = P_c^{-1/2} sum_{l<P_c}
+ * exp(-i k l) |rho^l c>, k = 2 pi m / L, over cyclic representatives c of period P_c
+ * with m P_c = 0 mod L, and the second copy is U_phi |c,k>; both copies carry the
+ * same block matrix.  The symmetric-group blocks use |J,M>, M = J, J-1, ..., -J.
+ *
+ * Panels.  A state in block form is the concatenation, in block order, of one
+ * column-major m x d panel per block (d = copies: 2 for E_m, 1 otherwise), stored as
+ * interleaved complex128 (the layout of a torch.complex128 tensor).  Its length is
+ * D = sum_blocks m * d (= 2^n for the ring groups; one copy per J for S_n).
+ *
+ * Controls u are float64 row-major [N][K] device arrays; gradients are float64
+ * [N][K] device arrays.  Outputs of the objective are float64 device arrays.
+ *
+ * Ownership.  Handles (qoc_basis, qoc_system, qoc_plan) are owned by the library
+ * until the matching *_free call.  Every array argument is owned by the caller; the
+ * library never frees it.  The hot-path calls (qoc_propagate, qoc_fidelity_grad,
+ * qoc_fidelity_grad_batched) allocate nothing: their scratch memory is the caller's
+ * workspace, sized by qoc_plan_workspace_size.
+ *
+ * Errors.  Every call returns a qoc_status; nothing throws or aborts across the ABI.
+ * Argument and symmetry checks happen before any device work.  A device failure
+ * returns QOC_ERR_DEVICE; qoc_last_error() then holds the HIP error text.  Calls
+ * taking a stream enqueue asynchronously on it unless stated otherwise.
+ */
+#ifndef QOC_H
+#define QOC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QOC_OK = 0,
+  QOC_ERR_INVALID_ARG = 1,   /* null pointer, size out of range, non-finite input */
+  QOC_ERR_SYMMETRY = 2,      /* a term is not invariant under the requested group */
+  QOC_ERR_UNSUPPORTED = 3,   /* valid request the library does not implement */
+  QOC_ERR_OUT_OF_MEMORY = 4, /* workspace too small, or a setup allocation failed */
+  QOC_ERR_DEVICE = 5,        /* HIP runtime error */
+  QOC_ERR_NUMERIC = 6        /* a numeric check failed (see qoc_last_error) */
+} qoc_status;
+
+typedef enum { QOC_GROUP_DIHEDRAL = 0, QOC_GROUP_CYCLIC = 1, QOC_GROUP_SYMMETRIC = 2 } qoc_group;
+typedef enum { QOC_C128 = 0, QOC_C64 = 1 } qoc_precision;
+typedef enum {
+  QOC_TERM_ONE_BODY = 0,     /* coeff * sum_q w_q sigma_a^(q) over selected qubits */
+  QOC_TERM_RING_PAIR = 1,    /* coeff * sum_{q=1..n} sigma_a^(q) sigma_b^(q+distance), indices mod n */
+  QOC_TERM_ALL_PAIRS = 2,    /* coeff * sum_{q<q'} sigma_a^(q) sigma_b^(q') */
+  QOC_TERM_PAULI_STRING = 3  /* coeff * prod_p sigma(x_p, z_p): (1,0)=X, (0,1)=Z, (1,1)=Y */
+} qoc_term_kind;
+typedef enum { QOC_SITES_ALL = 0, QOC_SITES_EVEN = 1, QOC_SITES_ODD = 2 } qoc_sites;
+
+/* One Hermitian Pauli-sum term with a real coefficient (Sec. II A: H_x, H_y, H_z and the
+ * ring coupling H_z,cpl; Eqs. (5)-(7)).  For ONE_BODY, w_q = (-1)^q when staggered,
+ * else 1, and `sites` selects even, odd or all qubits q.  op_a/op_b are 'x','y','z'.
+ * For PAULI_STRING, x_mask / z_mask are indexed by bit position p. */
+typedef struct {
+  int32_t kind;
+  int32_t distance;
+  int32_t sites;
+  int32_t staggered;
+  double coeff;
+  char op_a;
+  char op_b;
+  char pad_[6];
+  uint64_t x_mask;
+  uint64_t z_mask;
+} qoc_term;
+
+typedef struct qoc_basis_s* qoc_basis;
+typedef struct qoc_system_s* qoc_system;
+typedef struct qoc_plan_s* qoc_plan;
+
+/* Orbits and symmetry-adapted block table of the group (App. A, Eq. (A2); Table I).
+ * n: 1..30 for DIHEDRAL/CYCLIC (basis states are enumerated on the device),
+ * 1..4096 for SYMMETRIC (closed form, no enumeration).  stride must divide n
+ * (ring groups); it is ignored for SYMMETRIC.  Orbit representatives are computed
+ * on the device with integer arithmetic and the block sizes are cross-checked on
+ * the host against the character formula; a mismatch returns QOC_ERR_NUMERIC.
+ * Synchronises `stream` before returning. */
+qoc_status qoc_build_basis(int n, int group, int stride, void* stream, qoc_basis* out);
+void qoc_basis_free(qoc_basis basis);
+
+/* Block table: writes up to `cap` entries of sizes m_theta and copies d_theta (host
+ * arrays) and the number of blocks.  For SYMMETRIC, copies is 1 (one copy per J). */
+qoc_status qoc_basis_blocks(qoc_basis basis, int* nblocks, int32_t* sizes, int32_t* copies, int cap);
+
+/* Orbit representatives (host array, ascending): which = 0 for the orbits of the whole
+ * group, 1 for the orbits of its rotation subgroup, 2 + b for the representatives that
+ * index block b.  *count receives the total; at most `cap` are written. */
+qoc_status qoc_basis_reps(qoc_basis basis, int which, uint64_t* reps, int64_t cap, int64_t* count);
+
+/* Dense state (2^n interleaved complex128, device) -> block panels (device), and back
+ * (App. A: the columns of the adjoint matrix are the basis states above).
+ * Ring groups only; QOC_ERR_UNSUPPORTED for SYMMETRIC. */
+qoc_status qoc_state_to_blocks(qoc_basis basis, const void* dense_dev, void* blocks_dev, void* stream);
+qoc_status qoc_state_from_blocks(qoc_basis basis, const void* blocks_dev, void* dense_dev, void* stream);
+
+/* Project H0 and the K control Hamiltonians into every block: H_theta = A_theta^dag H
+ * A_theta (Sec. II A; Fig. 2's block structure).  h0 has n_h0 terms; hk holds the terms
+ * of H_1..H_K back to back, n_hk[k] of them for H_k.  Every term is first checked for
+ * exact invariance under the group generators on its integer bit masks; a term that
+ * breaks the symmetry returns QOC_ERR_SYMMETRY before device work.  The system keeps
+ * complex128 and complex64 copies of every block on the device.  K: 0..16.
+ * Synchronises `stream` before returning. */
+qoc_status qoc_project(qoc_basis basis, const qoc_term* h0, int n_h0, const qoc_term* hk,
+                       const int* n_hk, int K, void* stream, qoc_system* out);
+void qoc_system_free(qoc_system system);
+
+/* Host-only exact check that the sum of `count` terms is invariant under the group
+ * generators (rotation by `stride`, and the reflection for DIHEDRAL), compared on the
+ * integer Pauli masks and exactly equal coefficients after merging equal strings
+ * (Sec. II A: which sums carry S_n or D_n symmetry).  For SYMMETRIC, only uniform
+ * one-body sums and all-pairs sums with equal letters are accepted.  Returns QOC_OK or
+ * QOC_ERR_SYMMETRY (QOC_ERR_INVALID_ARG for malformed input).  n: 1..64 (ring groups). */
+qoc_status qoc_check_symmetry(int n, int group, int stride, const qoc_term* terms, int count);
+
+/* Copy block `block` of operator `op` (0 = H0, k = H_k) into a caller buffer as a dense
+ * column-major m x m interleaved complex128 matrix (device). */
+qoc_status qoc_system_block(qoc_system system, int block, int op, void* dst_dev, void* stream);
+
+/* Execution plan for N slices of length dt at a precision (QOC_C128 or QOC_C64).
+ * The plan fixes the Taylor degree menu, the Frechet-series length and the number of
+ * propagator slices held at once (segment) so that the workspace stays within
+ * max_workspace_bytes; when the whole pulse does not fit, propagators are recomputed
+ * segment by segment in the backward sweep.  u_bound > 0 bounds |u[j,k]| for every
+ * call that uses this plan; the plan uses it, with the exact 1-norms of the blocks, to
+ * bound dt*||H0 + sum u_k H_k||_1 by the triangle inequality.  A slice whose control
+ * exceeds u_bound makes the hot-path call report QOC_ERR_NUMERIC.
+ * Host-only; no device work. */
+qoc_status qoc_plan_create(qoc_system system, int precision, int N, double dt, double u_bound,
+                           size_t max_workspace_bytes, qoc_plan* out);
+void qoc_plan_free(qoc_plan plan);
+qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
+/* Plan facts: info[0] segment length, [1] number of segments, [2] Taylor degree step r,
+ * [3] largest degree, [4] Frechet series terms, [5] Frechet sub-steps, [6] bytes/slice. */
+qoc_status qoc_plan_info(qoc_plan plan, int64_t* info, int cap);
+
+/* Slice propagators U_j (Eq. (3)) for every block and slice: scaled Taylor polynomial
+ * (Paterson-Stockmeyer) with repeated squaring, matrix products on the MFMA units.
+ * U_out_dev receives, block after block, N column-major m x m interleaved complex128
+ * matrices (slice-major within a block).  Requires a plan whose segment covers N. */
+qoc_status qoc_propagate(qoc_plan plan, const double* u_dev, void* U_out_dev, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+/* Objective and exact gradient (Eqs. (3)-(4); App. B, Eq. (B2) taken to all orders).
+ * psi0_dev, psif_dev: block panels (interleaved complex128, length D).
+ * out_dev (float64, 8 entries): [0] F = |o|^2 / (||psi_N||^2 ||psi_f||^2),
+ * [1] |o|^2, [2] Re o, [3] Im o with o = <psi_f|psi_N>, [4] ||psi_N||^2,
+ * [5] ||psi_f||^2, [6] largest squaring count used, [7] status flags (0 = clean;
+ * bit 0: a slice exceeded the plan's norm bound; bit 1: non-finite value).
+ * grad_dev (float64 [N][K]) receives dF/du[j,k] = 2 Re(conj(o) do/du[j,k]) /
+ * (||psi_N||^2 ||psi_f||^2).  Fully asynchronous (no host synchronisation), so the
+ * call can be captured into a HIP graph. */
+qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi0_dev,
+                             const void* psif_dev, double* out_dev, double* grad_dev,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* Status text and the calling thread's last error detail. */
+const char* qoc_status_string(qoc_status status);
+const char* qoc_last_error(void);
+/* Library version (major*10000 + minor*100 + patch). */
+int qoc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QOC_H */

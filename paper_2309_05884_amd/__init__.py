@@ -1,0 +1,230 @@
+"""Symmetry-reduced GRAPE on AMD Instinct MI355X (gfx950).
+
+Thin Python layer over the C ABI of ``include/qoc.h``: it marshals arguments, takes
+device memory and the current stream from PyTorch, and raises on error.  Every step
+of the computation runs in the HIP library ``libqoc_gfx950.so``; there is no CPU
+fallback, and importing the compute entry points without the built library fails.
+
+Method: Wang, Okyay, Kumar & Wong, AVS Quantum Sci. 2023 -- block diagonalisation of
+ring (D_n) and permutation (S_n) symmetric Hamiltonians (Sec. II A, App. A), slice
+propagators (Eq. (3)), the state-transfer objective (Eq. (4)) and its gradient
+(App. B, Eq. (B2), taken exactly).
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _capi as C
+from ._capi import QocError
+
+__all__ = ["Basis", "System", "Plan", "fidelity_grad", "propagate", "GrapeFidelity", "QocError",
+           "library_path"]
+
+library_path = C.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Basis:
+    """Orbits and block table of a group acting on n qubits (qoc_build_basis)."""
+
+    def __init__(self, n: int, group: str = "dihedral", stride: int = 1):
+        self._h = ctypes.c_void_p()
+        L = C.lib()
+        C.check(L.qoc_build_basis(int(n), C.GROUPS[group], int(stride), _stream(), ctypes.byref(self._h)))
+        self.n, self.group, self.stride = n, group, stride
+        nb = ctypes.c_int()
+        C.check(L.qoc_basis_blocks(self._h, ctypes.byref(nb), None, None, 0))
+        sizes = (ctypes.c_int32 * nb.value)()
+        copies = (ctypes.c_int32 * nb.value)()
+        C.check(L.qoc_basis_blocks(self._h, ctypes.byref(nb), sizes, copies, nb.value))
+        self.sizes = [int(v) for v in sizes]
+        self.copies = [int(v) for v in copies]
+
+    @property
+    def dim(self):
+        return sum(m * d for m, d in zip(self.sizes, self.copies))
+
+    def reps(self, which: int) -> np.ndarray:
+        """which = 0: group orbits, 1: rotation orbits, 2 + b: representatives of block b."""
+        L = C.lib()
+        cnt = ctypes.c_int64()
+        C.check(L.qoc_basis_reps(self._h, int(which), None, 0, ctypes.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.uint64)
+        C.check(L.qoc_basis_reps(self._h, int(which), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                 cnt.value, ctypes.byref(cnt)))
+        return out
+
+    def to_blocks(self, dense):
+        torch = _torch()
+        dense = dense.to(torch.complex128).contiguous()
+        out = torch.empty(self.dim, dtype=torch.complex128, device=dense.device)
+        C.check(C.lib().qoc_state_to_blocks(self._h, _ptr(dense), _ptr(out), _stream()))
+        return out
+
+    def from_blocks(self, panel):
+        torch = _torch()
+        panel = panel.to(torch.complex128).contiguous()
+        out = torch.empty(2 ** self.n, dtype=torch.complex128, device=panel.device)
+        C.check(C.lib().qoc_state_from_blocks(self._h, _ptr(panel), _ptr(out), _stream()))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None) and C._lib is not None:
+            C._lib.qoc_basis_free(self._h)
+            self._h = None
+
+
+class System:
+    """H0 and the control Hamiltonians projected into every block (qoc_project)."""
+
+    def __init__(self, basis: Basis, h0_terms, hk_terms):
+        self.basis = basis  # keeps the basis alive
+        self.K = len(hk_terms)
+        h0 = C.make_terms(h0_terms)
+        flat = [t for lst in hk_terms for t in lst]
+        hk = C.make_terms(flat)
+        nhk = (ctypes.c_int * max(1, self.K))(*[len(l) for l in hk_terms])
+        self._h = ctypes.c_void_p()
+        C.check(C.lib().qoc_project(basis._h, h0, len(h0_terms), hk, nhk, self.K, _stream(), ctypes.byref(self._h)))
+
+    def block(self, b: int, op: int):
+        torch = _torch()
+        m = self.basis.sizes[b]
+        out = torch.empty((m, m), dtype=torch.complex128, device="cuda")
+        C.check(C.lib().qoc_system_block(self._h, int(b), int(op), _ptr(out), _stream()))
+        # the library writes column-major: transpose the row-major view
+        return out.t().contiguous()
+
+    def __del__(self):
+        if getattr(self, "_h", None) and C._lib is not None:
+            C._lib.qoc_system_free(self._h)
+            self._h = None
+
+
+class Plan:
+    """Execution plan for N slices of length dt at one precision (qoc_plan_create)."""
+
+    def __init__(self, system: System, precision: str = "c128", N: int = 1, dt: float = 0.01,
+                 u_bound: float = 1.0, max_workspace_bytes: int = 0):
+        self.system = system
+        self.precision, self.N, self.dt, self.u_bound = precision, int(N), float(dt), float(u_bound)
+        self.K = system.K
+        self._h = ctypes.c_void_p()
+        C.check(C.lib().qoc_plan_create(system._h, C.PRECISIONS[precision], int(N), float(dt), float(u_bound),
+                                        int(max_workspace_bytes), ctypes.byref(self._h)))
+        b = ctypes.c_size_t()
+        C.check(C.lib().qoc_plan_workspace_size(self._h, ctypes.byref(b)))
+        self.workspace_bytes = int(b.value)
+        info = (ctypes.c_int64 * 10)()
+        C.check(C.lib().qoc_plan_info(self._h, info, 10))
+        keys = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
+                "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid"]
+        self.info = dict(zip(keys, [int(v) for v in info]))
+        self._ws = None
+
+    def workspace(self):
+        torch = _torch()
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def __del__(self):
+        if getattr(self, "_h", None) and C._lib is not None:
+            C._lib.qoc_plan_free(self._h)
+            self._h = None
+
+
+def check_flags(out):
+    """Raise if the objective's status word (out[7]) reports a numeric problem (synchronises)."""
+    flags = int(out[7].item())
+    if flags:
+        what = []
+        if flags & 1:
+            what.append("a slice exceeded the plan's norm bound (|u| > u_bound)")
+        if flags & 2:
+            what.append("non-finite value")
+        raise QocError(6, "; ".join(what))
+
+
+def fidelity_grad(plan: Plan, u, psi0, psif, workspace=None, check=True):
+    """(out[8], grad[N,K]) on the device: out = [F, |o|^2, Re o, Im o, |psi_N|^2, |psi_f|^2,
+    max squarings, flags]."""
+    torch = _torch()
+    u = u.to(torch.float64).contiguous()
+    assert u.shape == (plan.N, plan.K) and u.is_cuda
+    psi0 = psi0.to(torch.complex128).contiguous()
+    psif = psif.to(torch.complex128).contiguous()
+    D = plan.system.basis.dim
+    assert psi0.numel() == D and psif.numel() == D
+    ws = workspace if workspace is not None else plan.workspace()
+    out = torch.empty(8, dtype=torch.float64, device=u.device)
+    grad = torch.empty((plan.N, plan.K), dtype=torch.float64, device=u.device)
+    C.check(C.lib().qoc_fidelity_grad(plan._h, _ptr(u), _ptr(psi0), _ptr(psif), _ptr(out), _ptr(grad), _ptr(ws),
+                                      ctypes.c_size_t(ws.numel()), _stream()))
+    if check:
+        check_flags(out)
+    return out, grad
+
+
+def propagate(plan: Plan, u, workspace=None):
+    """Slice propagators U_j of every block: list of (N, m, m) complex128 tensors."""
+    torch = _torch()
+    u = u.to(torch.float64).contiguous()
+    ws = workspace if workspace is not None else plan.workspace()
+    sizes = plan.system.basis.sizes
+    total = sum(plan.N * m * m for m in sizes)
+    flat = torch.empty(total, dtype=torch.complex128, device=u.device)
+    C.check(C.lib().qoc_propagate(plan._h, _ptr(u), _ptr(flat), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream()))
+    outs, off = [], 0
+    for m in sizes:
+        blk = flat[off:off + plan.N * m * m].view(plan.N, m, m).transpose(1, 2)  # column-major
+        outs.append(blk)
+        off += plan.N * m * m
+    return outs
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class GrapeFidelity(torch.autograd.Function):
+        """F(u) with the library's exact adjoint gradient (segment recompute inside the plan)."""
+
+        @staticmethod
+        def forward(ctx, u, plan, psi0, psif):
+            out, grad = fidelity_grad(plan, u.detach(), psi0, psif)
+            ctx.save_for_backward(grad)
+            return out[0].clone()
+
+        @staticmethod
+        def backward(ctx, gF):
+            (grad,) = ctx.saved_tensors
+            return gF * grad, None, None, None
+
+    return GrapeFidelity
+
+
+class _Lazy:
+    _fn = None
+
+    def apply(self, *a):
+        if _Lazy._fn is None:
+            _Lazy._fn = _autograd_function()
+        return _Lazy._fn.apply(*a)
+
+
+GrapeFidelity = _Lazy()

@@ -1,0 +1,39 @@
+"""Shared test helpers: oracle systems and panel layout (column-major m x d per block)."""
+import numpy as np
+
+import qoc_workloads as W
+from oracle import grape
+
+
+def flat_from_panels(panels):
+    return np.concatenate([np.asarray(P).flatten(order="F") for P in panels])
+
+
+def panels_from_flat(blocks, flat):
+    out, off = [], 0
+    for b in blocks:
+        s = b["m"] * b["d"]
+        out.append(np.asarray(flat[off:off + s]).reshape(b["d"], b["m"]).T)
+        off += s
+    return out
+
+
+def plain_states(blocks, rng):
+    """psi0 = first basis state of the first block (all-up), psi_f Gaussian in the first block."""
+    m0 = blocks[0]["m"]
+    pf = W.gaussian_panel(rng, m0)
+    psif = [pf[:, None]] + [np.zeros((b["m"], b["d"]), complex) for b in blocks[1:]]
+    psi0 = [np.eye(m0, dtype=complex)[:, [0]]] + [np.zeros((b["m"], b["d"]), complex) for b in blocks[1:]]
+    return psi0, psif
+
+
+def all_states(blocks, rng):
+    """psi_f then psi0: independent normalised Gaussians over every block and copy."""
+    D = sum(b["m"] * b["d"] for b in blocks)
+    vf = W.gaussian_panel(rng, D)
+    v0 = W.gaussian_panel(rng, D)
+    return panels_from_flat(blocks, v0), panels_from_flat(blocks, vf)
+
+
+def oracle_blocks(n, h0, hk, group="dihedral", stride=1):
+    return grape.block_system(n, h0, hk, group, stride, "convention")
