@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""GRAPE slices*blocks/s (objective + exact gradient) on one MI355X.
+
+Workload (synthetic, seeded): 12-qubit Heisenberg ring H0 = 0.5 sum sz + J sum (xx+yy+zz)
+with J ~ U[0.5, 1.5], two global controls u_x sum sx, u_y sum sy with u ~ U[-2, 2],
+N = 1000 slices of dt = 0.02, block-reduced under D_12 (9 distinct irreducible blocks,
+128..346 wide; E blocks carry two copies); psi0 and psi_f are independent normalised
+complex Gaussians over every block, so every block carries work.
+
+One step = one full hot-path call: all slice propagators (complex64 MFMA, FP64 norms),
+forward sweep, objective (FP64), backward sweep and exact gradient (FP64 accumulation).
+value = (slices x distinct blocks) per second of the timed steps.  The FP64 (complex128)
+path is timed beside it.  The roofline entry covers the dominant kernel, the propagator
+GEMM: algorithmic flops 8 m^3 per complex m x m product, with the products each slice
+needs for its (degree, squarings) choice, over its summed launch time measured with HIP
+events on the launch stream during the timed steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MFMA_PEAK = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix TFLOP/s, MI355X
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--cpu-slices", type=int, default=32, help="oracle sample size (slices, all blocks)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def build_problem(q, W, torch):
+    w = W.config2(seed=0, variant="all")
+    rng = w.notes["rng"]
+    B = q.Basis(12, "dihedral", 1)
+    S = q.System(B, w.h0, w.hk)
+    vf = W.gaussian_panel(rng, B.dim)
+    v0 = W.gaussian_panel(rng, B.dim)
+    dev = dict(u=torch.tensor(w.u, device="cuda"), psi0=torch.tensor(v0, device="cuda"),
+               psif=torch.tensor(vf, device="cuda"))
+    return w, B, S, v0, vf, dev
+
+
+def timed_steps(q, torch, plan, dev, steps, warmup):
+    for _ in range(warmup):
+        q.fidelity_grad(plan, dev["u"], dev["psi0"], dev["psif"])
+    torch.cuda.synchronize()
+    q.profile_begin(steps * 4096)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        out, grad = q.fidelity_grad(plan, dev["u"], dev["psi0"], dev["psif"], check=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = q.profile_end()
+    q.check_flags(out)
+    return e0.elapsed_time(e1) / steps, wall, prof, out, grad
+
+
+def gemm_flops(q, plan, dev, sizes):
+    """Algorithmic flops of the propagator GEMMs of one call (8 m^3 per complex product)."""
+    qs, ss, _ = q.slice_stats(plan, dev["u"])
+    r = plan.info["taylor_step"]
+    tot = 0.0
+    for b, m in enumerate(sizes):
+        prods = (r - 1) + (qs[b] - 1) + ss[b]
+        tot += 8.0 * m ** 3 * float(prods.sum())
+    return tot, qs, ss
+
+
+def cpu_baseline(w, v0, vf, nslices):
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import grape as og
+    ob = og.block_system(12, w.h0, w.hk)
+
+    def panels(v):
+        out, off = [], 0
+        for b in ob:
+            s = b["m"] * b["d"]
+            out.append(v[off:off + s].reshape(b["d"], b["m"]).T)
+            off += s
+        return out
+
+    t0 = time.perf_counter()
+    og.fidelity_grad(ob, w.u[:nslices], w.dt, panels(v0), panels(vf))
+    el = time.perf_counter() - t0
+    threads = max([i["num_threads"] for i in threadpool_info()] or [1])
+    return {"value": nslices * len(ob) / el, "unit": "slices*blocks/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {nslices} of {w.N} slices, all {len(ob)} blocks, FP64 eigendecomposition "
+                      f"propagators and Daleckii-Krein gradient ({el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (each GPU would take its own "
+              "share of blocks or problems); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2309_05884_amd as q
+    import qoc_workloads as W
+
+    torch.cuda.set_device(0)
+    w, B, S, v0, vf, dev = build_problem(q, W, torch)
+    nblocks = len(B.sizes)
+    units = w.N * nblocks
+    print(f"[bench] blocks {B.sizes} copies {B.copies}", file=sys.stderr, flush=True)
+
+    P32 = q.Plan(S, "c64", w.N, w.dt, 2.0)
+    print(f"[bench] c64 plan {P32.info} workspace {P32.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    ms32, wall32, prof32, out32, grad32 = timed_steps(q, torch, P32, dev, args.steps, args.warmup)
+    flops32, qs32, ss32 = gemm_flops(q, P32, dev, B.sizes)
+    print(f"[bench] c64 {ms32:.2f} ms/step  profile {prof32}", file=sys.stderr, flush=True)
+    del P32
+    torch.cuda.empty_cache()
+
+    P64 = q.Plan(S, "c128", w.N, w.dt, 2.0)
+    ms64, wall64, prof64, out64, grad64 = timed_steps(q, torch, P64, dev, args.fp64_steps, 1)
+    flops64, _, _ = gemm_flops(q, P64, dev, B.sizes)
+    print(f"[bench] c128 {ms64:.2f} ms/step  profile {prof64}", file=sys.stderr, flush=True)
+    del P64
+
+    gemm_ms, gemm_n = prof32["propagator_gemm"]
+    achieved = flops32 * args.steps / (gemm_ms * 1e-3) / 1e12
+    gemm64_ms, _ = prof64["propagator_gemm"]
+    achieved64 = flops64 * args.fp64_steps / (gemm64_ms * 1e-3) / 1e12
+    dF = abs(out32[0].item() - out64[0].item())
+    g64 = grad64.cpu()
+    dg = float((grad32.cpu() - g64).abs().max() / g64.abs().max())
+
+    line = {
+        "metric": "GRAPE slices*blocks/sec (fidelity+gradient), FP32-batched vs FP64, |dF|<=1e-6",
+        "value": units / (ms32 * 1e-3),
+        "unit": "slices*blocks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ring12_heisenberg_D12_allblocks", "n": 12, "group": "D12", "slices": w.N,
+                   "dt": w.dt, "controls": 2, "blocks": B.sizes, "copies": B.copies, "J": round(w.J, 6),
+                   "precision": "complex64 MFMA products; FP64 norms, objective and gradient accumulation"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK["c64"], "unit": "TFLOP/s",
+                     "frac": achieved / MFMA_PEAK["c64"], "traffic": None,
+                     "kernel": "k_expm_step<float>", "launches": gemm_n,
+                     "alg_flops_per_step": flops32, "kernel_ms_per_step": gemm_ms / args.steps},
+        "fp64": {"value": units / (ms64 * 1e-3), "ms_per_step": ms64, "steps": args.fp64_steps,
+                 "gemm_tflops": achieved64, "gemm_frac": achieved64 / MFMA_PEAK["c128"]},
+        "fp32_vs_fp64": {"speedup": ms64 / ms32, "dF": dF, "grad_rel_err": dg, "F64": out64[0].item()},
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, v0, vf, args.cpu_slices)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

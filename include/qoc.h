@@ -188,6 +188,24 @@ qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi
                              const void* psif_dev, double* out_dev, double* grad_dev,
                              void* workspace, size_t workspace_bytes, void* stream);
 
+/* Benchmark instrumentation (process-wide, not thread-safe while enabled).
+ * qoc_profile_begin pre-creates HIP events for up to max_launches kernel launches and
+ * enables recording: every kernel the hot-path calls enqueue is bracketed by events on
+ * the launch stream.  qoc_profile_end synchronises on them, disables recording and
+ * writes, per kernel kind, the summed duration in milliseconds and the launch count:
+ * [0] generator + norm, [1] propagator GEMM (powers, Horner, squarings), [2] Horner
+ * initial term, [3] forward sweep, [4] backward sweep, [5] objective, [6] gradient
+ * GEMM, [7] gradient vector kernels, [8] gradient reduction, [9] other. */
+qoc_status qoc_profile_begin(int max_launches);
+qoc_status qoc_profile_end(double* ms, int64_t* launches, int cap);
+
+/* Per block and slice (host arrays [nblocks][N]): the Taylor degree multiple q (degree
+ * q * r), squaring count s and FP64 norm dt*||H0 + sum_k u[j,k] H_k||_1 that the plan's
+ * propagators pick for these controls (the algorithmic work of Eq. (3)'s exponentials).
+ * Synchronises `stream`. */
+qoc_status qoc_plan_slice_stats(qoc_plan plan, const double* u_dev, int32_t* q, int32_t* s, double* norms,
+                                void* stream);
+
 /* Status text and the calling thread's last error detail. */
 const char* qoc_status_string(qoc_status status);
 const char* qoc_last_error(void);

@@ -20,7 +20,7 @@ from . import _capi as C
 from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "propagate", "GrapeFidelity", "QocError",
-           "library_path"]
+           "library_path", "profile_begin", "profile_end", "slice_stats"]
 
 library_path = C.LIB_PATH
 
@@ -147,6 +147,37 @@ class Plan:
         if getattr(self, "_h", None) and C._lib is not None:
             C._lib.qoc_plan_free(self._h)
             self._h = None
+
+
+PROFILE_KINDS = ["generator", "propagator_gemm", "horner_init", "sweep_fwd", "sweep_bwd", "objective",
+                 "gradient_gemm", "gradient_vector", "gradient_finish", "other"]
+
+
+def profile_begin(max_launches: int = 100000):
+    """Start recording HIP events around every hot-path kernel launch (benchmarks only)."""
+    C.check(C.lib().qoc_profile_begin(int(max_launches)))
+
+
+def profile_end():
+    """Stop recording; {kind: (total_ms, launches)} over the recorded launches."""
+    ms = (ctypes.c_double * 10)()
+    cnt = (ctypes.c_int64 * 10)()
+    C.check(C.lib().qoc_profile_end(ms, cnt, 10))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_KINDS)}
+
+
+def slice_stats(plan: "Plan", u):
+    """(q, s, norm) arrays of shape (nblocks, N): the propagators' degree multiple, squarings, norm."""
+    torch = _torch()
+    u = u.to(torch.float64).contiguous()
+    nb = len(plan.system.basis.sizes)
+    q = np.zeros((nb, plan.N), dtype=np.int32)
+    s = np.zeros((nb, plan.N), dtype=np.int32)
+    nrm = np.zeros((nb, plan.N), dtype=np.float64)
+    C.check(C.lib().qoc_plan_slice_stats(plan._h, _ptr(u), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         nrm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
+    return q, s, nrm
 
 
 def check_flags(out):

@@ -72,6 +72,7 @@ struct qoc_plan_s {
   int entries_per_seg = 0;
   int max_mpd = 0;
   size_t off_gacc = 0;
+  size_t sweep_lds_elems = 0;
   int max_cc = 0;
   std::vector<qoc::JobDev> jobs;
   std::vector<qoc::PanelDesc> panels;
@@ -94,6 +95,37 @@ __device__ inline T* tplane(char* ws, size_t off_T, long long elem_off) {
 }
 
 // ===================================================================== generator + norm
+// 1-norm of H0 + sum_k u_k H_k (FP64): one wave per column, lanes over rows (coalesced),
+// then the largest column sum over the work-group.  red: 256 doubles of LDS.
+__device__ inline double block_col_norm(const double* H, size_t plane, int mp, int m, int K, const double* uj,
+                                        double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double cmax = 0.0;
+  for (int c = wave; c < m; c += nw) {
+    double cs = 0.0;
+    for (int rr = lane; rr < m; rr += 64) {
+      const size_t idx = (size_t)rr + (size_t)c * mp;
+      double hr = 0.0, hi = 0.0;
+      for (int o = 0; o <= K; ++o) {
+        hr += uj[o] * H[(size_t)(2 * o) * plane + idx];
+        hi += uj[o] * H[(size_t)(2 * o + 1) * plane + idx];
+      }
+      cs += hypot(hr, hi);
+    }
+    cs = warp_sum(cs);
+    cmax = fmax(cmax, cs);
+  }
+  red[threadIdx.x] = cmax;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double v = red[0];
+  __syncthreads();
+  return v;
+}
+
 // One work-group per entry (job, slice of the segment).  Pass 1: FP64 column sums of
 // |H_j| (exact 1-norm), Pass 2: Y = -i dt 2^-s H_j in the working precision.
 template <typename T>
@@ -120,28 +152,9 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
     uj[k + 1] = u[(size_t)j * K + k];
     finite = finite && isfinite(uj[k + 1]);
   }
-  double cmax = 0.0;
-  for (int c = threadIdx.x; c < m; c += blockDim.x) {
-    double cs = 0.0;
-    for (int rr = 0; rr < m; ++rr) {
-      size_t idx = (size_t)rr + (size_t)c * mp;
-      double hr = 0.0, hi = 0.0;
-      for (int o = 0; o <= K; ++o) {
-        hr += uj[o] * H[(size_t)(2 * o) * plane + idx];
-        hi += uj[o] * H[(size_t)(2 * o + 1) * plane + idx];
-      }
-      cs += hypot(hr, hi);
-    }
-    cmax = fmax(cmax, cs);
-  }
-  red[threadIdx.x] = cmax;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
+  const double cmax = block_col_norm(H, plane, mp, m, K, uj, red);
   if (threadIdx.x == 0) {
-    double nx = dt * red[0];
+    double nx = dt * cmax;
     int flag = 0;
     if (!finite || !isfinite(nx)) flag |= 2;
     if (nx > norm_bound * (1.0 + 1e-12)) flag |= 1;
@@ -163,7 +176,7 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
   }
   __syncthreads();
   const double scale = ldexp(dt, -sq[0]);
-  const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
+  const size_t ent_stride = (size_t)(r + 3) * 2 * plane;
   T* Yre = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * ent_stride;
   T* Yim = Yre + plane;
   for (size_t idx = threadIdx.x; idx < plane; idx += blockDim.x) {
@@ -215,9 +228,10 @@ __global__ void __launch_bounds__(256) k_expm_step(const JobDev* jobs, int njobs
       const int h = qe - 1 + step - 1;
       ia = r + (h & 1); ib = ia; ic = r + ((h + 1) & 1);
     }
+    const bool final_op = (mode == STEP_SQUARE && step == se) || (mode == STEP_HORNER && se == 0 && step == qe - 1);
     const int mp = jb.mp;
     const size_t plane = (size_t)mp * mp;
-    T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 2) * 2 * plane;
+    T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
     TileOperands<T> op;
     op.A = base + (size_t)ia * 2 * plane;
     op.a_ps = plane;
@@ -242,29 +256,39 @@ __global__ void __launch_bounds__(256) k_expm_step(const JobDev* jobs, int njobs
     for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
       for (int ci = 0; ci < 2; ++ci) {
-        const int row = acc_row(op.row0, ri, 0);
+        const int rbase = acc_row_base(op.row0, ri);
         const int col = acc_col(op.col0, ci);
-        if (row >= mp || col >= mp) continue;
+        if (rbase >= mp || col >= mp) continue;
         typename Vec4<T>::type vr = acc.re[ri][ci], vi = acc.im[ri][ci];
         if (mode == STEP_HORNER) {
           for (int i = 1; i < r; ++i) {
             const T* P = base + (size_t)(i - 1) * 2 * plane;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const size_t idx = (size_t)(row + v) + (size_t)col * mp;
+              const size_t idx = (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
               vr[v] += (T)coef[i] * P[idx];
               vi[v] += (T)coef[i] * P[idx + plane];
             }
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (row + v == col && col < jb.m) vr[v] += (T)coef[0];
+            if (rbase + acc_row_off<T>(v) == col && col < jb.m) vr[v] += (T)coef[0];
         }
-        T* cr = C + (size_t)row + (size_t)col * mp;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          cr[v] = vr[v];
-          cr[v + plane] = vi[v];
+          T* cr = C + (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
+          cr[0] = vr[v];
+          cr[plane] = vi[v];
+        }
+        if (final_op) {
+          // conjugate transpose for the backward sweep: Udag[col][row] = conj(U[row][col])
+          T* D = base + (size_t)(r + 2) * 2 * plane;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            T* dr = D + (size_t)col + (size_t)(rbase + acc_row_off<T>(v)) * mp;
+            dr[0] = vr[v];
+            dr[plane] = -vi[v];
+          }
         }
       }
   }
@@ -273,7 +297,7 @@ __global__ void __launch_bounds__(256) k_expm_step(const JobDev* jobs, int njobs
 // T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1) r + i} Y^i (elementwise), one work-group per entry
 template <typename T>
 __global__ void __launch_bounds__(256) k_horner_init(const JobDev* jobs, int njobs, char* ws, size_t off_T,
-                                                     const int* ent_q, int r, int seg_len) {
+                                                     const int* ent_s, const int* ent_q, int r, int seg_len) {
   const int e = blockIdx.x;
   int J = 0;
   while (J + 1 < njobs && jobs[J + 1].ent_off <= e) ++J;
@@ -281,9 +305,10 @@ __global__ void __launch_bounds__(256) k_horner_init(const JobDev* jobs, int njo
   const int jl = e - (int)jb.ent_off;
   if (jl >= seg_len) return;
   const int q = ent_q[e];
+  const bool final_op = q == 1 && ent_s[e] == 0;
   const int mp = jb.mp, m = jb.m;
   const size_t plane = (size_t)mp * mp;
-  T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 2) * 2 * plane;
+  T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
   T* Tout = base + (size_t)r * 2 * plane;
   const T ctop = (T)kInvFact[q * r];
   T c[8];
@@ -299,13 +324,18 @@ __global__ void __launch_bounds__(256) k_horner_init(const JobDev* jobs, int njo
     if (rr == cc && rr < m) vr += c[0];
     Tout[idx] = vr;
     Tout[idx + plane] = vi;
+    if (final_op) {
+      T* D = base + (size_t)(r + 2) * 2 * plane;
+      D[(size_t)cc + (size_t)rr * mp] = vr;
+      D[(size_t)cc + (size_t)rr * mp + plane] = -vi;
+    }
   }
 }
 
 template <typename T>
 __device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int jl, int r, int s, int q) {
   const size_t plane = (size_t)jb.mp * jb.mp;
-  const T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 2) * 2 * plane;
+  const T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
   return base + (size_t)(r + ((q - 1 + s) & 1)) * 2 * plane;
 }
 
@@ -344,129 +374,112 @@ __global__ void k_zero_ints(int* p, int n) {
 }
 
 // ===================================================================== sweeps
-// Forward: one work-group (1024 threads) per job; psi in LDS; thread per output row.
-template <typename T>
-__global__ void __launch_bounds__(1024) k_sweep_fwd(const JobDev* jobs, int njobs, char* ws, size_t off_T,
-                                                    const int* ent_s, const int* ent_q, int r, int seg_j0,
-                                                    int seg_len, int N) {
-  extern __shared__ char smem_raw[];
-  const int J = blockIdx.x;
-  if (J >= njobs) return;
-  const JobDev jb = jobs[J];
-  const int m = jb.m, mp = jb.mp, d = jb.d;
-  T* sre = reinterpret_cast<T*>(smem_raw);  // [d][mp]
-  T* sim = sre + (size_t)d * mp;
-  const long long ncol = (long long)(N + 1) * d;
-  T* P = tplane<T>(ws, off_T, jb.psi_off);
-  const size_t ps = (size_t)mp * ncol;
-  for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
-    const int c = idx / mp, i = idx % mp;
-    const size_t g = ((size_t)seg_j0 * d + c) * mp + i;
-    sre[idx] = P[g];
-    sim[idx] = P[g + ps];
-  }
-  __syncthreads();
-  constexpr int RPT = 3;  // rows per thread (mp <= 3072)
-  for (int jl = 0; jl < seg_len; ++jl) {
-    const int e = (int)jb.ent_off + jl;
-    const T* U = entry_U<T>(jb, ws, off_T, jl, r, ent_s[e], ent_q[e]);
-    const size_t plane = (size_t)mp * mp;
-    T accr[RPT][2], acci[RPT][2];
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) accr[q][0] = accr[q][1] = acci[q][0] = acci[q][1] = T(0);
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int i = threadIdx.x + q * blockDim.x;
-      if (i >= m) continue;
-      for (int k = 0; k < m; ++k) {
-        const T ur = U[(size_t)i + (size_t)k * mp], ui = U[(size_t)i + (size_t)k * mp + plane];
-        for (int c = 0; c < d; ++c) {
-          const T pr = sre[c * mp + k], pi = sim[c * mp + k];
-          accr[q][c] += ur * pr - ui * pi;
-          acci[q][c] += ur * pi + ui * pr;
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const int i = threadIdx.x + q * blockDim.x;
-      if (i >= mp) continue;
-      for (int c = 0; c < d; ++c) {
-        const T vr = i < m ? accr[q][c] : T(0), vi = i < m ? acci[q][c] : T(0);
-        sre[c * mp + i] = vr;
-        sim[c * mp + i] = vi;
-        const size_t g = ((size_t)(seg_j0 + jl + 1) * d + c) * mp + i;
-        P[g] = vr;
-        P[g + ps] = vi;
-      }
-    }
-    __syncthreads();
-  }
+// Sweep through one segment, one work-group (16 waves) per block, the state in LDS.
+// DIR 0: psi_{j+1} = U_j psi_j from the forward store; DIR 1: lambda_j = U_j^dag
+// lambda_{j+1} with the conjugate transpose written by the last product of each slice,
+// so both directions read their matrix column by column (coalesced across lanes).
+// Wave w covers 64 rows and one of G k-ranges; partial sums meet in LDS.
+__host__ __device__ inline int sweep_kgroups(int mp) {
+  const int R = (mp + 63) / 64;
+  return R >= 16 ? 1 : 16 / R;
 }
 
-// Backward: lambda_j = U_j^dag lambda_{j+1}; one wave per output row (lanes over k).
-// Costate store column j holds lambda_{j+1}.
-template <typename T>
-__global__ void __launch_bounds__(1024) k_sweep_bwd(const JobDev* jobs, int njobs, char* ws, size_t off_T,
-                                                    const int* ent_s, const int* ent_q, int r, int seg_j0,
-                                                    int seg_len, int N) {
+template <typename T, int DIR>
+__global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, char* ws, size_t off_T,
+                                                const int* ent_s, const int* ent_q, int r, int seg_j0, int seg_len,
+                                                int N) {
   extern __shared__ char smem_raw[];
   const int J = blockIdx.x;
   if (J >= njobs) return;
   const JobDev jb = jobs[J];
   const int m = jb.m, mp = jb.mp, d = jb.d;
-  T* lre = reinterpret_cast<T*>(smem_raw);  // [d][mp]
-  T* lim = lre + (size_t)d * mp;
-  T* ore = lim + (size_t)d * mp;
-  T* oim = ore + (size_t)d * mp;
-  const long long ncol = (long long)N * d;
-  T* Lm = tplane<T>(ws, off_T, jb.lam_off);
+  const int R = (mp + 63) / 64, G = sweep_kgroups(mp);
+  T* sre = reinterpret_cast<T*>(smem_raw);  // state [d][mp]
+  T* sim = sre + (size_t)d * mp;
+  T* pre = sim + (size_t)d * mp;             // partial sums [G][d][mp]
+  T* pim = pre + (size_t)G * d * mp;
+  T* S = tplane<T>(ws, off_T, DIR == 0 ? jb.psi_off : jb.lam_off);
+  const size_t ncol = DIR == 0 ? (size_t)(N + 1) * d : (size_t)N * d;
   const size_t ps = (size_t)mp * ncol;
-  const int jtop = seg_j0 + seg_len - 1;  // column holding lambda_{jtop+1}
+  const int col_in = DIR == 0 ? seg_j0 : seg_j0 + seg_len - 1;
   for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
     const int c = idx / mp, i = idx % mp;
-    const size_t g = ((size_t)jtop * d + c) * mp + i;
-    lre[idx] = Lm[g];
-    lim[idx] = Lm[g + ps];
+    const size_t g = ((size_t)col_in * d + c) * mp + i;
+    sre[idx] = S[g];
+    sim[idx] = S[g + ps];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int jl = seg_len - 1; jl >= 0; --jl) {
-    const int j = seg_j0 + jl;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kchunk = (m + G - 1) / G;
+  const size_t plane = (size_t)mp * mp;
+  for (int it = 0; it < seg_len; ++it) {
+    const int jl = DIR == 0 ? it : seg_len - 1 - it;
     const int e = (int)jb.ent_off + jl;
-    const T* U = entry_U<T>(jb, ws, off_T, jl, r, ent_s[e], ent_q[e]);
-    const size_t plane = (size_t)mp * mp;
-    for (int i = wave; i < mp; i += nw) {
-      double sr[2] = {0.0, 0.0}, si[2] = {0.0, 0.0};
+    const T* Ub = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
+    const T* U = DIR == 0 ? Ub + (size_t)(r + ((ent_q[e] - 1 + ent_s[e]) & 1)) * 2 * plane
+                          : Ub + (size_t)(r + 2) * 2 * plane;
+    for (int task = wave; task < R * G; task += 16) {
+      const int rg = task % R, kg = task / R;
+      const int i = rg * 64 + lane;
+      const int k0 = kg * kchunk, k1 = min(m, k0 + kchunk);
+      T ar0 = T(0), ai0 = T(0), ar1 = T(0), ai1 = T(0);
       if (i < m) {
-        for (int k = lane; k < m; k += 64) {
-          const T ur = U[(size_t)k + (size_t)i * mp], ui = U[(size_t)k + (size_t)i * mp + plane];
-          for (int c = 0; c < d; ++c) {
-            const T lr = lre[c * mp + k], li = lim[c * mp + k];
-            // conj(u) * l
-            sr[c] += (double)(ur * lr + ui * li);
-            si[c] += (double)(ur * li - ui * lr);
+        const T* col = U + i;
+        int k = k0;
+        for (; k + 8 <= k1; k += 8) {
+          T ur[8], ui[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            ur[q] = col[(size_t)(k + q) * mp];
+            ui[q] = col[(size_t)(k + q) * mp + plane];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const T p0r = sre[k + q], p0i = sim[k + q];
+            ar0 += ur[q] * p0r - ui[q] * p0i;
+            ai0 += ur[q] * p0i + ui[q] * p0r;
+            if (d > 1) {
+              const T p1r = sre[mp + k + q], p1i = sim[mp + k + q];
+              ar1 += ur[q] * p1r - ui[q] * p1i;
+              ai1 += ur[q] * p1i + ui[q] * p1r;
+            }
+          }
+        }
+        for (; k < k1; ++k) {
+          const T ur = col[(size_t)k * mp], ui = col[(size_t)k * mp + plane];
+          ar0 += ur * sre[k] - ui * sim[k];
+          ai0 += ur * sim[k] + ui * sre[k];
+          if (d > 1) {
+            ar1 += ur * sre[mp + k] - ui * sim[mp + k];
+            ai1 += ur * sim[mp + k] + ui * sre[mp + k];
           }
         }
       }
-      for (int c = 0; c < d; ++c) {
-        const double a = warp_sum(sr[c]), b = warp_sum(si[c]);
-        if (lane == 0) {
-          ore[c * mp + i] = (T)a;
-          oim[c * mp + i] = (T)b;
+      if (i < mp) {
+        pre[((size_t)kg * d) * mp + i] = ar0;
+        pim[((size_t)kg * d) * mp + i] = ai0;
+        if (d > 1) {
+          pre[((size_t)kg * d + 1) * mp + i] = ar1;
+          pim[((size_t)kg * d + 1) * mp + i] = ai1;
         }
       }
     }
     __syncthreads();
+    const int col_out = DIR == 0 ? seg_j0 + jl + 1 : seg_j0 + jl - 1;
     for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
-      lre[idx] = ore[idx];
-      lim[idx] = oim[idx];
-      if (j >= 1) {
-        const int c = idx / mp, i = idx % mp;
-        const size_t g = ((size_t)(j - 1) * d + c) * mp + i;
-        Lm[g] = ore[idx];
-        Lm[g + ps] = oim[idx];
+      const int c = idx / mp, i = idx % mp;
+      T vr = T(0), vi = T(0);
+      if (i < m)
+        for (int kg = 0; kg < G; ++kg) {
+          vr += pre[((size_t)kg * d + c) * mp + i];
+          vi += pim[((size_t)kg * d + c) * mp + i];
+        }
+      sre[idx] = vr;
+      sim[idx] = vi;
+      if (col_out >= 0) {
+        const size_t g = ((size_t)col_out * d + c) * mp + i;
+        S[g] = vr;
+        S[g + ps] = vi;
       }
     }
     __syncthreads();
@@ -560,14 +573,14 @@ __global__ void __launch_bounds__(256) k_panel_gemm(const JobDev* jobs, const Pa
     for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
       for (int ci = 0; ci < 2; ++ci) {
-        const int row = acc_row(op.row0, ri, 0);
+        const int rbase = acc_row_base(op.row0, ri);
         const int col = acc_col(op.col0, ci);
-        if (row >= mp || col >= jb.cc) continue;
-        T* cr = C + (size_t)row + (size_t)col * mp;
+        if (rbase >= mp || col >= jb.cc) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          cr[v] = acc.re[ri][ci][v];
-          cr[v + vplane] = acc.im[ri][ci][v];
+          T* cr = C + (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
+          cr[0] = acc.re[ri][ci][v];
+          cr[vplane] = acc.im[ri][ci][v];
         }
       }
   }
@@ -771,6 +784,66 @@ __global__ void k_slot_axpy(const JobDev* jobs, int njobs, char* ws, size_t off_
     g[(size_t)dst * jb.gslot + idx] += g[(size_t)src * jb.gslot + idx];
 }
 
+// ===================================================================== profiler
+// Opt-in, process-wide launch timing for benchmarks: HIP events from a pre-created
+// pool are recorded on the launch stream around each kernel of the hot path.
+enum ProfKind {
+  PK_GENERATOR = 0, PK_EXPM_GEMM = 1, PK_HORNER_INIT = 2, PK_SWEEP_FWD = 3, PK_SWEEP_BWD = 4,
+  PK_OVERLAP = 5, PK_GRAD_GEMM = 6, PK_GRAD_VECTOR = 7, PK_GRAD_FINISH = 8, PK_OTHER = 9, PK_COUNT = 10
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::mutex mu;
+};
+static Profiler g_prof;
+
+template <class F>
+static void timed(int kind, hipStream_t st, F&& launch) {
+  if (g_prof.on && g_prof.used + 2 <= g_prof.pool.size()) {
+    hipEvent_t a = g_prof.pool[g_prof.used++], b = g_prof.pool[g_prof.used++];
+    QOC_HIP(hipEventRecord(a, st));
+    launch();
+    QOC_HIP(hipEventRecord(b, st));
+    g_prof.recs.push_back({kind, a, b});
+  } else {
+    launch();
+  }
+}
+
+// Norms and (q, s) choice of every slice, without forming the generators.
+__global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njobs, const double* H64, const double* u,
+                                                     int K, double dt, int N, const double* theta, int r, int qmax,
+                                                     int* q_out, int* s_out, double* n_out) {
+  __shared__ double red[256];
+  const int J = blockIdx.y, j = blockIdx.x;
+  if (J >= njobs || j >= N) return;
+  const JobDev jb = jobs[J];
+  const int m = jb.m, mp = jb.mp;
+  const size_t plane = (size_t)mp * mp;
+  const double* H = H64 + jb.h_off;
+  double uj[17];
+  uj[0] = 1.0;
+  for (int k = 0; k < K; ++k) uj[k + 1] = u[(size_t)j * K + k];
+  const double cmax = block_col_norm(H, plane, mp, m, K, uj, red);
+  if (threadIdx.x == 0) {
+    double nx = dt * cmax;
+    int best_q = qmax, best_s = 0, best_cost = 1 << 30;
+    for (int q = qmax; q >= 1; --q) {
+      int s = 0;
+      while (s < 62 && nx > ldexp(theta[q * r], s)) ++s;
+      if ((q - 1) + s < best_cost) { best_cost = (q - 1) + s; best_q = q; best_s = s; }
+    }
+    q_out[(size_t)J * N + j] = best_q;
+    s_out[(size_t)J * N + j] = best_s;
+    n_out[(size_t)J * N + j] = nx;
+  }
+}
+
 // ===================================================================== host driver
 static double fact(int n) {
   double f = 1.0;
@@ -810,26 +883,26 @@ struct Driver {
     const JobDev* dj = P->d_jobs.as<JobDev>();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     const int nent = P->entries_per_seg;
-    hipLaunchKernelGGL(k_generator<T>, dim3(nent), dim3(256), 0, st, dj, njobs, P->sys->h64.as<double>(), u, P->K,
+    timed(PK_GENERATOR, st, [&] { hipLaunchKernelGGL(k_generator<T>, dim3(nent), dim3(256), 0, st, dj, njobs, P->sys->h64.as<double>(), u, P->K,
                        P->dt, seg_j0, seg_len, P->N, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags,
-                       P->d_theta.as<double>(), P->r, P->qmax, P->smax, P->norm_bound);
+                       P->d_theta.as<double>(), P->r, P->qmax, P->smax, P->norm_bound); });
     QOC_HIP(hipGetLastError());
     const dim3 grid(P->grid_gemm);
     for (int i = 2; i <= P->r; ++i)
-      hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
-                         ent_q(P, ws), (int)STEP_POWER, i, P->r, seg_len);
-    hipLaunchKernelGGL(k_horner_init<T>, dim3(nent), dim3(256), 0, st, dj, njobs, ws, P->off_T, ent_q(P, ws), P->r,
-                       seg_len);
+      timed(PK_EXPM_GEMM, st, [&] { hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
+                         ent_q(P, ws), (int)STEP_POWER, i, P->r, seg_len); });
+    timed(PK_HORNER_INIT, st, [&] { hipLaunchKernelGGL(k_horner_init<T>, dim3(nent), dim3(256), 0, st, dj, njobs, ws, P->off_T, ent_s(P, ws), ent_q(P, ws),
+                       P->r, seg_len); });
     for (int t = 1; t <= P->qmax - 1; ++t)
-      hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
-                         ent_q(P, ws), (int)STEP_HORNER, t, P->r, seg_len);
+      timed(PK_EXPM_GEMM, st, [&] { hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
+                         ent_q(P, ws), (int)STEP_HORNER, t, P->r, seg_len); });
     for (int t = 1; t <= P->smax; ++t)
-      hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
-                         ent_q(P, ws), (int)STEP_SQUARE, t, P->r, seg_len);
+      timed(PK_EXPM_GEMM, st, [&] { hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
+                         ent_q(P, ws), (int)STEP_SQUARE, t, P->r, seg_len); });
     QOC_HIP(hipGetLastError());
   }
 
-  static size_t sweep_lds(const qoc_plan_s* P, int bufs) { return (size_t)bufs * 2 * P->max_mpd * sizeof(T); }
+  static size_t sweep_lds(const qoc_plan_s* P) { return (size_t)P->sweep_lds_elems * sizeof(T); }
 
   static void propagate(qoc_plan_s* P, const double* u, double2* out, const long long* out_off, char* ws,
                         hipStream_t st) {
@@ -839,8 +912,8 @@ struct Driver {
     for (int sg = 0; sg < P->nseg; ++sg) {
       const int j0 = sg * P->seg_len, len = std::min(P->seg_len, P->N - j0);
       expm_segment(P, ws, u, j0, len, st);
-      hipLaunchKernelGGL(k_export_U<T>, dim3(64, P->entries_per_seg), dim3(256), 0, st, P->d_jobs.as<JobDev>(), njobs,
-                         ws, P->off_T, ent_s(P, ws), ent_q(P, ws), P->r, j0, len, P->N, out, out_off);
+      timed(PK_OTHER, st, [&] { hipLaunchKernelGGL(k_export_U<T>, dim3(64, P->entries_per_seg), dim3(256), 0, st, P->d_jobs.as<JobDev>(), njobs,
+                         ws, P->off_T, ent_s(P, ws), ent_q(P, ws), P->r, j0, len, P->N, out, out_off); });
       QOC_HIP(hipGetLastError());
     }
   }
@@ -852,25 +925,25 @@ struct Driver {
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     const int N = P->N;
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);  // status ints only
-    hipLaunchKernelGGL(k_states_in<T>, dim3(8, njobs), dim3(256), 0, st, dj, njobs, (const double2*)psi0,
-                       (const double2*)psif, ws, P->off_T, N, flags);
+    timed(PK_OTHER, st, [&] { hipLaunchKernelGGL(k_states_in<T>, dim3(8, njobs), dim3(256), 0, st, dj, njobs, (const double2*)psi0,
+                       (const double2*)psif, ws, P->off_T, N, flags); });
     QOC_HIP(hipGetLastError());
     // forward: propagators of a segment, then the sequential sweep through it
     for (int sg = 0; sg < P->nseg; ++sg) {
       const int j0 = sg * P->seg_len, len = std::min(P->seg_len, N - j0);
       expm_segment(P, ws, u, j0, len, st);
-      hipLaunchKernelGGL(k_sweep_fwd<T>, dim3(njobs), dim3(1024), sweep_lds(P, 1), st, dj, njobs, ws, P->off_T,
-                         ent_s(P, ws), ent_q(P, ws), P->r, j0, len, N);
+      timed(PK_SWEEP_FWD, st, [&] { hipLaunchKernelGGL((k_sweep<T, 0>), dim3(njobs), dim3(1024), sweep_lds(P), st, dj, njobs, ws, P->off_T,
+                         ent_s(P, ws), ent_q(P, ws), P->r, j0, len, N); });
       QOC_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_overlap<T>, dim3(1), dim3(1024), 0, st, dj, njobs, ws, P->off_T, N, flags, out);
+    timed(PK_OVERLAP, st, [&] { hipLaunchKernelGGL(k_overlap<T>, dim3(1), dim3(1024), 0, st, dj, njobs, ws, P->off_T, N, flags, out); });
     QOC_HIP(hipGetLastError());
     // backward: the last segment's propagators are resident; earlier ones are recomputed
     for (int sg = P->nseg - 1; sg >= 0; --sg) {
       const int j0 = sg * P->seg_len, len = std::min(P->seg_len, N - j0);
       if (sg != P->nseg - 1) expm_segment(P, ws, u, j0, len, st);
-      hipLaunchKernelGGL(k_sweep_bwd<T>, dim3(njobs), dim3(1024), sweep_lds(P, 2), st, dj, njobs, ws, P->off_T,
-                         ent_s(P, ws), ent_q(P, ws), P->r, j0, len, N);
+      timed(PK_SWEEP_BWD, st, [&] { hipLaunchKernelGGL((k_sweep<T, 1>), dim3(njobs), dim3(1024), sweep_lds(P), st, dj, njobs, ws, P->off_T,
+                         ent_s(P, ws), ent_q(P, ws), P->r, j0, len, N); });
       QOC_HIP(hipGetLastError());
     }
     gradient(P, u, out, grad, ws, st);
@@ -888,54 +961,54 @@ struct Driver {
     const PanelDesc* dp = P->d_panels.as<PanelDesc>();
     const int npanel = (int)P->panels.size();
     auto gemm = [&](int vslot) {
-      hipLaunchKernelGGL(k_panel_gemm<T>, dim3(P->grid_gemm), dim3(256), 0, st, dj, dp, npanel, P->panel_items, H, ws,
-                         P->off_T, vslot);
+      timed(PK_GRAD_GEMM, st, [&] { hipLaunchKernelGGL(k_panel_gemm<T>, dim3(P->grid_gemm), dim3(256), 0, st, dj, dp, npanel, P->panel_items, H, ws,
+                         P->off_T, vslot); });
     };
     for (int j0 = 0; j0 < N; j0 += P->chunk) {
       const int ns = std::min(P->chunk, N - j0);
       // b-series, r = R-1 .. 0:  b_0 = lambda^{(r)}, b_{i+1} = +i (dt/R) H_j b_i / (i+1);
       // lambda^{(r-1)} = exp(-Y) lambda^{(r)} = sum_i b_i
-      hipLaunchKernelGGL(k_chunk_load<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, 1, bank0 + (R - 1) * Q, j0,
-                         ns, N);
+      timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_chunk_load<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, 1, bank0 + (R - 1) * Q, j0,
+                         ns, N); });
       for (int rr = R - 1; rr >= 0; --rr) {
         const int bank = bank0 + rr * Q;
         for (int i = 0; i + 1 < Q; ++i) {
           gemm(bank + i);
-          hipLaunchKernelGGL(k_series_combine<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, u, K, j0, ns,
-                             dtR / (i + 1), bank + i + 1, -1, 0);
+          timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_series_combine<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, u, K, j0, ns,
+                             dtR / (i + 1), bank + i + 1, -1, 0); });
         }
         if (rr > 0)
-          hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, bank - Q, bank, Q);
+          timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, bank - Q, bank, Q); });
       }
       QOC_HIP(hipGetLastError());
       // a-series, r = 0 .. R-1: a_0 = psi^{(r)}, a_{t+1} = -i (dt/R) H_j a_t / (t+1);
       // the dot products take every (i, t) with i + t <= Q - 1
-      hipLaunchKernelGGL(k_chunk_load<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, 0, slotA0, j0, ns, N);
+      timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_chunk_load<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, 0, slotA0, j0, ns, N); });
       int cur = slotA0, nxt = slotA1;
       bool first_dot = true;
       for (int rr = 0; rr < R; ++rr) {
         const int bank = bank0 + rr * Q;
         const bool need_next_state = rr + 1 < R;
-        if (need_next_state) hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, slotS, cur, 1);
+        if (need_next_state) timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, slotS, cur, 1); });
         for (int t = 0; t < Q; ++t) {
           gemm(cur);
           const double* wt = P->d_w.as<double>() + (size_t)t * Q;
-          hipLaunchKernelGGL(k_series_dot<T>, dim3((P->max_cc + 3) / 4, njobs), dim3(256), 0, st, dj, njobs, ws,
-                             P->off_T, P->off_gacc, K, bank, Q - t, wt, first_dot ? 1 : 0);
+          timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_series_dot<T>, dim3((P->max_cc + 3) / 4, njobs), dim3(256), 0, st, dj, njobs, ws,
+                             P->off_T, P->off_gacc, K, bank, Q - t, wt, first_dot ? 1 : 0); });
           first_dot = false;
           if (t + 1 < Q || need_next_state) {
-            hipLaunchKernelGGL(k_series_combine<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, u, K, j0, ns,
-                               -dtR / (t + 1), nxt, need_next_state ? slotS : -1, 0);
+            timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_series_combine<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, u, K, j0, ns,
+                               -dtR / (t + 1), nxt, need_next_state ? slotS : -1, 0); });
             std::swap(cur, nxt);
           }
         }
         // a_0 of the next sub-step is psi^{(r+1)} = sum_t a_t, held in slotS
         if (need_next_state)
-          hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, cur, slotS, 1);
+          timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, cur, slotS, 1); });
       }
       QOC_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_grad_finish, dim3((ns * K + 255) / 256), dim3(256), 0, st, dj, njobs, ws, P->off_gacc, K, j0,
-                         ns, dtR, out, grad);
+      timed(PK_GRAD_FINISH, st, [&] { hipLaunchKernelGGL(k_grad_finish, dim3((ns * K + 255) / 256), dim3(256), 0, st, dj, njobs, ws, P->off_gacc, K, j0,
+                         ns, dtR, out, grad); });
       QOC_HIP(hipGetLastError());
     }
   }
@@ -979,10 +1052,25 @@ qoc_status qoc_plan_create(qoc_system S, int precision, int N, double dt, double
     }
     P->norm_bound = nb;
     {
-      double th = theta[P->qmax * P->r];
-      int s = 0;
-      while (s < 62 && nb > std::ldexp(th, s)) ++s;
-      P->smax = s;
+      // squarings the per-slice choice can pick for any norm in (0, nb]: the choice is
+      // piecewise constant between the points theta_{qr} 2^s, so evaluate just above each
+      auto choose_s = [&](double nx) {
+        int best_s = 0, best_cost = 1 << 30;
+        for (int q = P->qmax; q >= 1; --q) {
+          int sq = 0;
+          while (sq < 62 && nx > std::ldexp(theta[q * P->r], sq)) ++sq;
+          if ((q - 1) + sq < best_cost) { best_cost = (q - 1) + sq; best_s = sq; }
+        }
+        return best_s;
+      };
+      int smax = choose_s(nb);
+      for (int q = 1; q <= P->qmax; ++q)
+        for (int sq = 0; sq < 62; ++sq) {
+          const double x = std::ldexp(theta[q * P->r], sq);
+          if (x >= nb) break;
+          smax = std::max(smax, choose_s(std::nextafter(x, 1e300)));
+        }
+      P->smax = smax;
     }
     QOC_REQUIRE(P->smax <= 40, QOC_ERR_NUMERIC, "dt * ||H|| bound too large");
     // Frechet series: R sub-steps with ||Y||_1 <= 2, Q terms with theta^Q / Q! <= unit / 8
@@ -1005,15 +1093,19 @@ qoc_status qoc_plan_create(qoc_system S, int precision, int N, double dt, double
       max_mp = std::max(max_mp, b.mp);
     }
     P->max_mpd = max_mpd;
-    QOC_REQUIRE(max_mp <= 3072, QOC_ERR_UNSUPPORTED, "blocks larger than 3072 are not supported by the sweep kernels");
-    QOC_REQUIRE((size_t)2 * 2 * max_mpd * P->elem <= 160 * 1024, QOC_ERR_UNSUPPORTED,
+    QOC_REQUIRE(max_mp <= 4096, QOC_ERR_UNSUPPORTED, "blocks larger than 4096 are not supported by the sweep kernels");
+    size_t lds_elems = 0;
+    for (auto& b : S->blocks)
+      lds_elems = std::max(lds_elems, (size_t)2 * b.d * b.mp * (1 + sweep_kgroups(b.mp)));
+    P->sweep_lds_elems = lds_elems;
+    QOC_REQUIRE(lds_elems * P->elem <= 160 * 1024, QOC_ERR_UNSUPPORTED,
                 "block panel too large for the LDS-resident sweep");
     const int nslots = S->K + 4 + P->R * P->Q;
     P->nslots = nslots;
     // per-slice bytes: expm buffers + states, per job
     size_t per_slice = 0, fixed = 0;
     for (auto& b : S->blocks) {
-      per_slice += (size_t)(P->r + 2) * 2 * b.mp * b.mp * P->elem;
+      per_slice += (size_t)(P->r + 3) * 2 * b.mp * b.mp * P->elem;
       fixed += (size_t)2 * b.mp * ((size_t)(N + 1) * b.d + (size_t)N * b.d) * P->elem;
     }
     // gradient chunk: columns per job chunk*d rounded to 16, capped at 4096 columns
@@ -1062,7 +1154,7 @@ qoc_status qoc_plan_create(qoc_system S, int precision, int N, double dt, double
       j.item_off = item_off;
       item_off += (long long)P->seg_len * j.tiles * j.tiles;
       j.ebuf_off = tel;
-      tel += (long long)P->seg_len * (P->r + 2) * 2 * b.mp * b.mp;
+      tel += (long long)P->seg_len * (P->r + 3) * 2 * b.mp * b.mp;
       j.psi_off = tel;
       tel += 2LL * b.mp * (N + 1) * b.d;
       j.lam_off = tel;
@@ -1118,14 +1210,14 @@ qoc_status qoc_plan_create(qoc_system S, int precision, int N, double dt, double
     else
       QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_expm_step<float>, 256, 0));
     P->grid_gemm = std::max(8, ncu * std::max(1, occ) / 8 * 8);
-    // the sweeps keep the state panels in LDS; allow the dynamic size beyond 64 KB
-    const int lds_fwd = (int)(2 * (size_t)max_mpd * P->elem), lds_bwd = 2 * lds_fwd;
+    // the sweeps keep the state and partial sums in LDS; allow the dynamic size beyond 64 KB
+    const int lds = (int)(P->sweep_lds_elems * P->elem);
     if (f64) {
-      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_fwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_fwd));
-      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_bwd<double>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bwd));
+      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     } else {
-      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_fwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_fwd));
-      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_bwd<float>, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bwd));
+      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     }
     *out = P.release();
   });
@@ -1146,7 +1238,7 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
     int64_t v[10] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, 0, P->smax, P->chunk,
                      P->grid_gemm};
     size_t per_slice = 0;
-    for (auto& j : P->jobs) per_slice += (size_t)(P->r + 2) * 2 * j.mp * j.mp * P->elem;
+    for (auto& j : P->jobs) per_slice += (size_t)(P->r + 3) * 2 * j.mp * j.mp * P->elem;
     v[6] = (int64_t)per_slice;
     for (int i = 0; i < cap && i < 10; ++i) info[i] = v[i];
   });
@@ -1186,6 +1278,64 @@ qoc_status qoc_fidelity_grad(qoc_plan P, const double* u_dev, const void* psi0_d
       Driver<double>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, st);
     else
       Driver<float>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, st);
+  });
+}
+
+
+qoc_status qoc_profile_begin(int max_launches) {
+  return guarded([&] {
+    QOC_REQUIRE(max_launches >= 0 && max_launches <= (1 << 22), QOC_ERR_INVALID_ARG, "max_launches out of range");
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    size_t want = (size_t)2 * max_launches;
+    while (g_prof.pool.size() < want) {
+      hipEvent_t e;
+      QOC_HIP(hipEventCreate(&e));
+      g_prof.pool.push_back(e);
+    }
+    g_prof.used = 0;
+    g_prof.recs.clear();
+    g_prof.on = true;
+  });
+}
+
+qoc_status qoc_profile_end(double* ms, int64_t* launches, int cap) {
+  return guarded([&] {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = false;
+    std::vector<double> acc(PK_COUNT, 0.0);
+    std::vector<int64_t> cnt(PK_COUNT, 0);
+    for (auto& r : g_prof.recs) {
+      QOC_HIP(hipEventSynchronize(r.b));
+      float t = 0.f;
+      QOC_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      acc[r.kind] += t;
+      cnt[r.kind] += 1;
+    }
+    for (int i = 0; i < cap && i < PK_COUNT; ++i) {
+      if (ms) ms[i] = acc[i];
+      if (launches) launches[i] = cnt[i];
+    }
+    g_prof.recs.clear();
+    g_prof.used = 0;
+  });
+}
+
+qoc_status qoc_plan_slice_stats(qoc_plan P, const double* u_dev, int32_t* q_host, int32_t* s_host, double* norm_host,
+                                void* stream) {
+  return guarded([&] {
+    QOC_REQUIRE(P && u_dev && q_host && s_host && norm_host, QOC_ERR_INVALID_ARG, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int njobs = (int)P->jobs.size();
+    const size_t cnt = (size_t)njobs * P->N;
+    DeviceBuffer q(cnt * 4), sbuf(cnt * 4), nrm(cnt * 8);
+    hipLaunchKernelGGL(k_slice_norms, dim3(P->N, njobs), dim3(256), 0, st, P->d_jobs.as<JobDev>(), njobs,
+                       P->sys->h64.as<double>(), u_dev, P->K, P->dt, P->N, P->d_theta.as<double>(), P->r, P->qmax,
+                       q.as<int>(), sbuf.as<int>(), nrm.as<double>());
+    QOC_HIP(hipGetLastError());
+    QOC_HIP(hipMemcpyAsync(q_host, q.ptr, cnt * 4, hipMemcpyDeviceToHost, st));
+    QOC_HIP(hipMemcpyAsync(s_host, sbuf.ptr, cnt * 4, hipMemcpyDeviceToHost, st));
+    QOC_HIP(hipMemcpyAsync(norm_host, nrm.ptr, cnt * 8, hipMemcpyDeviceToHost, st));
+    QOC_HIP(hipStreamSynchronize(st));
   });
 }
 

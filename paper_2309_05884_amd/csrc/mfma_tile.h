@@ -5,8 +5,9 @@
 // buffered: the next slab is fetched into registers while the current one feeds the
 // MFMAs).  Each wave owns a 32x32 quadrant as 2x2 tiles of v_mfma_*_16x16x4; a complex
 // product is four real MFMAs: Re += Ar*Br - Ai*Bi, Im += Ar*Bi + Ai*Br.
-// MFMA 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16]; the
-// accumulator element v of lane l is D[4*(l/16)+v][l%16].
+// MFMA 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16].  The
+// accumulator element v of lane l is D[4*(l/16)+v][l%16] for the FP32 instruction and
+// D[(l/16)+4v][l%16] for the FP64 one (measured on gfx950).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -156,11 +157,14 @@ __device__ inline void tile_mma(const TileOperands<T>& op, TileLds<T>& s, TileAc
   }
 }
 
-// Row/column of accumulator element v for sub-tile (ri, ci) of this lane.
-__device__ inline int acc_row(int row0, int ri, int v) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return row0 + (wave >> 1) * 32 + ri * 16 + 4 * (lane >> 4) + v;
+// First row of sub-tile ri of this wave, and the row offset of accumulator element v.
+__device__ inline int acc_row_base(int row0, int ri) {
+  const int wave = threadIdx.x >> 6;
+  return row0 + (wave >> 1) * 32 + ri * 16;
 }
+template <typename T> __device__ inline int acc_row_off(int v);
+template <> __device__ inline int acc_row_off<float>(int v) { return 4 * ((threadIdx.x & 63) >> 4) + v; }
+template <> __device__ inline int acc_row_off<double>(int v) { return ((threadIdx.x & 63) >> 4) + 4 * v; }
 __device__ inline int acc_col(int col0, int ci) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   return col0 + (wave & 1) * 32 + ci * 16 + (lane & 15);
