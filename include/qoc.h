@@ -154,18 +154,35 @@ qoc_status qoc_system_block(qoc_system system, int block, int op, void* dst_dev,
 /* Execution plan for N slices of length dt at a precision (QOC_C128 or QOC_C64).
  * The plan fixes the Taylor degree menu, the Frechet-series length and the number of
  * propagator slices held at once (segment) so that the workspace stays within
- * max_workspace_bytes; when the whole pulse does not fit, propagators are recomputed
- * segment by segment in the backward sweep.  u_bound > 0 bounds |u[j,k]| for every
+ * max_workspace_bytes (0: three quarters of the free device memory, at most 200 GiB);
+ * when the whole pulse does not fit, propagators are recomputed segment by segment in
+ * the backward sweep.  u_bound > 0 bounds |u[j,k]| for every
  * call that uses this plan; the plan uses it, with the exact 1-norms of the blocks, to
  * bound dt*||H0 + sum u_k H_k||_1 by the triangle inequality.  A slice whose control
  * exceeds u_bound makes the hot-path call report QOC_ERR_NUMERIC.
- * Host-only; no device work. */
+ * Host-only apart from reading the free device memory and uploading small tables. */
 qoc_status qoc_plan_create(qoc_system system, int precision, int N, double dt, double u_bound,
                            size_t max_workspace_bytes, qoc_plan* out);
+/* One plan for P independent problems run together (the batched form of the same
+ * computation: every block of every problem and every slice shares the launches).
+ * Problem p uses systems[p] (systems may repeat, e.g. one Hamiltonian with many
+ * candidate pulses), N[p] slices of length dt[p]; u_bound bounds every |u|.
+ * The hot-path calls then take concatenated arrays, problem after problem:
+ *   controls and gradients: [N[p]][K_p] float64 blocks back to back;
+ *   psi0 / psi_f: each problem's panels (length D_p) back to back;
+ *   objective output: [P][8] (layout of qoc_fidelity_grad's out_dev);
+ *   propagators (qoc_propagate): per problem, per block, N[p] m x m matrices.
+ * qoc_plan_info reports P, the number of (problem, block) jobs and the total lengths.
+ * P: 1..65535.  Host-only. */
+qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* N, const double* dt, int precision,
+                                   double u_bound, size_t max_workspace_bytes, qoc_plan* out);
 void qoc_plan_free(qoc_plan plan);
 qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
 /* Plan facts: info[0] segment length, [1] number of segments, [2] Taylor degree step r,
- * [3] largest degree, [4] Frechet series terms, [5] Frechet sub-steps, [6] bytes/slice. */
+ * [3] largest degree, [4] Frechet series terms, [5] Frechet sub-steps, [6] propagator
+ * bytes per slice, [7] largest squaring count, [8] gradient chunk (slices), [9] GEMM
+ * grid, [10] problems P, [11] (problem, block) jobs, [12] total controls (sum N_p K_p),
+ * [13] total panel length (sum D_p), [14] total propagator entries. */
 qoc_status qoc_plan_info(qoc_plan plan, int64_t* info, int cap);
 
 /* Slice propagators U_j (Eq. (3)) for every block and slice: scaled Taylor polynomial
@@ -199,7 +216,8 @@ qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi
 qoc_status qoc_profile_begin(int max_launches);
 qoc_status qoc_profile_end(double* ms, int64_t* launches, int cap);
 
-/* Per block and slice (host arrays [nblocks][N]): the Taylor degree multiple q (degree
+/* Per job and slice (host arrays [jobs][max N], jobs = (problem, block) pairs in order;
+ * entries beyond a problem's N are 0): the Taylor degree multiple q (degree
  * q * r), squaring count s and FP64 norm dt*||H0 + sum_k u[j,k] H_k||_1 that the plan's
  * propagators pick for these controls (the algorithmic work of Eq. (3)'s exponentials).
  * Synchronises `stream`. */

@@ -19,8 +19,8 @@ import numpy as np
 from . import _capi as C
 from ._capi import QocError
 
-__all__ = ["Basis", "System", "Plan", "fidelity_grad", "propagate", "GrapeFidelity", "QocError",
-           "library_path", "profile_begin", "profile_end", "slice_stats"]
+__all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "propagate", "GrapeFidelity",
+           "QocError", "library_path", "profile_begin", "profile_end", "slice_stats"]
 
 library_path = C.LIB_PATH
 
@@ -117,25 +117,49 @@ class System:
 
 
 class Plan:
-    """Execution plan for N slices of length dt at one precision (qoc_plan_create)."""
+    """Execution plan (qoc_plan_create / qoc_plan_create_batched).
+
+    ``Plan(system, precision, N, dt, u_bound)`` plans one problem; ``Plan.batched(systems,
+    precision, Ns, dts, u_bound)`` plans several independent problems that share every
+    launch (systems may repeat, e.g. one Hamiltonian with many candidate pulses)."""
+
+    INFO_KEYS = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
+                 "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid", "problems", "jobs",
+                 "total_controls", "total_panel", "total_propagator"]
 
     def __init__(self, system: System, precision: str = "c128", N: int = 1, dt: float = 0.01,
-                 u_bound: float = 1.0, max_workspace_bytes: int = 0):
-        self.system = system
-        self.precision, self.N, self.dt, self.u_bound = precision, int(N), float(dt), float(u_bound)
-        self.K = system.K
+                 u_bound: float = 1.0, max_workspace_bytes: int = 0, _batch=None):
+        self.precision, self.u_bound = precision, float(u_bound)
         self._h = ctypes.c_void_p()
-        C.check(C.lib().qoc_plan_create(system._h, C.PRECISIONS[precision], int(N), float(dt), float(u_bound),
-                                        int(max_workspace_bytes), ctypes.byref(self._h)))
+        if _batch is None:
+            self.systems, self.Ns, self.dts = [system], [int(N)], [float(dt)]
+            C.check(C.lib().qoc_plan_create(system._h, C.PRECISIONS[precision], int(N), float(dt), float(u_bound),
+                                            int(max_workspace_bytes), ctypes.byref(self._h)))
+        else:
+            self.systems, self.Ns, self.dts = _batch
+            P = len(self.systems)
+            arr = (ctypes.c_void_p * P)(*[s_._h.value for s_ in self.systems])
+            Ns = (ctypes.c_int * P)(*self.Ns)
+            dts = (ctypes.c_double * P)(*self.dts)
+            C.check(C.lib().qoc_plan_create_batched(arr, P, Ns, dts, C.PRECISIONS[precision], float(u_bound),
+                                                    int(max_workspace_bytes), ctypes.byref(self._h)))
+        self.system = self.systems[0]
+        self.N, self.dt, self.K = self.Ns[0], self.dts[0], self.systems[0].K
+        self.Ks = [s_.K for s_ in self.systems]
+        self.P = len(self.systems)
         b = ctypes.c_size_t()
         C.check(C.lib().qoc_plan_workspace_size(self._h, ctypes.byref(b)))
         self.workspace_bytes = int(b.value)
-        info = (ctypes.c_int64 * 10)()
-        C.check(C.lib().qoc_plan_info(self._h, info, 10))
-        keys = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
-                "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid"]
-        self.info = dict(zip(keys, [int(v) for v in info]))
+        info = (ctypes.c_int64 * 15)()
+        C.check(C.lib().qoc_plan_info(self._h, info, 15))
+        self.info = dict(zip(self.INFO_KEYS, [int(v) for v in info]))
         self._ws = None
+
+    @classmethod
+    def batched(cls, systems, precision="c64", Ns=None, dts=None, u_bound=1.0, max_workspace_bytes=0):
+        systems = list(systems)
+        return cls(None, precision, u_bound=u_bound, max_workspace_bytes=max_workspace_bytes,
+                   _batch=(systems, [int(n) for n in Ns], [float(d) for d in dts]))
 
     def workspace(self):
         torch = _torch()
@@ -170,10 +194,11 @@ def slice_stats(plan: "Plan", u):
     """(q, s, norm) arrays of shape (nblocks, N): the propagators' degree multiple, squarings, norm."""
     torch = _torch()
     u = u.to(torch.float64).contiguous()
-    nb = len(plan.system.basis.sizes)
-    q = np.zeros((nb, plan.N), dtype=np.int32)
-    s = np.zeros((nb, plan.N), dtype=np.int32)
-    nrm = np.zeros((nb, plan.N), dtype=np.float64)
+    nb = plan.info["jobs"]
+    Nmax = max(plan.Ns)
+    q = np.zeros((nb, Nmax), dtype=np.int32)
+    s = np.zeros((nb, Nmax), dtype=np.int32)
+    nrm = np.zeros((nb, Nmax), dtype=np.float64)
     C.check(C.lib().qoc_plan_slice_stats(plan._h, _ptr(u), q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                          s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                          nrm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream()))
@@ -192,41 +217,68 @@ def check_flags(out):
         raise QocError(6, "; ".join(what))
 
 
-def fidelity_grad(plan: Plan, u, psi0, psif, workspace=None, check=True):
-    """(out[8], grad[N,K]) on the device: out = [F, |o|^2, Re o, Im o, |psi_N|^2, |psi_f|^2,
-    max squarings, flags]."""
+def _run(plan, u_flat, psi0_flat, psif_flat, workspace, check):
     torch = _torch()
+    ws = workspace if workspace is not None else plan.workspace()
+    out = torch.empty((plan.P, 8), dtype=torch.float64, device=u_flat.device)
+    grad = torch.empty(plan.info["total_controls"], dtype=torch.float64, device=u_flat.device)
+    C.check(C.lib().qoc_fidelity_grad(plan._h, _ptr(u_flat), _ptr(psi0_flat), _ptr(psif_flat), _ptr(out),
+                                      _ptr(grad), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream()))
+    if check:
+        for p in range(plan.P):
+            check_flags(out[p])
+    return out, grad
+
+
+def fidelity_grad(plan: Plan, u, psi0, psif, workspace=None, check=True):
+    """(out[8], grad[N,K]) on the device for a one-problem plan: out = [F, |o|^2, Re o, Im o,
+    |psi_N|^2, |psi_f|^2, max squarings, flags]."""
+    torch = _torch()
+    assert plan.P == 1
     u = u.to(torch.float64).contiguous()
     assert u.shape == (plan.N, plan.K) and u.is_cuda
     psi0 = psi0.to(torch.complex128).contiguous()
     psif = psif.to(torch.complex128).contiguous()
     D = plan.system.basis.dim
     assert psi0.numel() == D and psif.numel() == D
-    ws = workspace if workspace is not None else plan.workspace()
-    out = torch.empty(8, dtype=torch.float64, device=u.device)
-    grad = torch.empty((plan.N, plan.K), dtype=torch.float64, device=u.device)
-    C.check(C.lib().qoc_fidelity_grad(plan._h, _ptr(u), _ptr(psi0), _ptr(psif), _ptr(out), _ptr(grad), _ptr(ws),
-                                      ctypes.c_size_t(ws.numel()), _stream()))
-    if check:
-        check_flags(out)
-    return out, grad
+    out, grad = _run(plan, u.reshape(-1), psi0, psif, workspace, check)
+    return out[0], grad.view(plan.N, plan.K)
+
+
+def fidelity_grad_batched(plan: Plan, us, psi0s, psifs, workspace=None, check=True):
+    """Batched form: lists of per-problem controls (N_p, K_p) and panels; returns
+    (out[P, 8], [grad_p (N_p, K_p)])."""
+    torch = _torch()
+    assert len(us) == plan.P == len(psi0s) == len(psifs)
+    u_flat = torch.cat([u.to(torch.float64).reshape(-1) for u in us]).contiguous()
+    p0 = torch.cat([v.to(torch.complex128).reshape(-1) for v in psi0s]).contiguous()
+    pf = torch.cat([v.to(torch.complex128).reshape(-1) for v in psifs]).contiguous()
+    assert u_flat.numel() == plan.info["total_controls"] and p0.numel() == plan.info["total_panel"]
+    out, grad = _run(plan, u_flat, p0, pf, workspace, check)
+    grads, off = [], 0
+    for N, K in zip(plan.Ns, plan.Ks):
+        grads.append(grad[off:off + N * K].view(N, K))
+        off += N * K
+    return out, grads
 
 
 def propagate(plan: Plan, u, workspace=None):
-    """Slice propagators U_j of every block: list of (N, m, m) complex128 tensors."""
+    """Slice propagators U_j of every block (one-problem plan): list of (N, m, m) complex128
+    tensors.  For a batched plan pass the concatenated controls; the result is one list per
+    problem."""
     torch = _torch()
-    u = u.to(torch.float64).contiguous()
+    u = u.to(torch.float64).contiguous().reshape(-1)
     ws = workspace if workspace is not None else plan.workspace()
-    sizes = plan.system.basis.sizes
-    total = sum(plan.N * m * m for m in sizes)
-    flat = torch.empty(total, dtype=torch.complex128, device=u.device)
+    flat = torch.empty(plan.info["total_propagator"], dtype=torch.complex128, device=u.device)
     C.check(C.lib().qoc_propagate(plan._h, _ptr(u), _ptr(flat), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream()))
-    outs, off = [], 0
-    for m in sizes:
-        blk = flat[off:off + plan.N * m * m].view(plan.N, m, m).transpose(1, 2)  # column-major
-        outs.append(blk)
-        off += plan.N * m * m
-    return outs
+    per_problem, off = [], 0
+    for sys_, N in zip(plan.systems, plan.Ns):
+        outs = []
+        for m in sys_.basis.sizes:
+            outs.append(flat[off:off + N * m * m].view(N, m, m).transpose(1, 2))  # column-major
+            off += N * m * m
+        per_problem.append(outs)
+    return per_problem[0] if plan.P == 1 else per_problem
 
 
 def _autograd_function():

@@ -1,5 +1,6 @@
 // GRAPE hot path on gfx950: slice propagators, forward/backward sweeps, objective and
-// exact gradient (Eqs. (3)-(4); App. B, Eq. (B2) to all orders).
+// exact gradient (Eqs. (3)-(4); App. B, Eq. (B2) to all orders), for one problem or a
+// batch of independent problems (each its own system, slice count and controls).
 //
 // Per block theta and slice j (an "entry"):
 //   X_j = -i dt (H0 + sum_k u[j,k] H_k)                                (Eq. (3))
@@ -12,12 +13,16 @@
 // Sweeps: psi_{j+1} = U_j psi_j (forward), lambda_j = U_j^dag lambda_{j+1} (backward),
 // one work-group per block with the state in LDS.  Objective o = <psi_f|psi_N> in FP64.
 // Gradient: do/du[j,k] = <lambda_{j+1}| L(X_j, -i dt H_k) |psi_j>, with L the Frechet
-// derivative of exp, evaluated through the vector series
-//   L(Y,E) = sum_{i,t} i! t!/(i+t+1)! (Y^dag)^i ... : <b_i|E|a_t>, a_t = Y^t psi/t!,
-//   b_i = (-Y)^i lambda/i!,
+// derivative of exp, through the vector series
+//   <lambda|L(Y,E)|psi> = sum_{i+t<Q} i! t!/(i+t+1)! <b_i|E|a_t>,
+//   a_t = Y^t psi / t!,  b_i = (-Y)^i lambda / i!   (Y anti-Hermitian),
 // over R sub-steps when ||X|| is large; the products H_o [vectors of all slices] are
 // GEMMs with the block operators shared by every slice, and the inner products are
 // accumulated in FP64.
+//
+// A "job" is one (problem, block) pair; jobs of a problem are contiguous.  Slices are
+// processed in segments of equal length for every job; a job whose problem has fewer
+// slices simply has less (or no) work in the later segments.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -30,19 +35,30 @@ namespace qoc {
 
 // ===================================================================== plan structures
 struct JobDev {
-  int m, mp, d, pad_;
-  long long h_off;       // operator planes of this block in the system buffer (elements)
-  long long ent_off;     // first entry index of this job within a segment
-  long long item_off;    // first expm GEMM item of this job
-  long long ebuf_off;    // expm buffers of this job (elements of T)
+  int m, mp, d, prob;
+  int N, K;              // the problem's slices and controls
+  int tiles, cc;         // ceil(mp / 64); gradient columns per chunk (multiple of 16)
+  double dt;
+  const double* h64;     // FP64 operator planes of this block
+  const void* hT;        // working-precision operator planes of this block
+  long long ent_off;     // first entry (slice of a segment) of this job
+  long long item_off;    // first propagator GEMM item of this job
+  long long ebuf_off;    // propagator buffers (elements of T)
   long long psi_off;     // forward states (elements of T), planes of mp x (N+1)d
   long long lam_off;     // costates (elements of T), planes of mp x N d
   long long gbase_off;   // gradient slots (elements of T)
-  long long gslot;       // elements per gradient slot (2 planes x mp x CC)
+  long long gslot;       // elements per gradient slot (2 planes x mp x cc)
   long long gacc_off;    // gradient accumulators (complex FP64 entries)
-  long long state_off;   // block offset in the caller's panels (complex entries)
-  int tiles;             // ceil(mp / 64)
-  int cc;                // gradient columns per chunk (multiple of 16)
+  long long state_off;   // block offset in the batch's concatenated panels (complex entries)
+  long long u_off;       // the problem's offset in the concatenated controls / gradients
+  long long uout_off;    // offset of this job's propagators in qoc_propagate's output
+};
+
+struct ProbDev {
+  int job_begin, job_end;
+  int N, K;
+  double dt;
+  long long u_off;
 };
 
 struct PanelDesc {       // one panel GEMM entry: Z_o = H_o * V for job J
@@ -51,13 +67,43 @@ struct PanelDesc {       // one panel GEMM entry: Z_o = H_o * V for job J
   int tiles_m, tiles_n;
 };
 
+// largest index i with key_i <= key over an ascending table (job / descriptor lookup)
+__device__ inline int find_job_by_ent(const JobDev* jobs, int n, long long key) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].ent_off <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ inline int find_job_by_item(const JobDev* jobs, int n, long long key) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].item_off <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ inline int find_desc(const PanelDesc* d, int n, long long key) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].item_off <= key) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// slices of job J inside the segment starting at seg_j0 (<= 0: none)
+__device__ inline int job_len(const JobDev& jb, int seg_j0, int seg_len) { return min(seg_len, jb.N - seg_j0); }
+
 }  // namespace qoc
 
 struct qoc_plan_s {
-  qoc_system_s* sys = nullptr;
+  std::vector<qoc_system_s*> systems;
+  int P = 1;
   int prec = 0;
-  int N = 0, K = 0;
-  double dt = 0.0, u_bound = 0.0;
+  int Nmax = 0, Kmax = 0;
+  double u_bound = 0.0;
   int r = 4, qmax = 4, smax = 0;
   double norm_bound = 0.0;
   int seg_len = 0, nseg = 0;
@@ -66,19 +112,25 @@ struct qoc_plan_s {
   int nslots = 0;
   size_t elem = 8;
   // workspace layout (bytes)
-  size_t off_flags = 0, off_ent = 0, off_T = 0, bytes = 0;
-  size_t ent_stride_T = 0;
+  size_t off_flags = 0, off_ent = 0, off_T = 0, off_gacc = 0, bytes = 0;
   long long expm_items = 0, panel_items = 0;
-  int entries_per_seg = 0;
-  int max_mpd = 0;
-  size_t off_gacc = 0;
+  long long entries_per_seg = 0;
   size_t sweep_lds_elems = 0;
   int max_cc = 0;
+  long long total_u = 0, total_D = 0, total_U = 0;
   std::vector<qoc::JobDev> jobs;
+  std::vector<qoc::ProbDev> probs;
   std::vector<qoc::PanelDesc> panels;
-  qoc::DeviceBuffer d_jobs, d_panels;
+  qoc::DeviceBuffer d_jobs, d_probs, d_panels;
   qoc::DeviceBuffer d_theta, d_w;
   int grid_gemm = 512;
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  ~qoc_plan_s() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (st2) (void)hipStreamDestroy(st2);
+  }
 };
 
 namespace qoc {
@@ -94,103 +146,132 @@ __device__ inline T* tplane(char* ws, size_t off_T, long long elem_off) {
   return reinterpret_cast<T*>(ws + off_T) + elem_off;
 }
 
-// ===================================================================== generator + norm
-// 1-norm of H0 + sum_k u_k H_k (FP64): one wave per column, lanes over rows (coalesced),
-// then the largest column sum over the work-group.  red: 256 doubles of LDS.
-__device__ inline double block_col_norm(const double* H, size_t plane, int mp, int m, int K, const double* uj,
-                                        double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double cmax = 0.0;
-  for (int c = wave; c < m; c += nw) {
-    double cs = 0.0;
-    for (int rr = lane; rr < m; rr += 64) {
-      const size_t idx = (size_t)rr + (size_t)c * mp;
-      double hr = 0.0, hi = 0.0;
-      for (int o = 0; o <= K; ++o) {
-        hr += uj[o] * H[(size_t)(2 * o) * plane + idx];
-        hi += uj[o] * H[(size_t)(2 * o + 1) * plane + idx];
-      }
-      cs += hypot(hr, hi);
-    }
-    cs = warp_sum(cs);
-    cmax = fmax(cmax, cs);
+__device__ inline void pick_degree(double nx, const double* theta, int r, int qmax, int* q_out, int* s_out) {
+  int best_q = qmax, best_s = 0, best_cost = 1 << 30;
+  for (int q = qmax; q >= 1; --q) {
+    int sq = 0;
+    while (sq < 62 && nx > ldexp(theta[q * r], sq)) ++sq;
+    if ((q - 1) + sq < best_cost) { best_cost = (q - 1) + sq; best_q = q; best_s = sq; }
   }
-  red[threadIdx.x] = cmax;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const double v = red[0];
-  __syncthreads();
-  return v;
+  *q_out = best_q;
+  *s_out = best_s;
 }
 
-// One work-group per entry (job, slice of the segment).  Pass 1: FP64 column sums of
-// |H_j| (exact 1-norm), Pass 2: Y = -i dt 2^-s H_j in the working precision.
+// ===================================================================== generator + norm
+// One work-group per job and group of GEN_SG slices.  Pass 1: FP64 column sums of
+// |H_j| for every slice of the group (one wave per column, lanes over rows, each operator
+// element read once for all slices), giving the exact 1-norms and each slice's (q, s).
+// Pass 2: Y = -i dt 2^-s H_j in the working precision, again reading H once per group.
+constexpr int GEN_SG = 8;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs, const double* H64, const double* u,
-                                                   int K, double dt, int seg_j0, int seg_len, int N, char* ws,
-                                                   size_t off_T, int* ent_s, int* ent_q, double* ent_norm, int* flags,
-                                                   const double* theta, int r, int qmax, int smax, double norm_bound) {
-  __shared__ double red[256];
-  __shared__ int sq[2];
-  const int e = blockIdx.x;
-  int J = 0;
-  while (J + 1 < njobs && jobs[J + 1].ent_off <= e) ++J;
+__global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs, const double* u, int seg_j0,
+                                                   int seg_len, int groups, char* ws, size_t off_T, int* ent_s,
+                                                   int* ent_q, double* ent_norm, int* flags, const double* theta,
+                                                   int r, int qmax, int smax, double norm_bound) {
+  __shared__ double red[GEN_SG][256];
+  __shared__ double us[GEN_SG][17];
+  __shared__ double scale[GEN_SG];
+  const int J = blockIdx.x / groups, g = blockIdx.x % groups;
+  if (J >= njobs) return;
   const JobDev jb = jobs[J];
-  const int jl = e - (int)jb.ent_off;
-  if (jl >= seg_len) return;
-  const int j = seg_j0 + jl;
-  const int m = jb.m, mp = jb.mp;
+  const int jl0 = g * GEN_SG;
+  const int len = job_len(jb, seg_j0, seg_len);
+  if (jl0 >= len) return;
+  const int ns = min(GEN_SG, len - jl0);
+  const int m = jb.m, mp = jb.mp, K = jb.K;
   const size_t plane = (size_t)mp * mp;
-  const double* H = H64 + jb.h_off;
-  double uj[17];
-  bool finite = true;
-  uj[0] = 1.0;
-  for (int k = 0; k < K; ++k) {
-    uj[k + 1] = u[(size_t)j * K + k];
-    finite = finite && isfinite(uj[k + 1]);
+  const double* H = jb.h64;
+  const double* uj = u + jb.u_off;
+  for (int idx = threadIdx.x; idx < GEN_SG * (K + 1); idx += blockDim.x) {
+    const int t = idx / (K + 1), o = idx % (K + 1);
+    double v = 0.0;
+    if (t < ns) v = o == 0 ? 1.0 : uj[(size_t)(seg_j0 + jl0 + t) * K + (o - 1)];
+    us[t][o] = v;
   }
-  const double cmax = block_col_norm(H, plane, mp, m, K, uj, red);
-  if (threadIdx.x == 0) {
-    double nx = dt * cmax;
-    int flag = 0;
-    if (!finite || !isfinite(nx)) flag |= 2;
-    if (nx > norm_bound * (1.0 + 1e-12)) flag |= 1;
-    int best_q = qmax, best_s = 0, best_cost = 1 << 30;
-    for (int q = qmax; q >= 1; --q) {
-      double th = theta[q * r];
-      int s = 0;
-      while (s < 62 && nx > ldexp(th, s)) ++s;
-      int cost = (q - 1) + s;
-      if (cost < best_cost) { best_cost = cost; best_q = q; best_s = s; }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double cmax[GEN_SG];
+#pragma unroll
+  for (int t = 0; t < GEN_SG; ++t) cmax[t] = 0.0;
+  for (int c = wave; c < m; c += nw) {
+    double cs[GEN_SG];
+#pragma unroll
+    for (int t = 0; t < GEN_SG; ++t) cs[t] = 0.0;
+    for (int rr = lane; rr < m; rr += 64) {
+      const size_t idx = (size_t)rr + (size_t)c * mp;
+      double hr[GEN_SG], hi[GEN_SG];
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
+      for (int o = 0; o <= K; ++o) {
+        const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
+#pragma unroll
+        for (int t = 0; t < GEN_SG; ++t) {
+          hr[t] += us[t][o] * ar;
+          hi[t] += us[t][o] * ai;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) cs[t] += hypot(hr[t], hi[t]);
     }
+#pragma unroll
+    for (int t = 0; t < GEN_SG; ++t) cmax[t] = fmax(cmax[t], warp_sum(cs[t]));
+  }
+#pragma unroll
+  for (int t = 0; t < GEN_SG; ++t) red[t][threadIdx.x] = cmax[t];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) red[t][threadIdx.x] = fmax(red[t][threadIdx.x], red[t][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < ns) {
+    const int t = threadIdx.x;
+    const long long e = jb.ent_off + jl0 + t;
+    const double nx = jb.dt * red[t][0];
+    bool finite = isfinite(nx);
+    for (int o = 1; o <= K; ++o) finite = finite && isfinite(us[t][o]);
+    int flag = 0;
+    if (!finite) flag |= 2;
+    if (nx > norm_bound * (1.0 + 1e-12)) flag |= 1;
+    int best_q, best_s;
+    pick_degree(nx, theta, r, qmax, &best_q, &best_s);
     if (best_s > smax) { flag |= 1; best_s = smax; }
     if (flag) atomicOr(flags, flag);
     atomicMax(flags + 1, best_s);
     ent_s[e] = best_s;
     ent_q[e] = best_q;
     ent_norm[e] = nx;
-    sq[0] = best_s;
+    scale[t] = ldexp(jb.dt, -best_s);
   }
   __syncthreads();
-  const double scale = ldexp(dt, -sq[0]);
   const size_t ent_stride = (size_t)(r + 3) * 2 * plane;
-  T* Yre = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * ent_stride;
-  T* Yim = Yre + plane;
+  T* Y0 = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl0 * ent_stride;
   for (size_t idx = threadIdx.x; idx < plane; idx += blockDim.x) {
     const int rr = (int)(idx % mp), c = (int)(idx / mp);
-    double hr = 0.0, hi = 0.0;
+    double hr[GEN_SG], hi[GEN_SG];
+#pragma unroll
+    for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
     if (rr < m && c < m) {
       for (int o = 0; o <= K; ++o) {
-        hr += uj[o] * H[(size_t)(2 * o) * plane + idx];
-        hi += uj[o] * H[(size_t)(2 * o + 1) * plane + idx];
+        const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
+#pragma unroll
+        for (int t = 0; t < GEN_SG; ++t) {
+          hr[t] += us[t][o] * ar;
+          hi[t] += us[t][o] * ai;
+        }
       }
     }
     // -i * scale * (hr + i hi) = scale * hi - i scale * hr
-    Yre[idx] = (T)(scale * hi);
-    Yim[idx] = (T)(-scale * hr);
+#pragma unroll
+    for (int t = 0; t < GEN_SG; ++t) {
+      if (t < ns) {
+        T* Y = Y0 + (size_t)t * ent_stride;
+        Y[idx] = (T)(scale[t] * hi[t]);
+        Y[idx + plane] = (T)(-scale[t] * hr[t]);
+      }
+    }
   }
 }
 
@@ -199,25 +280,31 @@ enum { STEP_POWER = 0, STEP_HORNER = 1, STEP_SQUARE = 2 };
 
 __constant__ double kInvFact[64];
 
+template <typename T> struct GemmWavesPerEU { static constexpr int value = 4; };
+template <> struct GemmWavesPerEU<double> { static constexpr int value = 2; };
+
+// One product step over every entry of the segment (persistent, XCD-grouped items).
+// Buffers of an entry: 0 = Y, i-1 = Y^i (i <= r), r and r+1 = ping-pong T, r+2 = U^dag.
+// The last power step also forms the Horner start T0; the last product of an entry
+// writes U^dag for the backward sweep.
 template <typename T>
-__global__ void __launch_bounds__(256) k_expm_step(const JobDev* jobs, int njobs, long long total_items, char* ws,
-                                                   size_t off_T, const int* ent_s, const int* ent_q, int mode, int step,
-                                                   int r, int seg_len) {
+__global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
+    k_expm_step(const JobDev* jobs, int njobs, long long total_items, char* ws, size_t off_T, const int* ent_s,
+                const int* ent_q, int mode, int step, int r, int seg_j0, int seg_len) {
   __shared__ TileLds<T> lds;
   const ItemRange rg = xcd_items(total_items);
   for (long long it = rg.begin; it < rg.end; it += rg.step) {
-    int J = 0;
-    while (J + 1 < njobs && jobs[J + 1].item_off <= it) ++J;
+    const int J = find_job_by_item(jobs, njobs, it);
     const JobDev jb = jobs[J];
     const long long local = it - jb.item_off;
     const int t2 = jb.tiles * jb.tiles;
     const int jl = (int)(local / t2);
-    if (jl >= seg_len) continue;
+    if (jl >= job_len(jb, seg_j0, seg_len)) continue;
     const int tile = (int)(local % t2);
     const int ti = tile / jb.tiles, tj = tile % jb.tiles;
-    const int e = (int)jb.ent_off + jl;
+    const long long e = jb.ent_off + jl;
     const int se = ent_s[e], qe = ent_q[e];
-    int ia, ib, ic;  // buffer indices: 0 = Y, i-1 = Y^i (i <= r), r, r+1 = ping-pong T
+    int ia, ib, ic;
     if (mode == STEP_POWER) {
       ia = step - 2; ib = 0; ic = step - 1;
     } else if (mode == STEP_HORNER) {
@@ -247,11 +334,17 @@ __global__ void __launch_bounds__(256) k_expm_step(const JobDev* jobs, int njobs
     TileAcc<T> acc;
     tile_mma(op, lds, acc);
     T* C = base + (size_t)ic * 2 * plane;
-    // Horner coefficients: T <- T Y^r + sum_{i<r} c_{l r + i} Y^i, l = q - 1 - step
     double coef[8];
+    double ctop = 0.0;
     const int lh = qe - 1 - step;
+    const bool init_T = mode == STEP_POWER && step == r;
+    const bool init_final = init_T && qe == 1 && se == 0;
     if (mode == STEP_HORNER)
       for (int i = 0; i < r; ++i) coef[i] = kInvFact[lh * r + i];
+    if (init_T) {
+      ctop = kInvFact[qe * r];
+      for (int i = 0; i < r; ++i) coef[i] = kInvFact[(qe - 1) * r + i];
+    }
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri)
 #pragma unroll
@@ -262,12 +355,12 @@ __global__ void __launch_bounds__(256) k_expm_step(const JobDev* jobs, int njobs
         typename Vec4<T>::type vr = acc.re[ri][ci], vi = acc.im[ri][ci];
         if (mode == STEP_HORNER) {
           for (int i = 1; i < r; ++i) {
-            const T* P = base + (size_t)(i - 1) * 2 * plane;
+            const T* Pp = base + (size_t)(i - 1) * 2 * plane;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const size_t idx = (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
-              vr[v] += (T)coef[i] * P[idx];
-              vi[v] += (T)coef[i] * P[idx + plane];
+              vr[v] += (T)coef[i] * Pp[idx];
+              vi[v] += (T)coef[i] * Pp[idx + plane];
             }
           }
 #pragma unroll
@@ -279,6 +372,41 @@ __global__ void __launch_bounds__(256) k_expm_step(const JobDev* jobs, int njobs
           T* cr = C + (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
           cr[0] = vr[v];
           cr[plane] = vi[v];
+        }
+        if (init_T) {
+          // T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i at this tile (the Horner start)
+          T* T0 = base + (size_t)r * 2 * plane;
+          typename Vec4<T>::type tr, ti;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            tr[v] = (T)ctop * vr[v];
+            ti[v] = (T)ctop * vi[v];
+          }
+          for (int i = 1; i < r; ++i) {
+            const T* Pp = base + (size_t)(i - 1) * 2 * plane;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const size_t idx = (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
+              tr[v] += (T)coef[i] * Pp[idx];
+              ti[v] += (T)coef[i] * Pp[idx + plane];
+            }
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = rbase + acc_row_off<T>(v);
+            if (row == col && col < jb.m) tr[v] += (T)coef[0];
+            T0[(size_t)row + (size_t)col * mp] = tr[v];
+            T0[(size_t)row + (size_t)col * mp + plane] = ti[v];
+          }
+          if (init_final) {
+            T* D = base + (size_t)(r + 2) * 2 * plane;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              T* dr = D + (size_t)col + (size_t)(rbase + acc_row_off<T>(v)) * mp;
+              dr[0] = tr[v];
+              dr[plane] = -ti[v];
+            }
+          }
         }
         if (final_op) {
           // conjugate transpose for the backward sweep: Udag[col][row] = conj(U[row][col])
@@ -294,44 +422,6 @@ __global__ void __launch_bounds__(256) k_expm_step(const JobDev* jobs, int njobs
   }
 }
 
-// T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1) r + i} Y^i (elementwise), one work-group per entry
-template <typename T>
-__global__ void __launch_bounds__(256) k_horner_init(const JobDev* jobs, int njobs, char* ws, size_t off_T,
-                                                     const int* ent_s, const int* ent_q, int r, int seg_len) {
-  const int e = blockIdx.x;
-  int J = 0;
-  while (J + 1 < njobs && jobs[J + 1].ent_off <= e) ++J;
-  const JobDev jb = jobs[J];
-  const int jl = e - (int)jb.ent_off;
-  if (jl >= seg_len) return;
-  const int q = ent_q[e];
-  const bool final_op = q == 1 && ent_s[e] == 0;
-  const int mp = jb.mp, m = jb.m;
-  const size_t plane = (size_t)mp * mp;
-  T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
-  T* Tout = base + (size_t)r * 2 * plane;
-  const T ctop = (T)kInvFact[q * r];
-  T c[8];
-  for (int i = 0; i < r; ++i) c[i] = (T)kInvFact[(q - 1) * r + i];
-  for (size_t idx = threadIdx.x; idx < plane; idx += blockDim.x) {
-    const int rr = (int)(idx % mp), cc = (int)(idx / mp);
-    T vr = ctop * base[(size_t)(r - 1) * 2 * plane + idx];
-    T vi = ctop * base[(size_t)(r - 1) * 2 * plane + plane + idx];
-    for (int i = 1; i < r; ++i) {
-      vr += c[i] * base[(size_t)(i - 1) * 2 * plane + idx];
-      vi += c[i] * base[(size_t)(i - 1) * 2 * plane + plane + idx];
-    }
-    if (rr == cc && rr < m) vr += c[0];
-    Tout[idx] = vr;
-    Tout[idx + plane] = vi;
-    if (final_op) {
-      T* D = base + (size_t)(r + 2) * 2 * plane;
-      D[(size_t)cc + (size_t)rr * mp] = vr;
-      D[(size_t)cc + (size_t)rr * mp + plane] = -vi;
-    }
-  }
-}
-
 template <typename T>
 __device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int jl, int r, int s, int q) {
   const size_t plane = (size_t)jb.mp * jb.mp;
@@ -343,12 +433,12 @@ __device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int
 // psi0 -> forward store column 0, psi_f -> costate column N-1 (planar, working precision)
 template <typename T>
 __global__ void k_states_in(const JobDev* jobs, int njobs, const double2* psi0, const double2* psif, char* ws,
-                            size_t off_T, int N, int* flags) {
-  const int J = blockIdx.y;
-  if (J >= njobs) return;
+                            size_t off_T, int* flags) {
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];
+  const int N = jb.N;
   const long long ncol_psi = (long long)(N + 1) * jb.d, ncol_lam = (long long)N * jb.d;
-  T* P = tplane<T>(ws, off_T, jb.psi_off);
+  T* Pp = tplane<T>(ws, off_T, jb.psi_off);
   T* Lm = tplane<T>(ws, off_T, jb.lam_off);
   const size_t pps = (size_t)jb.mp * ncol_psi, lps = (size_t)jb.mp * ncol_lam;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < jb.mp * jb.d; idx += gridDim.x * blockDim.x) {
@@ -359,12 +449,13 @@ __global__ void k_states_in(const JobDev* jobs, int njobs, const double2* psi0, 
       b = psif[jb.state_off + (long long)c * jb.m + i];
       if (!isfinite(a.x) || !isfinite(a.y) || !isfinite(b.x) || !isfinite(b.y)) atomicOr(flags, 2);
     }
-    const size_t cp = (size_t)c * jb.mp + i;                      // column c of the forward store
-    const size_t cl = ((size_t)(N - 1) * jb.d + c) * jb.mp + i;   // column (N-1)d + c of the costates
-    P[cp] = (T)a.x;
-    P[cp + pps] = (T)a.y;
+    const size_t cp = (size_t)c * jb.mp + i;
+    const size_t cl = ((size_t)(N - 1) * jb.d + c) * jb.mp + i;
+    Pp[cp] = (T)a.x;
+    Pp[cp + pps] = (T)a.y;
     Lm[cl] = (T)b.x;
     Lm[cl + lps] = (T)b.y;
+  }
   }
 }
 
@@ -374,26 +465,37 @@ __global__ void k_zero_ints(int* p, int n) {
 }
 
 // ===================================================================== sweeps
-// Sweep through one segment, one work-group (16 waves) per block, the state in LDS.
+// Sweep through one segment, one work-group (16 waves) per job, the state in LDS.
 // DIR 0: psi_{j+1} = U_j psi_j from the forward store; DIR 1: lambda_j = U_j^dag
 // lambda_{j+1} with the conjugate transpose written by the last product of each slice,
-// so both directions read their matrix column by column (coalesced across lanes).
-// Wave w covers 64 rows and one of G k-ranges; partial sums meet in LDS.
+// so both directions stream their matrix column by column.  A lane owns two adjacent
+// rows (8- or 16-byte loads), a wave 128 rows and one of G k-ranges; loads are unrolled
+// so that many bytes are in flight per lane; partial sums meet in LDS.
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { typedef double2 type; };
+template <> struct Vec2<float> { typedef float2 type; };
+template <typename T> struct SweepUnroll { static constexpr int value = 16; };
+template <> struct SweepUnroll<double> { static constexpr int value = 4; };
+
 __host__ __device__ inline int sweep_kgroups(int mp) {
-  const int R = (mp + 63) / 64;
+  const int R = (mp + 127) / 128;
   return R >= 16 ? 1 : 16 / R;
 }
 
 template <typename T, int DIR>
 __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, char* ws, size_t off_T,
-                                                const int* ent_s, const int* ent_q, int r, int seg_j0, int seg_len,
-                                                int N) {
-  extern __shared__ char smem_raw[];
+                                                const int* ent_s, const int* ent_q, int r, int seg_j0, int seg_len) {
+  typedef typename Vec2<T>::type T2;
+  typedef typename Vec4<T>::type T4;
+  constexpr int UNR = SweepUnroll<T>::value;
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   const int J = blockIdx.x;
   if (J >= njobs) return;
   const JobDev jb = jobs[J];
-  const int m = jb.m, mp = jb.mp, d = jb.d;
-  const int R = (mp + 63) / 64, G = sweep_kgroups(mp);
+  const int len = job_len(jb, seg_j0, seg_len);
+  if (len <= 0) return;
+  const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
+  const int R = (mp + 127) / 128, G = sweep_kgroups(mp);
   T* sre = reinterpret_cast<T*>(smem_raw);  // state [d][mp]
   T* sim = sre + (size_t)d * mp;
   T* pre = sim + (size_t)d * mp;             // partial sums [G][d][mp]
@@ -401,7 +503,7 @@ __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, c
   T* S = tplane<T>(ws, off_T, DIR == 0 ? jb.psi_off : jb.lam_off);
   const size_t ncol = DIR == 0 ? (size_t)(N + 1) * d : (size_t)N * d;
   const size_t ps = (size_t)mp * ncol;
-  const int col_in = DIR == 0 ? seg_j0 : seg_j0 + seg_len - 1;
+  const int col_in = DIR == 0 ? seg_j0 : seg_j0 + len - 1;
   for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
     const int c = idx / mp, i = idx % mp;
     const size_t g = ((size_t)col_in * d + c) * mp + i;
@@ -410,57 +512,85 @@ __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, c
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kchunk = (m + G - 1) / G;
+  const int kchunk = ((m + G - 1) / G + UNR - 1) / UNR * UNR;
   const size_t plane = (size_t)mp * mp;
-  for (int it = 0; it < seg_len; ++it) {
-    const int jl = DIR == 0 ? it : seg_len - 1 - it;
-    const int e = (int)jb.ent_off + jl;
+  for (int it = 0; it < len; ++it) {
+    const int jl = DIR == 0 ? it : len - 1 - it;
+    const long long e = jb.ent_off + jl;
     const T* Ub = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
     const T* U = DIR == 0 ? Ub + (size_t)(r + ((ent_q[e] - 1 + ent_s[e]) & 1)) * 2 * plane
                           : Ub + (size_t)(r + 2) * 2 * plane;
     for (int task = wave; task < R * G; task += 16) {
       const int rg = task % R, kg = task / R;
-      const int i = rg * 64 + lane;
+      const int i0 = rg * 128 + 2 * lane;  // rows i0, i0 + 1 (mp is even)
       const int k0 = kg * kchunk, k1 = min(m, k0 + kchunk);
-      T ar0 = T(0), ai0 = T(0), ar1 = T(0), ai1 = T(0);
-      if (i < m) {
-        const T* col = U + i;
+      T a0r0 = T(0), a0i0 = T(0), a0r1 = T(0), a0i1 = T(0);  // copy 0, rows i0 / i0+1
+      T a1r0 = T(0), a1i0 = T(0), a1r1 = T(0), a1i1 = T(0);  // copy 1
+      if (i0 < m) {
+        const T* col = U + i0;
         int k = k0;
-        for (; k + 8 <= k1; k += 8) {
-          T ur[8], ui[8];
+        for (; k + UNR <= k1; k += UNR) {
+          T2 ur[UNR], ui[UNR];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            ur[q] = col[(size_t)(k + q) * mp];
-            ui[q] = col[(size_t)(k + q) * mp + plane];
+          for (int q = 0; q < UNR; ++q) {
+            ur[q] = *reinterpret_cast<const T2*>(col + (size_t)(k + q) * mp);
+            ui[q] = *reinterpret_cast<const T2*>(col + (size_t)(k + q) * mp + plane);
           }
+          // state values four at a time (one wide LDS broadcast per four k)
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const T p0r = sre[k + q], p0i = sim[k + q];
-            ar0 += ur[q] * p0r - ui[q] * p0i;
-            ai0 += ur[q] * p0i + ui[q] * p0r;
+          for (int q4 = 0; q4 < UNR; q4 += 4) {
+            T pr4[4], pi4[4];
+            *reinterpret_cast<T4*>(pr4) = *reinterpret_cast<const T4*>(sre + k + q4);
+            *reinterpret_cast<T4*>(pi4) = *reinterpret_cast<const T4*>(sim + k + q4);
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+              const int q = q4 + e4;
+              const T pr = pr4[e4], pi = pi4[e4];
+              a0r0 += ur[q].x * pr - ui[q].x * pi;
+              a0i0 += ur[q].x * pi + ui[q].x * pr;
+              a0r1 += ur[q].y * pr - ui[q].y * pi;
+              a0i1 += ur[q].y * pi + ui[q].y * pr;
+            }
             if (d > 1) {
-              const T p1r = sre[mp + k + q], p1i = sim[mp + k + q];
-              ar1 += ur[q] * p1r - ui[q] * p1i;
-              ai1 += ur[q] * p1i + ui[q] * p1r;
+              *reinterpret_cast<T4*>(pr4) = *reinterpret_cast<const T4*>(sre + mp + k + q4);
+              *reinterpret_cast<T4*>(pi4) = *reinterpret_cast<const T4*>(sim + mp + k + q4);
+#pragma unroll
+              for (int e4 = 0; e4 < 4; ++e4) {
+                const int q = q4 + e4;
+                const T qr = pr4[e4], qi = pi4[e4];
+                a1r0 += ur[q].x * qr - ui[q].x * qi;
+                a1i0 += ur[q].x * qi + ui[q].x * qr;
+                a1r1 += ur[q].y * qr - ui[q].y * qi;
+                a1i1 += ur[q].y * qi + ui[q].y * qr;
+              }
             }
           }
         }
         for (; k < k1; ++k) {
-          const T ur = col[(size_t)k * mp], ui = col[(size_t)k * mp + plane];
-          ar0 += ur * sre[k] - ui * sim[k];
-          ai0 += ur * sim[k] + ui * sre[k];
+          const T2 ur = *reinterpret_cast<const T2*>(col + (size_t)k * mp);
+          const T2 ui = *reinterpret_cast<const T2*>(col + (size_t)k * mp + plane);
+          const T pr = sre[k], pi = sim[k];
+          a0r0 += ur.x * pr - ui.x * pi;
+          a0i0 += ur.x * pi + ui.x * pr;
+          a0r1 += ur.y * pr - ui.y * pi;
+          a0i1 += ur.y * pi + ui.y * pr;
           if (d > 1) {
-            ar1 += ur * sre[mp + k] - ui * sim[mp + k];
-            ai1 += ur * sim[mp + k] + ui * sre[mp + k];
+            const T qr = sre[mp + k], qi = sim[mp + k];
+            a1r0 += ur.x * qr - ui.x * qi;
+            a1i0 += ur.x * qi + ui.x * qr;
+            a1r1 += ur.y * qr - ui.y * qi;
+            a1i1 += ur.y * qi + ui.y * qr;
           }
         }
       }
-      if (i < mp) {
-        pre[((size_t)kg * d) * mp + i] = ar0;
-        pim[((size_t)kg * d) * mp + i] = ai0;
+      if (i0 < mp) {
+        T* p0 = pre + ((size_t)kg * d) * mp + i0;
+        T* q0 = pim + ((size_t)kg * d) * mp + i0;
+        p0[0] = a0r0; p0[1] = a0r1;
+        q0[0] = a0i0; q0[1] = a0i1;
         if (d > 1) {
-          pre[((size_t)kg * d + 1) * mp + i] = ar1;
-          pim[((size_t)kg * d + 1) * mp + i] = ai1;
+          p0[mp] = a1r0; p0[mp + 1] = a1r1;
+          q0[mp] = a1i0; q0[mp + 1] = a1i1;
         }
       }
     }
@@ -487,22 +617,25 @@ __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, c
 }
 
 // ===================================================================== objective
-// o = sum <psi_f|psi_N>, ||psi_N||^2, ||psi_f||^2 in FP64 with a fixed-order reduction.
+// Per problem (one work-group each): o = sum <psi_f|psi_N>, ||psi_N||^2, ||psi_f||^2 in
+// FP64 with a fixed-order reduction.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_overlap(const JobDev* jobs, int njobs, char* ws, size_t off_T, int N,
+__global__ void __launch_bounds__(1024) k_overlap(const JobDev* jobs, const ProbDev* probs, char* ws, size_t off_T,
                                                   const int* flags, double* out) {
   __shared__ double red[4][1024];
+  const ProbDev pb = probs[blockIdx.x];
   double o_r = 0.0, o_i = 0.0, nn = 0.0, nf = 0.0;
-  for (int J = 0; J < njobs; ++J) {
+  for (int J = pb.job_begin; J < pb.job_end; ++J) {
     const JobDev jb = jobs[J];
-    const T* P = tplane<T>(ws, off_T, jb.psi_off);
+    const int N = jb.N;
+    const T* Pp = tplane<T>(ws, off_T, jb.psi_off);
     const T* Lm = tplane<T>(ws, off_T, jb.lam_off);
     const size_t pps = (size_t)jb.mp * (N + 1) * jb.d, lps = (size_t)jb.mp * N * jb.d;
     for (int idx = threadIdx.x; idx < jb.m * jb.d; idx += blockDim.x) {
       const int c = idx / jb.m, i = idx % jb.m;
       const size_t gp = ((size_t)N * jb.d + c) * jb.mp + i;
       const size_t gl = ((size_t)(N - 1) * jb.d + c) * jb.mp + i;
-      const double pr = P[gp], pi = P[gp + pps], fr = Lm[gl], fi = Lm[gl + lps];
+      const double pr = Pp[gp], pi = Pp[gp + pps], fr = Lm[gl], fi = Lm[gl + lps];
       o_r += fr * pr + fi * pi;
       o_i += fr * pi - fi * pr;
       nn += pr * pr + pi * pi;
@@ -520,18 +653,19 @@ __global__ void __launch_bounds__(1024) k_overlap(const JobDev* jobs, int njobs,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    double* o = out + (size_t)blockIdx.x * 8;
     const double orr = red[0][0], oii = red[1][0], nN = red[2][0], nF = red[3][0];
     const double raw = orr * orr + oii * oii;
-    out[0] = raw / (nN * nF);
-    out[1] = raw;
-    out[2] = orr;
-    out[3] = oii;
-    out[4] = nN;
-    out[5] = nF;
+    o[0] = raw / (nN * nF);
+    o[1] = raw;
+    o[2] = orr;
+    o[3] = oii;
+    o[4] = nN;
+    o[5] = nF;
     int fl = flags[0];
-    if (!isfinite(out[0])) fl |= 2;
-    out[6] = (double)flags[1];
-    out[7] = (double)fl;
+    if (!isfinite(o[0])) fl |= 2;
+    o[6] = (double)flags[1];
+    o[7] = (double)fl;
   }
 }
 
@@ -539,15 +673,14 @@ __global__ void __launch_bounds__(1024) k_overlap(const JobDev* jobs, int njobs,
 // Z_o = H_o * V for every (job, o); V and Z are gradient slots of the job.
 template <typename T>
 __global__ void __launch_bounds__(256) k_panel_gemm(const JobDev* jobs, const PanelDesc* descs, int ndesc,
-                                                    long long total_items, const T* Hsys, char* ws, size_t off_T,
-                                                    int vslot) {
+                                                    long long total_items, char* ws, size_t off_T, int vslot,
+                                                    int j0) {
   __shared__ TileLds<T> lds;
   const ItemRange rg = xcd_items(total_items);
   for (long long it = rg.begin; it < rg.end; it += rg.step) {
-    int D = 0;
-    while (D + 1 < ndesc && descs[D + 1].item_off <= it) ++D;
-    const PanelDesc pd = descs[D];
+    const PanelDesc pd = descs[find_desc(descs, ndesc, it)];
     const JobDev jb = jobs[pd.job];
+    if (jb.N - j0 <= 0) continue;
     const long long local = it - pd.item_off;
     const int ti = (int)(local / pd.tiles_n), tj = (int)(local % pd.tiles_n);
     const int mp = jb.mp;
@@ -555,7 +688,7 @@ __global__ void __launch_bounds__(256) k_panel_gemm(const JobDev* jobs, const Pa
     const size_t vplane = (size_t)mp * jb.cc;
     T* g = tplane<T>(ws, off_T, jb.gbase_off);
     TileOperands<T> op;
-    op.A = Hsys + jb.h_off + (size_t)(2 * pd.op) * hplane;
+    op.A = reinterpret_cast<const T*>(jb.hT) + (size_t)(2 * pd.op) * hplane;
     op.a_ps = hplane;
     op.lda = mp;
     op.B = g + (size_t)vslot * jb.gslot;
@@ -589,11 +722,12 @@ __global__ void __launch_bounds__(256) k_panel_gemm(const JobDev* jobs, const Pa
 // Load a chunk of forward states (src = 0) or costates (src = 1) into a gradient slot.
 template <typename T>
 __global__ void k_chunk_load(const JobDev* jobs, int njobs, char* ws, size_t off_T, int src, int slot, int j0,
-                             int nslices, int N) {
-  const int J = blockIdx.y;
-  if (J >= njobs) return;
+                             int chunk) {
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];
-  const int mp = jb.mp, d = jb.d;
+  const int nsl = min(chunk, jb.N - j0);
+  if (nsl <= 0) continue;
+  const int mp = jb.mp, d = jb.d, N = jb.N;
   T* g = tplane<T>(ws, off_T, jb.gbase_off) + (size_t)slot * jb.gslot;
   const size_t vplane = (size_t)mp * jb.cc;
   const T* S = tplane<T>(ws, off_T, src == 0 ? jb.psi_off : jb.lam_off);
@@ -604,7 +738,7 @@ __global__ void k_chunk_load(const JobDev* jobs, int njobs, char* ws, size_t off
     const int col = (int)(idx / mp), i = (int)(idx % mp);
     const int jj = col / d, c = col % d;
     T vr = T(0), vi = T(0);
-    if (jj < nslices) {
+    if (jj < nsl) {
       const size_t gs = ((size_t)(j0 + jj) * d + c) * mp + i;
       vr = S[gs];
       vi = S[gs + sps];
@@ -612,27 +746,31 @@ __global__ void k_chunk_load(const JobDev* jobs, int njobs, char* ws, size_t off
     g[idx] = vr;
     g[idx + vplane] = vi;
   }
+  }
 }
 
-// next = coef (Z_0 + sum_k u[j,k] Z_k), coef = (sign i) (dt/R) / (t+1); optionally acc += next
+// next = (sign i) (dt_J / R) / (t+1) (Z_0 + sum_k u[j,k] Z_k); optionally acc += next
 template <typename T>
-__global__ void k_series_combine(const JobDev* jobs, int njobs, char* ws, size_t off_T, const double* u, int K,
-                                 int j0, int nslices, double coef_im, int out_slot, int acc_slot, int zero_acc_first) {
-  const int J = blockIdx.y;
-  if (J >= njobs) return;
+__global__ void k_series_combine(const JobDev* jobs, int njobs, char* ws, size_t off_T, const double* u, int j0,
+                                 int chunk, double sign_over, int R, int out_slot, int acc_slot) {
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];
-  const int mp = jb.mp, d = jb.d;
+  const int nsl = min(chunk, jb.N - j0);
+  if (nsl <= 0) continue;
+  const int mp = jb.mp, d = jb.d, K = jb.K;
+  const double* uj = u + jb.u_off;
   T* g = tplane<T>(ws, off_T, jb.gbase_off);
   const size_t vplane = (size_t)mp * jb.cc;
   const long long total = (long long)mp * jb.cc;
+  const T cf = (T)(sign_over * jb.dt / R);
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long long)gridDim.x * blockDim.x) {
     const int col = (int)(idx / mp);
     const int jj = col / d;
     T sr = g[idx], si = g[idx + vplane];  // Z_0
-    if (jj < nslices) {
+    if (jj < nsl) {
       for (int k = 1; k <= K; ++k) {
-        const T uk = (T)u[(size_t)(j0 + jj) * K + (k - 1)];
+        const T uk = (T)uj[(size_t)(j0 + jj) * K + (k - 1)];
         sr += uk * g[(size_t)k * jb.gslot + idx];
         si += uk * g[(size_t)k * jb.gslot + idx + vplane];
       }
@@ -640,49 +778,31 @@ __global__ void k_series_combine(const JobDev* jobs, int njobs, char* ws, size_t
       sr = si = T(0);
     }
     // (i c) * (sr + i si) = -c si + i c sr
-    const T c = (T)coef_im;
-    const T nr = -c * si, ni = c * sr;
+    const T nr = -cf * si, ni = cf * sr;
     T* o = g + (size_t)out_slot * jb.gslot;
     o[idx] = nr;
     o[idx + vplane] = ni;
     if (acc_slot >= 0) {
       T* a = g + (size_t)acc_slot * jb.gslot;
-      if (zero_acc_first) {
-        a[idx] = nr;
-        a[idx + vplane] = ni;
-      } else {
-        a[idx] += nr;
-        a[idx + vplane] += ni;
-      }
+      a[idx] += nr;
+      a[idx + vplane] += ni;
     }
+  }
   }
 }
 
-// slot_dst = slot_src (both gradient slots)
-template <typename T>
-__global__ void k_slot_copy(const JobDev* jobs, int njobs, char* ws, size_t off_T, int dst, int src) {
-  const int J = blockIdx.y;
-  if (J >= njobs) return;
-  const JobDev jb = jobs[J];
-  T* g = tplane<T>(ws, off_T, jb.gbase_off);
-  const long long total = 2LL * jb.mp * jb.cc;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x)
-    g[(size_t)dst * jb.gslot + idx] = g[(size_t)src * jb.gslot + idx];
-}
-
-// G[col][k] += sum_{i <= imax} w_{i,t} <b_i | Z_k>, FP64; one wave per (job, column)
+// G[col][k] += sum_{i < nb} w_{i,t} <b_i | Z_k>, FP64; one wave per (job, column)
 template <typename T>
 __global__ void __launch_bounds__(256) k_series_dot(const JobDev* jobs, int njobs, char* ws, size_t off_T,
-                                                    size_t off_gacc, int K, int bank_slot, int nb, const double* w,
-                                                    int zero_first) {
-  const int J = blockIdx.y;
-  if (J >= njobs) return;
+                                                    size_t off_gacc, int bank_slot, int nb, const double* w,
+                                                    int zero_first, int j0) {
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];
+  if (jb.N - j0 <= 0) continue;
   const int lane = threadIdx.x & 63;
-  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (col >= jb.cc) return;
-  const int mp = jb.mp;
+  for (int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); col < jb.cc;
+       col += gridDim.x * (blockDim.x >> 6)) {
+  const int mp = jb.mp, K = jb.K;
   const T* g = tplane<T>(ws, off_T, jb.gbase_off);
   const size_t vplane = (size_t)mp * jb.cc;
   double2* G = reinterpret_cast<double2*>(ws + off_gacc) + jb.gacc_off + (size_t)col * K;
@@ -708,16 +828,21 @@ __global__ void __launch_bounds__(256) k_series_dot(const JobDev* jobs, int njob
       G[k - 1] = make_double2(prev.x + ar, prev.y + ai);
     }
   }
+  }
+  }
 }
 
-// grad[j][k] = 2 Re(conj(o) (-i dt/R) sum_{jobs,copies} G) / (||psi_N||^2 ||psi_f||^2)
-__global__ void k_grad_finish(const JobDev* jobs, int njobs, const char* ws, size_t off_gacc, int K, int j0,
-                              int nslices, double dt_over_R, const double* out, double* grad) {
+// grad[j][k] = 2 Re(conj(o) (-i dt/R) sum_{jobs,copies} G) / (||psi_N||^2 ||psi_f||^2), per problem
+__global__ void k_grad_finish(const JobDev* jobs, const ProbDev* probs, const char* ws, size_t off_gacc, int j0,
+                              int chunk, int R, const double* out, double* grad) {
+  const ProbDev pb = probs[blockIdx.y];
+  const int nsl = min(chunk, pb.N - j0);
+  const int K = pb.K;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nslices * K) return;
+  if (nsl <= 0 || idx >= nsl * K) return;
   const int jj = idx / K, k = idx % K;
   double sr = 0.0, si = 0.0;
-  for (int J = 0; J < njobs; ++J) {
+  for (int J = pb.job_begin; J < pb.job_end; ++J) {
     const JobDev jb = jobs[J];
     const double2* G = reinterpret_cast<const double2*>(ws + off_gacc) + jb.gacc_off;
     for (int c = 0; c < jb.d; ++c) {
@@ -726,41 +851,42 @@ __global__ void k_grad_finish(const JobDev* jobs, int njobs, const char* ws, siz
       si += v.y;
     }
   }
+  const double a = pb.dt / R;
   // (-i a)(sr + i si) = a si - i a sr
-  const double dr = dt_over_R * si, di = -dt_over_R * sr;
-  const double orr = out[2], oii = out[3];
-  // Re(conj(o) * d)
-  const double re = orr * dr + oii * di;
-  grad[(size_t)(j0 + jj) * K + k] = 2.0 * re / (out[4] * out[5]);
+  const double dr = a * si, di = -a * sr;
+  const double* o = out + (size_t)blockIdx.y * 8;
+  const double re = o[2] * dr + o[3] * di;  // Re(conj(o) * d)
+  grad[pb.u_off + (size_t)(j0 + jj) * K + k] = 2.0 * re / (o[4] * o[5]);
 }
 
 // interleaved complex128 copy of U_j for qoc_propagate
 template <typename T>
 __global__ void k_export_U(const JobDev* jobs, int njobs, char* ws, size_t off_T, const int* ent_s, const int* ent_q,
-                           int r, int seg_j0, int seg_len, int N, double2* out, const long long* out_off) {
-  const int e = blockIdx.y;
-  int J = 0;
-  while (J + 1 < njobs && jobs[J + 1].ent_off <= e) ++J;
+                           int r, int seg_j0, int seg_len, double2* out) {
+  for (long long e = blockIdx.y; e < (long long)njobs * seg_len; e += gridDim.y) {
+  const int J = find_job_by_ent(jobs, njobs, e);
   const JobDev jb = jobs[J];
-  const int jl = e - (int)jb.ent_off;
-  if (jl >= seg_len) return;
+  const int jl = (int)(e - jb.ent_off);
+  if (jl >= job_len(jb, seg_j0, seg_len)) continue;
   const T* U = entry_U<T>(jb, ws, off_T, jl, r, ent_s[e], ent_q[e]);
   const size_t plane = (size_t)jb.mp * jb.mp;
-  double2* dst = out + out_off[J] + (size_t)(seg_j0 + jl) * jb.m * jb.m;
+  double2* dst = out + jb.uout_off + (size_t)(seg_j0 + jl) * jb.m * jb.m;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < (long long)jb.m * jb.m;
        idx += (long long)gridDim.x * blockDim.x) {
     const int rr = (int)(idx % jb.m), cc = (int)(idx / jb.m);
     const size_t s = (size_t)rr + (size_t)cc * jb.mp;
     dst[idx] = make_double2((double)U[s], (double)U[s + plane]);
   }
+  }
 }
 
 // dst = sum_{i < count} slot[first + i] (fixed order)
 template <typename T>
-__global__ void k_slot_sum(const JobDev* jobs, int njobs, char* ws, size_t off_T, int dst, int first, int count) {
-  const int J = blockIdx.y;
-  if (J >= njobs) return;
+__global__ void k_slot_sum(const JobDev* jobs, int njobs, char* ws, size_t off_T, int dst, int first, int count,
+                           int j0) {
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];
+  if (jb.N - j0 <= 0) continue;
   T* g = tplane<T>(ws, off_T, jb.gbase_off);
   const long long total = 2LL * jb.mp * jb.cc;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -769,19 +895,7 @@ __global__ void k_slot_sum(const JobDev* jobs, int njobs, char* ws, size_t off_T
     for (int i = 0; i < count; ++i) s += g[(size_t)(first + i) * jb.gslot + idx];
     g[(size_t)dst * jb.gslot + idx] = s;
   }
-}
-
-// dst += src
-template <typename T>
-__global__ void k_slot_axpy(const JobDev* jobs, int njobs, char* ws, size_t off_T, int dst, int src) {
-  const int J = blockIdx.y;
-  if (J >= njobs) return;
-  const JobDev jb = jobs[J];
-  T* g = tplane<T>(ws, off_T, jb.gbase_off);
-  const long long total = 2LL * jb.mp * jb.cc;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x)
-    g[(size_t)dst * jb.gslot + idx] += g[(size_t)src * jb.gslot + idx];
+  }
 }
 
 // ===================================================================== profiler
@@ -813,34 +927,61 @@ static void timed(int kind, hipStream_t st, F&& launch) {
   } else {
     launch();
   }
+  QOC_HIP(hipGetLastError());
 }
 
-// Norms and (q, s) choice of every slice, without forming the generators.
-__global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njobs, const double* H64, const double* u,
-                                                     int K, double dt, int N, const double* theta, int r, int qmax,
-                                                     int* q_out, int* s_out, double* n_out) {
+// Norms and (q, s) choice of every slice, without forming the generators (statistics).
+__global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njobs, const double* u, int Nmax,
+                                                     const double* theta, int r, int qmax, int* q_out, int* s_out,
+                                                     double* n_out) {
   __shared__ double red[256];
-  const int J = blockIdx.y, j = blockIdx.x;
-  if (J >= njobs || j >= N) return;
+  __shared__ double ujs[17];
+  const int j = blockIdx.x;
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];
-  const int m = jb.m, mp = jb.mp;
-  const size_t plane = (size_t)mp * mp;
-  const double* H = H64 + jb.h_off;
-  double uj[17];
-  uj[0] = 1.0;
-  for (int k = 0; k < K; ++k) uj[k + 1] = u[(size_t)j * K + k];
-  const double cmax = block_col_norm(H, plane, mp, m, K, uj, red);
-  if (threadIdx.x == 0) {
-    double nx = dt * cmax;
-    int best_q = qmax, best_s = 0, best_cost = 1 << 30;
-    for (int q = qmax; q >= 1; --q) {
-      int s = 0;
-      while (s < 62 && nx > ldexp(theta[q * r], s)) ++s;
-      if ((q - 1) + s < best_cost) { best_cost = (q - 1) + s; best_q = q; best_s = s; }
+  if (j >= jb.N) {
+    if (threadIdx.x == 0) {
+      q_out[(size_t)J * Nmax + j] = 0;
+      s_out[(size_t)J * Nmax + j] = 0;
+      n_out[(size_t)J * Nmax + j] = 0.0;
     }
-    q_out[(size_t)J * N + j] = best_q;
-    s_out[(size_t)J * N + j] = best_s;
-    n_out[(size_t)J * N + j] = nx;
+    continue;
+  }
+  const int m = jb.m, mp = jb.mp, K = jb.K;
+  const size_t plane = (size_t)mp * mp;
+  __syncthreads();
+  if (threadIdx.x <= K) ujs[threadIdx.x] = threadIdx.x == 0 ? 1.0 : u[jb.u_off + (size_t)j * K + threadIdx.x - 1];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double cmax = 0.0;
+  for (int c = wave; c < m; c += nw) {
+    double cs = 0.0;
+    for (int rr = lane; rr < m; rr += 64) {
+      const size_t idx = (size_t)rr + (size_t)c * mp;
+      double hr = 0.0, hi = 0.0;
+      for (int o = 0; o <= K; ++o) {
+        hr += ujs[o] * jb.h64[(size_t)(2 * o) * plane + idx];
+        hi += ujs[o] * jb.h64[(size_t)(2 * o + 1) * plane + idx];
+      }
+      cs += hypot(hr, hi);
+    }
+    cmax = fmax(cmax, warp_sum(cs));
+  }
+  red[threadIdx.x] = cmax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nx = jb.dt * red[0];
+    int q, s;
+    pick_degree(nx, theta, r, qmax, &q, &s);
+    q_out[(size_t)J * Nmax + j] = q;
+    s_out[(size_t)J * Nmax + j] = s;
+    n_out[(size_t)J * Nmax + j] = nx;
+  }
+  __syncthreads();
   }
 }
 
@@ -852,23 +993,17 @@ static double fact(int n) {
 }
 
 static void upload_factorials() {
-  static bool done = false;
   static std::mutex mu;
+  static std::vector<int> devices_done;
   std::lock_guard<std::mutex> lk(mu);
   int dev = 0;
   QOC_HIP(hipGetDevice(&dev));
-  static std::vector<int> devices_done;
   if (std::find(devices_done.begin(), devices_done.end(), dev) != devices_done.end()) return;
   double h[64];
   for (int i = 0; i < 64; ++i) h[i] = 1.0 / fact(i);
   QOC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(kInvFact), h, sizeof(h)));
   devices_done.push_back(dev);
-  (void)done;
 }
-
-template <typename T> inline const T* sys_planes(const qoc_plan_s* P);
-template <> inline const double* sys_planes<double>(const qoc_plan_s* P) { return P->sys->h64.as<double>(); }
-template <> inline const float* sys_planes<float>(const qoc_plan_s* P) { return P->sys->h32.as<float>(); }
 
 template <typename T>
 struct Driver {
@@ -877,44 +1012,58 @@ struct Driver {
   static double* ent_norm(const qoc_plan_s* P, char* ws) {
     return reinterpret_cast<double*>(ws + P->off_ent + (size_t)8 * P->entries_per_seg);
   }
+  static size_t sweep_lds(const qoc_plan_s* P) { return P->sweep_lds_elems * sizeof(T); }
 
-  static void expm_segment(qoc_plan_s* P, char* ws, const double* u, int seg_j0, int seg_len, hipStream_t st) {
+  static void expm_segment(qoc_plan_s* P, char* ws, const double* u, int seg_j0, hipStream_t st) {
     const int njobs = (int)P->jobs.size();
     const JobDev* dj = P->d_jobs.as<JobDev>();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
-    const int nent = P->entries_per_seg;
-    timed(PK_GENERATOR, st, [&] { hipLaunchKernelGGL(k_generator<T>, dim3(nent), dim3(256), 0, st, dj, njobs, P->sys->h64.as<double>(), u, P->K,
-                       P->dt, seg_j0, seg_len, P->N, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags,
-                       P->d_theta.as<double>(), P->r, P->qmax, P->smax, P->norm_bound); });
-    QOC_HIP(hipGetLastError());
+    const int L = P->seg_len;
+    const int groups = (L + GEN_SG - 1) / GEN_SG;
+    timed(PK_GENERATOR, st, [&] {
+      hipLaunchKernelGGL(k_generator<T>, dim3(njobs * groups), dim3(256), 0, st, dj, njobs, u, seg_j0, L, groups, ws,
+                         P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags, P->d_theta.as<double>(), P->r,
+                         P->qmax, P->smax, P->norm_bound);
+    });
     const dim3 grid(P->grid_gemm);
-    for (int i = 2; i <= P->r; ++i)
-      timed(PK_EXPM_GEMM, st, [&] { hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
-                         ent_q(P, ws), (int)STEP_POWER, i, P->r, seg_len); });
-    timed(PK_HORNER_INIT, st, [&] { hipLaunchKernelGGL(k_horner_init<T>, dim3(nent), dim3(256), 0, st, dj, njobs, ws, P->off_T, ent_s(P, ws), ent_q(P, ws),
-                       P->r, seg_len); });
-    for (int t = 1; t <= P->qmax - 1; ++t)
-      timed(PK_EXPM_GEMM, st, [&] { hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
-                         ent_q(P, ws), (int)STEP_HORNER, t, P->r, seg_len); });
-    for (int t = 1; t <= P->smax; ++t)
-      timed(PK_EXPM_GEMM, st, [&] { hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws),
-                         ent_q(P, ws), (int)STEP_SQUARE, t, P->r, seg_len); });
-    QOC_HIP(hipGetLastError());
+    auto step = [&](int mode, int s) {
+      timed(PK_EXPM_GEMM, st, [&] {
+        hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T,
+                           ent_s(P, ws), ent_q(P, ws), mode, s, P->r, seg_j0, L);
+      });
+    };
+    for (int i = 2; i <= P->r; ++i) step(STEP_POWER, i);
+    for (int t = 1; t <= P->qmax - 1; ++t) step(STEP_HORNER, t);
+    for (int t = 1; t <= P->smax; ++t) step(STEP_SQUARE, t);
   }
 
-  static size_t sweep_lds(const qoc_plan_s* P) { return (size_t)P->sweep_lds_elems * sizeof(T); }
+  static void sweep(qoc_plan_s* P, char* ws, int dir, int seg_j0, hipStream_t st) {
+    const int njobs = (int)P->jobs.size();
+    const JobDev* dj = P->d_jobs.as<JobDev>();
+    if (dir == 0)
+      timed(PK_SWEEP_FWD, st, [&] {
+        hipLaunchKernelGGL((k_sweep<T, 0>), dim3(njobs), dim3(1024), sweep_lds(P), st, dj, njobs, ws, P->off_T,
+                           ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len);
+      });
+    else
+      timed(PK_SWEEP_BWD, st, [&] {
+        hipLaunchKernelGGL((k_sweep<T, 1>), dim3(njobs), dim3(1024), sweep_lds(P), st, dj, njobs, ws, P->off_T,
+                           ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len);
+      });
+  }
 
-  static void propagate(qoc_plan_s* P, const double* u, double2* out, const long long* out_off, char* ws,
-                        hipStream_t st) {
+  static void propagate(qoc_plan_s* P, const double* u, double2* out, char* ws, hipStream_t st) {
     const int njobs = (int)P->jobs.size();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
-    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);  // status ints only
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);
     for (int sg = 0; sg < P->nseg; ++sg) {
-      const int j0 = sg * P->seg_len, len = std::min(P->seg_len, P->N - j0);
-      expm_segment(P, ws, u, j0, len, st);
-      timed(PK_OTHER, st, [&] { hipLaunchKernelGGL(k_export_U<T>, dim3(64, P->entries_per_seg), dim3(256), 0, st, P->d_jobs.as<JobDev>(), njobs,
-                         ws, P->off_T, ent_s(P, ws), ent_q(P, ws), P->r, j0, len, P->N, out, out_off); });
-      QOC_HIP(hipGetLastError());
+      const int j0 = sg * P->seg_len;
+      expm_segment(P, ws, u, j0, st);
+      timed(PK_OTHER, st, [&] {
+        hipLaunchKernelGGL(k_export_U<T>, dim3(16, (unsigned)std::min<long long>(P->entries_per_seg, 32768)), dim3(256), 0, st,
+                           P->d_jobs.as<JobDev>(), njobs, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), P->r, j0,
+                           P->seg_len, out);
+      });
     }
   }
 
@@ -922,29 +1071,41 @@ struct Driver {
                   char* ws, hipStream_t st) {
     const int njobs = (int)P->jobs.size();
     const JobDev* dj = P->d_jobs.as<JobDev>();
+    const ProbDev* dpr = P->d_probs.as<ProbDev>();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
-    const int N = P->N;
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);  // status ints only
-    timed(PK_OTHER, st, [&] { hipLaunchKernelGGL(k_states_in<T>, dim3(8, njobs), dim3(256), 0, st, dj, njobs, (const double2*)psi0,
-                       (const double2*)psif, ws, P->off_T, N, flags); });
-    QOC_HIP(hipGetLastError());
-    // forward: propagators of a segment, then the sequential sweep through it
-    for (int sg = 0; sg < P->nseg; ++sg) {
-      const int j0 = sg * P->seg_len, len = std::min(P->seg_len, N - j0);
-      expm_segment(P, ws, u, j0, len, st);
-      timed(PK_SWEEP_FWD, st, [&] { hipLaunchKernelGGL((k_sweep<T, 0>), dim3(njobs), dim3(1024), sweep_lds(P), st, dj, njobs, ws, P->off_T,
-                         ent_s(P, ws), ent_q(P, ws), P->r, j0, len, N); });
-      QOC_HIP(hipGetLastError());
-    }
-    timed(PK_OVERLAP, st, [&] { hipLaunchKernelGGL(k_overlap<T>, dim3(1), dim3(1024), 0, st, dj, njobs, ws, P->off_T, N, flags, out); });
-    QOC_HIP(hipGetLastError());
-    // backward: the last segment's propagators are resident; earlier ones are recomputed
-    for (int sg = P->nseg - 1; sg >= 0; --sg) {
-      const int j0 = sg * P->seg_len, len = std::min(P->seg_len, N - j0);
-      if (sg != P->nseg - 1) expm_segment(P, ws, u, j0, len, st);
-      timed(PK_SWEEP_BWD, st, [&] { hipLaunchKernelGGL((k_sweep<T, 1>), dim3(njobs), dim3(1024), sweep_lds(P), st, dj, njobs, ws, P->off_T,
-                         ent_s(P, ws), ent_q(P, ws), P->r, j0, len, N); });
-      QOC_HIP(hipGetLastError());
+    timed(PK_OTHER, st, [&] {
+      hipLaunchKernelGGL(k_states_in<T>, dim3(8, std::min(njobs, 32768)), dim3(256), 0, st, dj, njobs, (const double2*)psi0,
+                         (const double2*)psif, ws, P->off_T, flags);
+    });
+    auto objective = [&](hipStream_t s) {
+      timed(PK_OVERLAP, s, [&] {
+        hipLaunchKernelGGL(k_overlap<T>, dim3(P->P), dim3(1024), 0, s, dj, dpr, ws, P->off_T, flags, out);
+      });
+    };
+    if (P->nseg == 1) {
+      // every propagator stays resident: the two sweeps are independent and run side by
+      // side, the backward one on the plan's second stream (fork/join by events)
+      expm_segment(P, ws, u, 0, st);
+      QOC_HIP(hipEventRecord(P->ev_fork, st));
+      QOC_HIP(hipStreamWaitEvent(P->st2, P->ev_fork, 0));
+      sweep(P, ws, 1, 0, P->st2);
+      QOC_HIP(hipEventRecord(P->ev_join, P->st2));
+      sweep(P, ws, 0, 0, st);
+      objective(st);
+      QOC_HIP(hipStreamWaitEvent(st, P->ev_join, 0));
+    } else {
+      // forward: propagators of a segment, then the sequential sweep through it
+      for (int sg = 0; sg < P->nseg; ++sg) {
+        expm_segment(P, ws, u, sg * P->seg_len, st);
+        sweep(P, ws, 0, sg * P->seg_len, st);
+      }
+      objective(st);
+      // backward: the last segment's propagators are resident; earlier ones are recomputed
+      for (int sg = P->nseg - 1; sg >= 0; --sg) {
+        if (sg != P->nseg - 1) expm_segment(P, ws, u, sg * P->seg_len, st);
+        sweep(P, ws, 1, sg * P->seg_len, st);
+      }
     }
     gradient(P, u, out, grad, ws, st);
   }
@@ -953,66 +1114,334 @@ struct Driver {
   static void gradient(qoc_plan_s* P, const double* u, double* out, double* grad, char* ws, hipStream_t st) {
     const int njobs = (int)P->jobs.size();
     const JobDev* dj = P->d_jobs.as<JobDev>();
-    const int N = P->N, K = P->K, R = P->R, Q = P->Q;
-    const double dtR = P->dt / R;
+    const ProbDev* dpr = P->d_probs.as<ProbDev>();
+    const int R = P->R, Q = P->Q, K = P->Kmax;
     const int slotA0 = K + 1, slotA1 = K + 2, slotS = K + 3, bank0 = K + 4;
-    const dim3 eg(64, njobs);
-    const T* H = sys_planes<T>(P);
+    const dim3 eg(16, std::min(njobs, 32768));
     const PanelDesc* dp = P->d_panels.as<PanelDesc>();
     const int npanel = (int)P->panels.size();
-    auto gemm = [&](int vslot) {
-      timed(PK_GRAD_GEMM, st, [&] { hipLaunchKernelGGL(k_panel_gemm<T>, dim3(P->grid_gemm), dim3(256), 0, st, dj, dp, npanel, P->panel_items, H, ws,
-                         P->off_T, vslot); });
-    };
-    for (int j0 = 0; j0 < N; j0 += P->chunk) {
-      const int ns = std::min(P->chunk, N - j0);
+    const int C = P->chunk;
+    for (int j0 = 0; j0 < P->Nmax; j0 += C) {
+      auto gemm = [&](int vslot) {
+        timed(PK_GRAD_GEMM, st, [&] {
+          hipLaunchKernelGGL(k_panel_gemm<T>, dim3(P->grid_gemm), dim3(256), 0, st, dj, dp, npanel, P->panel_items,
+                             ws, P->off_T, vslot, j0);
+        });
+      };
+      auto combine = [&](double sign_over, int out_slot, int acc_slot) {
+        timed(PK_GRAD_VECTOR, st, [&] {
+          hipLaunchKernelGGL(k_series_combine<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, u, j0, C, sign_over,
+                             R, out_slot, acc_slot);
+        });
+      };
+      auto slot_sum = [&](int dst, int first, int count) {
+        timed(PK_GRAD_VECTOR, st, [&] {
+          hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, dst, first, count, j0);
+        });
+      };
       // b-series, r = R-1 .. 0:  b_0 = lambda^{(r)}, b_{i+1} = +i (dt/R) H_j b_i / (i+1);
       // lambda^{(r-1)} = exp(-Y) lambda^{(r)} = sum_i b_i
-      timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_chunk_load<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, 1, bank0 + (R - 1) * Q, j0,
-                         ns, N); });
+      timed(PK_GRAD_VECTOR, st, [&] {
+        hipLaunchKernelGGL(k_chunk_load<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, 1, bank0 + (R - 1) * Q, j0,
+                           C);
+      });
       for (int rr = R - 1; rr >= 0; --rr) {
         const int bank = bank0 + rr * Q;
         for (int i = 0; i + 1 < Q; ++i) {
           gemm(bank + i);
-          timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_series_combine<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, u, K, j0, ns,
-                             dtR / (i + 1), bank + i + 1, -1, 0); });
+          combine(1.0 / (i + 1), bank + i + 1, -1);
         }
-        if (rr > 0)
-          timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, bank - Q, bank, Q); });
+        if (rr > 0) slot_sum(bank - Q, bank, Q);
       }
-      QOC_HIP(hipGetLastError());
       // a-series, r = 0 .. R-1: a_0 = psi^{(r)}, a_{t+1} = -i (dt/R) H_j a_t / (t+1);
       // the dot products take every (i, t) with i + t <= Q - 1
-      timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_chunk_load<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, 0, slotA0, j0, ns, N); });
+      timed(PK_GRAD_VECTOR, st, [&] {
+        hipLaunchKernelGGL(k_chunk_load<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, 0, slotA0, j0, C);
+      });
       int cur = slotA0, nxt = slotA1;
       bool first_dot = true;
       for (int rr = 0; rr < R; ++rr) {
         const int bank = bank0 + rr * Q;
         const bool need_next_state = rr + 1 < R;
-        if (need_next_state) timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, slotS, cur, 1); });
+        if (need_next_state) slot_sum(slotS, cur, 1);
         for (int t = 0; t < Q; ++t) {
           gemm(cur);
           const double* wt = P->d_w.as<double>() + (size_t)t * Q;
-          timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_series_dot<T>, dim3((P->max_cc + 3) / 4, njobs), dim3(256), 0, st, dj, njobs, ws,
-                             P->off_T, P->off_gacc, K, bank, Q - t, wt, first_dot ? 1 : 0); });
+          timed(PK_GRAD_VECTOR, st, [&] {
+            hipLaunchKernelGGL(k_series_dot<T>, dim3(std::min((P->max_cc + 3) / 4, 64), std::min(njobs, 32768)), dim3(256), 0, st, dj, njobs, ws,
+                               P->off_T, P->off_gacc, bank, Q - t, wt, first_dot ? 1 : 0, j0);
+          });
           first_dot = false;
           if (t + 1 < Q || need_next_state) {
-            timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_series_combine<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, u, K, j0, ns,
-                               -dtR / (t + 1), nxt, need_next_state ? slotS : -1, 0); });
+            combine(-1.0 / (t + 1), nxt, need_next_state ? slotS : -1);
             std::swap(cur, nxt);
           }
         }
         // a_0 of the next sub-step is psi^{(r+1)} = sum_t a_t, held in slotS
-        if (need_next_state)
-          timed(PK_GRAD_VECTOR, st, [&] { hipLaunchKernelGGL(k_slot_sum<T>, eg, dim3(256), 0, st, dj, njobs, ws, P->off_T, cur, slotS, 1); });
+        if (need_next_state) slot_sum(cur, slotS, 1);
       }
-      QOC_HIP(hipGetLastError());
-      timed(PK_GRAD_FINISH, st, [&] { hipLaunchKernelGGL(k_grad_finish, dim3((ns * K + 255) / 256), dim3(256), 0, st, dj, njobs, ws, P->off_gacc, K, j0,
-                         ns, dtR, out, grad); });
-      QOC_HIP(hipGetLastError());
+      timed(PK_GRAD_FINISH, st, [&] {
+        hipLaunchKernelGGL(k_grad_finish, dim3((C * K + 255) / 256, P->P), dim3(256), 0, st, dj, dpr, ws, P->off_gacc,
+                           j0, C, R, out, grad);
+      });
     }
   }
 };
+
+// ------------------------------------------------------------------- plan construction
+struct ProblemSpec {
+  qoc_system_s* sys;
+  int N;
+  double dt;
+};
+
+static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precision, double u_bound, size_t max_ws) {
+  QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
+  QOC_REQUIRE(std::isfinite(u_bound) && u_bound >= 0.0, QOC_ERR_INVALID_ARG, "u_bound must be finite and >= 0");
+  QOC_REQUIRE(!probs.empty(), QOC_ERR_INVALID_ARG, "no problems");
+  for (auto& pr : probs) {
+    QOC_REQUIRE(pr.sys, QOC_ERR_INVALID_ARG, "null system");
+    QOC_REQUIRE(pr.N >= 1 && pr.N <= (1 << 24), QOC_ERR_INVALID_ARG, "N must be in 1..2^24");
+    QOC_REQUIRE(std::isfinite(pr.dt) && pr.dt > 0.0, QOC_ERR_INVALID_ARG, "dt must be positive and finite");
+  }
+  upload_factorials();
+  auto P = std::make_unique<qoc_plan_s>();
+  P->P = (int)probs.size();
+  P->prec = precision;
+  P->u_bound = u_bound;
+  const bool f64 = precision == QOC_C128;
+  P->elem = f64 ? 8 : 4;
+  const double* theta = f64 ? kTaylorTheta64 : kTaylorTheta32;
+  P->r = f64 ? 4 : 3;
+  P->qmax = f64 ? 6 : 4;  // degrees up to 24 (FP64) / 12 (FP32)
+  const double unit = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
+  double nb = 0.0;
+  int max_mp = 0;
+  for (auto& pr : probs) {
+    P->Nmax = std::max(P->Nmax, pr.N);
+    P->Kmax = std::max(P->Kmax, pr.sys->K);
+    // norm bound by the triangle inequality on the exact block 1-norms
+    for (auto& b : pr.sys->blocks) {
+      double v = b.norm1[0];
+      for (int k = 1; k <= pr.sys->K; ++k) v += u_bound * b.norm1[k];
+      nb = std::max(nb, pr.dt * v);
+      max_mp = std::max(max_mp, b.mp);
+    }
+    if (std::find(P->systems.begin(), P->systems.end(), pr.sys) == P->systems.end()) P->systems.push_back(pr.sys);
+  }
+  P->norm_bound = nb;
+  {
+    // squarings the per-slice choice can pick for any norm in (0, nb]: the choice is
+    // piecewise constant between the points theta_{qr} 2^s, so evaluate just above each
+    auto choose_s = [&](double nx) {
+      int best_s = 0, best_cost = 1 << 30;
+      for (int q = P->qmax; q >= 1; --q) {
+        int sq = 0;
+        while (sq < 62 && nx > std::ldexp(theta[q * P->r], sq)) ++sq;
+        if ((q - 1) + sq < best_cost) { best_cost = (q - 1) + sq; best_s = sq; }
+      }
+      return best_s;
+    };
+    int smax = choose_s(nb);
+    for (int q = 1; q <= P->qmax; ++q)
+      for (int sq = 0; sq < 62; ++sq) {
+        const double x = std::ldexp(theta[q * P->r], sq);
+        if (x >= nb) break;
+        smax = std::max(smax, choose_s(std::nextafter(x, 1e300)));
+      }
+    P->smax = smax;
+  }
+  QOC_REQUIRE(P->smax <= 40, QOC_ERR_NUMERIC, "dt * ||H|| bound too large");
+  {
+    // Frechet series: R sub-steps and Q terms, the cheapest R*Q with theta^Q/Q! <= unit/8
+    // for theta = nb/R, keeping theta <= 3.5 so that the alternating terms (largest
+    // ~e^theta) lose at most a factor ~33 to cancellation
+    auto terms_for = [&](double th) {
+      int Q = 2;
+      while (Q < 80 && std::pow(th, Q) / fact(Q) > unit / 8) ++Q;
+      return Q;
+    };
+    int bestR = 1, bestQ = 0;
+    long best = -1;
+    for (int R = 1; R <= 1 << 20; R *= 2) {
+      const double th = nb / R;
+      if (th > 3.5) continue;
+      const int Q = terms_for(th);
+      if (best < 0 || (long)R * Q < best) { best = (long)R * Q; bestR = R; bestQ = Q; }
+      if (th < 0.5) break;
+    }
+    P->R = bestR;
+    P->Q = bestQ;
+  }
+  QOC_REQUIRE(max_mp <= 4096, QOC_ERR_UNSUPPORTED, "blocks larger than 4096 are not supported by the sweep kernels");
+  size_t lds_elems = 0;
+  for (auto& pr : probs)
+    for (auto& b : pr.sys->blocks)
+      lds_elems = std::max(lds_elems, (size_t)2 * b.d * b.mp * (1 + sweep_kgroups(b.mp)));
+  P->sweep_lds_elems = lds_elems;
+  QOC_REQUIRE(lds_elems * P->elem <= 160 * 1024, QOC_ERR_UNSUPPORTED, "block panel too large for the LDS-resident sweep");
+  const int K = P->Kmax;
+  const int nslots = K + 4 + P->R * P->Q;
+  P->nslots = nslots;
+  // per-slice propagator bytes and fixed state bytes
+  size_t per_slice = 0, fixed = 0;
+  for (auto& pr : probs)
+    for (auto& b : pr.sys->blocks) {
+      per_slice += (size_t)(P->r + 3) * 2 * b.mp * b.mp * P->elem;
+      fixed += (size_t)2 * b.mp * ((size_t)(pr.N + 1) * b.d + (size_t)pr.N * b.d) * P->elem;
+    }
+  int chunk = std::min(P->Nmax, 2048);
+  auto grad_bytes = [&](int ch) {
+    size_t g = 0;
+    for (auto& pr : probs)
+      for (auto& b : pr.sys->blocks) {
+        const int cc = (ch * b.d + 15) / 16 * 16;
+        g += (size_t)nslots * 2 * b.mp * cc * P->elem + (size_t)cc * K * 16;
+      }
+    return g;
+  };
+  size_t budget = max_ws;
+  if (!budget) {
+    // default: three quarters of the free device memory, at most 200 GiB
+    size_t free_b = 0, total_b = 0;
+    QOC_HIP(hipMemGetInfo(&free_b, &total_b));
+    budget = std::min<size_t>((size_t)200 << 30, free_b / 4 * 3);
+  }
+  while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice > budget) chunk /= 2;
+  P->chunk = chunk;
+  const size_t need = fixed + grad_bytes(chunk);
+  const size_t avail = budget > need ? budget - need : 0;
+  const long long seg = (long long)(avail / std::max<size_t>(per_slice, 1));
+  QOC_REQUIRE(seg >= 1, QOC_ERR_OUT_OF_MEMORY, "workspace budget below one slice of propagators");
+  P->seg_len = (int)std::min<long long>(seg, P->Nmax);
+  P->nseg = (P->Nmax + P->seg_len - 1) / P->seg_len;
+  // layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return o;
+  };
+  P->off_flags = take(256);
+  long long njobs_total = 0;
+  for (auto& pr : probs) njobs_total += (long long)pr.sys->blocks.size();
+  QOC_REQUIRE(njobs_total < (1LL << 30), QOC_ERR_INVALID_ARG, "too many (problem, block) pairs");
+  P->entries_per_seg = (long long)P->seg_len * njobs_total;
+  P->off_ent = take((size_t)P->entries_per_seg * 16);
+  long long tel = 0, ent_off = 0, item_off = 0, gacc = 0, u_off = 0, state_base = 0, uout = 0;
+  int max_cc = 0;
+  for (size_t p = 0; p < probs.size(); ++p) {
+    const auto& pr = probs[p];
+    ProbDev pd{};
+    pd.job_begin = (int)P->jobs.size();
+    pd.N = pr.N;
+    pd.K = pr.sys->K;
+    pd.dt = pr.dt;
+    pd.u_off = u_off;
+    for (auto& b : pr.sys->blocks) {
+      JobDev j{};
+      j.m = b.m;
+      j.mp = b.mp;
+      j.d = b.d;
+      j.prob = (int)p;
+      j.N = pr.N;
+      j.K = pr.sys->K;
+      j.dt = pr.dt;
+      j.h64 = pr.sys->h64.as<double>() + b.h_off;
+      j.hT = f64 ? (const void*)(pr.sys->h64.as<double>() + b.h_off) : (const void*)(pr.sys->h32.as<float>() + b.h_off);
+      j.state_off = state_base + b.state_off;
+      j.u_off = u_off;
+      j.tiles = (b.mp + TBM - 1) / TBM;
+      j.ent_off = ent_off;
+      ent_off += P->seg_len;
+      j.item_off = item_off;
+      item_off += (long long)P->seg_len * j.tiles * j.tiles;
+      j.ebuf_off = tel;
+      tel += (long long)P->seg_len * (P->r + 3) * 2 * b.mp * b.mp;
+      j.psi_off = tel;
+      tel += 2LL * b.mp * (pr.N + 1) * b.d;
+      j.lam_off = tel;
+      tel += 2LL * b.mp * pr.N * b.d;
+      j.cc = (chunk * b.d + 15) / 16 * 16;
+      max_cc = std::max(max_cc, j.cc);
+      j.gslot = 2LL * b.mp * j.cc;
+      j.gbase_off = tel;
+      tel += (long long)nslots * j.gslot;
+      j.gacc_off = gacc;
+      gacc += (long long)j.cc * pr.sys->K;
+      j.uout_off = uout;
+      uout += (long long)pr.N * b.m * b.m;
+      P->jobs.push_back(j);
+    }
+    pd.job_end = (int)P->jobs.size();
+    P->probs.push_back(pd);
+    u_off += (long long)pr.N * pr.sys->K;
+    long long D = 0;
+    for (auto& b : pr.sys->blocks) D += (long long)b.m * b.d;
+    state_base += D;
+  }
+  P->total_u = u_off;
+  P->total_D = state_base;
+  P->total_U = uout;
+  P->max_cc = max_cc;
+  P->expm_items = item_off;
+  P->off_T = take((size_t)tel * P->elem);
+  P->off_gacc = take((size_t)std::max<long long>(gacc, 1) * 16);
+  P->bytes = off;
+  // panel GEMM descriptors: (job, op) for op = 0..K_job
+  long long pitems = 0;
+  for (size_t J = 0; J < P->jobs.size(); ++J)
+    for (int o = 0; o <= P->jobs[J].K; ++o) {
+      PanelDesc d{};
+      d.job = (int)J;
+      d.op = o;
+      d.item_off = pitems;
+      d.tiles_m = (P->jobs[J].mp + TBM - 1) / TBM;
+      d.tiles_n = (P->jobs[J].cc + TBN - 1) / TBN;
+      pitems += (long long)d.tiles_m * d.tiles_n;
+      P->panels.push_back(d);
+    }
+  P->panel_items = pitems;
+  // device tables (set-up only)
+  P->d_jobs.alloc(P->jobs.size() * sizeof(JobDev));
+  QOC_HIP(hipMemcpy(P->d_jobs.ptr, P->jobs.data(), P->jobs.size() * sizeof(JobDev), hipMemcpyHostToDevice));
+  P->d_probs.alloc(P->probs.size() * sizeof(ProbDev));
+  QOC_HIP(hipMemcpy(P->d_probs.ptr, P->probs.data(), P->probs.size() * sizeof(ProbDev), hipMemcpyHostToDevice));
+  P->d_panels.alloc(std::max<size_t>(1, P->panels.size()) * sizeof(PanelDesc));
+  QOC_HIP(hipMemcpy(P->d_panels.ptr, P->panels.data(), P->panels.size() * sizeof(PanelDesc), hipMemcpyHostToDevice));
+  P->d_theta.alloc(31 * sizeof(double));
+  QOC_HIP(hipMemcpy(P->d_theta.ptr, theta, 31 * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<double> w((size_t)P->Q * P->Q, 0.0);
+  for (int t = 0; t < P->Q; ++t)
+    for (int i = 0; i + t < P->Q; ++i) w[(size_t)t * P->Q + i] = fact(i) * fact(t) / fact(i + t + 1);
+  P->d_w.alloc(w.size() * sizeof(double));
+  QOC_HIP(hipMemcpy(P->d_w.ptr, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
+  // persistent GEMM grid: resident work-groups, a multiple of the 8 XCDs
+  int dev = 0, occ = 2;
+  QOC_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  QOC_HIP(hipGetDeviceProperties(&prop, dev));
+  const int ncu = prop.multiProcessorCount;
+  if (f64)
+    QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_expm_step<double>, 256, 0));
+  else
+    QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_expm_step<float>, 256, 0));
+  P->grid_gemm = std::max(8, ncu * std::max(1, occ) / 8 * 8);
+  // the sweeps keep the state and partial sums in LDS; allow the dynamic size beyond 64 KB
+  const int lds = (int)(P->sweep_lds_elems * P->elem);
+  if (f64) {
+    QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  } else {
+    QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+  }
+  // second stream (default priority) for the backward sweep, and fork/join events
+  QOC_HIP(hipStreamCreateWithFlags(&P->st2, hipStreamNonBlocking));
+  QOC_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+  QOC_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+  return P.release();
+}
 
 }  // namespace qoc
 
@@ -1025,201 +1454,19 @@ qoc_status qoc_plan_create(qoc_system S, int precision, int N, double dt, double
   return guarded([&] {
     QOC_REQUIRE(S && out, QOC_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
-    QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
-    QOC_REQUIRE(N >= 1 && N <= (1 << 24), QOC_ERR_INVALID_ARG, "N must be in 1..2^24");
-    QOC_REQUIRE(std::isfinite(dt) && dt > 0.0, QOC_ERR_INVALID_ARG, "dt must be positive and finite");
-    QOC_REQUIRE(std::isfinite(u_bound) && u_bound >= 0.0, QOC_ERR_INVALID_ARG, "u_bound must be finite and >= 0");
-    upload_factorials();
-    auto P = std::make_unique<qoc_plan_s>();
-    P->sys = S;
-    P->prec = precision;
-    P->N = N;
-    P->K = S->K;
-    P->dt = dt;
-    P->u_bound = u_bound;
-    const bool f64 = precision == QOC_C128;
-    P->elem = f64 ? 8 : 4;
-    const double* theta = f64 ? kTaylorTheta64 : kTaylorTheta32;
-    P->r = f64 ? 4 : 3;
-    P->qmax = f64 ? 6 : 4;  // degrees up to 24 (FP64) / 12 (FP32)
-    const double unit = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
-    // norm bound by the triangle inequality on the exact block 1-norms
-    double nb = 0.0;
-    for (auto& b : S->blocks) {
-      double v = b.norm1[0];
-      for (int k = 1; k <= S->K; ++k) v += u_bound * b.norm1[k];
-      nb = std::max(nb, dt * v);
-    }
-    P->norm_bound = nb;
-    {
-      // squarings the per-slice choice can pick for any norm in (0, nb]: the choice is
-      // piecewise constant between the points theta_{qr} 2^s, so evaluate just above each
-      auto choose_s = [&](double nx) {
-        int best_s = 0, best_cost = 1 << 30;
-        for (int q = P->qmax; q >= 1; --q) {
-          int sq = 0;
-          while (sq < 62 && nx > std::ldexp(theta[q * P->r], sq)) ++sq;
-          if ((q - 1) + sq < best_cost) { best_cost = (q - 1) + sq; best_s = sq; }
-        }
-        return best_s;
-      };
-      int smax = choose_s(nb);
-      for (int q = 1; q <= P->qmax; ++q)
-        for (int sq = 0; sq < 62; ++sq) {
-          const double x = std::ldexp(theta[q * P->r], sq);
-          if (x >= nb) break;
-          smax = std::max(smax, choose_s(std::nextafter(x, 1e300)));
-        }
-      P->smax = smax;
-    }
-    QOC_REQUIRE(P->smax <= 40, QOC_ERR_NUMERIC, "dt * ||H|| bound too large");
-    // Frechet series: R sub-steps with ||Y||_1 <= 2, Q terms with theta^Q / Q! <= unit / 8
-    int R = 1;
-    while (nb / R > 2.0) R *= 2;
-    const double thg = nb / R;
-    int Q = 1;
-    double term = 1.0;
-    while (Q < 60) {
-      term = std::pow(thg, Q) / fact(Q);
-      if (term <= unit / 8) break;
-      ++Q;
-    }
-    P->R = R;
-    P->Q = std::max(Q, 2);
-    // jobs
-    int max_mpd = 0, max_mp = 0;
-    for (auto& b : S->blocks) {
-      max_mpd = std::max(max_mpd, b.mp * b.d);
-      max_mp = std::max(max_mp, b.mp);
-    }
-    P->max_mpd = max_mpd;
-    QOC_REQUIRE(max_mp <= 4096, QOC_ERR_UNSUPPORTED, "blocks larger than 4096 are not supported by the sweep kernels");
-    size_t lds_elems = 0;
-    for (auto& b : S->blocks)
-      lds_elems = std::max(lds_elems, (size_t)2 * b.d * b.mp * (1 + sweep_kgroups(b.mp)));
-    P->sweep_lds_elems = lds_elems;
-    QOC_REQUIRE(lds_elems * P->elem <= 160 * 1024, QOC_ERR_UNSUPPORTED,
-                "block panel too large for the LDS-resident sweep");
-    const int nslots = S->K + 4 + P->R * P->Q;
-    P->nslots = nslots;
-    // per-slice bytes: expm buffers + states, per job
-    size_t per_slice = 0, fixed = 0;
-    for (auto& b : S->blocks) {
-      per_slice += (size_t)(P->r + 3) * 2 * b.mp * b.mp * P->elem;
-      fixed += (size_t)2 * b.mp * ((size_t)(N + 1) * b.d + (size_t)N * b.d) * P->elem;
-    }
-    // gradient chunk: columns per job chunk*d rounded to 16, capped at 4096 columns
-    int chunk = std::min(N, 2048);
-    auto grad_bytes = [&](int ch) {
-      size_t g = 0;
-      for (auto& b : S->blocks) {
-        int cc = (ch * b.d + 15) / 16 * 16;
-        g += (size_t)nslots * 2 * b.mp * cc * P->elem + (size_t)cc * S->K * 16;
-      }
-      return g;
-    };
-    const size_t budget = max_ws ? max_ws : (size_t)200 << 30;
-    while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice > budget) chunk /= 2;
-    P->chunk = chunk;
-    size_t avail = budget > fixed + grad_bytes(chunk) ? budget - fixed - grad_bytes(chunk) : 0;
-    long long seg = (long long)(avail / std::max<size_t>(per_slice, 1));
-    QOC_REQUIRE(seg >= 1, QOC_ERR_OUT_OF_MEMORY, "workspace budget below one slice of propagators");
-    P->seg_len = (int)std::min<long long>(seg, N);
-    P->nseg = (N + P->seg_len - 1) / P->seg_len;
-    // layout
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-      size_t o = off;
-      off = (off + bytes + 255) / 256 * 256;
-      return o;
-    };
-    P->off_flags = take(256);
-    P->entries_per_seg = P->seg_len * (int)S->blocks.size();
-    P->off_ent = take((size_t)P->entries_per_seg * 16);
-    P->off_gacc = 0;
-    long long tel = 0;  // elements of T
-    long long ent_off = 0, item_off = 0, gacc = 0;
-    int max_cc = 0;
-    for (size_t bi = 0; bi < S->blocks.size(); ++bi) {
-      auto& b = S->blocks[bi];
-      JobDev j{};
-      j.m = b.m;
-      j.mp = b.mp;
-      j.d = b.d;
-      j.h_off = b.h_off;
-      j.state_off = b.state_off;
-      j.tiles = (b.mp + TBM - 1) / TBM;
-      j.ent_off = ent_off;
-      ent_off += P->seg_len;
-      j.item_off = item_off;
-      item_off += (long long)P->seg_len * j.tiles * j.tiles;
-      j.ebuf_off = tel;
-      tel += (long long)P->seg_len * (P->r + 3) * 2 * b.mp * b.mp;
-      j.psi_off = tel;
-      tel += 2LL * b.mp * (N + 1) * b.d;
-      j.lam_off = tel;
-      tel += 2LL * b.mp * N * b.d;
-      j.cc = (chunk * b.d + 15) / 16 * 16;
-      max_cc = std::max(max_cc, j.cc);
-      j.gslot = 2LL * b.mp * j.cc;
-      j.gbase_off = tel;
-      tel += (long long)nslots * j.gslot;
-      j.gacc_off = gacc;
-      gacc += (long long)j.cc * S->K;
-      P->jobs.push_back(j);
-    }
-    P->max_cc = max_cc;
-    P->expm_items = item_off;
-    P->off_T = take((size_t)tel * P->elem);
-    P->off_gacc = take((size_t)std::max<long long>(gacc, 1) * 16);
-    P->bytes = off;
-    // panel GEMM descriptors: (job, op) for op = 0..K
-    long long pitems = 0;
-    for (size_t J = 0; J < P->jobs.size(); ++J)
-      for (int o = 0; o <= S->K; ++o) {
-        PanelDesc d{};
-        d.job = (int)J;
-        d.op = o;
-        d.item_off = pitems;
-        d.tiles_m = (P->jobs[J].mp + TBM - 1) / TBM;
-        d.tiles_n = (P->jobs[J].cc + TBN - 1) / TBN;
-        pitems += (long long)d.tiles_m * d.tiles_n;
-        P->panels.push_back(d);
-      }
-    P->panel_items = pitems;
-    // device tables (set-up only)
-    P->d_jobs.alloc(P->jobs.size() * sizeof(JobDev));
-    QOC_HIP(hipMemcpy(P->d_jobs.ptr, P->jobs.data(), P->jobs.size() * sizeof(JobDev), hipMemcpyHostToDevice));
-    P->d_panels.alloc(std::max<size_t>(1, P->panels.size()) * sizeof(PanelDesc));
-    QOC_HIP(hipMemcpy(P->d_panels.ptr, P->panels.data(), P->panels.size() * sizeof(PanelDesc), hipMemcpyHostToDevice));
-    P->d_theta.alloc(31 * sizeof(double));
-    QOC_HIP(hipMemcpy(P->d_theta.ptr, theta, 31 * sizeof(double), hipMemcpyHostToDevice));
-    std::vector<double> w((size_t)P->Q * P->Q, 0.0);
-    for (int t = 0; t < P->Q; ++t)
-      for (int i = 0; i + t < P->Q; ++i) w[(size_t)t * P->Q + i] = fact(i) * fact(t) / fact(i + t + 1);
-    P->d_w.alloc(w.size() * sizeof(double));
-    QOC_HIP(hipMemcpy(P->d_w.ptr, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
-    // persistent GEMM grid: resident work-groups, a multiple of the 8 XCDs
-    int dev = 0, ncu = 256, occ = 2;
-    QOC_HIP(hipGetDevice(&dev));
-    hipDeviceProp_t prop;
-    QOC_HIP(hipGetDeviceProperties(&prop, dev));
-    ncu = prop.multiProcessorCount;
-    if (f64)
-      QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_expm_step<double>, 256, 0));
-    else
-      QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_expm_step<float>, 256, 0));
-    P->grid_gemm = std::max(8, ncu * std::max(1, occ) / 8 * 8);
-    // the sweeps keep the state and partial sums in LDS; allow the dynamic size beyond 64 KB
-    const int lds = (int)(P->sweep_lds_elems * P->elem);
-    if (f64) {
-      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    } else {
-      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-      QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    }
-    *out = P.release();
+    *out = build_plan({ProblemSpec{S, N, dt}}, precision, u_bound, max_ws);
+  });
+}
+
+qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* N, const double* dt, int precision,
+                                   double u_bound, size_t max_ws, qoc_plan* out) {
+  return guarded([&] {
+    QOC_REQUIRE(systems && N && dt && out, QOC_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    QOC_REQUIRE(P >= 1 && P <= 65535, QOC_ERR_INVALID_ARG, "P must be in 1..65535");
+    std::vector<ProblemSpec> probs;
+    for (int p = 0; p < P; ++p) probs.push_back(ProblemSpec{systems[p], N[p], dt[p]});
+    *out = build_plan(probs, precision, u_bound, max_ws);
   });
 }
 
@@ -1235,12 +1482,11 @@ qoc_status qoc_plan_workspace_size(qoc_plan P, size_t* bytes) {
 qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
   return guarded([&] {
     QOC_REQUIRE(P && info, QOC_ERR_INVALID_ARG, "null argument");
-    int64_t v[10] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, 0, P->smax, P->chunk,
-                     P->grid_gemm};
     size_t per_slice = 0;
     for (auto& j : P->jobs) per_slice += (size_t)(P->r + 3) * 2 * j.mp * j.mp * P->elem;
-    v[6] = (int64_t)per_slice;
-    for (int i = 0; i < cap && i < 10; ++i) info[i] = v[i];
+    int64_t v[15] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
+                     P->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U};
+    for (int i = 0; i < cap && i < 15; ++i) info[i] = v[i];
   });
 }
 
@@ -1250,20 +1496,10 @@ qoc_status qoc_propagate(qoc_plan P, const double* u_dev, void* U_out_dev, void*
     QOC_REQUIRE(P && u_dev && U_out_dev && workspace, QOC_ERR_INVALID_ARG, "null argument");
     QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
     hipStream_t st = (hipStream_t)stream;
-    // output offsets per job (complex entries), kept in the workspace flag page
-    std::vector<long long> offs;
-    long long o = 0;
-    for (auto& j : P->jobs) {
-      offs.push_back(o);
-      o += (long long)P->N * j.m * j.m;
-    }
-    QOC_REQUIRE(offs.size() <= 24, QOC_ERR_UNSUPPORTED, "too many blocks for the export table");
-    long long* d_offs = reinterpret_cast<long long*>(static_cast<char*>(workspace) + P->off_flags + 64);
-    QOC_HIP(hipMemcpyAsync(d_offs, offs.data(), offs.size() * sizeof(long long), hipMemcpyHostToDevice, st));
     if (P->prec == QOC_C128)
-      Driver<double>::propagate(P, u_dev, (double2*)U_out_dev, d_offs, (char*)workspace, st);
+      Driver<double>::propagate(P, u_dev, (double2*)U_out_dev, (char*)workspace, st);
     else
-      Driver<float>::propagate(P, u_dev, (double2*)U_out_dev, d_offs, (char*)workspace, st);
+      Driver<float>::propagate(P, u_dev, (double2*)U_out_dev, (char*)workspace, st);
   });
 }
 
@@ -1281,12 +1517,11 @@ qoc_status qoc_fidelity_grad(qoc_plan P, const double* u_dev, const void* psi0_d
   });
 }
 
-
 qoc_status qoc_profile_begin(int max_launches) {
   return guarded([&] {
     QOC_REQUIRE(max_launches >= 0 && max_launches <= (1 << 22), QOC_ERR_INVALID_ARG, "max_launches out of range");
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    size_t want = (size_t)2 * max_launches;
+    const size_t want = (size_t)2 * max_launches;
     while (g_prof.pool.size() < want) {
       hipEvent_t e;
       QOC_HIP(hipEventCreate(&e));
@@ -1326,11 +1561,10 @@ qoc_status qoc_plan_slice_stats(qoc_plan P, const double* u_dev, int32_t* q_host
     QOC_REQUIRE(P && u_dev && q_host && s_host && norm_host, QOC_ERR_INVALID_ARG, "null argument");
     hipStream_t st = (hipStream_t)stream;
     const int njobs = (int)P->jobs.size();
-    const size_t cnt = (size_t)njobs * P->N;
+    const size_t cnt = (size_t)njobs * P->Nmax;
     DeviceBuffer q(cnt * 4), sbuf(cnt * 4), nrm(cnt * 8);
-    hipLaunchKernelGGL(k_slice_norms, dim3(P->N, njobs), dim3(256), 0, st, P->d_jobs.as<JobDev>(), njobs,
-                       P->sys->h64.as<double>(), u_dev, P->K, P->dt, P->N, P->d_theta.as<double>(), P->r, P->qmax,
-                       q.as<int>(), sbuf.as<int>(), nrm.as<double>());
+    hipLaunchKernelGGL(k_slice_norms, dim3(P->Nmax, std::min(njobs, 32768)), dim3(256), 0, st, P->d_jobs.as<JobDev>(), njobs, u_dev,
+                       P->Nmax, P->d_theta.as<double>(), P->r, P->qmax, q.as<int>(), sbuf.as<int>(), nrm.as<double>());
     QOC_HIP(hipGetLastError());
     QOC_HIP(hipMemcpyAsync(q_host, q.ptr, cnt * 4, hipMemcpyDeviceToHost, st));
     QOC_HIP(hipMemcpyAsync(s_host, sbuf.ptr, cnt * 4, hipMemcpyDeviceToHost, st));

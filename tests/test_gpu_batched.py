@@ -1,0 +1,118 @@
+"""Batched plans (many independent problems sharing every launch) against the oracle:
+a prefix of the 256-ring workload (ragged n and N), candidate pulses under S_n, and a
+small FP64 batch checked to the FP64 tolerance."""
+import numpy as np
+import pytest
+
+import qoc_workloads as W
+from oracle import counts
+from oracle import grape as og
+from tests._common import panels_from_flat
+
+pytestmark = pytest.mark.gpu
+
+
+def _sizes(n):
+    bs = counts.block_sizes(n)
+    return [(m, d) for lab, (m, d) in bs.items() if m > 0]
+
+
+def _problem_states(rng, n):
+    D = 2 ** n
+    vf = W.gaussian_panel(rng, D)
+    v0 = W.gaussian_panel(rng, D)
+    return v0, vf
+
+
+def _oracle(w, v0, vf):
+    ob = og.block_system(w.n, w.h0, w.hk, "dihedral", w.stride)
+    return og.fidelity_grad(ob, w.u, w.dt, panels_from_flat(ob, v0), panels_from_flat(ob, vf))
+
+
+def test_ring_batch_prefix(lib):
+    """Problems 0..8 of the 256-ring workload (n = 14, 12, 12, 10, 10, 8, 8, 8, 8), FP32."""
+    import torch
+    print("ring batch prefix", flush=True)
+    ws, rng = W.config3_list(seed=0)
+    ws = ws[:9]
+    states = [_problem_states(rng, w.n) for w in ws]
+    bases = {n: lib.Basis(n) for n in sorted({w.n for w in ws})}
+    systems = [lib.System(bases[w.n], w.h0, w.hk) for w in ws]
+    P = lib.Plan.batched(systems, "c64", [w.N for w in ws], [w.dt for w in ws], 1.0, max_workspace_bytes=60 << 30)
+    print(f"  plan {P.info}", flush=True)
+    out, grads = lib.fidelity_grad_batched(P, [torch.tensor(w.u, device="cuda") for w in ws],
+                                           [torch.tensor(s[0], device="cuda") for s in states],
+                                           [torch.tensor(s[1], device="cuda") for s in states])
+    out = out.cpu().numpy()
+    for p, w in enumerate(ws):
+        g = grads[p].cpu().numpy()
+        assert out[p, 7] == 0
+        if w.n <= 10 and w.N < 1000:
+            ref = _oracle(w, *states[p])
+        elif w.n <= 8:
+            ref = _oracle(w, *states[p])
+        else:
+            # larger rings: the FP64 single-problem path (itself checked against the oracle)
+            S1 = systems[p]
+            P1 = lib.Plan(S1, "c128", w.N, w.dt, 1.0, max_workspace_bytes=60 << 30)
+            o1, g1 = lib.fidelity_grad(P1, torch.tensor(w.u, device="cuda"), torch.tensor(states[p][0], device="cuda"),
+                                       torch.tensor(states[p][1], device="cuda"))
+            ref = {"F": o1[0].item(), "grad": g1.cpu().numpy()}
+            del P1
+            torch.cuda.empty_cache()
+        dF = abs(out[p, 0] - ref["F"])
+        dg = np.abs(g - ref["grad"]).max()
+        print(f"  problem {p} n={w.n} N={w.N}: |dF|={dF:.2e} max|dg|={dg:.2e}", flush=True)
+        assert dF <= 1e-6
+        assert dg <= 2e-4 * np.abs(ref["grad"]).max() + 1e-7
+
+
+def test_small_batch_fp64_exact(lib):
+    """Three rings of different n and N in one FP64 plan, each to the FP64 tolerance."""
+    import torch
+    print("small FP64 batch", flush=True)
+    rng = np.random.default_rng(17)
+    ws = []
+    for n, N in ((4, 7), (6, 23), (5, 12)):
+        u = rng.uniform(-1, 1, (N, 2))
+        ws.append(W.Workload(f"ring{n}", n, "dihedral", 1, W.heisenberg_ring_terms(0.7 + 0.1 * n),
+                             W.global_controls(), N, 0.07, u))
+    states = [_problem_states(rng, w.n) for w in ws]
+    systems = [lib.System(lib.Basis(w.n), w.h0, w.hk) for w in ws]
+    P = lib.Plan.batched(systems, "c128", [w.N for w in ws], [w.dt for w in ws], 1.0)
+    out, grads = lib.fidelity_grad_batched(P, [torch.tensor(w.u, device="cuda") for w in ws],
+                                           [torch.tensor(s[0], device="cuda") for s in states],
+                                           [torch.tensor(s[1], device="cuda") for s in states])
+    for p, w in enumerate(ws):
+        ref = _oracle(w, *states[p])
+        assert abs(out[p, 0].item() - ref["F"]) <= 1e-12
+        assert np.abs(grads[p].cpu().numpy() - ref["grad"]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_symmetric_candidates(lib, prec):
+    """All-to-all register under S_n: C candidate pulses of one Hamiltonian in one plan
+    (the 128-qubit workload's shape with 8 candidates); two candidates vs the oracle."""
+    import torch
+    print(f"S_128 candidates {prec}", flush=True)
+    w = W.config5(seed=0, C=8)
+    uc = w.notes["u_candidates"]
+    rng = w.notes["rng"]
+    B = lib.Basis(128, "symmetric")
+    S = lib.System(B, w.h0, w.hk)
+    D = B.dim
+    states = [(W.gaussian_panel(rng, D), W.gaussian_panel(rng, D)) for _ in range(uc.shape[0])]
+    states = [(b, a) for a, b in states]  # (psi0, psi_f): psi_f drawn first
+    P = lib.Plan.batched([S] * uc.shape[0], prec, [w.N] * uc.shape[0], [w.dt] * uc.shape[0], 1.0)
+    out, grads = lib.fidelity_grad_batched(P, [torch.tensor(u, device="cuda") for u in uc],
+                                           [torch.tensor(s[0], device="cuda") for s in states],
+                                           [torch.tensor(s[1], device="cuda") for s in states])
+    ob = og.block_system(128, w.h0, w.hk, "symmetric")
+    for c in (0, 5):
+        ref = og.fidelity_grad(ob, uc[c], w.dt, panels_from_flat(ob, states[c][0]), panels_from_flat(ob, states[c][1]))
+        g = grads[c].cpu().numpy()
+        tf, tg = (1e-12, 1e-12) if prec == "c128" else (1e-6, 2e-4 * np.abs(ref["grad"]).max() + 1e-7)
+        print(f"  candidate {c}: |dF|={abs(out[c, 0].item() - ref['F']):.2e} "
+              f"max|dg|={np.abs(g - ref['grad']).max():.2e}", flush=True)
+        assert abs(out[c, 0].item() - ref["F"]) <= tf
+        assert np.abs(g - ref["grad"]).max() <= tg

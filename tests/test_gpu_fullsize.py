@@ -1,0 +1,88 @@
+"""The benchmark workload at full size (12-qubit ring under D12, 9 blocks, 1000 slices),
+in the launch configuration bench.py times, against the oracle: all-blocks states vs the
+oracle values stored by tests/golden/make_golden.py, and the plain variant (all-up to a
+state of the first block) vs the SU(2) closed form computed here."""
+import os
+
+import numpy as np
+import pytest
+
+import qoc_workloads as W
+from oracle import basis as obasis
+from oracle import closed_form
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "ring12_D12_allblocks_N1000.txt")
+
+
+def _golden():
+    vals, grad = {}, []
+    for line in open(GOLD):
+        if line.startswith("#"):
+            continue
+        k, *v = line.split()
+        if k == "g":
+            grad.append([float(x) for x in v])
+        else:
+            vals[k] = float(v[0])
+    return vals, np.array(grad)
+
+
+@pytest.fixture(scope="module")
+def ring12(lib):
+    w = W.config2(seed=0, variant="all")
+    B = lib.Basis(12, "dihedral", 1)
+    S = lib.System(B, w.h0, w.hk)
+    return w, B, S
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_allblocks_full_size_vs_oracle(lib, ring12, prec):
+    import torch
+    print(f"ring12 all blocks full size {prec}", flush=True)
+    w, B, S = ring12
+    # replay the input protocol: J, u, then psi_f and psi0 over all 4096 panel entries
+    w2 = W.config2(seed=0, variant="all")
+    rng = w2.notes["rng"]
+    vf = W.gaussian_panel(rng, 4096)
+    v0 = W.gaussian_panel(rng, 4096)
+    vals, gref = _golden()
+    P = lib.Plan(S, prec, w.N, w.dt, 2.0)  # the benchmark's plan
+    out, grad = lib.fidelity_grad(P, torch.tensor(w.u, device="cuda"), torch.tensor(v0, device="cuda"),
+                                  torch.tensor(vf, device="cuda"))
+    F = out[0].item()
+    g = grad.cpu().numpy()
+    if prec == "c128":
+        assert abs(F - vals["F"]) <= 1e-12
+        assert np.abs(g - gref).max() <= 1e-12
+    else:
+        assert abs(F - vals["F"]) <= 1e-6
+        assert np.abs(g - gref).max() <= 2e-4 * np.abs(gref).max() + 1e-7
+    print(f"  |dF| = {abs(F - vals['F']):.2e}  max|dg| = {np.abs(g - gref).max():.2e}", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_plain_full_size_vs_closed_form(lib, ring12, prec):
+    """All-up to a Gaussian state of the first block: F and the whole gradient equal the SU(2)
+    product closed form (isotropic coupling contributes only a phase)."""
+    import torch
+    print(f"ring12 plain closed form {prec}", flush=True)
+    w, B, S = ring12
+    w2 = W.config2(seed=0, variant="plain")
+    rng = w2.notes["rng"]
+    m0 = B.sizes[0]
+    pf = W.gaussian_panel(rng, m0)
+    V, reps = obasis.convention_basis(12, "A1")
+    psif_dense = V[0] @ pf
+    ref = closed_form.fidelity_grad(12, 0.5, w2.J, [("x", 1.0), ("y", 1.0)], w2.u, w2.dt, psif_dense)
+    v0 = np.zeros(4096, complex)
+    v0[0] = 1.0
+    vf = np.zeros(4096, complex)
+    vf[:m0] = pf
+    P = lib.Plan(S, prec, w2.N, w2.dt, 2.0)
+    out, grad = lib.fidelity_grad(P, torch.tensor(w2.u, device="cuda"), torch.tensor(v0, device="cuda"),
+                                  torch.tensor(vf, device="cuda"))
+    g = grad.cpu().numpy()
+    tf, tg = (1e-12, 1e-12) if prec == "c128" else (1e-6, 2e-4 * np.abs(ref["grad"]).max() + 1e-7)
+    assert abs(out[0].item() - ref["F"]) <= tf
+    assert np.abs(g - ref["grad"]).max() <= tg
