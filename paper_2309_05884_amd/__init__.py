@@ -20,7 +20,7 @@ from . import _capi as C
 from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "propagate", "GrapeFidelity",
-           "QocError", "library_path", "profile_begin", "profile_end", "slice_stats"]
+           "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep"]
 
 library_path = C.LIB_PATH
 
@@ -279,6 +279,37 @@ def propagate(plan: Plan, u, workspace=None):
             off += N * m * m
         per_problem.append(outs)
     return per_problem[0] if plan.P == 1 else per_problem
+
+
+class CapturedStep:
+    """The whole hot path (propagators, both sweeps, objective, gradient) captured once into
+    a HIP graph and replayed.  Inputs are read from, and outputs written to, the tensors
+    given at capture time; copy new controls into ``self.u`` before ``replay()``."""
+
+    def __init__(self, plan: Plan, u, psi0, psif):
+        torch = _torch()
+        self.plan = plan
+        self.u = u.to(torch.float64).contiguous().clone()
+        self.psi0 = psi0.to(torch.complex128).contiguous().clone()
+        self.psif = psif.to(torch.complex128).contiguous().clone()
+        self.ws = plan.workspace()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            _run(plan, self.u.reshape(-1), self.psi0, self.psif, self.ws, False)  # warm-up outside capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=side):
+            self.out, self.grad = _run(plan, self.u.reshape(-1), self.psi0, self.psif, self.ws, False)
+
+    def replay(self):
+        """Run the captured step; returns (out, grad) shaped as fidelity_grad (one problem) or
+        fidelity_grad_batched (out[P, 8] and the flat concatenated gradient) would."""
+        self.graph.replay()
+        if self.plan.P == 1:
+            return self.out[0], self.grad.view(self.plan.N, self.plan.K)
+        return self.out, self.grad
 
 
 def _autograd_function():

@@ -3,7 +3,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libqoc_gfx950.so")
+# QOC_LIBRARY may name another build of the same library (same ABI), e.g. a tuned variant
+LIB_PATH = os.environ.get("QOC_LIBRARY") or os.path.join(HERE, "libqoc_gfx950.so")
 
 QOC_OK = 0
 STATUS = {0: "QOC_OK", 1: "QOC_ERR_INVALID_ARG", 2: "QOC_ERR_SYMMETRY", 3: "QOC_ERR_UNSUPPORTED",

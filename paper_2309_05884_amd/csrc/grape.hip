@@ -37,7 +37,8 @@ namespace qoc {
 struct JobDev {
   int m, mp, d, prob;
   int N, K;              // the problem's slices and controls
-  int tiles, cc;         // ceil(mp / 64); gradient columns per chunk (multiple of 16)
+  int tiles_m, tiles_n;  // propagator GEMM tiles per matrix (rows, columns)
+  int cc;                // gradient columns per chunk (multiple of 16)
   double dt;
   const double* h64;     // FP64 operator planes of this block
   const void* hT;        // working-precision operator planes of this block
@@ -280,8 +281,7 @@ enum { STEP_POWER = 0, STEP_HORNER = 1, STEP_SQUARE = 2 };
 
 __constant__ double kInvFact[64];
 
-template <typename T> struct GemmWavesPerEU { static constexpr int value = 4; };
-template <> struct GemmWavesPerEU<double> { static constexpr int value = 2; };
+template <typename T> struct GemmWavesPerEU { static constexpr int value = 2; };
 
 // One product step over every entry of the segment (persistent, XCD-grouped items).
 // Buffers of an entry: 0 = Y, i-1 = Y^i (i <= r), r and r+1 = ping-pong T, r+2 = U^dag.
@@ -297,11 +297,11 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
     const int J = find_job_by_item(jobs, njobs, it);
     const JobDev jb = jobs[J];
     const long long local = it - jb.item_off;
-    const int t2 = jb.tiles * jb.tiles;
+    const int t2 = jb.tiles_m * jb.tiles_n;
     const int jl = (int)(local / t2);
     if (jl >= job_len(jb, seg_j0, seg_len)) continue;
     const int tile = (int)(local % t2);
-    const int ti = tile / jb.tiles, tj = tile % jb.tiles;
+    const int ti = tile / jb.tiles_n, tj = tile % jb.tiles_n;
     const long long e = jb.ent_off + jl;
     const int se = ent_s[e], qe = ent_q[e];
     int ia, ib, ic;
@@ -329,8 +329,8 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
     op.M = mp;
     op.N = mp;
     op.K = mp;
-    op.row0 = ti * TBM;
-    op.col0 = tj * TBN;
+    op.row0 = ti * TileCfg<T>::BM;
+    op.col0 = tj * TileCfg<T>::BN;
     TileAcc<T> acc;
     tile_mma(op, lds, acc);
     T* C = base + (size_t)ic * 2 * plane;
@@ -346,11 +346,11 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
       for (int i = 0; i < r; ++i) coef[i] = kInvFact[(qe - 1) * r + i];
     }
 #pragma unroll
-    for (int ri = 0; ri < 2; ++ri)
+    for (int ri = 0; ri < TileCfg<T>::SM; ++ri)
 #pragma unroll
-      for (int ci = 0; ci < 2; ++ci) {
-        const int rbase = acc_row_base(op.row0, ri);
-        const int col = acc_col(op.col0, ci);
+      for (int ci = 0; ci < TileCfg<T>::SN; ++ci) {
+        const int rbase = acc_row_base<T>(op.row0, ri);
+        const int col = acc_col<T>(op.col0, ci);
         if (rbase >= mp || col >= mp) continue;
         typename Vec4<T>::type vr = acc.re[ri][ci], vi = acc.im[ri][ci];
         if (mode == STEP_HORNER) {
@@ -672,7 +672,7 @@ __global__ void __launch_bounds__(1024) k_overlap(const JobDev* jobs, const Prob
 // ===================================================================== gradient series
 // Z_o = H_o * V for every (job, o); V and Z are gradient slots of the job.
 template <typename T>
-__global__ void __launch_bounds__(256) k_panel_gemm(const JobDev* jobs, const PanelDesc* descs, int ndesc,
+__global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value) k_panel_gemm(const JobDev* jobs, const PanelDesc* descs, int ndesc,
                                                     long long total_items, char* ws, size_t off_T, int vslot,
                                                     int j0) {
   __shared__ TileLds<T> lds;
@@ -697,17 +697,17 @@ __global__ void __launch_bounds__(256) k_panel_gemm(const JobDev* jobs, const Pa
     op.M = mp;
     op.N = jb.cc;
     op.K = mp;
-    op.row0 = ti * TBM;
-    op.col0 = tj * TBN;
+    op.row0 = ti * TileCfg<T>::BM;
+    op.col0 = tj * TileCfg<T>::BN;
     TileAcc<T> acc;
     tile_mma(op, lds, acc);
     T* C = g + (size_t)pd.op * jb.gslot;
 #pragma unroll
-    for (int ri = 0; ri < 2; ++ri)
+    for (int ri = 0; ri < TileCfg<T>::SM; ++ri)
 #pragma unroll
-      for (int ci = 0; ci < 2; ++ci) {
-        const int rbase = acc_row_base(op.row0, ri);
-        const int col = acc_col(op.col0, ci);
+      for (int ci = 0; ci < TileCfg<T>::SN; ++ci) {
+        const int rbase = acc_row_base<T>(op.row0, ri);
+        const int col = acc_col<T>(op.col0, ci);
         if (rbase >= mp || col >= jb.cc) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -1075,7 +1075,7 @@ struct Driver {
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);  // status ints only
     timed(PK_OTHER, st, [&] {
-      hipLaunchKernelGGL(k_states_in<T>, dim3(8, std::min(njobs, 32768)), dim3(256), 0, st, dj, njobs, (const double2*)psi0,
+      hipLaunchKernelGGL(k_states_in<T>, dim3(std::max(1, std::min(64, 8192 / njobs)), std::min(njobs, 32768)), dim3(256), 0, st, dj, njobs, (const double2*)psi0,
                          (const double2*)psif, ws, P->off_T, flags);
     });
     auto objective = [&](hipStream_t s) {
@@ -1117,7 +1117,8 @@ struct Driver {
     const ProbDev* dpr = P->d_probs.as<ProbDev>();
     const int R = P->R, Q = P->Q, K = P->Kmax;
     const int slotA0 = K + 1, slotA1 = K + 2, slotS = K + 3, bank0 = K + 4;
-    const dim3 eg(16, std::min(njobs, 32768));
+    // per-job vector kernels: about 8k work-groups in total, at most 256 per job
+    const dim3 eg(std::max(1, std::min(256, 8192 / njobs)), std::min(njobs, 32768));
     const PanelDesc* dp = P->d_panels.as<PanelDesc>();
     const int npanel = (int)P->panels.size();
     const int C = P->chunk;
@@ -1168,7 +1169,7 @@ struct Driver {
           gemm(cur);
           const double* wt = P->d_w.as<double>() + (size_t)t * Q;
           timed(PK_GRAD_VECTOR, st, [&] {
-            hipLaunchKernelGGL(k_series_dot<T>, dim3(std::min((P->max_cc + 3) / 4, 64), std::min(njobs, 32768)), dim3(256), 0, st, dj, njobs, ws,
+            hipLaunchKernelGGL(k_series_dot<T>, dim3(std::max(1, std::min((P->max_cc + 3) / 4, 8192 / njobs)), std::min(njobs, 32768)), dim3(256), 0, st, dj, njobs, ws,
                                P->off_T, P->off_gacc, bank, Q - t, wt, first_dot ? 1 : 0, j0);
           });
           first_dot = false;
@@ -1210,6 +1211,9 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->prec = precision;
   P->u_bound = u_bound;
   const bool f64 = precision == QOC_C128;
+  // work-group tile of the GEMM kernels (see mfma_tile.h)
+  const int tbm = f64 ? TileCfg<double>::BM : TileCfg<float>::BM;
+  const int tbn = f64 ? TileCfg<double>::BN : TileCfg<float>::BN;
   P->elem = f64 ? 8 : 4;
   const double* theta = f64 ? kTaylorTheta64 : kTaylorTheta32;
   P->r = f64 ? 4 : 3;
@@ -1351,11 +1355,12 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       j.hT = f64 ? (const void*)(pr.sys->h64.as<double>() + b.h_off) : (const void*)(pr.sys->h32.as<float>() + b.h_off);
       j.state_off = state_base + b.state_off;
       j.u_off = u_off;
-      j.tiles = (b.mp + TBM - 1) / TBM;
+      j.tiles_m = (b.mp + tbm - 1) / tbm;
+      j.tiles_n = (b.mp + tbn - 1) / tbn;
       j.ent_off = ent_off;
       ent_off += P->seg_len;
       j.item_off = item_off;
-      item_off += (long long)P->seg_len * j.tiles * j.tiles;
+      item_off += (long long)P->seg_len * j.tiles_m * j.tiles_n;
       j.ebuf_off = tel;
       tel += (long long)P->seg_len * (P->r + 3) * 2 * b.mp * b.mp;
       j.psi_off = tel;
@@ -1396,8 +1401,8 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       d.job = (int)J;
       d.op = o;
       d.item_off = pitems;
-      d.tiles_m = (P->jobs[J].mp + TBM - 1) / TBM;
-      d.tiles_n = (P->jobs[J].cc + TBN - 1) / TBN;
+      d.tiles_m = (P->jobs[J].mp + tbm - 1) / tbm;
+      d.tiles_n = (P->jobs[J].cc + tbn - 1) / tbn;
       pitems += (long long)d.tiles_m * d.tiles_n;
       P->panels.push_back(d);
     }

@@ -1,10 +1,15 @@
-// 64x64 complex GEMM tile on the gfx950 matrix cores (planar complex, column-major).
+// Complex GEMM tile on the gfx950 matrix cores (planar complex, column-major).
 //
-// A work-group of 256 threads (4 wave64s) computes C[64x64] += A[64xK] * B[Kx64] with
-// K a multiple of 16.  Operands are staged through LDS in 16-deep slabs (double
-// buffered: the next slab is fetched into registers while the current one feeds the
-// MFMAs).  Each wave owns a 32x32 quadrant as 2x2 tiles of v_mfma_*_16x16x4; a complex
-// product is four real MFMAs: Re += Ar*Br - Ai*Bi, Im += Ar*Bi + Ai*Br.
+// A work-group of 256 threads (4 wave64s in a 2x2 arrangement) computes
+// C[BM x BN] = A[BM x K] * B[K x BN], K a multiple of 16.  Each wave owns a
+// (BM/2) x (BN/2) quadrant as SM x SN sub-tiles of v_mfma_*_16x16x4; a complex product is
+// complex multiply-add built from real MFMAs.  FP32 uses 128 x 128 tiles
+// (each wave 4 x 4 sub-tiles: twice the MFMAs per LDS read and half the operand re-reads
+// of a 64 x 64 tile); FP64 uses 64 x 64 (its accumulators are twice as wide).
+// The complex product takes three real MFMAs per sub-tile and k step instead of four
+// (Gauss's 3M form, see TileAcc).
+// Operands are staged through double-buffered LDS in 16-deep slabs; the next slab is
+// loaded into registers while the current one feeds the MFMAs.
 // MFMA 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16].  The
 // accumulator element v of lane l is D[4*(l/16)+v][l%16] for the FP32 instruction and
 // D[(l/16)+4v][l%16] for the FP64 one (measured on gfx950).
@@ -24,19 +29,27 @@ template <> struct Vec4<float> { typedef f4v type; };
 __device__ inline d4v mfma16(double a, double b, d4v c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline f4v mfma16(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-constexpr int TBM = 64, TBN = 64, TBK = 16;
-constexpr int TPAD = 4;  // LDS row padding (elements)
+// Work-group tile BM x BN, SM x SN sub-tiles per wave, LDS row padding PAD (elements):
+// consecutive k rows of a slab start 16 (FP32) or 32 (FP64) banks apart.
+template <typename T> struct TileCfg;
+template <> struct TileCfg<float> { static constexpr int BM = 128, BN = 64, SM = 4, SN = 2, PAD = 16; };
+template <> struct TileCfg<double> { static constexpr int BM = 64, BN = 64, SM = 2, SN = 2, PAD = 16; };
+constexpr int TBK = 16;
 
 template <typename T>
 struct TileLds {
-  T a[2][2][TBK][TBM + TPAD];  // [buffer][plane][k][row]
-  T b[2][2][TBK][TBN + TPAD];  // [buffer][plane][k][col]
+  T a[2][2][TBK][TileCfg<T>::BM + TileCfg<T>::PAD];  // [buffer][plane][k][row]
+  T b[2][2][TBK][TileCfg<T>::BN + TileCfg<T>::PAD];  // [buffer][plane][k][col]
 };
 
+// Accumulators.  Inside the K loop the complex product is formed with three real products
+// (Gauss): re = Ar*Br, x = Ai*Bi, im = (Ar+Ai)*(Br+Bi); tile_mma returns
+// re = Ar*Br - Ai*Bi and im = (Ar+Ai)*(Br+Bi) - Ar*Br - Ai*Bi.
 template <typename T>
 struct TileAcc {
-  typename Vec4<T>::type re[2][2];
-  typename Vec4<T>::type im[2][2];
+  typename Vec4<T>::type re[TileCfg<T>::SM][TileCfg<T>::SN];
+  typename Vec4<T>::type im[TileCfg<T>::SM][TileCfg<T>::SN];
+  typename Vec4<T>::type x[TileCfg<T>::SM][TileCfg<T>::SN];
 };
 
 // Operand pointers of one tile product.  Planes: re at p, im at p + plane stride.
@@ -52,122 +65,208 @@ struct TileOperands {
   int row0, col0;
 };
 
+// 16-byte vectors of the working type (4 floats, 2 doubles).
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+
+// Slab loads, 16-byte vectors, thread t handles plane t/128 (tt = t%128):
+//  A (BM x 16): vectors f = tt + 128 i (i < NA): k = f / CV, rows (f % CV) * VEC .. with
+//    CV = BM/VEC vectors per k row; a wave's stores to LDS cover whole k rows;
+//  B (16 x BN): column tt/TPC, KB = BN/8 consecutive k from (tt%TPC)*KB (NB vectors).
 template <typename T>
-__device__ inline void tile_fetch(const TileOperands<T>& op, int k0, T (&ra)[8], T (&rb)[8]) {
+struct SlabShape {
+  static constexpr int VEC = Vec16<T>::n;
+  static constexpr int CV = TileCfg<T>::BM / VEC;
+  static constexpr int NA = TileCfg<T>::BM * TBK / (128 * VEC);
+  static constexpr int KB = TileCfg<T>::BN / 8;
+  static constexpr int NB = KB / VEC;
+  static constexpr int TPC = TBK / KB;
+  static_assert(NA >= 1 && NB >= 1 && TBK % KB == 0, "slab mapping");
+};
+
+template <typename T>
+struct SlabRegs {
+  typename Vec16<T>::type a[SlabShape<T>::NA];
+  typename Vec16<T>::type b[SlabShape<T>::NB];
+};
+
+template <typename T>
+__device__ inline void tile_fetch(const TileOperands<T>& op, int k0, SlabRegs<T>& r) {
+  typedef typename Vec16<T>::type V;
+  typedef SlabShape<T> S;
   const int t = threadIdx.x;
   const int plane = t >> 7, tt = t & 127;
-  {  // A: 8 consecutive rows of one k column
-    const int kk = tt >> 3, ii = (tt & 7) * 8;
-    const int row = op.row0 + ii;
-    if (row < op.M) {
-      const T* p = op.A + plane * op.a_ps + (long long)(k0 + kk) * op.lda + row;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ra[e] = p[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) ra[e] = T(0);
-    }
+  for (int i = 0; i < S::NA; ++i) {
+    const int f = tt + 128 * i;
+    const int kk = f / S::CV, row = op.row0 + (f % S::CV) * S::VEC;
+    if (row < op.M)
+      r.a[i] = *reinterpret_cast<const V*>(op.A + plane * op.a_ps + (long long)(k0 + kk) * op.lda + row);
+    else
+      r.a[i] = V{};
   }
-  {  // B: 8 consecutive k of one column
-    const int jj = tt >> 1, kk = (tt & 1) * 8;
-    const int col = op.col0 + jj;
-    if (col < op.N) {
-      const T* p = op.B + plane * op.b_ps + (long long)col * op.ldb + k0 + kk;
+  const int col = op.col0 + tt / S::TPC, kk = (tt % S::TPC) * S::KB;
+  const V* p = reinterpret_cast<const V*>(op.B + plane * op.b_ps + (long long)col * op.ldb + k0 + kk);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rb[e] = p[e];
-    } else {
+  for (int i = 0; i < S::NB; ++i) r.b[i] = col < op.N ? p[i] : V{};
+}
+
+template <typename T>
+__device__ inline void tile_stash(TileLds<T>& s, int buf, const SlabRegs<T>& r) {
+  typedef typename Vec16<T>::type V;
+  typedef SlabShape<T> S;
+  const int t = threadIdx.x;
+  const int plane = t >> 7, tt = t & 127;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) rb[e] = T(0);
+  for (int i = 0; i < S::NA; ++i) {
+    const int f = tt + 128 * i;
+    *reinterpret_cast<V*>(&s.a[buf][plane][f / S::CV][(f % S::CV) * S::VEC]) = r.a[i];
+  }
+  const int jj = tt / S::TPC, kk = (tt % S::TPC) * S::KB;
+#pragma unroll
+  for (int i = 0; i < S::NB; ++i)
+#pragma unroll
+    for (int e = 0; e < S::VEC; ++e) s.b[buf][plane][kk + i * S::VEC + e][jj] = r.b[i][e];
+}
+
+// Wave placement inside the work-group tile (the wave index is uniform: a scalar).
+__device__ inline int tile_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// MFMA operands of one 4-deep k step: this lane's rows of A and columns of B.
+template <typename T>
+struct StepOps {
+  T ar[TileCfg<T>::SM], ai[TileCfg<T>::SM], br[TileCfg<T>::SN], bi[TileCfg<T>::SN];
+};
+
+template <typename T>
+__device__ inline void step_load(const TileLds<T>& s, int buf, int kq, int r0, int c0, StepOps<T>& o) {
+#pragma unroll
+  for (int q = 0; q < TileCfg<T>::SM; ++q) {
+    o.ar[q] = s.a[buf][0][kq][r0 + q * 16];
+    o.ai[q] = s.a[buf][1][kq][r0 + q * 16];
+  }
+#pragma unroll
+  for (int q = 0; q < TileCfg<T>::SN; ++q) {
+    o.br[q] = s.b[buf][0][kq][c0 + q * 16];
+    o.bi[q] = s.b[buf][1][kq][c0 + q * 16];
+  }
+}
+
+// Three real MFMAs per sub-tile and k step (see TileAcc); all 3 SM SN of a step are
+// independent, so dependent MFMAs are a full step apart.
+template <typename T, bool FULL>
+__device__ inline void step_mfma(const StepOps<T>& o, const bool (&rv)[TileCfg<T>::SM],
+                                 const bool (&cv)[TileCfg<T>::SN], TileAcc<T>& acc) {
+  constexpr int SM = TileCfg<T>::SM, SN = TileCfg<T>::SN;
+  T as[SM], bs[SN];
+#pragma unroll
+  for (int q = 0; q < SM; ++q) as[q] = o.ar[q] + o.ai[q];
+#pragma unroll
+  for (int q = 0; q < SN; ++q) bs[q] = o.br[q] + o.bi[q];
+#pragma unroll
+  for (int ri = 0; ri < SM; ++ri)
+#pragma unroll
+    for (int ci = 0; ci < SN; ++ci) {
+      if (!FULL && !(rv[ri] && cv[ci])) continue;
+      acc.re[ri][ci] = mfma16(o.ar[ri], o.br[ci], acc.re[ri][ci]);
+      acc.x[ri][ci] = mfma16(o.ai[ri], o.bi[ci], acc.x[ri][ci]);
+      acc.im[ri][ci] = mfma16(as[ri], bs[ci], acc.im[ri][ci]);
+    }
+}
+
+// One 16-deep slab: the operands of step k+1 are read from LDS while the MFMAs of step k
+// run (two register stages); on interior tiles the scheduler is told to interleave them.
+template <typename T, bool FULL>
+__device__ inline void tile_slab(const TileLds<T>& s, int buf, const bool (&rv)[TileCfg<T>::SM],
+                                 const bool (&cv)[TileCfg<T>::SN], TileAcc<T>& acc) {
+  constexpr int SM = TileCfg<T>::SM, SN = TileCfg<T>::SN;
+  const int lane = threadIdx.x & 63, wave = tile_wave();
+  const int r0 = (wave >> 1) * (TileCfg<T>::BM / 2) + (lane & 15);
+  const int c0 = (wave & 1) * (TileCfg<T>::BN / 2) + (lane & 15);
+  const int kl = lane >> 4;
+  StepOps<T> o[2];
+  step_load(s, buf, kl, r0, c0, o[0]);
+#pragma unroll
+  for (int k4 = 0; k4 < TBK / 4; ++k4) {
+    if (k4 + 1 < TBK / 4) step_load(s, buf, (k4 + 1) * 4 + kl, r0, c0, o[(k4 + 1) & 1]);
+    step_mfma<T, FULL>(o[k4 & 1], rv, cv, acc);
+    if (FULL && k4 + 1 < TBK / 4) {
+      // ds reads of the next step (merged in pairs) spread over this step's MFMAs
+      constexpr int NRD = SM + SN, NMF = 3 * SM * SN / NRD;
+#pragma unroll
+      for (int g = 0; g < NRD; ++g) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
+      }
     }
   }
 }
 
-template <typename T>
-__device__ inline void tile_stash(TileLds<T>& s, int buf, const T (&ra)[8], const T (&rb)[8]) {
-  const int t = threadIdx.x;
-  const int plane = t >> 7, tt = t & 127;
-  {
-    const int kk = tt >> 3, ii = (tt & 7) * 8;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) s.a[buf][plane][kk][ii + e] = ra[e];
-  }
-  {
-    const int jj = tt >> 1, kk = (tt & 1) * 8;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) s.b[buf][plane][kk + e][jj] = rb[e];
-  }
-}
-
-// Full K loop for one 64x64 output tile; acc is zeroed here.
-template <typename T>
-__device__ inline void tile_mma(const TileOperands<T>& op, TileLds<T>& s, TileAcc<T>& acc) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  bool rv[2], cv[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    rv[q] = op.row0 + wr * 32 + q * 16 < op.M;
-    cv[q] = op.col0 + wc * 32 + q * 16 < op.N;
-  }
-#pragma unroll
-  for (int ri = 0; ri < 2; ++ri)
-#pragma unroll
-    for (int ci = 0; ci < 2; ++ci) {
-      acc.re[ri][ci] = typename Vec4<T>::type{0, 0, 0, 0};
-      acc.im[ri][ci] = typename Vec4<T>::type{0, 0, 0, 0};
-    }
-  T ra[8], rb[8];
+template <typename T, bool FULL>
+__device__ inline void tile_kloop(const TileOperands<T>& op, TileLds<T>& s, const bool (&rv)[TileCfg<T>::SM],
+                                  const bool (&cv)[TileCfg<T>::SN], TileAcc<T>& acc) {
+  SlabRegs<T> r;
   const int nk = op.K / TBK;
-  tile_fetch(op, 0, ra, rb);
-  __syncthreads();  // previous users of the LDS buffers are done
-  tile_stash(s, 0, ra, rb);
+  tile_fetch(op, 0, r);
+  __syncthreads();  // the previous tile's readers are done with both buffers
+  tile_stash(s, 0, r);
   __syncthreads();
   for (int kb = 0; kb < nk; ++kb) {
     const int buf = kb & 1;
-    if (kb + 1 < nk) tile_fetch(op, (kb + 1) * TBK, ra, rb);
-#pragma unroll
-    for (int k4 = 0; k4 < TBK / 4; ++k4) {
-      const int kq = k4 * 4 + (lane >> 4);
-      const int rr = lane & 15;
-      T ar[2], ai[2], br[2], bi[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        ar[q] = s.a[buf][0][kq][wr * 32 + q * 16 + rr];
-        ai[q] = s.a[buf][1][kq][wr * 32 + q * 16 + rr];
-        br[q] = s.b[buf][0][kq][wc * 32 + q * 16 + rr];
-        bi[q] = s.b[buf][1][kq][wc * 32 + q * 16 + rr];
-      }
-#pragma unroll
-      for (int ri = 0; ri < 2; ++ri) {
-        if (!rv[ri]) continue;
-#pragma unroll
-        for (int ci = 0; ci < 2; ++ci) {
-          if (!cv[ci]) continue;
-          acc.re[ri][ci] = mfma16(ar[ri], br[ci], acc.re[ri][ci]);
-          acc.re[ri][ci] = mfma16(-ai[ri], bi[ci], acc.re[ri][ci]);
-          acc.im[ri][ci] = mfma16(ar[ri], bi[ci], acc.im[ri][ci]);
-          acc.im[ri][ci] = mfma16(ai[ri], br[ci], acc.im[ri][ci]);
-        }
-      }
-    }
-    if (kb + 1 < nk) {
-      tile_stash(s, buf ^ 1, ra, rb);
-    }
+    if (kb + 1 < nk) tile_fetch(op, (kb + 1) * TBK, r);
+    tile_slab<T, FULL>(s, buf, rv, cv, acc);
+    if (kb + 1 < nk) tile_stash(s, buf ^ 1, r);
     __syncthreads();
   }
 }
 
-// First row of sub-tile ri of this wave, and the row offset of accumulator element v.
+// Full K loop for one output tile; acc is zeroed here.  Interior tiles run a copy of the
+// loop without the per-sub-tile range checks; every check is wave-uniform.
+template <typename T>
+__device__ inline void tile_mma(const TileOperands<T>& op, TileLds<T>& s, TileAcc<T>& acc) {
+  constexpr int SM = TileCfg<T>::SM, SN = TileCfg<T>::SN;
+#pragma unroll
+  for (int ri = 0; ri < SM; ++ri)
+#pragma unroll
+    for (int ci = 0; ci < SN; ++ci) {
+      acc.re[ri][ci] = typename Vec4<T>::type{0, 0, 0, 0};
+      acc.im[ri][ci] = typename Vec4<T>::type{0, 0, 0, 0};
+      acc.x[ri][ci] = typename Vec4<T>::type{0, 0, 0, 0};
+    }
+  const int wave = tile_wave();
+  const int wr = wave >> 1, wc = wave & 1;
+  bool rv[SM], cv[SN];
+#pragma unroll
+  for (int q = 0; q < SM; ++q) rv[q] = op.row0 + wr * (TileCfg<T>::BM / 2) + q * 16 < op.M;
+#pragma unroll
+  for (int q = 0; q < SN; ++q) cv[q] = op.col0 + wc * (TileCfg<T>::BN / 2) + q * 16 < op.N;
+  if (op.row0 + TileCfg<T>::BM <= op.M && op.col0 + TileCfg<T>::BN <= op.N)
+    tile_kloop<T, true>(op, s, rv, cv, acc);
+  else
+    tile_kloop<T, false>(op, s, rv, cv, acc);
+#pragma unroll
+  for (int ri = 0; ri < SM; ++ri)
+#pragma unroll
+    for (int ci = 0; ci < SN; ++ci) {
+      const typename Vec4<T>::type p1 = acc.re[ri][ci];
+      acc.re[ri][ci] = p1 - acc.x[ri][ci];
+      acc.im[ri][ci] = acc.im[ri][ci] - p1 - acc.x[ri][ci];
+    }
+}
+
+// First row of sub-tile ri of this wave, the row offset of accumulator element v, and
+// the column of sub-tile ci held by this lane.
+template <typename T>
 __device__ inline int acc_row_base(int row0, int ri) {
-  const int wave = threadIdx.x >> 6;
-  return row0 + (wave >> 1) * 32 + ri * 16;
+  return row0 + (tile_wave() >> 1) * (TileCfg<T>::BM / 2) + ri * 16;
 }
 template <typename T> __device__ inline int acc_row_off(int v);
 template <> __device__ inline int acc_row_off<float>(int v) { return 4 * ((threadIdx.x & 63) >> 4) + v; }
 template <> __device__ inline int acc_row_off<double>(int v) { return ((threadIdx.x & 63) >> 4) + 4 * v; }
+template <typename T>
 __device__ inline int acc_col(int col0, int ci) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  return col0 + (wave & 1) * 32 + ci * 16 + (lane & 15);
+  return col0 + (tile_wave() & 1) * (TileCfg<T>::BN / 2) + ci * 16 + (threadIdx.x & 15);
 }
 
 // Persistent scheduling: work-group w runs on XCD w % 8; each XCD takes a contiguous

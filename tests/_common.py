@@ -1,4 +1,7 @@
-"""Shared test helpers: oracle systems and panel layout (column-major m x d per block)."""
+"""Shared test helpers: oracle systems, panel layout (column-major m x d per block) and
+the reader of the stored oracle values under tests/golden/."""
+import os
+
 import numpy as np
 
 import qoc_workloads as W
@@ -37,3 +40,25 @@ def all_states(blocks, rng):
 
 def oracle_blocks(n, h0, hk, group="dihedral", stride=1):
     return grape.block_system(n, h0, hk, group, stride, "convention")
+
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _num(tok):
+    # values are written as Python float reprs (older files: numpy scalar reprs)
+    return float(tok.replace("np.float64(", "").rstrip(")"))
+
+
+def read_golden(name):
+    """(scalars, gradient[N, K]) from a file written by tests/golden/make_golden.py."""
+    vals, grad = {}, []
+    for line in open(os.path.join(GOLDEN_DIR, name)):
+        if line.startswith("#"):
+            continue
+        k, *v = line.split()
+        if k == "g":
+            grad.append([_num(x) for x in v])
+        else:
+            vals[k] = _num(v[0])
+    return vals, np.array(grad)

@@ -2,6 +2,8 @@
 
 Calls only the FP64 CPU oracle and the seeded input generators.  Usage:
     python tests/golden/make_golden.py ring12       # 12-qubit ring, D12, all blocks, N=1000
+    python tests/golden/make_golden.py ring14       # 14-qubit ring, two-site group, first 8 slices
+    python tests/golden/make_golden.py sym128       # S_128, 8 candidates, candidates 0 and 5
 The output files hold F, o, ||psi_N||^2 and the full gradient, one value per line.
 """
 import os
@@ -41,12 +43,64 @@ def ring12():
     with open(path, "w") as fh:
         fh.write("# oracle (FP64, eigendecomposition + Daleckii-Krein) for qoc_workloads.config2(seed=0, "
                  "variant='all'), psi_f then psi0 Gaussian panels; written by make_golden.py\n")
-        fh.write(f"F {r['F']!r}\nF_raw {r['F_raw']!r}\no_re {r['o'].real!r}\no_im {r['o'].imag!r}\n")
-        fh.write(f"normN2 {r['normN2']!r}\n")
+        fh.write(f"F {float(r['F'])!r}\nF_raw {float(r['F_raw'])!r}\no_re {float(r['o'].real)!r}\n")
+        fh.write(f"o_im {float(r['o'].imag)!r}\nnormN2 {float(r['normN2'])!r}\n")
         for j in range(w.N):
             fh.write("g " + " ".join(repr(float(v)) for v in r["grad"][j]) + "\n")
     print(path, f"{time.time() - t:.1f} s", r["F"])
 
 
+def ring14(nslices=8):
+    """The 14-qubit staggered-control workload under the two-site group (blocks 1300, 1044,
+    3 x 2340): the first `nslices` slices of its 4000-slice pulse, all blocks carrying state
+    (psi_f then psi0 drawn after u)."""
+    w = W.config4(seed=0, variant="all")
+    rng = w.notes["rng"]
+    t = time.time()
+    ob = og.block_system(14, w.h0, w.hk, "dihedral", 2)
+    D = sum(b["m"] * b["d"] for b in ob)
+    vf = W.gaussian_panel(rng, D)
+    v0 = W.gaussian_panel(rng, D)
+    r = og.fidelity_grad(ob, w.u[:nslices], w.dt, panels(ob, v0), panels(ob, vf))
+    path = os.path.join(HERE, f"ring14_T2R_allblocks_N{nslices}.txt")
+    with open(path, "w") as fh:
+        fh.write("# oracle (FP64, eigendecomposition + Daleckii-Krein) for qoc_workloads.config4(seed=0, "
+                 f"variant='all'), first {nslices} slices, psi_f then psi0 Gaussian panels; written by "
+                 "make_golden.py\n")
+        fh.write(f"F {float(r['F'])!r}\nF_raw {float(r['F_raw'])!r}\no_re {float(r['o'].real)!r}\n")
+        fh.write(f"o_im {float(r['o'].imag)!r}\nnormN2 {float(r['normN2'])!r}\n")
+        for j in range(nslices):
+            fh.write("g " + " ".join(repr(float(v)) for v in r["grad"][j]) + "\n")
+    print(path, f"{time.time() - t:.1f} s", r["F"])
+
+
+def sym128(C=8, which=(0, 5)):
+    """The all-to-all S_128 workload with C candidate pulses (500 slices each); states are
+    drawn after the pulses, psi_f then psi0 per candidate.  Candidates `which` are written."""
+    w = W.config5(seed=0, C=C)
+    rng = w.notes["rng"]
+    uc = w.notes["u_candidates"]
+    t = time.time()
+    ob = og.block_system(128, w.h0, w.hk, "symmetric")
+    D = sum(b["m"] * b["d"] for b in ob)
+    states = []
+    for _ in range(C):
+        vf = W.gaussian_panel(rng, D)
+        v0 = W.gaussian_panel(rng, D)
+        states.append((v0, vf))
+    for c in which:
+        r = og.fidelity_grad(ob, uc[c], w.dt, panels(ob, states[c][0]), panels(ob, states[c][1]))
+        path = os.path.join(HERE, f"sym128_C{C}_cand{c}_N{w.N}.txt")
+        with open(path, "w") as fh:
+            fh.write(f"# oracle (FP64, eigendecomposition + Daleckii-Krein) for qoc_workloads.config5(seed=0, C={C}), "
+                     f"candidate {c}, states psi_f then psi0 per candidate drawn after the pulses; written by "
+                     "make_golden.py\n")
+            fh.write(f"F {float(r['F'])!r}\nF_raw {float(r['F_raw'])!r}\no_re {float(r['o'].real)!r}\n")
+            fh.write(f"o_im {float(r['o'].imag)!r}\nnormN2 {float(r['normN2'])!r}\n")
+            for j in range(w.N):
+                fh.write("g " + " ".join(repr(float(v)) for v in r["grad"][j]) + "\n")
+        print(path, f"{time.time() - t:.1f} s", r["F"], flush=True)
+
+
 if __name__ == "__main__":
-    {"ring12": ring12}[sys.argv[1]]()
+    {"ring12": ring12, "ring14": ring14, "sym128": sym128}[sys.argv[1]]()

@@ -1,31 +1,18 @@
-"""The benchmark workload at full size (12-qubit ring under D12, 9 blocks, 1000 slices),
-in the launch configuration bench.py times, against the oracle: all-blocks states vs the
+"""Full-size workloads against the oracle.  The benchmark workload (12-qubit ring under D12,
+9 blocks, 1000 slices) in the launch configuration bench.py times: all-blocks states vs the
 oracle values stored by tests/golden/make_golden.py, and the plain variant (all-up to a
-state of the first block) vs the SU(2) closed form computed here."""
-import os
-
+state of the first block) vs the SU(2) closed form computed here.  The 14-qubit ring with
+staggered controls under the two-site group (blocks up to 2340 wide), first 8 slices of its
+pulse, vs stored oracle values."""
 import numpy as np
 import pytest
 
 import qoc_workloads as W
 from oracle import basis as obasis
 from oracle import closed_form
+from tests._common import read_golden
 
 pytestmark = pytest.mark.gpu
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "ring12_D12_allblocks_N1000.txt")
-
-
-def _golden():
-    vals, grad = {}, []
-    for line in open(GOLD):
-        if line.startswith("#"):
-            continue
-        k, *v = line.split()
-        if k == "g":
-            grad.append([float(x) for x in v])
-        else:
-            vals[k] = float(v[0])
-    return vals, np.array(grad)
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +33,7 @@ def test_allblocks_full_size_vs_oracle(lib, ring12, prec):
     rng = w2.notes["rng"]
     vf = W.gaussian_panel(rng, 4096)
     v0 = W.gaussian_panel(rng, 4096)
-    vals, gref = _golden()
+    vals, gref = read_golden("ring12_D12_allblocks_N1000.txt")
     P = lib.Plan(S, prec, w.N, w.dt, 2.0)  # the benchmark's plan
     out, grad = lib.fidelity_grad(P, torch.tensor(w.u, device="cuda"), torch.tensor(v0, device="cuda"),
                                   torch.tensor(vf, device="cuda"))
@@ -86,3 +73,32 @@ def test_plain_full_size_vs_closed_form(lib, ring12, prec):
     tf, tg = (1e-12, 1e-12) if prec == "c128" else (1e-6, 2e-4 * np.abs(ref["grad"]).max() + 1e-7)
     assert abs(out[0].item() - ref["F"]) <= tf
     assert np.abs(g - ref["grad"]).max() <= tg
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_ring14_two_site_group_vs_oracle(lib, prec):
+    """Largest ring blocks (1300, 1044 and three 2340-wide E blocks, 4 controls): the first
+    8 slices of the 14-qubit staggered-control pulse, every block carrying state."""
+    import torch
+    print(f"ring14 two-site group {prec}", flush=True)
+    w = W.config4(seed=0, variant="all")
+    rng = w.notes["rng"]
+    B = lib.Basis(14, "dihedral", 2)
+    S = lib.System(B, w.h0, w.hk)
+    vf = W.gaussian_panel(rng, B.dim)
+    v0 = W.gaussian_panel(rng, B.dim)
+    vals, gref = read_golden("ring14_T2R_allblocks_N8.txt")
+    N = gref.shape[0]
+    P = lib.Plan(S, prec, N, w.dt, 2.0)
+    out, grad = lib.fidelity_grad(P, torch.tensor(w.u[:N], device="cuda"), torch.tensor(v0, device="cuda"),
+                                  torch.tensor(vf, device="cuda"))
+    F = out[0].item()
+    g = grad.cpu().numpy()
+    print(f"  sizes {B.sizes}  |dF| = {abs(F - vals['F']):.2e}  max|dg| = {np.abs(g - gref).max():.2e}", flush=True)
+    assert abs(out[4].item() - vals["normN2"]) <= (1e-12 if prec == "c128" else 1e-6)
+    if prec == "c128":
+        assert abs(F - vals["F"]) <= 1e-12
+        assert np.abs(g - gref).max() <= 1e-12
+    else:
+        assert abs(F - vals["F"]) <= 1e-6
+        assert np.abs(g - gref).max() <= 2e-4 * np.abs(gref).max() + 1e-7
