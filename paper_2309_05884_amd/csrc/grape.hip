@@ -345,6 +345,7 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
       ctop = kInvFact[qe * r];
       for (int i = 0; i < r; ++i) coef[i] = kInvFact[(qe - 1) * r + i];
     }
+    typedef typename Vec4<T>::type V4;
 #pragma unroll
     for (int ri = 0; ri < TileCfg<T>::SM; ++ri)
 #pragma unroll
@@ -352,57 +353,40 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
         const int rbase = acc_row_base<T>(op.row0, ri);
         const int col = acc_col<T>(op.col0, ci);
         if (rbase >= mp || col >= mp) continue;
-        typename Vec4<T>::type vr = acc.re[ri][ci], vi = acc.im[ri][ci];
+        const int row0 = rbase + acc_row_off<T>(0);  // this lane's first accumulator row
+        const size_t at = (size_t)row0 + (size_t)col * mp;
+        V4 vr = acc.re[ri][ci], vi = acc.im[ri][ci];
         if (mode == STEP_HORNER) {
           for (int i = 1; i < r; ++i) {
-            const T* Pp = base + (size_t)(i - 1) * 2 * plane;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const size_t idx = (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
-              vr[v] += (T)coef[i] * Pp[idx];
-              vi[v] += (T)coef[i] * Pp[idx + plane];
-            }
+            const T* Pp = base + (size_t)(i - 1) * 2 * plane + at;
+            vr += (T)coef[i] * acc_load<T>(Pp);
+            vi += (T)coef[i] * acc_load<T>(Pp + plane);
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (rbase + acc_row_off<T>(v) == col && col < jb.m) vr[v] += (T)coef[0];
+            if (row0 + v * AccRowStep<T>::value == col && col < jb.m) vr[v] += (T)coef[0];
         }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          T* cr = C + (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
-          cr[0] = vr[v];
-          cr[plane] = vi[v];
-        }
+        acc_store<T>(C + at, vr);
+        acc_store<T>(C + at + plane, vi);
         if (init_T) {
           // T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i at this tile (the Horner start)
-          T* T0 = base + (size_t)r * 2 * plane;
-          typename Vec4<T>::type tr, ti;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            tr[v] = (T)ctop * vr[v];
-            ti[v] = (T)ctop * vi[v];
-          }
+          V4 tr = (T)ctop * vr, ti = (T)ctop * vi;
           for (int i = 1; i < r; ++i) {
-            const T* Pp = base + (size_t)(i - 1) * 2 * plane;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const size_t idx = (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
-              tr[v] += (T)coef[i] * Pp[idx];
-              ti[v] += (T)coef[i] * Pp[idx + plane];
-            }
+            const T* Pp = base + (size_t)(i - 1) * 2 * plane + at;
+            tr += (T)coef[i] * acc_load<T>(Pp);
+            ti += (T)coef[i] * acc_load<T>(Pp + plane);
           }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = rbase + acc_row_off<T>(v);
-            if (row == col && col < jb.m) tr[v] += (T)coef[0];
-            T0[(size_t)row + (size_t)col * mp] = tr[v];
-            T0[(size_t)row + (size_t)col * mp + plane] = ti[v];
-          }
+          for (int v = 0; v < 4; ++v)
+            if (row0 + v * AccRowStep<T>::value == col && col < jb.m) tr[v] += (T)coef[0];
+          T* T0 = base + (size_t)r * 2 * plane + at;
+          acc_store<T>(T0, tr);
+          acc_store<T>(T0 + plane, ti);
           if (init_final) {
             T* D = base + (size_t)(r + 2) * 2 * plane;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              T* dr = D + (size_t)col + (size_t)(rbase + acc_row_off<T>(v)) * mp;
+              T* dr = D + (size_t)col + (size_t)(row0 + v * AccRowStep<T>::value) * mp;
               dr[0] = tr[v];
               dr[plane] = -ti[v];
             }
@@ -413,7 +397,7 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
           T* D = base + (size_t)(r + 2) * 2 * plane;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            T* dr = D + (size_t)col + (size_t)(rbase + acc_row_off<T>(v)) * mp;
+            T* dr = D + (size_t)col + (size_t)(row0 + v * AccRowStep<T>::value) * mp;
             dr[0] = vr[v];
             dr[plane] = -vi[v];
           }
@@ -471,23 +455,23 @@ __global__ void k_zero_ints(int* p, int n) {
 // so both directions stream their matrix column by column.  A lane owns two adjacent
 // rows (8- or 16-byte loads), a wave 128 rows and one of G k-ranges; loads are unrolled
 // so that many bytes are in flight per lane; partial sums meet in LDS.
-template <typename T> struct Vec2;
-template <> struct Vec2<double> { typedef double2 type; };
-template <> struct Vec2<float> { typedef float2 type; };
-template <typename T> struct SweepUnroll { static constexpr int value = 16; };
+template <typename T> struct SweepUnroll { static constexpr int value = 8; };
 template <> struct SweepUnroll<double> { static constexpr int value = 4; };
 
-__host__ __device__ inline int sweep_kgroups(int mp) {
-  const int R = (mp + 127) / 128;
+// Sweep work split: a lane owns 16 bytes of consecutive rows (4 FP32 / 2 FP64), a wave a
+// row group of 64 such; the 16 waves cover R row groups x G column (k) groups.
+__host__ __device__ inline int sweep_rows_per_group(int elem) { return 64 * (16 / elem); }
+__host__ __device__ inline int sweep_kgroups(int mp, int elem) {
+  const int R = (mp + sweep_rows_per_group(elem) - 1) / sweep_rows_per_group(elem);
   return R >= 16 ? 1 : 16 / R;
 }
 
 template <typename T, int DIR>
 __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, char* ws, size_t off_T,
                                                 const int* ent_s, const int* ent_q, int r, int seg_j0, int seg_len) {
-  typedef typename Vec2<T>::type T2;
+  typedef typename Vec16<T>::type TV;
   typedef typename Vec4<T>::type T4;
-  constexpr int UNR = SweepUnroll<T>::value;
+  constexpr int UNR = SweepUnroll<T>::value, RPL = Vec16<T>::n;
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   const int J = blockIdx.x;
   if (J >= njobs) return;
@@ -495,7 +479,8 @@ __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, c
   const int len = job_len(jb, seg_j0, seg_len);
   if (len <= 0) return;
   const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
-  const int R = (mp + 127) / 128, G = sweep_kgroups(mp);
+  const int RG = sweep_rows_per_group((int)sizeof(T));
+  const int R = (mp + RG - 1) / RG, G = sweep_kgroups(mp, (int)sizeof(T));
   T* sre = reinterpret_cast<T*>(smem_raw);  // state [d][mp]
   T* sim = sre + (size_t)d * mp;
   T* pre = sim + (size_t)d * mp;             // partial sums [G][d][mp]
@@ -522,75 +507,69 @@ __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, c
                           : Ub + (size_t)(r + 2) * 2 * plane;
     for (int task = wave; task < R * G; task += 16) {
       const int rg = task % R, kg = task / R;
-      const int i0 = rg * 128 + 2 * lane;  // rows i0, i0 + 1 (mp is even)
+      const int i0 = rg * RG + RPL * lane;  // rows i0 .. i0 + RPL - 1 (mp is a multiple of 16)
       const int k0 = kg * kchunk, k1 = min(m, k0 + kchunk);
-      T a0r0 = T(0), a0i0 = T(0), a0r1 = T(0), a0i1 = T(0);  // copy 0, rows i0 / i0+1
-      T a1r0 = T(0), a1i0 = T(0), a1r1 = T(0), a1i1 = T(0);  // copy 1
+      T a[2][2][RPL];  // [copy][re, im][row]
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) a[c][0][t] = a[c][1][t] = T(0);
       if (i0 < m) {
         const T* col = U + i0;
         int k = k0;
         for (; k + UNR <= k1; k += UNR) {
-          T2 ur[UNR], ui[UNR];
+          TV ur[UNR], ui[UNR];
 #pragma unroll
           for (int q = 0; q < UNR; ++q) {
-            ur[q] = *reinterpret_cast<const T2*>(col + (size_t)(k + q) * mp);
-            ui[q] = *reinterpret_cast<const T2*>(col + (size_t)(k + q) * mp + plane);
+            ur[q] = *reinterpret_cast<const TV*>(col + (size_t)(k + q) * mp);
+            ui[q] = *reinterpret_cast<const TV*>(col + (size_t)(k + q) * mp + plane);
           }
           // state values four at a time (one wide LDS broadcast per four k)
 #pragma unroll
-          for (int q4 = 0; q4 < UNR; q4 += 4) {
-            T pr4[4], pi4[4];
-            *reinterpret_cast<T4*>(pr4) = *reinterpret_cast<const T4*>(sre + k + q4);
-            *reinterpret_cast<T4*>(pi4) = *reinterpret_cast<const T4*>(sim + k + q4);
+          for (int c = 0; c < 2; ++c) {
+            if (c >= d) break;
 #pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-              const int q = q4 + e4;
-              const T pr = pr4[e4], pi = pi4[e4];
-              a0r0 += ur[q].x * pr - ui[q].x * pi;
-              a0i0 += ur[q].x * pi + ui[q].x * pr;
-              a0r1 += ur[q].y * pr - ui[q].y * pi;
-              a0i1 += ur[q].y * pi + ui[q].y * pr;
-            }
-            if (d > 1) {
-              *reinterpret_cast<T4*>(pr4) = *reinterpret_cast<const T4*>(sre + mp + k + q4);
-              *reinterpret_cast<T4*>(pi4) = *reinterpret_cast<const T4*>(sim + mp + k + q4);
+            for (int q4 = 0; q4 < UNR; q4 += 4) {
+              T pr4[4], pi4[4];
+              *reinterpret_cast<T4*>(pr4) = *reinterpret_cast<const T4*>(sre + c * mp + k + q4);
+              *reinterpret_cast<T4*>(pi4) = *reinterpret_cast<const T4*>(sim + c * mp + k + q4);
 #pragma unroll
               for (int e4 = 0; e4 < 4; ++e4) {
-                const int q = q4 + e4;
-                const T qr = pr4[e4], qi = pi4[e4];
-                a1r0 += ur[q].x * qr - ui[q].x * qi;
-                a1i0 += ur[q].x * qi + ui[q].x * qr;
-                a1r1 += ur[q].y * qr - ui[q].y * qi;
-                a1i1 += ur[q].y * qi + ui[q].y * qr;
+                const T* urq = reinterpret_cast<const T*>(&ur[q4 + e4]);
+                const T* uiq = reinterpret_cast<const T*>(&ui[q4 + e4]);
+#pragma unroll
+                for (int t = 0; t < RPL; ++t) {
+                  a[c][0][t] += urq[t] * pr4[e4] - uiq[t] * pi4[e4];
+                  a[c][1][t] += urq[t] * pi4[e4] + uiq[t] * pr4[e4];
+                }
               }
             }
           }
         }
         for (; k < k1; ++k) {
-          const T2 ur = *reinterpret_cast<const T2*>(col + (size_t)k * mp);
-          const T2 ui = *reinterpret_cast<const T2*>(col + (size_t)k * mp + plane);
-          const T pr = sre[k], pi = sim[k];
-          a0r0 += ur.x * pr - ui.x * pi;
-          a0i0 += ur.x * pi + ui.x * pr;
-          a0r1 += ur.y * pr - ui.y * pi;
-          a0i1 += ur.y * pi + ui.y * pr;
-          if (d > 1) {
-            const T qr = sre[mp + k], qi = sim[mp + k];
-            a1r0 += ur.x * qr - ui.x * qi;
-            a1i0 += ur.x * qi + ui.x * qr;
-            a1r1 += ur.y * qr - ui.y * qi;
-            a1i1 += ur.y * qi + ui.y * qr;
+          const TV ur = *reinterpret_cast<const TV*>(col + (size_t)k * mp);
+          const TV ui = *reinterpret_cast<const TV*>(col + (size_t)k * mp + plane);
+          const T* urq = reinterpret_cast<const T*>(&ur);
+          const T* uiq = reinterpret_cast<const T*>(&ui);
+          for (int c = 0; c < d; ++c) {
+            const T pr = sre[c * mp + k], pi = sim[c * mp + k];
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              a[c][0][t] += urq[t] * pr - uiq[t] * pi;
+              a[c][1][t] += urq[t] * pi + uiq[t] * pr;
+            }
           }
         }
       }
       if (i0 < mp) {
-        T* p0 = pre + ((size_t)kg * d) * mp + i0;
-        T* q0 = pim + ((size_t)kg * d) * mp + i0;
-        p0[0] = a0r0; p0[1] = a0r1;
-        q0[0] = a0i0; q0[1] = a0i1;
-        if (d > 1) {
-          p0[mp] = a1r0; p0[mp + 1] = a1r1;
-          q0[mp] = a1i0; q0[mp + 1] = a1i1;
+        for (int c = 0; c < d; ++c) {
+          T* p0 = pre + ((size_t)kg * d + c) * mp + i0;
+          T* q0 = pim + ((size_t)kg * d + c) * mp + i0;
+#pragma unroll
+          for (int t = 0; t < RPL; ++t) {
+            p0[t] = a[c][0][t];
+            q0[t] = a[c][1][t];
+          }
         }
       }
     }
@@ -709,12 +688,9 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value) k_panel_gemm(co
         const int rbase = acc_row_base<T>(op.row0, ri);
         const int col = acc_col<T>(op.col0, ci);
         if (rbase >= mp || col >= jb.cc) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          T* cr = C + (size_t)(rbase + acc_row_off<T>(v)) + (size_t)col * mp;
-          cr[0] = acc.re[ri][ci][v];
-          cr[vplane] = acc.im[ri][ci][v];
-        }
+        T* cr = C + (size_t)(rbase + acc_row_off<T>(0)) + (size_t)col * mp;
+        acc_store<T>(cr, acc.re[ri][ci]);
+        acc_store<T>(cr + vplane, acc.im[ri][ci]);
       }
   }
 }
@@ -1281,7 +1257,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   size_t lds_elems = 0;
   for (auto& pr : probs)
     for (auto& b : pr.sys->blocks)
-      lds_elems = std::max(lds_elems, (size_t)2 * b.d * b.mp * (1 + sweep_kgroups(b.mp)));
+      lds_elems = std::max(lds_elems, (size_t)2 * b.d * b.mp * (1 + sweep_kgroups(b.mp, (int)P->elem)));
   P->sweep_lds_elems = lds_elems;
   QOC_REQUIRE(lds_elems * P->elem <= 160 * 1024, QOC_ERR_UNSUPPORTED, "block panel too large for the LDS-resident sweep");
   const int K = P->Kmax;

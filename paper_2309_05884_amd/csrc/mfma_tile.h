@@ -264,6 +264,24 @@ __device__ inline int acc_row_base(int row0, int ri) {
 template <typename T> __device__ inline int acc_row_off(int v);
 template <> __device__ inline int acc_row_off<float>(int v) { return 4 * ((threadIdx.x & 63) >> 4) + v; }
 template <> __device__ inline int acc_row_off<double>(int v) { return ((threadIdx.x & 63) >> 4) + 4 * v; }
+// Rows of accumulator elements v = 0..3 are row0 + v * AccRowStep: contiguous for FP32
+// (one 16-byte access in a column-major matrix), four apart for FP64.
+template <typename T> struct AccRowStep;
+template <> struct AccRowStep<float> { static constexpr int value = 1; };
+template <> struct AccRowStep<double> { static constexpr int value = 4; };
+template <typename T>
+__device__ inline typename Vec4<T>::type acc_load(const T* p);
+template <>
+__device__ inline f4v acc_load<float>(const float* p) { return *reinterpret_cast<const f4v*>(p); }
+template <>
+__device__ inline d4v acc_load<double>(const double* p) { return d4v{p[0], p[4], p[8], p[12]}; }
+template <typename T>
+__device__ inline void acc_store(T* p, typename Vec4<T>::type v);
+template <>
+__device__ inline void acc_store<float>(float* p, f4v v) { *reinterpret_cast<f4v*>(p) = v; }
+template <>
+__device__ inline void acc_store<double>(double* p, d4v v) { p[0] = v[0]; p[4] = v[1]; p[8] = v[2]; p[12] = v[3]; }
+
 template <typename T>
 __device__ inline int acc_col(int col0, int ci) {
   return col0 + (tile_wave() & 1) * (TileCfg<T>::BN / 2) + ci * 16 + (threadIdx.x & 15);
