@@ -197,7 +197,9 @@ qoc_status qoc_propagate(qoc_plan plan, const double* u_dev, void* U_out_dev, vo
  * out_dev (float64, 8 entries): [0] F = |o|^2 / (||psi_N||^2 ||psi_f||^2),
  * [1] |o|^2, [2] Re o, [3] Im o with o = <psi_f|psi_N>, [4] ||psi_N||^2,
  * [5] ||psi_f||^2, [6] largest squaring count used, [7] status flags (0 = clean;
- * bit 0: a slice exceeded the plan's norm bound; bit 1: non-finite value).
+ * bit 0: a slice exceeded the plan's norm bound; bit 1: non-finite value; bit 2: a
+ * co-operative sweep's hand-off between work-groups stalled and the sweep gave up, so
+ * the outputs are invalid).
  * grad_dev (float64 [N][K]) receives dF/du[j,k] = 2 Re(conj(o) do/du[j,k]) /
  * (||psi_N||^2 ||psi_f||^2).  Fully asynchronous (no host synchronisation), so the
  * call can be captured into a HIP graph. */

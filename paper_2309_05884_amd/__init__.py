@@ -214,6 +214,8 @@ def check_flags(out):
             what.append("a slice exceeded the plan's norm bound (|u| > u_bound)")
         if flags & 2:
             what.append("non-finite value")
+        if flags & 4:
+            what.append("a co-operative sweep stalled and gave up (outputs invalid)")
         raise QocError(6, "; ".join(what))
 
 

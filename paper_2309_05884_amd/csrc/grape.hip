@@ -113,7 +113,10 @@ struct qoc_plan_s {
   int nslots = 0;
   size_t elem = 8;
   // workspace layout (bytes)
-  size_t off_flags = 0, off_ent = 0, off_T = 0, off_gacc = 0, bytes = 0;
+  size_t off_flags = 0, off_ent = 0, off_T = 0, off_gacc = 0, off_sync = 0, bytes = 0;
+  bool coop = false;      // co-operative sweeps (several work-groups per job)
+  int coop_w = 1;         // largest number of work-groups of a job
+  size_t coop_lds = 0;    // dynamic LDS of the co-operative sweep (bytes)
   long long expm_items = 0, panel_items = 0;
   long long entries_per_seg = 0;
   size_t sweep_lds_elems = 0;
@@ -448,6 +451,13 @@ __global__ void k_zero_ints(int* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+__global__ void k_fold_flags(const int* flags, int nprob, double* out) {
+  for (int p = threadIdx.x; p < nprob; p += blockDim.x) {
+    const int fl = (int)out[(size_t)p * 8 + 7] | flags[0];
+    out[(size_t)p * 8 + 7] = (double)fl;
+  }
+}
+
 // ===================================================================== sweeps
 // Sweep through one segment, one work-group (16 waves) per job, the state in LDS.
 // DIR 0: psi_{j+1} = U_j psi_j from the forward store; DIR 1: lambda_j = U_j^dag
@@ -466,16 +476,15 @@ __host__ __device__ inline int sweep_kgroups(int mp, int elem) {
   return R >= 16 ? 1 : 16 / R;
 }
 
+// One work-group sweeps one job through the segment: 16 waves split the rows and the
+// columns of U_j; the state and the partial sums live in LDS.
 template <typename T, int DIR>
-__global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, char* ws, size_t off_T,
-                                                const int* ent_s, const int* ent_q, int r, int seg_j0, int seg_len) {
+__device__ void sweep_solo(const JobDev& jb, char* ws, size_t off_T, const int* ent_s, const int* ent_q, int r,
+                           int seg_j0, int seg_len) {
   typedef typename Vec16<T>::type TV;
   typedef typename Vec4<T>::type T4;
   constexpr int UNR = SweepUnroll<T>::value, RPL = Vec16<T>::n;
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
-  const int J = blockIdx.x;
-  if (J >= njobs) return;
-  const JobDev jb = jobs[J];
   const int len = job_len(jb, seg_j0, seg_len);
   if (len <= 0) return;
   const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
@@ -592,6 +601,200 @@ __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, c
       }
     }
     __syncthreads();
+  }
+}
+
+template <typename T, int DIR>
+__global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, char* ws, size_t off_T,
+                                                const int* ent_s, const int* ent_q, int r, int seg_j0, int seg_len) {
+  const int J = blockIdx.x;
+  if (J >= njobs) return;
+  const JobDev jb = jobs[J];
+  sweep_solo<T, DIR>(jb, ws, off_T, ent_s, ent_q, r, seg_j0, seg_len);
+}
+
+// ---- co-operative sweep: the rows of a job are split over W = ceil(mp / RB) work-groups
+// (RB = 64 FP32 / 32 FP64 rows); after every slice each group publishes its rows of the
+// new state in the state panel and the groups meet on a per-job counter (agent-scope
+// release / acquire).  All waits are bounded.  Group 0 first waits (bounded) for the
+// other groups to arrive; if they are not all resident it runs the job alone
+// (sweep_solo) and the late groups leave, so the sweep never depends on co-residency.
+// Control words per job: [0] arrivals, [1] decision, [2] slice counter (zeroed before
+// the launch).
+constexpr int kCoopGo = 1, kCoopSolo = 2;
+constexpr long kArriveSpins = 1L << 15;  // ~ms: group 0 waits this long for the others
+constexpr long kStepSpins = 1L << 20;    // a stalled hand-off (tens of ms) aborts the sweep
+constexpr int kFlagSweepAbort = 4;       // status bit 2: a co-operative sweep gave up
+
+template <typename T> struct CoopRows { static constexpr int value = 16 * Vec16<T>::n; };
+
+__device__ inline int coop_decide(int* ctl, int W, int* flags) {
+  __shared__ int decision;
+  if (threadIdx.x == 0) {
+    if (W == 1) {
+      decision = kCoopGo;
+    } else if (blockIdx.x == 0) {
+      long s = 0;
+      while (__hip_atomic_load(ctl + 0, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < W - 1 && ++s < kArriveSpins)
+        __builtin_amdgcn_s_sleep(2);
+      const int all = __hip_atomic_load(ctl + 0, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= W - 1;
+      // the others read the decision; once written it never changes
+      decision = all ? kCoopGo : kCoopSolo;
+      __hip_atomic_store(ctl + 1, decision, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_fetch_add(ctl + 0, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      int st = 0;
+      long s = 0;
+      while ((st = __hip_atomic_load(ctl + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) == 0 && ++s < kStepSpins)
+        __builtin_amdgcn_s_sleep(2);
+      if (st == 0) __hip_atomic_fetch_or(flags, kFlagSweepAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      decision = st == kCoopGo ? kCoopGo : 0;  // solo or no decision: this group leaves
+    }
+  }
+  __syncthreads();
+  return decision;
+}
+
+template <typename T, int DIR>
+__global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njobs, char* ws, size_t off_T,
+                                                     const int* ent_s, const int* ent_q, int r, int seg_j0,
+                                                     int seg_len, int* ctl_all, int* flags) {
+  typedef typename Vec16<T>::type TV;
+  constexpr int RPL = Vec16<T>::n, RB = CoopRows<T>::value, UNR = 4;
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  const int J = blockIdx.y;
+  if (J >= njobs) return;
+  const JobDev jb = jobs[J];
+  const int len = job_len(jb, seg_j0, seg_len);
+  if (len <= 0) return;
+  const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
+  const int W = (mp + RB - 1) / RB;
+  if ((int)blockIdx.x >= W) return;
+  int* ctl = ctl_all + 4 * J;
+  const int mode = coop_decide(ctl, W, flags);
+  if (mode == kCoopSolo) {
+    sweep_solo<T, DIR>(jb, ws, off_T, ent_s, ent_q, r, seg_j0, seg_len);
+    return;
+  }
+  if (mode != kCoopGo) return;
+  T* sre = reinterpret_cast<T*>(smem_raw);  // state [d][mp]
+  T* sim = sre + (size_t)d * mp;
+  T* pre = sim + (size_t)d * mp;             // wave partials [16][d][RB]
+  T* pim = pre + (size_t)16 * d * RB;
+  __shared__ int abort_now;
+  T* S = tplane<T>(ws, off_T, DIR == 0 ? jb.psi_off : jb.lam_off);
+  const size_t ncol = DIR == 0 ? (size_t)(N + 1) * d : (size_t)N * d;
+  const size_t ps = (size_t)mp * ncol;
+  const size_t plane = (size_t)mp * mp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rv = lane & 15, kk = lane >> 4;
+  const int r0 = blockIdx.x * RB, row = r0 + rv * RPL;  // this lane's rows row .. row + RPL - 1
+  const int KC = ((m + 15) / 16 + 3) / 4 * 4;           // columns per wave (multiple of 4)
+  const int kw0 = wave * KC, kw1 = min(m, kw0 + KC);
+  int col_prev = DIR == 0 ? seg_j0 : seg_j0 + len - 1;
+  for (int it = 0; it < len; ++it) {
+    const int jl = DIR == 0 ? it : len - 1 - it;
+    if (threadIdx.x == 0) {
+      abort_now = 0;
+      if (it > 0) {
+        long s = 0;
+        while (__hip_atomic_load(ctl + 2, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < W * it) {
+          if (++s >= kStepSpins) {
+            __hip_atomic_fetch_or(flags, kFlagSweepAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            abort_now = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    __syncthreads();
+    if (abort_now) return;
+    // the input state (written by every group in the previous slice) into LDS
+    for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
+      const int c = idx / mp, i = idx % mp;
+      const size_t g = ((size_t)col_prev * d + c) * mp + i;
+      sre[idx] = __hip_atomic_load(S + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sim[idx] = __hip_atomic_load(S + g + ps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const long long e = jb.ent_off + jl;
+    const T* Ub = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
+    const T* U = DIR == 0 ? Ub + (size_t)(r + ((ent_q[e] - 1 + ent_s[e]) & 1)) * 2 * plane
+                          : Ub + (size_t)(r + 2) * 2 * plane;
+    T a[2][2][RPL];  // [copy][re, im][row]
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) a[c][0][t] = a[c][1][t] = T(0);
+    if (row < m) {
+      for (int kb = kw0; kb < kw1; kb += 4 * UNR) {
+        TV ur[UNR], ui[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int k = kb + 4 * u + kk;
+          if (k < kw1) {
+            ur[u] = *reinterpret_cast<const TV*>(U + row + (size_t)k * mp);
+            ui[u] = *reinterpret_cast<const TV*>(U + row + (size_t)k * mp + plane);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int k = kb + 4 * u + kk;
+          if (k >= kw1) break;
+          const T* urq = reinterpret_cast<const T*>(&ur[u]);
+          const T* uiq = reinterpret_cast<const T*>(&ui[u]);
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            if (c >= d) break;
+            const T pr = sre[c * mp + k], pi = sim[c * mp + k];
+#pragma unroll
+            for (int t = 0; t < RPL; ++t) {
+              a[c][0][t] += urq[t] * pr - uiq[t] * pi;
+              a[c][1][t] += urq[t] * pi + uiq[t] * pr;
+            }
+          }
+        }
+      }
+    }
+    // sum the four column phases of the wave, then the 16 waves
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          T v = a[c][h][t];
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+          a[c][h][t] = v;
+        }
+    if (kk == 0)
+      for (int c = 0; c < d; ++c)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          pre[((size_t)wave * d + c) * RB + rv * RPL + t] = a[c][0][t];
+          pim[((size_t)wave * d + c) * RB + rv * RPL + t] = a[c][1][t];
+        }
+    __syncthreads();
+    const int col_out = DIR == 0 ? seg_j0 + jl + 1 : seg_j0 + jl - 1;
+    if ((int)threadIdx.x < RB * d) {
+      const int c = threadIdx.x / RB, i = threadIdx.x % RB;
+      T vr = T(0), vi = T(0);
+      for (int w = 0; w < 16; ++w) {
+        vr += pre[((size_t)w * d + c) * RB + i];
+        vi += pim[((size_t)w * d + c) * RB + i];
+      }
+      if (r0 + i >= m) vr = vi = T(0);
+      if (col_out >= 0 && r0 + i < mp) {
+        const size_t g = ((size_t)col_out * d + c) * mp + r0 + i;
+        S[g] = vr;
+        S[g + ps] = vi;
+      }
+    }
+    __syncthreads();  // this group's rows are written (and the partials consumed)
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctl + 2, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    col_prev = col_out;
   }
 }
 
@@ -1016,6 +1219,21 @@ struct Driver {
   static void sweep(qoc_plan_s* P, char* ws, int dir, int seg_j0, hipStream_t st) {
     const int njobs = (int)P->jobs.size();
     const JobDev* dj = P->d_jobs.as<JobDev>();
+    if (P->coop) {
+      int* ctl = reinterpret_cast<int*>(ws + P->off_sync) + (size_t)dir * 4 * njobs;
+      int* flags = reinterpret_cast<int*>(ws + P->off_flags);
+      const dim3 grid(P->coop_w, njobs);
+      timed(dir == 0 ? PK_SWEEP_FWD : PK_SWEEP_BWD, st, [&] {
+        hipLaunchKernelGGL(k_zero_ints, dim3((4 * njobs + 255) / 256), dim3(256), 0, st, ctl, 4 * njobs);
+        if (dir == 0)
+          hipLaunchKernelGGL((k_sweep_coop<T, 0>), grid, dim3(1024), P->coop_lds, st, dj, njobs, ws, P->off_T,
+                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags);
+        else
+          hipLaunchKernelGGL((k_sweep_coop<T, 1>), grid, dim3(1024), P->coop_lds, st, dj, njobs, ws, P->off_T,
+                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags);
+      });
+      return;
+    }
     if (dir == 0)
       timed(PK_SWEEP_FWD, st, [&] {
         hipLaunchKernelGGL((k_sweep<T, 0>), dim3(njobs), dim3(1024), sweep_lds(P), st, dj, njobs, ws, P->off_T,
@@ -1070,6 +1288,8 @@ struct Driver {
       sweep(P, ws, 0, 0, st);
       objective(st);
       QOC_HIP(hipStreamWaitEvent(st, P->ev_join, 0));
+      // status bits raised by the backward sweep after the objective was written
+      hipLaunchKernelGGL(k_fold_flags, dim3(1), dim3(64), 0, st, flags, P->P, out);
     } else {
       // forward: propagators of a segment, then the sequential sweep through it
       for (int sg = 0; sg < P->nseg; ++sg) {
@@ -1368,6 +1588,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->expm_items = item_off;
   P->off_T = take((size_t)tel * P->elem);
   P->off_gacc = take((size_t)std::max<long long>(gacc, 1) * 16);
+  P->off_sync = take((size_t)2 * 4 * sizeof(int) * P->jobs.size());  // co-operative sweep control words
   P->bytes = off;
   // panel GEMM descriptors: (job, op) for op = 0..K_job
   long long pitems = 0;
@@ -1410,12 +1631,33 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->grid_gemm = std::max(8, ncu * std::max(1, occ) / 8 * 8);
   // the sweeps keep the state and partial sums in LDS; allow the dynamic size beyond 64 KB
   const int lds = (int)(P->sweep_lds_elems * P->elem);
+  // co-operative sweeps when every work-group of both concurrent sweeps fits on its own CU
+  {
+    const int rb = f64 ? CoopRows<double>::value : CoopRows<float>::value;
+    long long groups = 0;
+    size_t elems = P->sweep_lds_elems;
+    int wmax = 1;
+    for (auto& j : P->jobs) {
+      const int w = (j.mp + rb - 1) / rb;
+      groups += w;
+      wmax = std::max(wmax, w);
+      elems = std::max(elems, (size_t)2 * j.d * j.mp + (size_t)2 * 16 * j.d * rb);
+    }
+    P->coop = 2 * groups <= ncu && elems * P->elem <= 160 * 1024;
+    P->coop_w = wmax;
+    P->coop_lds = elems * P->elem;
+  }
+  const int clds = (int)P->coop_lds;
   if (f64) {
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_coop<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, clds));
+    QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_coop<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, clds));
   } else {
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_coop<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, clds));
+    QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_coop<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, clds));
   }
   // second stream (default priority) for the backward sweep, and fork/join events
   QOC_HIP(hipStreamCreateWithFlags(&P->st2, hipStreamNonBlocking));
