@@ -27,6 +27,24 @@ if ROOT not in sys.path:
 
 MFMA_PEAK = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix TFLOP/s, MI355X
 
+# HBM-side bytes of k_expm_step<float> on this workload, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE; mean KiB per dispatch over the 12 dispatches of
+# `bench.py --steps 1 --warmup 1 --fp64-steps 0 --copy-calibration 256`), each scaled
+# by what the same counter reads for the 256 MiB calibration copy (FETCH_SIZE reads
+# half of the bytes copied: x2.0; WRITE_SIZE all of them: x1.0).  Valid only for the
+# kernel sources they were taken with (sha1 of mfma_tile.h + grape.hip).
+TRAFFIC = {"sources_sha1": "41fbd9cb8eee9859c2ac0101860d4ec68fb67910", "variant": "fp32 128x64",
+           "fetch_kib": 20651052.7, "fetch_scale": 2.0, "write_kib": 7918390.7, "write_scale": 1.0}
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("mfma_tile.h", "grape.hip"):
+        with open(os.path.join(ROOT, "paper_2309_05884_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -136,9 +154,12 @@ def main():
     print(f"[bench] blocks {B.sizes} copies {B.copies}", file=sys.stderr, flush=True)
 
     P32 = q.Plan(S, "c64", w.N, w.dt, 2.0)
-    print(f"[bench] c64 plan {P32.info} workspace {P32.workspace_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+    tune32 = P32.autotune(dev["u"])
+    print(f"[bench] c64 plan {P32.info} workspace {P32.workspace_bytes / 2**30:.1f} GiB; GEMM variant "
+          f"{P32.variant_name} (autotune ms {tune32[1]})", file=sys.stderr, flush=True)
     ms32, wall32, prof32, out32, grad32 = timed_steps(q, torch, P32, dev, args.steps, args.warmup)
     flops32, qs32, ss32 = gemm_flops(q, P32, dev, B.sizes)
+    var32 = P32.variant_name
     print(f"[bench] c64 {ms32:.2f} ms/step  profile {prof32}", file=sys.stderr, flush=True)
     del P32
     torch.cuda.empty_cache()
@@ -148,18 +169,24 @@ def main():
     fp64 = cmp = None
     if args.fp64_steps > 0:
         P64 = q.Plan(S, "c128", w.N, w.dt, 2.0)
+        tune64 = P64.autotune(dev["u"])
         ms64, wall64, prof64, out64, grad64 = timed_steps(q, torch, P64, dev, args.fp64_steps, 1)
         flops64, _, _ = gemm_flops(q, P64, dev, B.sizes)
         print(f"[bench] c128 {ms64:.2f} ms/step  profile {prof64}", file=sys.stderr, flush=True)
+        var64 = P64.variant_name
         del P64
         gemm64_ms, _ = prof64["propagator_gemm"]
         achieved64 = flops64 * args.fp64_steps / (gemm64_ms * 1e-3) / 1e12
         g64 = grad64.cpu()
         fp64 = {"value": units / (ms64 * 1e-3), "ms_per_step": ms64, "steps": args.fp64_steps,
-                "gemm_tflops": achieved64, "gemm_frac": achieved64 / MFMA_PEAK["c128"]}
+                "gemm_tflops": achieved64, "gemm_frac": achieved64 / MFMA_PEAK["c128"],
+                "gemm_variant": var64, "autotune_ms": tune64[1]}
         cmp = {"speedup": ms64 / ms32, "dF": abs(out32[0].item() - out64[0].item()),
                "grad_rel_err": float((grad32.cpu() - g64).abs().max() / g64.abs().max()), "F64": out64[0].item()}
 
+    traffic = None
+    if kernel_sources_sha1() == TRAFFIC["sources_sha1"] and var32 == TRAFFIC["variant"]:
+        traffic = 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
     line = {
         "metric": "GRAPE slices*blocks/sec (fidelity+gradient), FP32-batched vs FP64, |dF|<=1e-6",
         "value": units / (ms32 * 1e-3),
@@ -177,9 +204,15 @@ def main():
                    "dt": w.dt, "controls": 2, "blocks": B.sizes, "copies": B.copies, "J": round(w.J, 6),
                    "precision": "complex64 MFMA products; FP64 norms, objective and gradient accumulation"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK["c64"], "unit": "TFLOP/s",
-                     "frac": achieved / MFMA_PEAK["c64"], "traffic": None,
-                     "kernel": "k_expm_step<float>", "launches": gemm_n,
-                     "alg_flops_per_step": flops32, "kernel_ms_per_step": gemm_ms / args.steps},
+                     "frac": achieved / MFMA_PEAK["c64"], "traffic": traffic,
+                     "traffic_unit": "bytes per launch (HBM side)",
+                     "kernel": "k_expm_step<float>", "gemm_variant": var32, "autotune_ms": tune32[1],
+                     "launches": gemm_n,
+                     "alg_flops_per_launch": flops32 * args.steps / gemm_n,
+                     "avg_launch_ms": gemm_ms / gemm_n, "kernel_ms_per_step": gemm_ms / args.steps,
+                     "executed_mfma_frac": 0.75 * achieved / MFMA_PEAK["c64"],
+                     "note": "algorithmic flops 8 m^3 per complex m x m product; the kernel forms each with "
+                             "three real MFMA products (Gauss), 6 m^3 executed flops"},
         "fp64": fp64,
         "fp32_vs_fp64": cmp,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},

@@ -182,8 +182,23 @@ qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
  * [3] largest degree, [4] Frechet series terms, [5] Frechet sub-steps, [6] propagator
  * bytes per slice, [7] largest squaring count, [8] gradient chunk (slices), [9] GEMM
  * grid, [10] problems P, [11] (problem, block) jobs, [12] total controls (sum N_p K_p),
- * [13] total panel length (sum D_p), [14] total propagator entries. */
+ * [13] total panel length (sum D_p), [14] total propagator entries, [15] GEMM tile
+ * variant in use. */
 qoc_status qoc_plan_info(qoc_plan plan, int64_t* info, int cap);
+
+/* GEMM tile variants.  The propagator and panel GEMMs are compiled for 3 work-group tile
+ * shapes per precision (qoc_variant_name: e.g. "fp32 128x64"); every shape accumulates
+ * each output element in the same order, so results do not depend on the choice.  A new
+ * plan uses variant 0.  qoc_plan_set_variant selects one (host call; synchronises the
+ * device).  qoc_plan_autotune times every variant on the plan's own work (the first
+ * segment's propagators for controls u_dev, plus one gradient panel GEMM) with HIP
+ * events on `stream`, keeps the fastest and returns its index in *chosen and, when
+ * times_ms is not null, each variant's time (ms, 3 entries).  It synchronises and uses
+ * the caller's workspace as scratch; the plan's results are unchanged. */
+qoc_status qoc_plan_set_variant(qoc_plan plan, int variant);
+const char* qoc_variant_name(int precision, int variant);
+qoc_status qoc_plan_autotune(qoc_plan plan, const double* u_dev, void* workspace, size_t workspace_bytes,
+                             void* stream, int* chosen, double* times_ms);
 
 /* Slice propagators U_j (Eq. (3)) for every block and slice: scaled Taylor polynomial
  * (Paterson-Stockmeyer) with repeated squaring, matrix products on the MFMA units.

@@ -125,7 +125,8 @@ class Plan:
 
     INFO_KEYS = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
                  "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid", "problems", "jobs",
-                 "total_controls", "total_panel", "total_propagator"]
+                 "total_controls", "total_panel", "total_propagator", "gemm_variant"]
+    N_VARIANTS = 3
 
     def __init__(self, system: System, precision: str = "c128", N: int = 1, dt: float = 0.01,
                  u_bound: float = 1.0, max_workspace_bytes: int = 0, _batch=None):
@@ -150,10 +151,36 @@ class Plan:
         b = ctypes.c_size_t()
         C.check(C.lib().qoc_plan_workspace_size(self._h, ctypes.byref(b)))
         self.workspace_bytes = int(b.value)
-        info = (ctypes.c_int64 * 15)()
-        C.check(C.lib().qoc_plan_info(self._h, info, 15))
-        self.info = dict(zip(self.INFO_KEYS, [int(v) for v in info]))
         self._ws = None
+        self._refresh_info()
+
+    def _refresh_info(self):
+        n = len(self.INFO_KEYS)
+        info = (ctypes.c_int64 * n)()
+        C.check(C.lib().qoc_plan_info(self._h, info, n))
+        self.info = dict(zip(self.INFO_KEYS, [int(v) for v in info]))
+
+    @property
+    def variant_name(self):
+        return C.lib().qoc_variant_name(C.PRECISIONS[self.precision], self.info["gemm_variant"]).decode()
+
+    def set_variant(self, v: int):
+        """Use GEMM tile variant v (0..N_VARIANTS-1); results do not change."""
+        C.check(C.lib().qoc_plan_set_variant(self._h, int(v)))
+        self._refresh_info()
+
+    def autotune(self, u):
+        """Time every GEMM tile variant on this plan's work for controls u (device tensor,
+        concatenated for a batch) and keep the fastest; returns (chosen, [ms per variant])."""
+        torch = _torch()
+        u = u.to(torch.float64).contiguous().reshape(-1)
+        ws = self.workspace()
+        chosen = ctypes.c_int()
+        times = (ctypes.c_double * self.N_VARIANTS)()
+        C.check(C.lib().qoc_plan_autotune(self._h, _ptr(u), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(),
+                                          ctypes.byref(chosen), times))
+        self._refresh_info()
+        return int(chosen.value), [float(t) for t in times]
 
     @classmethod
     def batched(cls, systems, precision="c64", Ns=None, dts=None, u_bound=1.0, max_workspace_bytes=0):

@@ -9,6 +9,7 @@ LIB_PATH = os.environ.get("QOC_LIBRARY") or os.path.join(HERE, "libqoc_gfx950.so
 QOC_OK = 0
 STATUS = {0: "QOC_OK", 1: "QOC_ERR_INVALID_ARG", 2: "QOC_ERR_SYMMETRY", 3: "QOC_ERR_UNSUPPORTED",
           4: "QOC_ERR_OUT_OF_MEMORY", 5: "QOC_ERR_DEVICE", 6: "QOC_ERR_NUMERIC"}
+STATUS_CODE = {v: k for k, v in STATUS.items()}
 GROUPS = {"dihedral": 0, "cyclic": 1, "symmetric": 2}
 PRECISIONS = {"c128": 0, "c64": 1}
 TERM_KINDS = {"one_body": 0, "ring_pair": 1, "all_pairs": 2, "pauli": 3}
@@ -64,6 +65,10 @@ PROTOTYPES = {
     "qoc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "qoc_last_error": (ctypes.c_char_p, []),
     "qoc_version": (ctypes.c_int, []),
+    "qoc_plan_set_variant": (ctypes.c_int, [vp, ctypes.c_int]),
+    "qoc_variant_name": (ctypes.c_char_p, [ctypes.c_int, ctypes.c_int]),
+    "qoc_plan_autotune": (ctypes.c_int, [vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_double)]),
 }
 
 

@@ -128,6 +128,8 @@ struct qoc_plan_s {
   qoc::DeviceBuffer d_jobs, d_probs, d_panels;
   qoc::DeviceBuffer d_theta, d_w;
   int grid_gemm = 512;
+  int variant = 0;        // GEMM tile variant (index into the precision's table)
+  int ncu = 256;
   hipStream_t st2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   ~qoc_plan_s() {
@@ -284,17 +286,16 @@ enum { STEP_POWER = 0, STEP_HORNER = 1, STEP_SQUARE = 2 };
 
 __constant__ double kInvFact[64];
 
-template <typename T> struct GemmWavesPerEU { static constexpr int value = 2; };
-
 // One product step over every entry of the segment (persistent, XCD-grouped items).
 // Buffers of an entry: 0 = Y, i-1 = Y^i (i <= r), r and r+1 = ping-pong T, r+2 = U^dag.
 // The last power step also forms the Horner start T0; the last product of an entry
 // writes U^dag for the backward sweep.
-template <typename T>
-__global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
+template <typename Shape>
+__global__ void __launch_bounds__(256, Shape::WAVES)
     k_expm_step(const JobDev* jobs, int njobs, long long total_items, char* ws, size_t off_T, const int* ent_s,
                 const int* ent_q, int mode, int step, int r, int seg_j0, int seg_len) {
-  __shared__ TileLds<T> lds;
+  typedef typename Shape::T T;
+  __shared__ TileLds<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
   for (long long it = rg.begin; it < rg.end; it += rg.step) {
     const int J = find_job_by_item(jobs, njobs, it);
@@ -332,10 +333,10 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
     op.M = mp;
     op.N = mp;
     op.K = mp;
-    op.row0 = ti * TileCfg<T>::BM;
-    op.col0 = tj * TileCfg<T>::BN;
-    TileAcc<T> acc;
-    tile_mma(op, lds, acc);
+    op.row0 = ti * Shape::BM;
+    op.col0 = tj * Shape::BN;
+    TileAcc<Shape> acc;
+    tile_mma<Shape>(op, lds, acc);
     T* C = base + (size_t)ic * 2 * plane;
     double coef[8];
     double ctop = 0.0;
@@ -350,11 +351,11 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value)
     }
     typedef typename Vec4<T>::type V4;
 #pragma unroll
-    for (int ri = 0; ri < TileCfg<T>::SM; ++ri)
+    for (int ri = 0; ri < Shape::SM; ++ri)
 #pragma unroll
-      for (int ci = 0; ci < TileCfg<T>::SN; ++ci) {
-        const int rbase = acc_row_base<T>(op.row0, ri);
-        const int col = acc_col<T>(op.col0, ci);
+      for (int ci = 0; ci < Shape::SN; ++ci) {
+        const int rbase = acc_row_base<Shape>(op.row0, ri);
+        const int col = acc_col<Shape>(op.col0, ci);
         if (rbase >= mp || col >= mp) continue;
         const int row0 = rbase + acc_row_off<T>(0);  // this lane's first accumulator row
         const size_t at = (size_t)row0 + (size_t)col * mp;
@@ -853,11 +854,12 @@ __global__ void __launch_bounds__(1024) k_overlap(const JobDev* jobs, const Prob
 
 // ===================================================================== gradient series
 // Z_o = H_o * V for every (job, o); V and Z are gradient slots of the job.
-template <typename T>
-__global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value) k_panel_gemm(const JobDev* jobs, const PanelDesc* descs, int ndesc,
-                                                    long long total_items, char* ws, size_t off_T, int vslot,
-                                                    int j0) {
-  __shared__ TileLds<T> lds;
+template <typename Shape>
+__global__ void __launch_bounds__(256, Shape::WAVES)
+    k_panel_gemm(const JobDev* jobs, const PanelDesc* descs, int ndesc, long long total_items, char* ws,
+                 size_t off_T, int vslot, int j0) {
+  typedef typename Shape::T T;
+  __shared__ TileLds<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
   for (long long it = rg.begin; it < rg.end; it += rg.step) {
     const PanelDesc pd = descs[find_desc(descs, ndesc, it)];
@@ -879,17 +881,17 @@ __global__ void __launch_bounds__(256, GemmWavesPerEU<T>::value) k_panel_gemm(co
     op.M = mp;
     op.N = jb.cc;
     op.K = mp;
-    op.row0 = ti * TileCfg<T>::BM;
-    op.col0 = tj * TileCfg<T>::BN;
-    TileAcc<T> acc;
-    tile_mma(op, lds, acc);
+    op.row0 = ti * Shape::BM;
+    op.col0 = tj * Shape::BN;
+    TileAcc<Shape> acc;
+    tile_mma<Shape>(op, lds, acc);
     T* C = g + (size_t)pd.op * jb.gslot;
 #pragma unroll
-    for (int ri = 0; ri < TileCfg<T>::SM; ++ri)
+    for (int ri = 0; ri < Shape::SM; ++ri)
 #pragma unroll
-      for (int ci = 0; ci < TileCfg<T>::SN; ++ci) {
-        const int rbase = acc_row_base<T>(op.row0, ri);
-        const int col = acc_col<T>(op.col0, ci);
+      for (int ci = 0; ci < Shape::SN; ++ci) {
+        const int rbase = acc_row_base<Shape>(op.row0, ri);
+        const int col = acc_col<Shape>(op.col0, ci);
         if (rbase >= mp || col >= jb.cc) continue;
         T* cr = C + (size_t)(rbase + acc_row_off<T>(0)) + (size_t)col * mp;
         acc_store<T>(cr, acc.re[ri][ci]);
@@ -1184,6 +1186,82 @@ static void upload_factorials() {
   devices_done.push_back(dev);
 }
 
+// ================================================================ GEMM tile variants
+// The GEMM kernels are compiled for a few work-group tile shapes per precision; a plan
+// uses one (default: the first) and qoc_plan_autotune picks the fastest on the plan's own
+// work.  Every shape accumulates each output element over k in the same order, so the
+// choice does not change any result bit.
+typedef void (*ExpmLaunch)(dim3, hipStream_t, const JobDev*, int, long long, char*, size_t, const int*,
+                           const int*, int, int, int, int, int);
+typedef void (*PanelLaunch)(dim3, hipStream_t, const JobDev*, const PanelDesc*, int, long long, char*, size_t, int,
+                            int);
+struct GemmVariant {
+  const char* name;
+  int bm, bn;
+  ExpmLaunch expm;
+  PanelLaunch panel;
+  const void* expm_fn;  // for occupancy queries
+};
+template <typename C>
+void launch_expm(dim3 g, hipStream_t st, const JobDev* j, int nj, long long items, char* ws, size_t offT,
+                 const int* es, const int* eq, int mode, int step, int r, int j0, int len) {
+  hipLaunchKernelGGL(k_expm_step<C>, g, dim3(256), 0, st, j, nj, items, ws, offT, es, eq, mode, step, r, j0, len);
+}
+template <typename C>
+void launch_panel(dim3 g, hipStream_t st, const JobDev* j, const PanelDesc* d, int nd, long long items, char* ws,
+                  size_t offT, int vslot, int j0) {
+  hipLaunchKernelGGL(k_panel_gemm<C>, g, dim3(256), 0, st, j, d, nd, items, ws, offT, vslot, j0);
+}
+template <typename C>
+GemmVariant make_variant(const char* name) {
+  return GemmVariant{name, C::BM, C::BN, launch_expm<C>, launch_panel<C>, (const void*)k_expm_step<C>};
+}
+static const GemmVariant kVariants32[] = {
+    make_variant<TileShape<float, 4, 2, 2>>("fp32 128x64"),
+    make_variant<TileShape<float, 2, 2, 4>>("fp32 64x64"),
+    make_variant<TileShape<float, 2, 4, 2>>("fp32 64x128"),
+};
+static const GemmVariant kVariants64[] = {
+    make_variant<TileShape<double, 2, 2, 2>>("fp64 64x64"),
+    make_variant<TileShape<double, 1, 2, 2>>("fp64 32x64"),
+    make_variant<TileShape<double, 2, 1, 2>>("fp64 64x32"),
+};
+constexpr int kNumVariants = 3;
+static const GemmVariant& gemm_variant(const qoc_plan_s* P) {
+  return P->prec == QOC_C128 ? kVariants64[P->variant] : kVariants32[P->variant];
+}
+
+// Tile counts and item offsets of the propagator and panel GEMMs for variant v, the
+// persistent grid for its occupancy, and the device copies of both tables (set-up only:
+// synchronous copies).
+static void apply_variant(qoc_plan_s* P, int v) {
+  QOC_REQUIRE(v >= 0 && v < kNumVariants, QOC_ERR_INVALID_ARG, "unknown GEMM variant");
+  P->variant = v;
+  const GemmVariant& g = gemm_variant(P);
+  long long items = 0;
+  for (auto& j : P->jobs) {
+    j.tiles_m = (j.mp + g.bm - 1) / g.bm;
+    j.tiles_n = (j.mp + g.bn - 1) / g.bn;
+    j.item_off = items;
+    items += (long long)P->seg_len * j.tiles_m * j.tiles_n;
+  }
+  P->expm_items = items;
+  long long pitems = 0;
+  for (auto& d : P->panels) {
+    d.item_off = pitems;
+    d.tiles_m = (P->jobs[d.job].mp + g.bm - 1) / g.bm;
+    d.tiles_n = (P->jobs[d.job].cc + g.bn - 1) / g.bn;
+    pitems += (long long)d.tiles_m * d.tiles_n;
+  }
+  P->panel_items = pitems;
+  int occ = 1;
+  QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, g.expm_fn, 256, 0));
+  P->grid_gemm = std::max(8, P->ncu * std::max(1, occ) / 8 * 8);
+  QOC_HIP(hipMemcpy(P->d_jobs.ptr, P->jobs.data(), P->jobs.size() * sizeof(JobDev), hipMemcpyHostToDevice));
+  if (!P->panels.empty())
+    QOC_HIP(hipMemcpy(P->d_panels.ptr, P->panels.data(), P->panels.size() * sizeof(PanelDesc), hipMemcpyHostToDevice));
+}
+
 template <typename T>
 struct Driver {
   static int* ent_s(const qoc_plan_s* P, char* ws) { return reinterpret_cast<int*>(ws + P->off_ent); }
@@ -1207,8 +1285,8 @@ struct Driver {
     const dim3 grid(P->grid_gemm);
     auto step = [&](int mode, int s) {
       timed(PK_EXPM_GEMM, st, [&] {
-        hipLaunchKernelGGL(k_expm_step<T>, grid, dim3(256), 0, st, dj, njobs, P->expm_items, ws, P->off_T,
-                           ent_s(P, ws), ent_q(P, ws), mode, s, P->r, seg_j0, L);
+        gemm_variant(P).expm(grid, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), mode, s,
+                             P->r, seg_j0, L);
       });
     };
     for (int i = 2; i <= P->r; ++i) step(STEP_POWER, i);
@@ -1244,6 +1322,15 @@ struct Driver {
         hipLaunchKernelGGL((k_sweep<T, 1>), dim3(njobs), dim3(1024), sweep_lds(P), st, dj, njobs, ws, P->off_T,
                            ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len);
       });
+  }
+
+  // Timing pass of the autotuner: the first segment's propagators and one panel GEMM.
+  static void tune_pass(qoc_plan_s* P, const double* u, char* ws, hipStream_t st) {
+    int* flags = reinterpret_cast<int*>(ws + P->off_flags);
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);
+    expm_segment(P, ws, u, 0, st);
+    gemm_variant(P).panel(dim3(P->grid_gemm), st, P->d_jobs.as<JobDev>(), P->d_panels.as<PanelDesc>(),
+                          (int)P->panels.size(), P->panel_items, ws, P->off_T, P->Kmax + 1, 0);
   }
 
   static void propagate(qoc_plan_s* P, const double* u, double2* out, char* ws, hipStream_t st) {
@@ -1321,8 +1408,7 @@ struct Driver {
     for (int j0 = 0; j0 < P->Nmax; j0 += C) {
       auto gemm = [&](int vslot) {
         timed(PK_GRAD_GEMM, st, [&] {
-          hipLaunchKernelGGL(k_panel_gemm<T>, dim3(P->grid_gemm), dim3(256), 0, st, dj, dp, npanel, P->panel_items,
-                             ws, P->off_T, vslot, j0);
+          gemm_variant(P).panel(dim3(P->grid_gemm), st, dj, dp, npanel, P->panel_items, ws, P->off_T, vslot, j0);
         });
       };
       auto combine = [&](double sign_over, int out_slot, int acc_slot) {
@@ -1407,9 +1493,6 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->prec = precision;
   P->u_bound = u_bound;
   const bool f64 = precision == QOC_C128;
-  // work-group tile of the GEMM kernels (see mfma_tile.h)
-  const int tbm = f64 ? TileCfg<double>::BM : TileCfg<float>::BM;
-  const int tbn = f64 ? TileCfg<double>::BN : TileCfg<float>::BN;
   P->elem = f64 ? 8 : 4;
   const double* theta = f64 ? kTaylorTheta64 : kTaylorTheta32;
   P->r = f64 ? 4 : 3;
@@ -1528,7 +1611,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   QOC_REQUIRE(njobs_total < (1LL << 30), QOC_ERR_INVALID_ARG, "too many (problem, block) pairs");
   P->entries_per_seg = (long long)P->seg_len * njobs_total;
   P->off_ent = take((size_t)P->entries_per_seg * 16);
-  long long tel = 0, ent_off = 0, item_off = 0, gacc = 0, u_off = 0, state_base = 0, uout = 0;
+  long long tel = 0, ent_off = 0, gacc = 0, u_off = 0, state_base = 0, uout = 0;
   int max_cc = 0;
   for (size_t p = 0; p < probs.size(); ++p) {
     const auto& pr = probs[p];
@@ -1551,12 +1634,8 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       j.hT = f64 ? (const void*)(pr.sys->h64.as<double>() + b.h_off) : (const void*)(pr.sys->h32.as<float>() + b.h_off);
       j.state_off = state_base + b.state_off;
       j.u_off = u_off;
-      j.tiles_m = (b.mp + tbm - 1) / tbm;
-      j.tiles_n = (b.mp + tbn - 1) / tbn;
       j.ent_off = ent_off;
       ent_off += P->seg_len;
-      j.item_off = item_off;
-      item_off += (long long)P->seg_len * j.tiles_m * j.tiles_n;
       j.ebuf_off = tel;
       tel += (long long)P->seg_len * (P->r + 3) * 2 * b.mp * b.mp;
       j.psi_off = tel;
@@ -1585,32 +1664,23 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->total_D = state_base;
   P->total_U = uout;
   P->max_cc = max_cc;
-  P->expm_items = item_off;
   P->off_T = take((size_t)tel * P->elem);
   P->off_gacc = take((size_t)std::max<long long>(gacc, 1) * 16);
   P->off_sync = take((size_t)2 * 4 * sizeof(int) * P->jobs.size());  // co-operative sweep control words
   P->bytes = off;
-  // panel GEMM descriptors: (job, op) for op = 0..K_job
-  long long pitems = 0;
+  // panel GEMM descriptors: (job, op) for op = 0..K_job (tiles set by apply_variant)
   for (size_t J = 0; J < P->jobs.size(); ++J)
     for (int o = 0; o <= P->jobs[J].K; ++o) {
       PanelDesc d{};
       d.job = (int)J;
       d.op = o;
-      d.item_off = pitems;
-      d.tiles_m = (P->jobs[J].mp + tbm - 1) / tbm;
-      d.tiles_n = (P->jobs[J].cc + tbn - 1) / tbn;
-      pitems += (long long)d.tiles_m * d.tiles_n;
       P->panels.push_back(d);
     }
-  P->panel_items = pitems;
   // device tables (set-up only)
   P->d_jobs.alloc(P->jobs.size() * sizeof(JobDev));
-  QOC_HIP(hipMemcpy(P->d_jobs.ptr, P->jobs.data(), P->jobs.size() * sizeof(JobDev), hipMemcpyHostToDevice));
   P->d_probs.alloc(P->probs.size() * sizeof(ProbDev));
   QOC_HIP(hipMemcpy(P->d_probs.ptr, P->probs.data(), P->probs.size() * sizeof(ProbDev), hipMemcpyHostToDevice));
   P->d_panels.alloc(std::max<size_t>(1, P->panels.size()) * sizeof(PanelDesc));
-  QOC_HIP(hipMemcpy(P->d_panels.ptr, P->panels.data(), P->panels.size() * sizeof(PanelDesc), hipMemcpyHostToDevice));
   P->d_theta.alloc(31 * sizeof(double));
   QOC_HIP(hipMemcpy(P->d_theta.ptr, theta, 31 * sizeof(double), hipMemcpyHostToDevice));
   std::vector<double> w((size_t)P->Q * P->Q, 0.0);
@@ -1618,17 +1688,14 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     for (int i = 0; i + t < P->Q; ++i) w[(size_t)t * P->Q + i] = fact(i) * fact(t) / fact(i + t + 1);
   P->d_w.alloc(w.size() * sizeof(double));
   QOC_HIP(hipMemcpy(P->d_w.ptr, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
-  // persistent GEMM grid: resident work-groups, a multiple of the 8 XCDs
-  int dev = 0, occ = 2;
+  // persistent GEMM grid (resident work-groups, a multiple of the 8 XCDs) and tile tables
+  int dev = 0;
   QOC_HIP(hipGetDevice(&dev));
   hipDeviceProp_t prop;
   QOC_HIP(hipGetDeviceProperties(&prop, dev));
   const int ncu = prop.multiProcessorCount;
-  if (f64)
-    QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_expm_step<double>, 256, 0));
-  else
-    QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_expm_step<float>, 256, 0));
-  P->grid_gemm = std::max(8, ncu * std::max(1, occ) / 8 * 8);
+  P->ncu = ncu;
+  apply_variant(P.get(), 0);
   // the sweeps keep the state and partial sums in LDS; allow the dynamic size beyond 64 KB
   const int lds = (int)(P->sweep_lds_elems * P->elem);
   // co-operative sweeps when every work-group of both concurrent sweeps fits on its own CU
@@ -1707,9 +1774,68 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
     QOC_REQUIRE(P && info, QOC_ERR_INVALID_ARG, "null argument");
     size_t per_slice = 0;
     for (auto& j : P->jobs) per_slice += (size_t)(P->r + 3) * 2 * j.mp * j.mp * P->elem;
-    int64_t v[15] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
-                     P->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U};
-    for (int i = 0; i < cap && i < 15; ++i) info[i] = v[i];
+    int64_t v[16] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
+                     P->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U,
+                     P->variant};
+    for (int i = 0; i < cap && i < 16; ++i) info[i] = v[i];
+  });
+}
+
+qoc_status qoc_plan_set_variant(qoc_plan P, int variant) {
+  return guarded([&] {
+    QOC_REQUIRE(P, QOC_ERR_INVALID_ARG, "null plan");
+    QOC_REQUIRE(variant >= 0 && variant < kNumVariants, QOC_ERR_INVALID_ARG, "variant out of range");
+    QOC_HIP(hipDeviceSynchronize());
+    apply_variant(P, variant);
+  });
+}
+
+const char* qoc_variant_name(int precision, int variant) {
+  if (variant < 0 || variant >= kNumVariants) return "";
+  return precision == QOC_C128 ? kVariants64[variant].name : kVariants32[variant].name;
+}
+
+qoc_status qoc_plan_autotune(qoc_plan P, const double* u_dev, void* workspace, size_t ws_bytes, void* stream,
+                             int* chosen, double* times_ms) {
+  return guarded([&] {
+    QOC_REQUIRE(P && u_dev && workspace, QOC_ERR_INVALID_ARG, "null argument");
+    QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
+    hipStream_t st = (hipStream_t)stream;
+    QOC_HIP(hipStreamSynchronize(st));
+    hipEvent_t e0, e1;
+    QOC_HIP(hipEventCreate(&e0));
+    QOC_HIP(hipEventCreate(&e1));
+    auto run = [&] {
+      if (P->prec == QOC_C128)
+        Driver<double>::tune_pass(P, u_dev, (char*)workspace, st);
+      else
+        Driver<float>::tune_pass(P, u_dev, (char*)workspace, st);
+    };
+    int best = 0;
+    double best_ms = 0.0;
+    for (int v = 0; v < kNumVariants; ++v) {
+      apply_variant(P, v);
+      run();  // warm-up
+      double t = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {
+        QOC_HIP(hipEventRecord(e0, st));
+        run();
+        QOC_HIP(hipEventRecord(e1, st));
+        QOC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        QOC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        t = std::min(t, (double)ms);
+      }
+      if (times_ms) times_ms[v] = t;
+      if (v == 0 || t < best_ms) {
+        best = v;
+        best_ms = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    apply_variant(P, best);
+    if (chosen) *chosen = best;
   });
 }
 

@@ -2,10 +2,10 @@
 //
 // A work-group of 256 threads (4 wave64s in a 2x2 arrangement) computes
 // C[BM x BN] = A[BM x K] * B[K x BN], K a multiple of 16.  Each wave owns a
-// (BM/2) x (BN/2) quadrant as SM x SN sub-tiles of v_mfma_*_16x16x4; a complex product is
-// complex multiply-add built from real MFMAs.  FP32 uses 128 x 128 tiles
-// (each wave 4 x 4 sub-tiles: twice the MFMAs per LDS read and half the operand re-reads
-// of a 64 x 64 tile); FP64 uses 64 x 64 (its accumulators are twice as wide).
+// (BM/2) x (BN/2) quadrant as SM x SN sub-tiles of v_mfma_*_16x16x4, and each complex
+// multiply-add is built from real MFMAs.  The tile shape is a template parameter
+// (TileShape); the library compiles a few shapes per precision and a plan picks one,
+// by default or by timing them on its own work (qoc_plan_autotune).
 // The complex product takes three real MFMAs per sub-tile and k step instead of four
 // (Gauss's 3M form, see TileAcc).
 // Operands are staged through double-buffered LDS in 16-deep slabs; the next slab is
@@ -29,27 +29,31 @@ template <> struct Vec4<float> { typedef f4v type; };
 __device__ inline d4v mfma16(double a, double b, d4v c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline f4v mfma16(float a, float b, f4v c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
-// Work-group tile BM x BN, SM x SN sub-tiles per wave, LDS row padding PAD (elements):
-// consecutive k rows of a slab start 16 (FP32) or 32 (FP64) banks apart.
-template <typename T> struct TileCfg;
-template <> struct TileCfg<float> { static constexpr int BM = 128, BN = 64, SM = 4, SN = 2, PAD = 16; };
-template <> struct TileCfg<double> { static constexpr int BM = 64, BN = 64, SM = 2, SN = 2, PAD = 16; };
+// Work-group tile shape: 4 waves in a 2 x 2 arrangement, each owning SM x SN 16 x 16
+// sub-tiles, so the work-group computes BM x BN = 32 SM x 32 SN.  WAVES is the occupancy
+// the kernels are compiled for (waves per SIMD).  LDS rows carry PAD elements of
+// padding: consecutive k rows of a slab start 16 (FP32) or 32 (FP64) banks apart.
+template <typename T_, int SM_, int SN_, int WAVES_>
+struct TileShape {
+  typedef T_ T;
+  static constexpr int SM = SM_, SN = SN_, BM = 32 * SM_, BN = 32 * SN_, PAD = 16, WAVES = WAVES_;
+};
 constexpr int TBK = 16;
 
-template <typename T>
+template <typename C>
 struct TileLds {
-  T a[2][2][TBK][TileCfg<T>::BM + TileCfg<T>::PAD];  // [buffer][plane][k][row]
-  T b[2][2][TBK][TileCfg<T>::BN + TileCfg<T>::PAD];  // [buffer][plane][k][col]
+  typename C::T a[2][2][TBK][C::BM + C::PAD];  // [buffer][plane][k][row]
+  typename C::T b[2][2][TBK][C::BN + C::PAD];  // [buffer][plane][k][col]
 };
 
 // Accumulators.  Inside the K loop the complex product is formed with three real products
 // (Gauss): re = Ar*Br, x = Ai*Bi, im = (Ar+Ai)*(Br+Bi); tile_mma returns
 // re = Ar*Br - Ai*Bi and im = (Ar+Ai)*(Br+Bi) - Ar*Br - Ai*Bi.
-template <typename T>
+template <typename C>
 struct TileAcc {
-  typename Vec4<T>::type re[TileCfg<T>::SM][TileCfg<T>::SN];
-  typename Vec4<T>::type im[TileCfg<T>::SM][TileCfg<T>::SN];
-  typename Vec4<T>::type x[TileCfg<T>::SM][TileCfg<T>::SN];
+  typename Vec4<typename C::T>::type re[C::SM][C::SN];
+  typename Vec4<typename C::T>::type im[C::SM][C::SN];
+  typename Vec4<typename C::T>::type x[C::SM][C::SN];
 };
 
 // Operand pointers of one tile product.  Planes: re at p, im at p + plane stride.
@@ -74,27 +78,28 @@ template <> struct Vec16<double> { typedef double2 type; static constexpr int n 
 //  A (BM x 16): vectors f = tt + 128 i (i < NA): k = f / CV, rows (f % CV) * VEC .. with
 //    CV = BM/VEC vectors per k row; a wave's stores to LDS cover whole k rows;
 //  B (16 x BN): column tt/TPC, KB = BN/8 consecutive k from (tt%TPC)*KB (NB vectors).
-template <typename T>
+template <typename C>
 struct SlabShape {
-  static constexpr int VEC = Vec16<T>::n;
-  static constexpr int CV = TileCfg<T>::BM / VEC;
-  static constexpr int NA = TileCfg<T>::BM * TBK / (128 * VEC);
-  static constexpr int KB = TileCfg<T>::BN / 8;
+  static constexpr int VEC = Vec16<typename C::T>::n;
+  static constexpr int CV = C::BM / VEC;
+  static constexpr int NA = C::BM * TBK / (128 * VEC);
+  static constexpr int KB = C::BN / 8;
   static constexpr int NB = KB / VEC;
   static constexpr int TPC = TBK / KB;
   static_assert(NA >= 1 && NB >= 1 && TBK % KB == 0, "slab mapping");
 };
 
-template <typename T>
+template <typename C>
 struct SlabRegs {
-  typename Vec16<T>::type a[SlabShape<T>::NA];
-  typename Vec16<T>::type b[SlabShape<T>::NB];
+  typename Vec16<typename C::T>::type a[SlabShape<C>::NA];
+  typename Vec16<typename C::T>::type b[SlabShape<C>::NB];
 };
 
-template <typename T>
-__device__ inline void tile_fetch(const TileOperands<T>& op, int k0, SlabRegs<T>& r) {
+template <typename C>
+__device__ inline void tile_fetch(const TileOperands<typename C::T>& op, int k0, SlabRegs<C>& r) {
+  typedef typename C::T T;
   typedef typename Vec16<T>::type V;
-  typedef SlabShape<T> S;
+  typedef SlabShape<C> S;
   const int t = threadIdx.x;
   const int plane = t >> 7, tt = t & 127;
 #pragma unroll
@@ -112,10 +117,10 @@ __device__ inline void tile_fetch(const TileOperands<T>& op, int k0, SlabRegs<T>
   for (int i = 0; i < S::NB; ++i) r.b[i] = col < op.N ? p[i] : V{};
 }
 
-template <typename T>
-__device__ inline void tile_stash(TileLds<T>& s, int buf, const SlabRegs<T>& r) {
-  typedef typename Vec16<T>::type V;
-  typedef SlabShape<T> S;
+template <typename C>
+__device__ inline void tile_stash(TileLds<C>& s, int buf, const SlabRegs<C>& r) {
+  typedef typename Vec16<typename C::T>::type V;
+  typedef SlabShape<C> S;
   const int t = threadIdx.x;
   const int plane = t >> 7, tt = t & 127;
 #pragma unroll
@@ -134,20 +139,20 @@ __device__ inline void tile_stash(TileLds<T>& s, int buf, const SlabRegs<T>& r) 
 __device__ inline int tile_wave() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // MFMA operands of one 4-deep k step: this lane's rows of A and columns of B.
-template <typename T>
+template <typename C>
 struct StepOps {
-  T ar[TileCfg<T>::SM], ai[TileCfg<T>::SM], br[TileCfg<T>::SN], bi[TileCfg<T>::SN];
+  typename C::T ar[C::SM], ai[C::SM], br[C::SN], bi[C::SN];
 };
 
-template <typename T>
-__device__ inline void step_load(const TileLds<T>& s, int buf, int kq, int r0, int c0, StepOps<T>& o) {
+template <typename C>
+__device__ inline void step_load(const TileLds<C>& s, int buf, int kq, int r0, int c0, StepOps<C>& o) {
 #pragma unroll
-  for (int q = 0; q < TileCfg<T>::SM; ++q) {
+  for (int q = 0; q < C::SM; ++q) {
     o.ar[q] = s.a[buf][0][kq][r0 + q * 16];
     o.ai[q] = s.a[buf][1][kq][r0 + q * 16];
   }
 #pragma unroll
-  for (int q = 0; q < TileCfg<T>::SN; ++q) {
+  for (int q = 0; q < C::SN; ++q) {
     o.br[q] = s.b[buf][0][kq][c0 + q * 16];
     o.bi[q] = s.b[buf][1][kq][c0 + q * 16];
   }
@@ -155,10 +160,11 @@ __device__ inline void step_load(const TileLds<T>& s, int buf, int kq, int r0, i
 
 // Three real MFMAs per sub-tile and k step (see TileAcc); all 3 SM SN of a step are
 // independent, so dependent MFMAs are a full step apart.
-template <typename T, bool FULL>
-__device__ inline void step_mfma(const StepOps<T>& o, const bool (&rv)[TileCfg<T>::SM],
-                                 const bool (&cv)[TileCfg<T>::SN], TileAcc<T>& acc) {
-  constexpr int SM = TileCfg<T>::SM, SN = TileCfg<T>::SN;
+template <typename C, bool FULL>
+__device__ inline void step_mfma(const StepOps<C>& o, const bool (&rv)[C::SM], const bool (&cv)[C::SN],
+                                 TileAcc<C>& acc) {
+  typedef typename C::T T;
+  constexpr int SM = C::SM, SN = C::SN;
   T as[SM], bs[SN];
 #pragma unroll
   for (int q = 0; q < SM; ++q) as[q] = o.ar[q] + o.ai[q];
@@ -177,20 +183,20 @@ __device__ inline void step_mfma(const StepOps<T>& o, const bool (&rv)[TileCfg<T
 
 // One 16-deep slab: the operands of step k+1 are read from LDS while the MFMAs of step k
 // run (two register stages); on interior tiles the scheduler is told to interleave them.
-template <typename T, bool FULL>
-__device__ inline void tile_slab(const TileLds<T>& s, int buf, const bool (&rv)[TileCfg<T>::SM],
-                                 const bool (&cv)[TileCfg<T>::SN], TileAcc<T>& acc) {
-  constexpr int SM = TileCfg<T>::SM, SN = TileCfg<T>::SN;
+template <typename C, bool FULL>
+__device__ inline void tile_slab(const TileLds<C>& s, int buf, const bool (&rv)[C::SM], const bool (&cv)[C::SN],
+                                 TileAcc<C>& acc) {
+  constexpr int SM = C::SM, SN = C::SN;
   const int lane = threadIdx.x & 63, wave = tile_wave();
-  const int r0 = (wave >> 1) * (TileCfg<T>::BM / 2) + (lane & 15);
-  const int c0 = (wave & 1) * (TileCfg<T>::BN / 2) + (lane & 15);
+  const int r0 = (wave >> 1) * (C::BM / 2) + (lane & 15);
+  const int c0 = (wave & 1) * (C::BN / 2) + (lane & 15);
   const int kl = lane >> 4;
-  StepOps<T> o[2];
+  StepOps<C> o[2];
   step_load(s, buf, kl, r0, c0, o[0]);
 #pragma unroll
   for (int k4 = 0; k4 < TBK / 4; ++k4) {
     if (k4 + 1 < TBK / 4) step_load(s, buf, (k4 + 1) * 4 + kl, r0, c0, o[(k4 + 1) & 1]);
-    step_mfma<T, FULL>(o[k4 & 1], rv, cv, acc);
+    step_mfma<C, FULL>(o[k4 & 1], rv, cv, acc);
     if (FULL && k4 + 1 < TBK / 4) {
       // ds reads of the next step (merged in pairs) spread over this step's MFMAs
       constexpr int NRD = SM + SN, NMF = 3 * SM * SN / NRD;
@@ -203,10 +209,10 @@ __device__ inline void tile_slab(const TileLds<T>& s, int buf, const bool (&rv)[
   }
 }
 
-template <typename T, bool FULL>
-__device__ inline void tile_kloop(const TileOperands<T>& op, TileLds<T>& s, const bool (&rv)[TileCfg<T>::SM],
-                                  const bool (&cv)[TileCfg<T>::SN], TileAcc<T>& acc) {
-  SlabRegs<T> r;
+template <typename C, bool FULL>
+__device__ inline void tile_kloop(const TileOperands<typename C::T>& op, TileLds<C>& s, const bool (&rv)[C::SM],
+                                  const bool (&cv)[C::SN], TileAcc<C>& acc) {
+  SlabRegs<C> r;
   const int nk = op.K / TBK;
   tile_fetch(op, 0, r);
   __syncthreads();  // the previous tile's readers are done with both buffers
@@ -215,7 +221,7 @@ __device__ inline void tile_kloop(const TileOperands<T>& op, TileLds<T>& s, cons
   for (int kb = 0; kb < nk; ++kb) {
     const int buf = kb & 1;
     if (kb + 1 < nk) tile_fetch(op, (kb + 1) * TBK, r);
-    tile_slab<T, FULL>(s, buf, rv, cv, acc);
+    tile_slab<C, FULL>(s, buf, rv, cv, acc);
     if (kb + 1 < nk) tile_stash(s, buf ^ 1, r);
     __syncthreads();
   }
@@ -223,9 +229,10 @@ __device__ inline void tile_kloop(const TileOperands<T>& op, TileLds<T>& s, cons
 
 // Full K loop for one output tile; acc is zeroed here.  Interior tiles run a copy of the
 // loop without the per-sub-tile range checks; every check is wave-uniform.
-template <typename T>
-__device__ inline void tile_mma(const TileOperands<T>& op, TileLds<T>& s, TileAcc<T>& acc) {
-  constexpr int SM = TileCfg<T>::SM, SN = TileCfg<T>::SN;
+template <typename C>
+__device__ inline void tile_mma(const TileOperands<typename C::T>& op, TileLds<C>& s, TileAcc<C>& acc) {
+  typedef typename C::T T;
+  constexpr int SM = C::SM, SN = C::SN;
 #pragma unroll
   for (int ri = 0; ri < SM; ++ri)
 #pragma unroll
@@ -238,13 +245,13 @@ __device__ inline void tile_mma(const TileOperands<T>& op, TileLds<T>& s, TileAc
   const int wr = wave >> 1, wc = wave & 1;
   bool rv[SM], cv[SN];
 #pragma unroll
-  for (int q = 0; q < SM; ++q) rv[q] = op.row0 + wr * (TileCfg<T>::BM / 2) + q * 16 < op.M;
+  for (int q = 0; q < SM; ++q) rv[q] = op.row0 + wr * (C::BM / 2) + q * 16 < op.M;
 #pragma unroll
-  for (int q = 0; q < SN; ++q) cv[q] = op.col0 + wc * (TileCfg<T>::BN / 2) + q * 16 < op.N;
-  if (op.row0 + TileCfg<T>::BM <= op.M && op.col0 + TileCfg<T>::BN <= op.N)
-    tile_kloop<T, true>(op, s, rv, cv, acc);
+  for (int q = 0; q < SN; ++q) cv[q] = op.col0 + wc * (C::BN / 2) + q * 16 < op.N;
+  if (op.row0 + C::BM <= op.M && op.col0 + C::BN <= op.N)
+    tile_kloop<C, true>(op, s, rv, cv, acc);
   else
-    tile_kloop<T, false>(op, s, rv, cv, acc);
+    tile_kloop<C, false>(op, s, rv, cv, acc);
 #pragma unroll
   for (int ri = 0; ri < SM; ++ri)
 #pragma unroll
@@ -257,9 +264,9 @@ __device__ inline void tile_mma(const TileOperands<T>& op, TileLds<T>& s, TileAc
 
 // First row of sub-tile ri of this wave, the row offset of accumulator element v, and
 // the column of sub-tile ci held by this lane.
-template <typename T>
+template <typename C>
 __device__ inline int acc_row_base(int row0, int ri) {
-  return row0 + (tile_wave() >> 1) * (TileCfg<T>::BM / 2) + ri * 16;
+  return row0 + (tile_wave() >> 1) * (C::BM / 2) + ri * 16;
 }
 template <typename T> __device__ inline int acc_row_off(int v);
 template <> __device__ inline int acc_row_off<float>(int v) { return 4 * ((threadIdx.x & 63) >> 4) + v; }
@@ -282,9 +289,9 @@ __device__ inline void acc_store<float>(float* p, f4v v) { *reinterpret_cast<f4v
 template <>
 __device__ inline void acc_store<double>(double* p, d4v v) { p[0] = v[0]; p[4] = v[1]; p[8] = v[2]; p[12] = v[3]; }
 
-template <typename T>
+template <typename C>
 __device__ inline int acc_col(int col0, int ci) {
-  return col0 + (tile_wave() & 1) * (TileCfg<T>::BN / 2) + ci * 16 + (threadIdx.x & 15);
+  return col0 + (tile_wave() & 1) * (C::BN / 2) + ci * 16 + (threadIdx.x & 15);
 }
 
 // Persistent scheduling: work-group w runs on XCD w % 8; each XCD takes a contiguous

@@ -112,3 +112,16 @@ def test_symmetry_check_rejects_malformed_terms():
     assert _check(6, 0, 1, [W.one_body(float("nan"), "x")]) == 1
     assert _check(6, 0, 1, [W.one_body(1.0, "q")]) == 1
     assert _check(6, 0, 1, [W.ring_pair(1.0, "zz", 6)]) == 1
+
+
+def test_gemm_variant_names_and_bad_handles():
+    """Three GEMM tile variants per precision, named by precision and work-group tile;
+    variant selection and autotuning reject null plans and out-of-range indices on the host."""
+    L = C.lib()
+    for prec, tag in ((0, "fp64"), (1, "fp32")):
+        names = [L.qoc_variant_name(prec, v).decode() for v in range(3)]
+        assert all(n.startswith(tag + " ") and "x" in n for n in names), names
+        assert len(set(names)) == 3
+        assert L.qoc_variant_name(prec, 3) == b"" and L.qoc_variant_name(prec, -1) == b""
+    assert L.qoc_plan_set_variant(None, 0) == C.STATUS_CODE["QOC_ERR_INVALID_ARG"]
+    assert L.qoc_plan_autotune(None, None, None, 0, None, None, None) == C.STATUS_CODE["QOC_ERR_INVALID_ARG"]
