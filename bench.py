@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -94,12 +96,14 @@ def timed_steps(q, torch, plan, dev, steps, warmup):
 
 
 def gemm_flops(q, plan, dev, sizes):
-    """Algorithmic flops of the propagator GEMMs of one call (8 m^3 per complex product)."""
+    """Algorithmic flops of the propagator GEMMs of one call (8 m^3 per complex product):
+    (r - 1) + (q - 1) + s products for Paterson-Stockmeyer degree q r, 4 + s for the
+    four-product degree-12 scheme (q = 0)."""
     qs, ss, _ = q.slice_stats(plan, dev["u"])
     r = plan.info["taylor_step"]
     tot = 0.0
     for b, m in enumerate(sizes):
-        prods = (r - 1) + (qs[b] - 1) + ss[b]
+        prods = np.where(qs[b] == 0, 4 + ss[b], (r - 1) + (qs[b] - 1) + ss[b])
         tot += 8.0 * m ** 3 * float(prods.sum())
     return tot, qs, ss
 

@@ -233,10 +233,12 @@ qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi
 qoc_status qoc_profile_begin(int max_launches);
 qoc_status qoc_profile_end(double* ms, int64_t* launches, int cap);
 
-/* Per job and slice (host arrays [jobs][max N], jobs = (problem, block) pairs in order;
- * entries beyond a problem's N are 0): the Taylor degree multiple q (degree
- * q * r), squaring count s and FP64 norm dt*||H0 + sum_k u[j,k] H_k||_1 that the plan's
- * propagators pick for these controls (the algorithmic work of Eq. (3)'s exponentials).
+/* Per job and slice (host arrays [jobs][max N], jobs = (problem, block) pairs in order):
+ * the evaluation the plan's propagators pick for these controls (the algorithmic work of
+ * Eq. (3)'s exponentials): q >= 1 for Paterson-Stockmeyer Taylor of degree q * r
+ * ((r - 1) + (q - 1) matrix products), q = 0 for the four-product degree-12 Taylor
+ * evaluation (Bader, Blanes & Casas 2019); squaring count s; FP64 norm
+ * dt*||H0 + sum_k u[j,k] H_k||_1.  Entries beyond a problem's N: q = -1, s = 0, norm 0.
  * Synchronises `stream`. */
 qoc_status qoc_plan_slice_stats(qoc_plan plan, const double* u_dev, int32_t* q, int32_t* s, double* norms,
                                 void* stream);

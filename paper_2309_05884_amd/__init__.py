@@ -218,7 +218,9 @@ def profile_end():
 
 
 def slice_stats(plan: "Plan", u):
-    """(q, s, norm) arrays of shape (nblocks, N): the propagators' degree multiple, squarings, norm."""
+    """(q, s, norm) arrays of shape (jobs, max N): the propagators' evaluation (q >= 1:
+    Paterson-Stockmeyer degree q r; q = 0: the four-product degree-12 scheme; -1 beyond a
+    problem's N), squarings and FP64 norm."""
     torch = _torch()
     u = u.to(torch.float64).contiguous()
     nb = plan.info["jobs"]

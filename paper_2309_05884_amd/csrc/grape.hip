@@ -29,6 +29,7 @@
 
 #include "mfma_tile.h"
 #include "qoc_internal.h"
+#include "taylor12.h"
 #include "taylor_table.h"
 
 namespace qoc {
@@ -106,6 +107,7 @@ struct qoc_plan_s {
   int Nmax = 0, Kmax = 0;
   double u_bound = 0.0;
   int r = 4, qmax = 4, smax = 0;
+  int t12 = 0;  // slices may use the four-product degree-12 evaluation
   double norm_bound = 0.0;
   int seg_len = 0, nseg = 0;
   int R = 1, Q = 1;
@@ -152,16 +154,34 @@ __device__ inline T* tplane(char* ws, size_t off_T, long long elem_off) {
   return reinterpret_cast<T*>(ws + off_T) + elem_off;
 }
 
-__device__ inline void pick_degree(double nx, const double* theta, int r, int qmax, int* q_out, int* s_out) {
+// Evaluation scheme of a slice with ||X||_1 = nx: Paterson-Stockmeyer Taylor of degree
+// q r (powers Y^2..Y^r, q-1 Horner products: r-1+q-1 products) or, q = 0, the four-product
+// degree-12 scheme (A^2, A^3 and two products); then s squarings.  The cheapest in
+// products wins, ties to the larger Paterson-Stockmeyer degree.  The degree-12 scheme is
+// offered only when t12 is set (FP32 plans: its epilogues move more data per product, which
+// the FP64 accumulator layout makes four times as costly, and its products of non-unitary
+// intermediates raise the unitarity error about threefold).
+__host__ __device__ inline void pick_degree(double nx, const double* theta, int r, int qmax, int t12, int* q_out,
+                                            int* s_out) {
   int best_q = qmax, best_s = 0, best_cost = 1 << 30;
   for (int q = qmax; q >= 1; --q) {
     int sq = 0;
     while (sq < 62 && nx > ldexp(theta[q * r], sq)) ++sq;
-    if ((q - 1) + sq < best_cost) { best_cost = (q - 1) + sq; best_q = q; best_s = sq; }
+    const int cost = (r - 1) + (q - 1) + sq;
+    if (cost < best_cost) { best_cost = cost; best_q = q; best_s = sq; }
+  }
+  if (t12) {
+    int s12 = 0;
+    while (s12 < 62 && nx > ldexp(theta[12], s12)) ++s12;
+    if (4 + s12 < best_cost) { best_q = 0; best_s = s12; }
   }
   *q_out = best_q;
   *s_out = best_s;
 }
+
+// The Horner chain of a degree-12 (q = 0) entry ends where a q = 1 chain would: in the
+// first ping-pong buffer.
+__host__ __device__ inline int qeff(int q) { return q > 0 ? q : 1; }
 
 // ===================================================================== generator + norm
 // One work-group per job and group of GEN_SG slices.  Pass 1: FP64 column sums of
@@ -174,7 +194,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs, const double* u, int seg_j0,
                                                    int seg_len, int groups, char* ws, size_t off_T, int* ent_s,
                                                    int* ent_q, double* ent_norm, int* flags, const double* theta,
-                                                   int r, int qmax, int smax, double norm_bound) {
+                                                   int r, int qmax, int t12, int smax, double norm_bound) {
   __shared__ double red[GEN_SG][256];
   __shared__ double us[GEN_SG][17];
   __shared__ double scale[GEN_SG];
@@ -242,7 +262,7 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
     if (!finite) flag |= 2;
     if (nx > norm_bound * (1.0 + 1e-12)) flag |= 1;
     int best_q, best_s;
-    pick_degree(nx, theta, r, qmax, &best_q, &best_s);
+    pick_degree(nx, theta, r, qmax, t12, &best_q, &best_s);
     if (best_s > smax) { flag |= 1; best_s = smax; }
     if (flag) atomicOr(flags, flag);
     atomicMax(flags + 1, best_s);
@@ -282,9 +302,10 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
 }
 
 // ===================================================================== expm GEMM steps
-enum { STEP_POWER = 0, STEP_HORNER = 1, STEP_SQUARE = 2 };
+enum { STEP_POWER = 0, STEP_HORNER = 1, STEP_SQUARE = 2, STEP_T12 = 3 };
 
 __constant__ double kInvFact[64];
+__constant__ double kT12c[4][4];  // the degree-12 scheme's coefficients (taylor12.h)
 
 // One product step over every entry of the segment (persistent, XCD-grouped items).
 // Buffers of an entry: 0 = Y, i-1 = Y^i (i <= r), r and r+1 = ping-pong T, r+2 = U^dag.
@@ -308,18 +329,28 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     const int ti = tile / jb.tiles_n, tj = tile % jb.tiles_n;
     const long long e = jb.ent_off + jl;
     const int se = ent_s[e], qe = ent_q[e];
+    const bool t12 = qe == 0;  // the four-product degree-12 scheme
     int ia, ib, ic;
     if (mode == STEP_POWER) {
+      if (t12 && step > 3) continue;  // it needs Y^2 and Y^3 only
       ia = step - 2; ib = 0; ic = step - 1;
+    } else if (mode == STEP_T12) {
+      if (!t12) continue;
+      if (step == 1) {  // B4 B4 (B4 in buffer r) -> A6 = B3 + B4^2 in buffer r+1
+        ia = r; ib = r; ic = r + 1;
+      } else {          // (B2 + A6) A6 + B1 -> T12 in buffer r
+        ia = 1; ib = r + 1; ic = r;
+      }
     } else if (mode == STEP_HORNER) {
       if (qe - 1 < step) continue;
       ia = r + ((step - 1) & 1); ib = r - 1; ic = r + (step & 1);
     } else {
       if (se < step) continue;
-      const int h = qe - 1 + step - 1;
+      const int h = qeff(qe) - 1 + step - 1;
       ia = r + (h & 1); ib = ia; ic = r + ((h + 1) & 1);
     }
-    const bool final_op = (mode == STEP_SQUARE && step == se) || (mode == STEP_HORNER && se == 0 && step == qe - 1);
+    const bool final_op = (mode == STEP_SQUARE && step == se) || (mode == STEP_HORNER && se == 0 && step == qe - 1) ||
+                          (mode == STEP_T12 && step == 2 && se == 0);
     const int mp = jb.mp;
     const size_t plane = (size_t)mp * mp;
     T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
@@ -341,8 +372,9 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     double coef[8];
     double ctop = 0.0;
     const int lh = qe - 1 - step;
-    const bool init_T = mode == STEP_POWER && step == r;
+    const bool init_T = mode == STEP_POWER && step == r && !t12;
     const bool init_final = init_T && qe == 1 && se == 0;
+    const bool init_B4 = mode == STEP_POWER && step == 3 && t12;
     if (mode == STEP_HORNER)
       for (int i = 0; i < r; ++i) coef[i] = kInvFact[lh * r + i];
     if (init_T) {
@@ -370,8 +402,60 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
           for (int v = 0; v < 4; ++v)
             if (row0 + v * AccRowStep<T>::value == col && col < jb.m) vr[v] += (T)coef[0];
         }
+        if (mode == STEP_T12) {
+          // sum_k c[k] P_k at this tile for P_0 = I, P_1..3 = Y, Y^2, Y^3 (buffers 0..2)
+          const V4 y1r = acc_load<T>(base + at), y1i = acc_load<T>(base + at + plane);
+          const V4 y2r = acc_load<T>(base + 2 * plane + at), y2i = acc_load<T>(base + 3 * plane + at);
+          auto combo = [&](int i, V4& cr, V4& ci) {
+            cr = (T)kT12c[i][1] * y1r;
+            ci = (T)kT12c[i][1] * y1i;
+            cr += (T)kT12c[i][2] * y2r;
+            ci += (T)kT12c[i][2] * y2i;
+            if (step == 1) {
+              const V4 y3r = acc_load<T>(base + 4 * plane + at), y3i = acc_load<T>(base + 5 * plane + at);
+              cr += (T)kT12c[i][3] * y3r;
+              ci += (T)kT12c[i][3] * y3i;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (row0 + v * AccRowStep<T>::value == col && col < jb.m) cr[v] += (T)kT12c[i][0];
+          };
+          if (step == 1) {
+            // A6 = B3 + B4^2 (the product); buffer 0 <- B1, buffer 1 <- B2 + A6 (neither is an
+            // operand of this step, and each tile rewrites only its own elements)
+            V4 br, bi;
+            combo(2, br, bi);
+            vr += br;
+            vi += bi;
+            V4 b1r, b1i, b2r, b2i;
+            combo(0, b1r, b1i);
+            combo(1, b2r, b2i);
+            acc_store<T>(base + at, b1r);
+            acc_store<T>(base + at + plane, b1i);
+            acc_store<T>(base + 2 * plane + at, b2r + vr);
+            acc_store<T>(base + 3 * plane + at, b2i + vi);
+          } else {
+            // T12 = B1 (buffer 0) + (B2 + A6) A6
+            vr += y1r;
+            vi += y1i;
+          }
+        }
         acc_store<T>(C + at, vr);
         acc_store<T>(C + at + plane, vi);
+        if (init_B4) {
+          // B4 = sum_k c[3][k] P_k (the product is Y^3) into buffer r: the degree-12 scheme's start
+          const V4 y1r = acc_load<T>(base + at), y1i = acc_load<T>(base + at + plane);
+          const V4 y2r = acc_load<T>(base + 2 * plane + at), y2i = acc_load<T>(base + 3 * plane + at);
+          V4 br = (T)kT12c[3][3] * vr, bi = (T)kT12c[3][3] * vi;
+          br += (T)kT12c[3][1] * y1r + (T)kT12c[3][2] * y2r;
+          bi += (T)kT12c[3][1] * y1i + (T)kT12c[3][2] * y2i;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (row0 + v * AccRowStep<T>::value == col && col < jb.m) br[v] += (T)kT12c[3][0];
+          T* B4 = base + (size_t)r * 2 * plane + at;
+          acc_store<T>(B4, br);
+          acc_store<T>(B4 + plane, bi);
+        }
         if (init_T) {
           // T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i at this tile (the Horner start)
           V4 tr = (T)ctop * vr, ti = (T)ctop * vi;
@@ -414,7 +498,7 @@ template <typename T>
 __device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int jl, int r, int s, int q) {
   const size_t plane = (size_t)jb.mp * jb.mp;
   const T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
-  return base + (size_t)(r + ((q - 1 + s) & 1)) * 2 * plane;
+  return base + (size_t)(r + ((qeff(q) - 1 + s) & 1)) * 2 * plane;
 }
 
 // ===================================================================== state set-up
@@ -513,7 +597,7 @@ __device__ void sweep_solo(const JobDev& jb, char* ws, size_t off_T, const int* 
     const int jl = DIR == 0 ? it : len - 1 - it;
     const long long e = jb.ent_off + jl;
     const T* Ub = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
-    const T* U = DIR == 0 ? Ub + (size_t)(r + ((ent_q[e] - 1 + ent_s[e]) & 1)) * 2 * plane
+    const T* U = DIR == 0 ? Ub + (size_t)(r + ((qeff(ent_q[e]) - 1 + ent_s[e]) & 1)) * 2 * plane
                           : Ub + (size_t)(r + 2) * 2 * plane;
     for (int task = wave; task < R * G; task += 16) {
       const int rg = task % R, kg = task / R;
@@ -721,7 +805,7 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
     __syncthreads();
     const long long e = jb.ent_off + jl;
     const T* Ub = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
-    const T* U = DIR == 0 ? Ub + (size_t)(r + ((ent_q[e] - 1 + ent_s[e]) & 1)) * 2 * plane
+    const T* U = DIR == 0 ? Ub + (size_t)(r + ((qeff(ent_q[e]) - 1 + ent_s[e]) & 1)) * 2 * plane
                           : Ub + (size_t)(r + 2) * 2 * plane;
     T a[2][2][RPL];  // [copy][re, im][row]
 #pragma unroll
@@ -1113,7 +1197,7 @@ static void timed(int kind, hipStream_t st, F&& launch) {
 
 // Norms and (q, s) choice of every slice, without forming the generators (statistics).
 __global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njobs, const double* u, int Nmax,
-                                                     const double* theta, int r, int qmax, int* q_out, int* s_out,
+                                                     const double* theta, int r, int qmax, int t12, int* q_out, int* s_out,
                                                      double* n_out) {
   __shared__ double red[256];
   __shared__ double ujs[17];
@@ -1122,7 +1206,7 @@ __global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njo
   const JobDev jb = jobs[J];
   if (j >= jb.N) {
     if (threadIdx.x == 0) {
-      q_out[(size_t)J * Nmax + j] = 0;
+      q_out[(size_t)J * Nmax + j] = -1;
       s_out[(size_t)J * Nmax + j] = 0;
       n_out[(size_t)J * Nmax + j] = 0.0;
     }
@@ -1157,7 +1241,7 @@ __global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njo
   if (threadIdx.x == 0) {
     const double nx = jb.dt * red[0];
     int q, s;
-    pick_degree(nx, theta, r, qmax, &q, &s);
+    pick_degree(nx, theta, r, qmax, t12, &q, &s);
     q_out[(size_t)J * Nmax + j] = q;
     s_out[(size_t)J * Nmax + j] = s;
     n_out[(size_t)J * Nmax + j] = nx;
@@ -1183,6 +1267,7 @@ static void upload_factorials() {
   double h[64];
   for (int i = 0; i < 64; ++i) h[i] = 1.0 / fact(i);
   QOC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(kInvFact), h, sizeof(h)));
+  QOC_HIP(hipMemcpyToSymbol(HIP_SYMBOL(kT12c), kT12, sizeof(kT12)));
   devices_done.push_back(dev);
 }
 
@@ -1280,7 +1365,7 @@ struct Driver {
     timed(PK_GENERATOR, st, [&] {
       hipLaunchKernelGGL(k_generator<T>, dim3(njobs * groups), dim3(256), 0, st, dj, njobs, u, seg_j0, L, groups, ws,
                          P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags, P->d_theta.as<double>(), P->r,
-                         P->qmax, P->smax, P->norm_bound);
+                         P->qmax, P->t12, P->smax, P->norm_bound);
     });
     const dim3 grid(P->grid_gemm);
     auto step = [&](int mode, int s) {
@@ -1290,6 +1375,10 @@ struct Driver {
       });
     };
     for (int i = 2; i <= P->r; ++i) step(STEP_POWER, i);
+    if (P->t12) {
+      step(STEP_T12, 1);
+      step(STEP_T12, 2);
+    }
     for (int t = 1; t <= P->qmax - 1; ++t) step(STEP_HORNER, t);
     for (int t = 1; t <= P->smax; ++t) step(STEP_SQUARE, t);
   }
@@ -1497,6 +1586,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   const double* theta = f64 ? kTaylorTheta64 : kTaylorTheta32;
   P->r = f64 ? 4 : 3;
   P->qmax = f64 ? 6 : 4;  // degrees up to 24 (FP64) / 12 (FP32)
+  P->t12 = f64 ? 0 : 1;
   const double unit = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
   double nb = 0.0;
   int max_mp = 0;
@@ -1517,18 +1607,17 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     // squarings the per-slice choice can pick for any norm in (0, nb]: the choice is
     // piecewise constant between the points theta_{qr} 2^s, so evaluate just above each
     auto choose_s = [&](double nx) {
-      int best_s = 0, best_cost = 1 << 30;
-      for (int q = P->qmax; q >= 1; --q) {
-        int sq = 0;
-        while (sq < 62 && nx > std::ldexp(theta[q * P->r], sq)) ++sq;
-        if ((q - 1) + sq < best_cost) { best_cost = (q - 1) + sq; best_s = sq; }
-      }
-      return best_s;
+      int q = 0, sq = 0;
+      pick_degree(nx, theta, P->r, P->qmax, P->t12, &q, &sq);
+      return sq;
     };
     int smax = choose_s(nb);
-    for (int q = 1; q <= P->qmax; ++q)
+    std::vector<int> degrees;
+    for (int q = 1; q <= P->qmax; ++q) degrees.push_back(q * P->r);
+    degrees.push_back(12);
+    for (int p : degrees)
       for (int sq = 0; sq < 62; ++sq) {
-        const double x = std::ldexp(theta[q * P->r], sq);
+        const double x = std::ldexp(theta[p], sq);
         if (x >= nb) break;
         smax = std::max(smax, choose_s(std::nextafter(x, 1e300)));
       }
@@ -1913,7 +2002,8 @@ qoc_status qoc_plan_slice_stats(qoc_plan P, const double* u_dev, int32_t* q_host
     const size_t cnt = (size_t)njobs * P->Nmax;
     DeviceBuffer q(cnt * 4), sbuf(cnt * 4), nrm(cnt * 8);
     hipLaunchKernelGGL(k_slice_norms, dim3(P->Nmax, std::min(njobs, 32768)), dim3(256), 0, st, P->d_jobs.as<JobDev>(), njobs, u_dev,
-                       P->Nmax, P->d_theta.as<double>(), P->r, P->qmax, q.as<int>(), sbuf.as<int>(), nrm.as<double>());
+                       P->Nmax, P->d_theta.as<double>(), P->r, P->qmax, P->t12, q.as<int>(), sbuf.as<int>(),
+                       nrm.as<double>());
     QOC_HIP(hipGetLastError());
     QOC_HIP(hipMemcpyAsync(q_host, q.ptr, cnt * 4, hipMemcpyDeviceToHost, st));
     QOC_HIP(hipMemcpyAsync(s_host, sbuf.ptr, cnt * 4, hipMemcpyDeviceToHost, st));

@@ -112,7 +112,11 @@ def test_symmetric_candidates(lib, prec):
                                            [torch.tensor(s[0], device="cuda") for s in states],
                                            [torch.tensor(s[1], device="cuda") for s in states])
     tf = 1e-12 if prec == "c128" else 1e-6
-    assert np.abs(out[:, 4].cpu().numpy() - 1.0).max() <= tf
+    # |psi_N|^2 - 1: FP64 keeps it at rounding level; an FP32 propagator is unitary to about
+    # 2e-7 per slice (the degree-12 evaluation), which can accumulate over the 500 slices
+    # (F and the gradient are normalised by |psi_N|^2 and are held to tf below)
+    tn = 1e-12 if prec == "c128" else 500 * 2e-7
+    assert np.abs(out[:, 4].cpu().numpy() - 1.0).max() <= tn
     for c in (0, 5):
         vals, gref = read_golden(f"sym128_C8_cand{c}_N{w.N}.txt")
         g = grads[c].cpu().numpy()

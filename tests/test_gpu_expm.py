@@ -59,3 +59,29 @@ def test_squarings_engage_for_large_norm(lib):
     for b, blk in enumerate(ob):
         Uo = og.propagator(blk["H0"], blk["Hk"], w.u[1], 3.0)
         assert np.abs(Us[b][1] - Uo).max() < 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [("c128", 2e-12), ("c64", 3e-6)])
+def test_both_taylor_evaluations_match(lib, prec, tol):
+    """Norms from 1e-3 to ~4 make an FP32 plan pick Paterson-Stockmeyer degrees (q >= 1) and
+    the four-product degree-12 evaluation (q = 0), with and without squarings (FP64 plans
+    use Paterson-Stockmeyer only); every propagator matches the oracle's
+    eigendecomposition."""
+    import torch
+    print(f"both Taylor evaluations {prec}", flush=True)
+    w = W.config1(N=4)
+    ob = oracle_blocks(6, w.h0, w.hk)
+    seen = set()
+    for dt in (0.0005, 0.005, 0.03, 0.08, 0.15, 0.3, 0.6, 1.2):
+        B, P, Us = _run(lib, 6, w.h0, w.hk, w.u, dt, prec)
+        qs, ss, _ = lib.slice_stats(P, torch.tensor(w.u, device="cuda"))
+        for b, blk in enumerate(ob):
+            for j in range(4):
+                seen.add((int(qs[b, j]) == 0, int(ss[b, j]) > 0))
+                Uo = og.propagator(blk["H0"], blk["Hk"], w.u[j], dt)
+                assert np.abs(Us[b][j] - Uo).max() < tol, (dt, blk["label"], j, int(qs[b, j]), int(ss[b, j]))
+    print(f"  (degree-12 scheme, squarings) combinations seen: {sorted(seen)}", flush=True)
+    if prec == "c64":
+        assert (True, False) in seen and (True, True) in seen and (False, False) in seen
+    else:
+        assert not any(t12 for t12, _ in seen) and (False, True) in seen and (False, False) in seen
