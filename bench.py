@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--cpu-slices", type=int, default=32, help="oracle sample size (slices, all blocks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dense-slices", type=int, default=16,
+                    help="slices of the same pulse timed on the dense 4096-dim space (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -168,6 +170,30 @@ def main():
     del P32
     torch.cuda.empty_cache()
 
+    dense = None
+    if args.dense_slices > 0:
+        # the same hot path on the dense 2^12 space (trivial group: one 4096-wide block)
+        Bd = q.Basis(12, "cyclic", 12)
+        Sd = q.System(Bd, w.h0, w.hk)
+        Nd = args.dense_slices
+        Pd = q.Plan(Sd, "c64", Nd, w.dt, 2.0)
+        ud = dev["u"][:Nd].contiguous()
+        d0, df = B.from_blocks(dev["psi0"]), B.from_blocks(dev["psif"])
+        q.fidelity_grad(Pd, ud, d0, df)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        od, gd = q.fidelity_grad(Pd, ud, d0, df)
+        e1.record()
+        torch.cuda.synchronize()
+        msd = e0.elapsed_time(e1)
+        dense = {"n": 12, "dim": 4096, "slices": Nd, "ms": msd, "ms_per_slice": msd / Nd,
+                 "blocks_ms_per_slice": ms32 / w.N, "symmetry_speedup": (msd / Nd) / (ms32 / w.N),
+                 "precision": "complex64 MFMA, same kernels, trivial group"}
+        print(f"[bench] dense 4096: {msd:.1f} ms for {Nd} slices", file=sys.stderr, flush=True)
+        del Pd, Sd, Bd
+        torch.cuda.empty_cache()
+
     gemm_ms, gemm_n = prof32["propagator_gemm"]
     achieved = flops32 * args.steps / (gemm_ms * 1e-3) / 1e12
     fp64 = cmp = None
@@ -220,6 +246,7 @@ def main():
         "fp64": fp64,
         "fp32_vs_fp64": cmp,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},
+        "dense_comparison": dense,
     }
     if not args.no_cpu_baseline:
         print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)

@@ -43,9 +43,9 @@
  *
  * Ownership.  Handles (qoc_basis, qoc_system, qoc_plan) are owned by the library
  * until the matching *_free call.  Every array argument is owned by the caller; the
- * library never frees it.  The hot-path calls (qoc_propagate, qoc_fidelity_grad,
- * qoc_fidelity_grad_batched) allocate nothing: their scratch memory is the caller's
- * workspace, sized by qoc_plan_workspace_size.
+ * library never frees it.  The hot-path calls (qoc_propagate, qoc_fidelity_grad, for
+ * single-problem and batched plans alike) allocate nothing: their scratch memory is the
+ * caller's workspace, sized by qoc_plan_workspace_size.
  *
  * Errors.  Every call returns a qoc_status; nothing throws or aborts across the ABI.
  * Argument and symmetry checks happen before any device work.  A device failure
@@ -216,7 +216,9 @@ qoc_status qoc_propagate(qoc_plan plan, const double* u_dev, void* U_out_dev, vo
  * co-operative sweep's hand-off between work-groups stalled and the sweep gave up, so
  * the outputs are invalid).
  * grad_dev (float64 [N][K]) receives dF/du[j,k] = 2 Re(conj(o) do/du[j,k]) /
- * (||psi_N||^2 ||psi_f||^2).  Fully asynchronous (no host synchronisation), so the
+ * (||psi_N||^2 ||psi_f||^2).  For a batched plan every array concatenates the
+ * problems in plan order (u and grad: N_p x K_p each; panels: D_p each) and out_dev
+ * holds 8 entries per problem.  Fully asynchronous (no host synchronisation), so the
  * call can be captured into a HIP graph. */
 qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi0_dev,
                              const void* psif_dev, double* out_dev, double* grad_dev,
@@ -227,9 +229,10 @@ qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi
  * enables recording: every kernel the hot-path calls enqueue is bracketed by events on
  * the launch stream.  qoc_profile_end synchronises on them, disables recording and
  * writes, per kernel kind, the summed duration in milliseconds and the launch count:
- * [0] generator + norm, [1] propagator GEMM (powers, Horner, squarings), [2] Horner
- * initial term, [3] forward sweep, [4] backward sweep, [5] objective, [6] gradient
- * GEMM, [7] gradient vector kernels, [8] gradient reduction, [9] other. */
+ * [0] generator + norm, [1] propagator GEMM (powers, Horner or degree-12 steps,
+ * squarings), [2] unused (the Horner start is formed inside the propagator GEMM),
+ * [3] forward sweep, [4] backward sweep, [5] objective, [6] gradient GEMM, [7] gradient
+ * vector kernels, [8] gradient reduction, [9] other. */
 qoc_status qoc_profile_begin(int max_launches);
 qoc_status qoc_profile_end(double* ms, int64_t* launches, int cap);
 
