@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--cpu-slices", type=int, default=32, help="oracle sample size (slices, all blocks)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sym-candidates", type=int, default=64,
+                    help="S_128 candidate pulses timed in one batched plan (0: skip)")
     ap.add_argument("--dense-slices", type=int, default=16,
                     help="slices of the same pulse timed on the dense 4096-dim space (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -194,6 +196,37 @@ def main():
         del Pd, Sd, Bd
         torch.cuda.empty_cache()
 
+    sym = None
+    if args.sym_candidates > 0:
+        # batched: C candidate pulses of the all-to-all S_128 register in one plan (65 blocks
+        # of 129..1 states, 500 slices each); every block of every candidate carries state
+        ws = W.config5(seed=0, C=args.sym_candidates)
+        uc = ws.notes["u_candidates"]
+        rs = ws.notes["rng"]
+        Bs = q.Basis(128, "symmetric")
+        Ss = q.System(Bs, ws.h0, ws.hk)
+        C = uc.shape[0]
+        Ps = q.Plan.batched([Ss] * C, "c64", [ws.N] * C, [ws.dt] * C, 1.0)
+        us = [torch.tensor(x, device="cuda") for x in uc]
+        p0 = [torch.tensor(W.gaussian_panel(rs, Bs.dim), device="cuda") for _ in range(C)]
+        pf = [torch.tensor(W.gaussian_panel(rs, Bs.dim), device="cuda") for _ in range(C)]
+        Ps.autotune(torch.cat([x.reshape(-1) for x in us]))
+        q.fidelity_grad_batched(Ps, us, p0, pf)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        outs, _ = q.fidelity_grad_batched(Ps, us, p0, pf, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        mss = e0.elapsed_time(e1)
+        units_s = C * len(Bs.sizes) * ws.N
+        sym = {"workload": "allpairs128_S128_candidates", "candidates": C, "slices": ws.N, "blocks": len(Bs.sizes),
+               "ms_per_step": mss, "value": units_s / (mss * 1e-3), "unit": "slices*blocks/s",
+               "gemm_variant": Ps.variant_name, "flags": int(outs[:, 7].abs().max().item())}
+        print(f"[bench] S_128 x {C}: {mss:.1f} ms", file=sys.stderr, flush=True)
+        del Ps, Ss, Bs
+        torch.cuda.empty_cache()
+
     gemm_ms, gemm_n = prof32["propagator_gemm"]
     achieved = flops32 * args.steps / (gemm_ms * 1e-3) / 1e12
     fp64 = cmp = None
@@ -247,6 +280,7 @@ def main():
         "fp32_vs_fp64": cmp,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},
         "dense_comparison": dense,
+        "batched_sym128": sym,
     }
     if not args.no_cpu_baseline:
         print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)
