@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sym-candidates", type=int, default=64,
                     help="S_128 candidate pulses timed in one batched plan (0: skip)")
+    ap.add_argument("--ring14-slices", type=int, default=64,
+                    help="slices of the 14-qubit staggered-control ring timed (0: skip)")
+    ap.add_argument("--batch-problems", type=int, default=8,
+                    help="problems of the 256-ring batched workload timed in one plan (0: skip)")
     ap.add_argument("--dense-slices", type=int, default=16,
                     help="slices of the same pulse timed on the dense 4096-dim space (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -110,6 +114,41 @@ def gemm_flops(q, plan, dev, sizes):
         prods = np.where(qs[b] == 0, 4 + ss[b], (r - 1) + (qs[b] - 1) + ss[b])
         tot += 8.0 * m ** 3 * float(prods.sum())
     return tot, qs, ss
+
+
+def gemm_flops_jobs(q, plan, u_flat, job_sizes):
+    """gemm_flops for any plan: job_sizes lists m per (problem, block) job in plan order."""
+    qs, ss, _ = q.slice_stats(plan, u_flat)
+    r = plan.info["taylor_step"]
+    tot = 0.0
+    for b, m in enumerate(job_sizes):
+        valid = qs[b] >= 0
+        prods = np.where(qs[b] == 0, 4 + ss[b], (r - 1) + (qs[b] - 1) + ss[b])
+        tot += 8.0 * m ** 3 * float(prods[valid].sum())
+    return tot
+
+
+def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, precision="c64"):
+    """Time `steps` calls of run() after `warmup`, with the library's per-kernel events;
+    returns throughput and the propagator GEMM's fraction of the MFMA peak."""
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    q.profile_begin(steps * 8192)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    prof = q.profile_end()
+    ms = e0.elapsed_time(e1) / steps
+    flops = gemm_flops_jobs(q, plan, u_flat, job_sizes)
+    gemm_ms, gemm_n = prof["propagator_gemm"]
+    tf = flops * steps / (gemm_ms * 1e-3) / 1e12
+    return {"ms_per_step": ms, "value": units / (ms * 1e-3), "unit": "slices*blocks/s",
+            "gemm_tflops": tf, "gemm_frac": tf / MFMA_PEAK[precision], "gemm_ms_per_step": gemm_ms / steps,
+            "gemm_variant": plan.variant_name, "steps": steps}
 
 
 def cpu_baseline(w, v0, vf, nslices):
@@ -210,21 +249,59 @@ def main():
         us = [torch.tensor(x, device="cuda") for x in uc]
         p0 = [torch.tensor(W.gaussian_panel(rs, Bs.dim), device="cuda") for _ in range(C)]
         pf = [torch.tensor(W.gaussian_panel(rs, Bs.dim), device="cuda") for _ in range(C)]
-        Ps.autotune(torch.cat([x.reshape(-1) for x in us]))
-        q.fidelity_grad_batched(Ps, us, p0, pf)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        outs, _ = q.fidelity_grad_batched(Ps, us, p0, pf, check=False)
-        e1.record()
-        torch.cuda.synchronize()
-        mss = e0.elapsed_time(e1)
-        units_s = C * len(Bs.sizes) * ws.N
-        sym = {"workload": "allpairs128_S128_candidates", "candidates": C, "slices": ws.N, "blocks": len(Bs.sizes),
-               "ms_per_step": mss, "value": units_s / (mss * 1e-3), "unit": "slices*blocks/s",
-               "gemm_variant": Ps.variant_name, "flags": int(outs[:, 7].abs().max().item())}
-        print(f"[bench] S_128 x {C}: {mss:.1f} ms", file=sys.stderr, flush=True)
+        uflat = torch.cat([x.reshape(-1) for x in us])
+        Ps.autotune(uflat)
+        sym = profiled_leg(q, torch, Ps, lambda: q.fidelity_grad_batched(Ps, us, p0, pf, check=False), 2, 1, uflat,
+                           list(Bs.sizes) * C, C * len(Bs.sizes) * ws.N)
+        sym.update({"workload": "allpairs128_S128_candidates", "candidates": C, "slices": ws.N,
+                    "blocks": len(Bs.sizes)})
+        print(f"[bench] S_128 x {C}: {sym}", file=sys.stderr, flush=True)
         del Ps, Ss, Bs
+        torch.cuda.empty_cache()
+
+    ring14 = None
+    if args.ring14_slices > 0:
+        # the 14-qubit ring with staggered controls under the two-site group (blocks 1300,
+        # 1044, 3 x 2340, 4 controls), first slices of its 4000-slice pulse, all blocks
+        w4 = W.config4(seed=0, variant="all")
+        r4 = w4.notes["rng"]
+        B4 = q.Basis(14, "dihedral", 2)
+        S4 = q.System(B4, w4.h0, w4.hk)
+        N4 = args.ring14_slices
+        P4 = q.Plan(S4, "c64", N4, w4.dt, 2.0)
+        u4 = torch.tensor(w4.u[:N4], device="cuda")
+        f4 = torch.tensor(W.gaussian_panel(r4, B4.dim), device="cuda")
+        z4 = torch.tensor(W.gaussian_panel(r4, B4.dim), device="cuda")
+        P4.autotune(u4)
+        ring14 = profiled_leg(q, torch, P4, lambda: q.fidelity_grad(P4, u4, z4, f4, check=False), 2, 1, u4,
+                              list(B4.sizes), len(B4.sizes) * N4)
+        ring14.update({"workload": "ring14_stagger_T2R_allblocks", "slices": N4, "blocks": list(B4.sizes)})
+        print(f"[bench] ring14: {ring14}", file=sys.stderr, flush=True)
+        del P4, S4, B4
+        torch.cuda.empty_cache()
+
+    batch = None
+    if args.batch_problems > 0:
+        # the first problems of the 256-ring batched workload (ragged n and N) in one plan
+        wl, rb = W.config3_list(seed=0)
+        wl = wl[:args.batch_problems]
+        states = [(W.gaussian_panel(rb, 2 ** x.n), W.gaussian_panel(rb, 2 ** x.n)) for x in wl]
+        bases = {x.n: q.Basis(x.n) for x in wl}
+        systems = [q.System(bases[x.n], x.h0, x.hk) for x in wl]
+        Pb = q.Plan.batched(systems, "c64", [x.N for x in wl], [x.dt for x in wl], 1.0)
+        ub = [torch.tensor(x.u, device="cuda") for x in wl]
+        p0 = [torch.tensor(st[0], device="cuda") for st in states]
+        pf = [torch.tensor(st[1], device="cuda") for st in states]
+        uflat = torch.cat([x.reshape(-1) for x in ub])
+        Pb.autotune(uflat)
+        sizes = [m for x in wl for m in bases[x.n].sizes]
+        units_b = sum(len(bases[x.n].sizes) * x.N for x in wl)
+        batch = profiled_leg(q, torch, Pb, lambda: q.fidelity_grad_batched(Pb, ub, p0, pf, check=False), 2, 1, uflat,
+                             sizes, units_b)
+        batch.update({"workload": "batch_rings_prefix", "problems": len(wl), "n": [x.n for x in wl],
+                      "slices": [x.N for x in wl]})
+        print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
+        del Pb, systems, bases
         torch.cuda.empty_cache()
 
     gemm_ms, gemm_n = prof32["propagator_gemm"]
@@ -281,6 +358,8 @@ def main():
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},
         "dense_comparison": dense,
         "batched_sym128": sym,
+        "ring14_stagger": ring14,
+        "batched_rings": batch,
     }
     if not args.no_cpu_baseline:
         print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)

@@ -183,7 +183,11 @@ qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
  * bytes per slice, [7] largest squaring count, [8] gradient chunk (slices), [9] GEMM
  * grid, [10] problems P, [11] (problem, block) jobs, [12] total controls (sum N_p K_p),
  * [13] total panel length (sum D_p), [14] total propagator entries, [15] GEMM tile
- * variant in use. */
+ * variant in use, [16] slices per Taylor-scratch chunk.
+ * Workspace: U and U^dag of every slice of a segment, Taylor scratch (Y..Y^r and two
+ * ping-pong buffers) of one chunk of slices, states, gradient slots.  When the budget holds
+ * everything, segment = chunk = N; otherwise the propagators of earlier segments are
+ * recomputed during the backward sweep. */
 qoc_status qoc_plan_info(qoc_plan plan, int64_t* info, int cap);
 
 /* GEMM tile variants.  The propagator and panel GEMMs are compiled for 3 work-group tile

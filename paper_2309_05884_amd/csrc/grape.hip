@@ -45,7 +45,8 @@ struct JobDev {
   const void* hT;        // working-precision operator planes of this block
   long long ent_off;     // first entry (slice of a segment) of this job
   long long item_off;    // first propagator GEMM item of this job
-  long long ebuf_off;    // propagator buffers (elements of T)
+  long long ubuf_off;    // propagators of the segment: per slice U and U^dag (elements of T)
+  long long sbuf_off;    // Taylor scratch of one chunk: per slice Y..Y^r and two ping-pong buffers
   long long psi_off;     // forward states (elements of T), planes of mp x (N+1)d
   long long lam_off;     // costates (elements of T), planes of mp x N d
   long long gbase_off;   // gradient slots (elements of T)
@@ -110,6 +111,7 @@ struct qoc_plan_s {
   int t12 = 0;  // slices may use the four-product degree-12 evaluation
   double norm_bound = 0.0;
   int seg_len = 0, nseg = 0;
+  int echunk = 0;  // slices whose Taylor scratch is resident at once (the segment is formed in chunks)
   int R = 1, Q = 1;
   int chunk = 0;  // slices per gradient chunk
   int nslots = 0;
@@ -192,17 +194,20 @@ constexpr int GEN_SG = 8;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs, const double* u, int seg_j0,
-                                                   int seg_len, int groups, char* ws, size_t off_T, int* ent_s,
+                                                   int seg_len, int c0, int clen, int groups, char* ws, size_t off_T,
+                                                   int* ent_s,
                                                    int* ent_q, double* ent_norm, int* flags, const double* theta,
-                                                   int r, int qmax, int t12, int smax, double norm_bound) {
+                                                   int r, int qmax, int t12, int smax, double norm_bound,
+                                                   int skip_n) {
   __shared__ double red[GEN_SG][256];
   __shared__ double us[GEN_SG][17];
   __shared__ double scale[GEN_SG];
   const int J = blockIdx.x / groups, g = blockIdx.x % groups;
   if (J >= njobs) return;
   const JobDev jb = jobs[J];
-  const int jl0 = g * GEN_SG;
-  const int len = job_len(jb, seg_j0, seg_len);
+  if (jb.N <= skip_n) return;  // recompute pass: this job's propagators are still resident
+  const int jl0 = c0 + g * GEN_SG;  // slices jl0 .. of the segment; chunk slots jl0 - c0 ..
+  const int len = min(job_len(jb, seg_j0, seg_len), c0 + clen);
   if (jl0 >= len) return;
   const int ns = min(GEN_SG, len - jl0);
   const int m = jb.m, mp = jb.mp, K = jb.K;
@@ -272,8 +277,8 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
     scale[t] = ldexp(jb.dt, -best_s);
   }
   __syncthreads();
-  const size_t ent_stride = (size_t)(r + 3) * 2 * plane;
-  T* Y0 = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl0 * ent_stride;
+  const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
+  T* Y0 = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)(jl0 - c0) * ent_stride;
   for (size_t idx = threadIdx.x; idx < plane; idx += blockDim.x) {
     const int rr = (int)(idx % mp), c = (int)(idx / mp);
     double hr[GEN_SG], hi[GEN_SG];
@@ -307,14 +312,15 @@ enum { STEP_POWER = 0, STEP_HORNER = 1, STEP_SQUARE = 2, STEP_T12 = 3 };
 __constant__ double kInvFact[64];
 __constant__ double kT12c[4][4];  // the degree-12 scheme's coefficients (taylor12.h)
 
-// One product step over every entry of the segment (persistent, XCD-grouped items).
-// Buffers of an entry: 0 = Y, i-1 = Y^i (i <= r), r and r+1 = ping-pong T, r+2 = U^dag.
-// The last power step also forms the Horner start T0; the last product of an entry
-// writes U^dag for the backward sweep.
+// One product step over every entry of a chunk of the segment (persistent, XCD-grouped
+// items).  Taylor scratch of an entry (one slot per chunk slice): 0 = Y, i-1 = Y^i (i <= r),
+// r and r+1 = ping-pong T.  The last power step also forms the Horner start T0; the last
+// product of an entry writes U and U^dag into the segment's propagator storage.
 template <typename Shape>
 __global__ void __launch_bounds__(256, Shape::WAVES)
     k_expm_step(const JobDev* jobs, int njobs, long long total_items, char* ws, size_t off_T, const int* ent_s,
-                const int* ent_q, int mode, int step, int r, int seg_j0, int seg_len) {
+                const int* ent_q, int mode, int step, int r, int seg_j0, int seg_len, int c0, int clen,
+                int skip_n) {
   typedef typename Shape::T T;
   __shared__ TileLds<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
@@ -323,8 +329,9 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     const JobDev jb = jobs[J];
     const long long local = it - jb.item_off;
     const int t2 = jb.tiles_m * jb.tiles_n;
-    const int jl = (int)(local / t2);
-    if (jl >= job_len(jb, seg_j0, seg_len)) continue;
+    const int jc = (int)(local / t2);  // slot in the chunk
+    const int jl = c0 + jc;            // slice of the segment
+    if (jc >= clen || jl >= job_len(jb, seg_j0, seg_len) || jb.N <= skip_n) continue;
     const int tile = (int)(local % t2);
     const int ti = tile / jb.tiles_n, tj = tile % jb.tiles_n;
     const long long e = jb.ent_off + jl;
@@ -353,7 +360,8 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
                           (mode == STEP_T12 && step == 2 && se == 0);
     const int mp = jb.mp;
     const size_t plane = (size_t)mp * mp;
-    T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
+    T* base = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)jc * (size_t)(r + 2) * 2 * plane;
+    T* ubase = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * 4 * plane;  // U, then U^dag
     TileOperands<T> op;
     op.A = base + (size_t)ia * 2 * plane;
     op.a_ps = plane;
@@ -368,7 +376,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     op.col0 = tj * Shape::BN;
     TileAcc<Shape> acc;
     tile_mma<Shape>(op, lds, acc);
-    T* C = base + (size_t)ic * 2 * plane;
+    T* C = final_op ? ubase : base + (size_t)ic * 2 * plane;  // the last product of an entry is U
     double coef[8];
     double ctop = 0.0;
     const int lh = qe - 1 - step;
@@ -467,11 +475,11 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             if (row0 + v * AccRowStep<T>::value == col && col < jb.m) tr[v] += (T)coef[0];
-          T* T0 = base + (size_t)r * 2 * plane + at;
+          T* T0 = (init_final ? ubase : base + (size_t)r * 2 * plane) + at;
           acc_store<T>(T0, tr);
           acc_store<T>(T0 + plane, ti);
           if (init_final) {
-            T* D = base + (size_t)(r + 2) * 2 * plane;
+            T* D = ubase + 2 * plane;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               T* dr = D + (size_t)col + (size_t)(row0 + v * AccRowStep<T>::value) * mp;
@@ -482,7 +490,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
         }
         if (final_op) {
           // conjugate transpose for the backward sweep: Udag[col][row] = conj(U[row][col])
-          T* D = base + (size_t)(r + 2) * 2 * plane;
+          T* D = ubase + 2 * plane;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             T* dr = D + (size_t)col + (size_t)(row0 + v * AccRowStep<T>::value) * mp;
@@ -495,10 +503,9 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
 }
 
 template <typename T>
-__device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int jl, int r, int s, int q) {
+__device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int jl, int dagger) {
   const size_t plane = (size_t)jb.mp * jb.mp;
-  const T* base = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
-  return base + (size_t)(r + ((qeff(q) - 1 + s) & 1)) * 2 * plane;
+  return tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * 4 * plane + (dagger ? 2 * plane : 0);
 }
 
 // ===================================================================== state set-up
@@ -595,10 +602,7 @@ __device__ void sweep_solo(const JobDev& jb, char* ws, size_t off_T, const int* 
   const size_t plane = (size_t)mp * mp;
   for (int it = 0; it < len; ++it) {
     const int jl = DIR == 0 ? it : len - 1 - it;
-    const long long e = jb.ent_off + jl;
-    const T* Ub = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
-    const T* U = DIR == 0 ? Ub + (size_t)(r + ((qeff(ent_q[e]) - 1 + ent_s[e]) & 1)) * 2 * plane
-                          : Ub + (size_t)(r + 2) * 2 * plane;
+    const T* U = entry_U<T>(jb, ws, off_T, jl, DIR);
     for (int task = wave; task < R * G; task += 16) {
       const int rg = task % R, kg = task / R;
       const int i0 = rg * RG + RPL * lane;  // rows i0 .. i0 + RPL - 1 (mp is a multiple of 16)
@@ -803,10 +807,7 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
       sim[idx] = __hip_atomic_load(S + g + ps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    const long long e = jb.ent_off + jl;
-    const T* Ub = tplane<T>(ws, off_T, jb.ebuf_off) + (size_t)jl * (size_t)(r + 3) * 2 * plane;
-    const T* U = DIR == 0 ? Ub + (size_t)(r + ((qeff(ent_q[e]) - 1 + ent_s[e]) & 1)) * 2 * plane
-                          : Ub + (size_t)(r + 2) * 2 * plane;
+    const T* U = entry_U<T>(jb, ws, off_T, jl, DIR);
     T a[2][2][RPL];  // [copy][re, im][row]
 #pragma unroll
     for (int c = 0; c < 2; ++c)
@@ -1133,7 +1134,7 @@ __global__ void k_export_U(const JobDev* jobs, int njobs, char* ws, size_t off_T
   const JobDev jb = jobs[J];
   const int jl = (int)(e - jb.ent_off);
   if (jl >= job_len(jb, seg_j0, seg_len)) continue;
-  const T* U = entry_U<T>(jb, ws, off_T, jl, r, ent_s[e], ent_q[e]);
+  const T* U = entry_U<T>(jb, ws, off_T, jl, 0);
   const size_t plane = (size_t)jb.mp * jb.mp;
   double2* dst = out + jb.uout_off + (size_t)(seg_j0 + jl) * jb.m * jb.m;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < (long long)jb.m * jb.m;
@@ -1277,7 +1278,7 @@ static void upload_factorials() {
 // work.  Every shape accumulates each output element over k in the same order, so the
 // choice does not change any result bit.
 typedef void (*ExpmLaunch)(dim3, hipStream_t, const JobDev*, int, long long, char*, size_t, const int*,
-                           const int*, int, int, int, int, int);
+                           const int*, int, int, int, int, int, int, int, int);
 typedef void (*PanelLaunch)(dim3, hipStream_t, const JobDev*, const PanelDesc*, int, long long, char*, size_t, int,
                             int);
 struct GemmVariant {
@@ -1289,8 +1290,10 @@ struct GemmVariant {
 };
 template <typename C>
 void launch_expm(dim3 g, hipStream_t st, const JobDev* j, int nj, long long items, char* ws, size_t offT,
-                 const int* es, const int* eq, int mode, int step, int r, int j0, int len) {
-  hipLaunchKernelGGL(k_expm_step<C>, g, dim3(256), 0, st, j, nj, items, ws, offT, es, eq, mode, step, r, j0, len);
+                 const int* es, const int* eq, int mode, int step, int r, int j0, int len, int c0, int clen,
+                 int skip_n) {
+  hipLaunchKernelGGL(k_expm_step<C>, g, dim3(256), 0, st, j, nj, items, ws, offT, es, eq, mode, step, r, j0, len, c0,
+                     clen, skip_n);
 }
 template <typename C>
 void launch_panel(dim3 g, hipStream_t st, const JobDev* j, const PanelDesc* d, int nd, long long items, char* ws,
@@ -1328,7 +1331,7 @@ static void apply_variant(qoc_plan_s* P, int v) {
     j.tiles_m = (j.mp + g.bm - 1) / g.bm;
     j.tiles_n = (j.mp + g.bn - 1) / g.bn;
     j.item_off = items;
-    items += (long long)P->seg_len * j.tiles_m * j.tiles_n;
+    items += (long long)P->echunk * j.tiles_m * j.tiles_n;
   }
   P->expm_items = items;
   long long pitems = 0;
@@ -1356,31 +1359,39 @@ struct Driver {
   }
   static size_t sweep_lds(const qoc_plan_s* P) { return P->sweep_lds_elems * sizeof(T); }
 
-  static void expm_segment(qoc_plan_s* P, char* ws, const double* u, int seg_j0, hipStream_t st) {
+  // Propagators of the segment starting at seg_j0.  skip_n > 0 (backward recompute): jobs
+  // with N <= skip_n are left alone -- their last segment is this one, whose propagators
+  // no later segment overwrote.
+  static void expm_segment(qoc_plan_s* P, char* ws, const double* u, int seg_j0, hipStream_t st, int skip_n = 0) {
     const int njobs = (int)P->jobs.size();
     const JobDev* dj = P->d_jobs.as<JobDev>();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     const int L = P->seg_len;
-    const int groups = (L + GEN_SG - 1) / GEN_SG;
-    timed(PK_GENERATOR, st, [&] {
-      hipLaunchKernelGGL(k_generator<T>, dim3(njobs * groups), dim3(256), 0, st, dj, njobs, u, seg_j0, L, groups, ws,
-                         P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags, P->d_theta.as<double>(), P->r,
-                         P->qmax, P->t12, P->smax, P->norm_bound);
-    });
     const dim3 grid(P->grid_gemm);
-    auto step = [&](int mode, int s) {
-      timed(PK_EXPM_GEMM, st, [&] {
-        gemm_variant(P).expm(grid, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), mode, s,
-                             P->r, seg_j0, L);
+    // the segment in chunks of echunk slices: Taylor scratch for one chunk, U and U^dag of
+    // every slice kept
+    for (int c0 = 0; c0 < L; c0 += P->echunk) {
+      const int clen = std::min(P->echunk, L - c0);
+      const int groups = (clen + GEN_SG - 1) / GEN_SG;
+      timed(PK_GENERATOR, st, [&] {
+        hipLaunchKernelGGL(k_generator<T>, dim3(njobs * groups), dim3(256), 0, st, dj, njobs, u, seg_j0, L, c0, clen,
+                           groups, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags,
+                           P->d_theta.as<double>(), P->r, P->qmax, P->t12, P->smax, P->norm_bound, skip_n);
       });
-    };
-    for (int i = 2; i <= P->r; ++i) step(STEP_POWER, i);
-    if (P->t12) {
-      step(STEP_T12, 1);
-      step(STEP_T12, 2);
+      auto step = [&](int mode, int s) {
+        timed(PK_EXPM_GEMM, st, [&] {
+          gemm_variant(P).expm(grid, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), mode, s,
+                               P->r, seg_j0, L, c0, clen, skip_n);
+        });
+      };
+      for (int i = 2; i <= P->r; ++i) step(STEP_POWER, i);
+      if (P->t12) {
+        step(STEP_T12, 1);
+        step(STEP_T12, 2);
+      }
+      for (int t = 1; t <= P->qmax - 1; ++t) step(STEP_HORNER, t);
+      for (int t = 1; t <= P->smax; ++t) step(STEP_SQUARE, t);
     }
-    for (int t = 1; t <= P->qmax - 1; ++t) step(STEP_HORNER, t);
-    for (int t = 1; t <= P->smax; ++t) step(STEP_SQUARE, t);
   }
 
   static void sweep(qoc_plan_s* P, char* ws, int dir, int seg_j0, hipStream_t st) {
@@ -1475,7 +1486,7 @@ struct Driver {
       objective(st);
       // backward: the last segment's propagators are resident; earlier ones are recomputed
       for (int sg = P->nseg - 1; sg >= 0; --sg) {
-        if (sg != P->nseg - 1) expm_segment(P, ws, u, sg * P->seg_len, st);
+        if (sg != P->nseg - 1) expm_segment(P, ws, u, sg * P->seg_len, st, (sg + 1) * P->seg_len);
         sweep(P, ws, 1, sg * P->seg_len, st);
       }
     }
@@ -1655,11 +1666,13 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   const int K = P->Kmax;
   const int nslots = K + 4 + P->R * P->Q;
   P->nslots = nslots;
-  // per-slice propagator bytes and fixed state bytes
-  size_t per_slice = 0, fixed = 0;
+  // per-slice bytes: U and U^dag kept for the segment, Taylor scratch (Y..Y^r, two
+  // ping-pong buffers) for one chunk; fixed state bytes
+  size_t per_slice = 0, per_scratch = 0, fixed = 0;
   for (auto& pr : probs)
     for (auto& b : pr.sys->blocks) {
-      per_slice += (size_t)(P->r + 3) * 2 * b.mp * b.mp * P->elem;
+      per_slice += (size_t)2 * 2 * b.mp * b.mp * P->elem;
+      per_scratch += (size_t)(P->r + 2) * 2 * b.mp * b.mp * P->elem;
       fixed += (size_t)2 * b.mp * ((size_t)(pr.N + 1) * b.d + (size_t)pr.N * b.d) * P->elem;
     }
   int chunk = std::min(P->Nmax, 2048);
@@ -1679,13 +1692,25 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     QOC_HIP(hipMemGetInfo(&free_b, &total_b));
     budget = std::min<size_t>((size_t)200 << 30, free_b / 4 * 3);
   }
-  while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice > budget) chunk /= 2;
+  while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice + per_scratch > budget) chunk /= 2;
   P->chunk = chunk;
   const size_t need = fixed + grad_bytes(chunk);
   const size_t avail = budget > need ? budget - need : 0;
-  const long long seg = (long long)(avail / std::max<size_t>(per_slice, 1));
-  QOC_REQUIRE(seg >= 1, QOC_ERR_OUT_OF_MEMORY, "workspace budget below one slice of propagators");
-  P->seg_len = (int)std::min<long long>(seg, P->Nmax);
+  if ((size_t)P->Nmax * (per_slice + per_scratch) <= avail) {
+    // everything resident: one segment formed in one pass
+    P->seg_len = P->echunk = P->Nmax;
+  } else {
+    // Taylor scratch for a chunk of slices (at most an eighth of the budget, at least 8 slices
+    // when they fit), U and U^dag of as many slices as the rest holds
+    long long ec = (long long)(avail / 8 / std::max<size_t>(per_scratch, 1));
+    ec = std::max<long long>(1, std::min<long long>(ec, P->Nmax));
+    if (ec < 8) ec = std::max<long long>(1, std::min<long long>(8, (long long)(avail / 2 / std::max<size_t>(per_scratch, 1))));
+    const size_t left = avail > (size_t)ec * per_scratch ? avail - (size_t)ec * per_scratch : 0;
+    const long long seg = (long long)(left / std::max<size_t>(per_slice, 1));
+    QOC_REQUIRE(seg >= 1, QOC_ERR_OUT_OF_MEMORY, "workspace budget below one slice of propagators");
+    P->seg_len = (int)std::min<long long>(seg, P->Nmax);
+    P->echunk = (int)std::min<long long>(ec, P->seg_len);
+  }
   P->nseg = (P->Nmax + P->seg_len - 1) / P->seg_len;
   // layout
   size_t off = 0;
@@ -1725,8 +1750,10 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       j.u_off = u_off;
       j.ent_off = ent_off;
       ent_off += P->seg_len;
-      j.ebuf_off = tel;
-      tel += (long long)P->seg_len * (P->r + 3) * 2 * b.mp * b.mp;
+      j.ubuf_off = tel;
+      tel += (long long)P->seg_len * 2 * 2 * b.mp * b.mp;
+      j.sbuf_off = tel;
+      tel += (long long)P->echunk * (P->r + 2) * 2 * b.mp * b.mp;
       j.psi_off = tel;
       tel += 2LL * b.mp * (pr.N + 1) * b.d;
       j.lam_off = tel;
@@ -1862,11 +1889,11 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
   return guarded([&] {
     QOC_REQUIRE(P && info, QOC_ERR_INVALID_ARG, "null argument");
     size_t per_slice = 0;
-    for (auto& j : P->jobs) per_slice += (size_t)(P->r + 3) * 2 * j.mp * j.mp * P->elem;
-    int64_t v[16] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
+    for (auto& j : P->jobs) per_slice += (size_t)(2 + P->r + 2) * 2 * j.mp * j.mp * P->elem;
+    int64_t v[17] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
                      P->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U,
-                     P->variant};
-    for (int i = 0; i < cap && i < 16; ++i) info[i] = v[i];
+                     P->variant, P->echunk};
+    for (int i = 0; i < cap && i < 17; ++i) info[i] = v[i];
   });
 }
 

@@ -168,3 +168,26 @@ def test_autograd_function(lib):
     (3.0 * F).backward()
     assert abs(F.item() - ref["F"]) <= 1e-12
     assert np.abs(u.grad.cpu().numpy() - 3.0 * ref["grad"]).max() <= 3e-12
+
+
+def test_workspace_budgets_bitwise_equal(lib):
+    """Smaller workspaces form the propagators in chunks of slices (Taylor scratch for one
+    chunk) and then in segments recomputed during the backward sweep; every budget gives
+    the same objective and gradient bit for bit."""
+    print("workspace budgets", flush=True)
+    w = W.config1(N=48)
+    ob = oracle_blocks(6, w.h0, w.hk)
+    psi0, psif = all_states(ob, np.random.default_rng(6))
+    out1, g1, P1 = _device(lib, 6, "dihedral", 1, w.h0, w.hk, w.u, w.dt, psi0, psif, "c64")
+    assert P1.info["segments"] == 1 and P1.info["expm_chunk"] == 48
+    full = P1.workspace_bytes
+    seen = set()
+    for frac in (0.9, 0.75, 0.5, 0.35):
+        o, g, P = _device(lib, 6, "dihedral", 1, w.h0, w.hk, w.u, w.dt, psi0, psif, "c64", max_ws=int(full * frac))
+        info = P.info
+        seen.add((info["segments"] > 1, info["expm_chunk"] < info["segment"]))
+        print(f"  budget {frac}: segments {info['segments']} segment {info['segment']} chunk {info['expm_chunk']}",
+              flush=True)
+        assert np.array_equal(o[:6], out1[:6]) and np.array_equal(g, g1)
+    assert (False, True) in seen or (True, True) in seen
+    assert any(seg for seg, _ in seen)
