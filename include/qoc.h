@@ -154,7 +154,7 @@ qoc_status qoc_system_block(qoc_system system, int block, int op, void* dst_dev,
 /* Execution plan for N slices of length dt at a precision (QOC_C128 or QOC_C64).
  * The plan fixes the Taylor degree menu, the Frechet-series length and the number of
  * propagator slices held at once (segment) so that the workspace stays within
- * max_workspace_bytes (0: three quarters of the free device memory, at most 200 GiB);
+ * max_workspace_bytes (0: 85 % of the free device memory, at most 240 GiB);
  * when the whole pulse does not fit, propagators are recomputed segment by segment in
  * the backward sweep.  u_bound > 0 bounds |u[j,k]| for every
  * call that uses this plan; the plan uses it, with the exact 1-norms of the blocks, to

@@ -87,6 +87,36 @@ __device__ inline int find_job_by_item(const JobDev* jobs, int n, long long key)
   }
   return lo;
 }
+// Item -> job for a work-group that walks increasing item indices: the cached job is
+// reused while the item stays in its range, then a short forward scan (bounded) or a
+// binary search finds the next one.
+struct ItemCursor {
+  int J = -1;
+  long long beg = 0, end = -1;
+};
+template <typename Rec>
+__device__ inline int cursor_find(const Rec* recs, int n, long long key, ItemCursor& c) {
+  if (key >= c.beg && key < c.end) return c.J;
+  int J = -1;
+  if (c.J >= 0 && key >= c.end) {
+    J = c.J;
+    for (int k = 0; k < 8 && J + 1 < n && recs[J + 1].item_off <= key; ++k) ++J;
+    if (J + 1 < n && recs[J + 1].item_off <= key) J = -1;  // still short: search
+  }
+  if (J < 0) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (recs[mid].item_off <= key) lo = mid; else hi = mid - 1;
+    }
+    J = lo;
+  }
+  c.J = J;
+  c.beg = recs[J].item_off;
+  c.end = J + 1 < n ? recs[J + 1].item_off : (1LL << 62);
+  return J;
+}
+
 __device__ inline int find_desc(const PanelDesc* d, int n, long long key) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -324,8 +354,9 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   typedef typename Shape::T T;
   __shared__ TileLds<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
+  ItemCursor cur;
   for (long long it = rg.begin; it < rg.end; it += rg.step) {
-    const int J = find_job_by_item(jobs, njobs, it);
+    const int J = cursor_find(jobs, njobs, it, cur);
     const JobDev jb = jobs[J];
     const long long local = it - jb.item_off;
     const int t2 = jb.tiles_m * jb.tiles_n;
@@ -946,8 +977,9 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   typedef typename Shape::T T;
   __shared__ TileLds<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
+  ItemCursor cur;
   for (long long it = rg.begin; it < rg.end; it += rg.step) {
-    const PanelDesc pd = descs[find_desc(descs, ndesc, it)];
+    const PanelDesc pd = descs[cursor_find(descs, ndesc, it, cur)];
     const JobDev jb = jobs[pd.job];
     if (jb.N - j0 <= 0) continue;
     const long long local = it - pd.item_off;
@@ -1306,7 +1338,7 @@ GemmVariant make_variant(const char* name) {
 }
 static const GemmVariant kVariants32[] = {
     make_variant<TileShape<float, 4, 2, 2>>("fp32 128x64"),
-    make_variant<TileShape<float, 2, 2, 4>>("fp32 64x64"),
+    make_variant<TileShape<float, 2, 2, 3>>("fp32 64x64"),
     make_variant<TileShape<float, 2, 4, 2>>("fp32 64x128"),
 };
 static const GemmVariant kVariants64[] = {
@@ -1687,10 +1719,11 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   };
   size_t budget = max_ws;
   if (!budget) {
-    // default: three quarters of the free device memory, at most 200 GiB
+    // default: 85 % of the free device memory (the rest for the caller's tensors and the
+    // allocator), at most 240 GiB of the 288 GB part
     size_t free_b = 0, total_b = 0;
     QOC_HIP(hipMemGetInfo(&free_b, &total_b));
-    budget = std::min<size_t>((size_t)200 << 30, free_b / 4 * 3);
+    budget = std::min<size_t>((size_t)240 << 30, free_b / 20 * 17);
   }
   while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice + per_scratch > budget) chunk /= 2;
   P->chunk = chunk;
