@@ -148,7 +148,8 @@ def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, p
     tf = flops * steps / (gemm_ms * 1e-3) / 1e12
     return {"ms_per_step": ms, "value": units / (ms * 1e-3), "unit": "slices*blocks/s",
             "gemm_tflops": tf, "gemm_frac": tf / MFMA_PEAK[precision], "gemm_ms_per_step": gemm_ms / steps,
-            "gemm_variant": plan.variant_name, "steps": steps}
+            "gemm_variant": plan.variant_name, "steps": steps, "segments": plan.info["segments"],
+            "workspace_gb": plan.workspace_bytes / 1e9}
 
 
 def cpu_baseline(w, v0, vf, nslices):

@@ -346,6 +346,15 @@ __constant__ double kT12c[4][4];  // the degree-12 scheme's coefficients (taylor
 // items).  Taylor scratch of an entry (one slot per chunk slice): 0 = Y, i-1 = Y^i (i <= r),
 // r and r+1 = ping-pong T.  The last power step also forms the Horner start T0; the last
 // product of an entry writes U and U^dag into the segment's propagator storage.
+// One tile product of the propagator formation: operands, where the result goes.
+template <typename T>
+struct ExpmItem {
+  TileOperands<T> op;
+  T* base;   // Taylor scratch of the entry's chunk slot
+  T* ubase;  // U, then U^dag, of the entry
+  int m, ic, se, qe;
+};
+
 template <typename Shape>
 __global__ void __launch_bounds__(256, Shape::WAVES)
     k_expm_step(const JobDev* jobs, int njobs, long long total_items, char* ws, size_t off_T, const int* ent_s,
@@ -355,14 +364,15 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   __shared__ TileLds<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
   ItemCursor cur;
-  for (long long it = rg.begin; it < rg.end; it += rg.step) {
+  // item -> tile product; false when this step has nothing to do for the item
+  auto prep = [&](long long it, ExpmItem<T>& x) -> bool {
     const int J = cursor_find(jobs, njobs, it, cur);
     const JobDev jb = jobs[J];
     const long long local = it - jb.item_off;
     const int t2 = jb.tiles_m * jb.tiles_n;
     const int jc = (int)(local / t2);  // slot in the chunk
     const int jl = c0 + jc;            // slice of the segment
-    if (jc >= clen || jl >= job_len(jb, seg_j0, seg_len) || jb.N <= skip_n) continue;
+    if (jc >= clen || jl >= job_len(jb, seg_j0, seg_len) || jb.N <= skip_n) return false;
     const int tile = (int)(local % t2);
     const int ti = tile / jb.tiles_n, tj = tile % jb.tiles_n;
     const long long e = jb.ent_off + jl;
@@ -370,43 +380,64 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     const bool t12 = qe == 0;  // the four-product degree-12 scheme
     int ia, ib, ic;
     if (mode == STEP_POWER) {
-      if (t12 && step > 3) continue;  // it needs Y^2 and Y^3 only
+      if (t12 && step > 3) return false;  // it needs Y^2 and Y^3 only
       ia = step - 2; ib = 0; ic = step - 1;
     } else if (mode == STEP_T12) {
-      if (!t12) continue;
+      if (!t12) return false;
       if (step == 1) {  // B4 B4 (B4 in buffer r) -> A6 = B3 + B4^2 in buffer r+1
         ia = r; ib = r; ic = r + 1;
       } else {          // (B2 + A6) A6 + B1 -> T12 in buffer r
         ia = 1; ib = r + 1; ic = r;
       }
     } else if (mode == STEP_HORNER) {
-      if (qe - 1 < step) continue;
+      if (qe - 1 < step) return false;
       ia = r + ((step - 1) & 1); ib = r - 1; ic = r + (step & 1);
     } else {
-      if (se < step) continue;
+      if (se < step) return false;
       const int h = qeff(qe) - 1 + step - 1;
       ia = r + (h & 1); ib = ia; ic = r + ((h + 1) & 1);
     }
-    const bool final_op = (mode == STEP_SQUARE && step == se) || (mode == STEP_HORNER && se == 0 && step == qe - 1) ||
-                          (mode == STEP_T12 && step == 2 && se == 0);
     const int mp = jb.mp;
     const size_t plane = (size_t)mp * mp;
-    T* base = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)jc * (size_t)(r + 2) * 2 * plane;
-    T* ubase = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * 4 * plane;  // U, then U^dag
-    TileOperands<T> op;
-    op.A = base + (size_t)ia * 2 * plane;
-    op.a_ps = plane;
-    op.lda = mp;
-    op.B = base + (size_t)ib * 2 * plane;
-    op.b_ps = plane;
-    op.ldb = mp;
-    op.M = mp;
-    op.N = mp;
-    op.K = mp;
-    op.row0 = ti * Shape::BM;
-    op.col0 = tj * Shape::BN;
+    x.base = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)jc * (size_t)(r + 2) * 2 * plane;
+    x.ubase = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * 4 * plane;
+    x.m = jb.m;
+    x.ic = ic;
+    x.se = se;
+    x.qe = qe;
+    x.op.A = x.base + (size_t)ia * 2 * plane;
+    x.op.a_ps = plane;
+    x.op.lda = mp;
+    x.op.B = x.base + (size_t)ib * 2 * plane;
+    x.op.b_ps = plane;
+    x.op.ldb = mp;
+    x.op.M = mp;
+    x.op.N = mp;
+    x.op.K = mp;
+    x.op.row0 = ti * Shape::BM;
+    x.op.col0 = tj * Shape::BN;
+    return true;
+  };
+  long long it = rg.begin;
+  ExpmItem<T> x;
+  while (it < rg.end && !prep(it, x)) it += rg.step;
+  if (it >= rg.end) return;
+  int buf = tile_start<Shape>(x.op, lds);
+  for (;;) {
+    long long nx = it + rg.step;
+    ExpmItem<T> xn = x;
+    while (nx < rg.end && !prep(nx, xn)) nx += rg.step;
+    const bool more = nx < rg.end;
     TileAcc<Shape> acc;
-    tile_mma<Shape>(op, lds, acc);
+    tile_mma<Shape>(x.op, lds, acc, buf, more, xn.op);
+    const int se = x.se, qe = x.qe, ic = x.ic;
+    const bool t12 = qe == 0;
+    const bool final_op = (mode == STEP_SQUARE && step == se) || (mode == STEP_HORNER && se == 0 && step == qe - 1) ||
+                          (mode == STEP_T12 && step == 2 && se == 0);
+    const int mp = x.op.M;
+    const size_t plane = (size_t)mp * mp;
+    T* const base = x.base;
+    T* const ubase = x.ubase;
     T* C = final_op ? ubase : base + (size_t)ic * 2 * plane;  // the last product of an entry is U
     double coef[8];
     double ctop = 0.0;
@@ -425,8 +456,8 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     for (int ri = 0; ri < Shape::SM; ++ri)
 #pragma unroll
       for (int ci = 0; ci < Shape::SN; ++ci) {
-        const int rbase = acc_row_base<Shape>(op.row0, ri);
-        const int col = acc_col<Shape>(op.col0, ci);
+        const int rbase = acc_row_base<Shape>(x.op.row0, ri);
+        const int col = acc_col<Shape>(x.op.col0, ci);
         if (rbase >= mp || col >= mp) continue;
         const int row0 = rbase + acc_row_off<T>(0);  // this lane's first accumulator row
         const size_t at = (size_t)row0 + (size_t)col * mp;
@@ -439,7 +470,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (row0 + v * AccRowStep<T>::value == col && col < jb.m) vr[v] += (T)coef[0];
+            if (row0 + v * AccRowStep<T>::value == col && col < x.m) vr[v] += (T)coef[0];
         }
         if (mode == STEP_T12) {
           // sum_k c[k] P_k at this tile for P_0 = I, P_1..3 = Y, Y^2, Y^3 (buffers 0..2)
@@ -457,7 +488,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              if (row0 + v * AccRowStep<T>::value == col && col < jb.m) cr[v] += (T)kT12c[i][0];
+              if (row0 + v * AccRowStep<T>::value == col && col < x.m) cr[v] += (T)kT12c[i][0];
           };
           if (step == 1) {
             // A6 = B3 + B4^2 (the product); buffer 0 <- B1, buffer 1 <- B2 + A6 (neither is an
@@ -490,7 +521,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
           bi += (T)kT12c[3][1] * y1i + (T)kT12c[3][2] * y2i;
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (row0 + v * AccRowStep<T>::value == col && col < jb.m) br[v] += (T)kT12c[3][0];
+            if (row0 + v * AccRowStep<T>::value == col && col < x.m) br[v] += (T)kT12c[3][0];
           T* B4 = base + (size_t)r * 2 * plane + at;
           acc_store<T>(B4, br);
           acc_store<T>(B4 + plane, bi);
@@ -505,7 +536,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            if (row0 + v * AccRowStep<T>::value == col && col < jb.m) tr[v] += (T)coef[0];
+            if (row0 + v * AccRowStep<T>::value == col && col < x.m) tr[v] += (T)coef[0];
           T* T0 = (init_final ? ubase : base + (size_t)r * 2 * plane) + at;
           acc_store<T>(T0, tr);
           acc_store<T>(T0 + plane, ti);
@@ -530,6 +561,9 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
           }
         }
       }
+    if (!more) break;
+    it = nx;
+    x = xn;
   }
 }
 
@@ -978,42 +1012,63 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   __shared__ TileLds<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
   ItemCursor cur;
-  for (long long it = rg.begin; it < rg.end; it += rg.step) {
+  struct Item {
+    TileOperands<T> op;
+    T* C;
+    long long vplane;
+  };
+  auto prep = [&](long long it, Item& x) -> bool {
     const PanelDesc pd = descs[cursor_find(descs, ndesc, it, cur)];
     const JobDev jb = jobs[pd.job];
-    if (jb.N - j0 <= 0) continue;
+    if (jb.N - j0 <= 0) return false;
     const long long local = it - pd.item_off;
     const int ti = (int)(local / pd.tiles_n), tj = (int)(local % pd.tiles_n);
     const int mp = jb.mp;
     const size_t hplane = (size_t)mp * mp;
     const size_t vplane = (size_t)mp * jb.cc;
     T* g = tplane<T>(ws, off_T, jb.gbase_off);
-    TileOperands<T> op;
-    op.A = reinterpret_cast<const T*>(jb.hT) + (size_t)(2 * pd.op) * hplane;
-    op.a_ps = hplane;
-    op.lda = mp;
-    op.B = g + (size_t)vslot * jb.gslot;
-    op.b_ps = vplane;
-    op.ldb = mp;
-    op.M = mp;
-    op.N = jb.cc;
-    op.K = mp;
-    op.row0 = ti * Shape::BM;
-    op.col0 = tj * Shape::BN;
+    x.op.A = reinterpret_cast<const T*>(jb.hT) + (size_t)(2 * pd.op) * hplane;
+    x.op.a_ps = hplane;
+    x.op.lda = mp;
+    x.op.B = g + (size_t)vslot * jb.gslot;
+    x.op.b_ps = vplane;
+    x.op.ldb = mp;
+    x.op.M = mp;
+    x.op.N = jb.cc;
+    x.op.K = mp;
+    x.op.row0 = ti * Shape::BM;
+    x.op.col0 = tj * Shape::BN;
+    x.C = g + (size_t)pd.op * jb.gslot;
+    x.vplane = (long long)vplane;
+    return true;
+  };
+  long long it = rg.begin;
+  Item x;
+  while (it < rg.end && !prep(it, x)) it += rg.step;
+  if (it >= rg.end) return;
+  int buf = tile_start<Shape>(x.op, lds);
+  for (;;) {
+    long long nx = it + rg.step;
+    Item xn = x;
+    while (nx < rg.end && !prep(nx, xn)) nx += rg.step;
+    const bool more = nx < rg.end;
     TileAcc<Shape> acc;
-    tile_mma<Shape>(op, lds, acc);
-    T* C = g + (size_t)pd.op * jb.gslot;
+    tile_mma<Shape>(x.op, lds, acc, buf, more, xn.op);
+    const int mp = x.op.M;
 #pragma unroll
     for (int ri = 0; ri < Shape::SM; ++ri)
 #pragma unroll
       for (int ci = 0; ci < Shape::SN; ++ci) {
-        const int rbase = acc_row_base<Shape>(op.row0, ri);
-        const int col = acc_col<Shape>(op.col0, ci);
-        if (rbase >= mp || col >= jb.cc) continue;
-        T* cr = C + (size_t)(rbase + acc_row_off<T>(0)) + (size_t)col * mp;
+        const int rbase = acc_row_base<Shape>(x.op.row0, ri);
+        const int col = acc_col<Shape>(x.op.col0, ci);
+        if (rbase >= mp || col >= x.op.N) continue;
+        T* cr = x.C + (size_t)(rbase + acc_row_off<T>(0)) + (size_t)col * mp;
         acc_store<T>(cr, acc.re[ri][ci]);
-        acc_store<T>(cr + vplane, acc.im[ri][ci]);
+        acc_store<T>(cr + x.vplane, acc.im[ri][ci]);
       }
+    if (!more) break;
+    it = nx;
+    x = xn;
   }
 }
 

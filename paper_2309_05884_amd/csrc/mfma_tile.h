@@ -9,7 +9,8 @@
 // The complex product takes three real MFMAs per sub-tile and k step instead of four
 // (Gauss's 3M form, see TileAcc).
 // Operands are staged through double-buffered LDS in 16-deep slabs; the next slab is
-// loaded into registers while the current one feeds the MFMAs.
+// loaded into registers while the current one feeds the MFMAs, and in a persistent loop
+// the next tile's first slab is loaded during the current tile's last one.
 // MFMA 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16].  The
 // accumulator element v of lane l is D[4*(l/16)+v][l%16] for the FP32 instruction and
 // D[(l/16)+4v][l%16] for the FP64 one (measured on gfx950).
@@ -41,7 +42,7 @@ struct TileShape {
 constexpr int TBK = 16;
 
 template <typename C>
-struct TileLds {
+struct alignas(16) TileLds {
   typename C::T a[2][2][TBK][C::BM + C::PAD];  // [buffer][plane][k][row]
   typename C::T b[2][2][TBK][C::BN + C::PAD];  // [buffer][plane][k][col]
 };
@@ -69,14 +70,18 @@ struct TileOperands {
   int row0, col0;
 };
 
-// 16-byte vectors of the working type (4 floats, 2 doubles).
+// 16-byte vectors of the working type (4 floats, 2 doubles): clang vector types, so that
+// a copy is a vector load or store (HIP's float4 is a struct, copied with memcpy, which
+// keeps an array of them out of registers).
+typedef double d2v __attribute__((ext_vector_type(2)));
 template <typename T> struct Vec16;
-template <> struct Vec16<float> { typedef float4 type; static constexpr int n = 4; };
-template <> struct Vec16<double> { typedef double2 type; static constexpr int n = 2; };
+template <> struct Vec16<float> { typedef f4v type; static constexpr int n = 4; };
+template <> struct Vec16<double> { typedef d2v type; static constexpr int n = 2; };
 
 // Slab loads, 16-byte vectors, thread t handles plane t/128 (tt = t%128):
 //  A (BM x 16): vectors f = tt + 128 i (i < NA): k = f / CV, rows (f % CV) * VEC .. with
-//    CV = BM/VEC vectors per k row; a wave's stores to LDS cover whole k rows;
+//    CV = BM/VEC vectors per k row; a wave's stores to LDS cover whole k rows.  CV divides
+//    128, so a lane's NA vectors share their rows and sit 128/CV k rows apart;
 //  B (16 x BN): column tt/TPC, KB = BN/8 consecutive k from (tt%TPC)*KB (NB vectors).
 template <typename C>
 struct SlabShape {
@@ -86,7 +91,7 @@ struct SlabShape {
   static constexpr int KB = C::BN / 8;
   static constexpr int NB = KB / VEC;
   static constexpr int TPC = TBK / KB;
-  static_assert(NA >= 1 && NB >= 1 && TBK % KB == 0, "slab mapping");
+  static_assert(NA >= 1 && NB >= 1 && TBK % KB == 0 && 128 % CV == 0, "slab mapping");
 };
 
 template <typename C>
@@ -95,26 +100,59 @@ struct SlabRegs {
   typename Vec16<typename C::T>::type b[SlabShape<C>::NB];
 };
 
+// This lane's source addresses for the next slab of one tile product.  Rows of A at or
+// beyond M and columns of B at or beyond N (edge tiles) are read from the last valid
+// row / column instead: those values reach only outputs that are never stored, and every
+// load stays inside the operands, with no branch in the K loop.
 template <typename C>
-__device__ inline void tile_fetch(const TileOperands<typename C::T>& op, int k0, SlabRegs<C>& r) {
-  typedef typename C::T T;
-  typedef typename Vec16<T>::type V;
+struct SlabSrc {
+  const typename C::T* a;  // A vector 0; vector i is 128/CV k rows further
+  const typename C::T* b;  // first B vector; the NB vectors are consecutive
+};
+
+template <typename C>
+__device__ inline SlabSrc<C> slab_src(const TileOperands<typename C::T>& op) {
   typedef SlabShape<C> S;
   const int t = threadIdx.x;
   const int plane = t >> 7, tt = t & 127;
+  int row = op.row0 + (tt % S::CV) * S::VEC;
+  row = row < op.M ? row : op.M - S::VEC;
+  int col = op.col0 + tt / S::TPC;
+  col = col < op.N ? col : op.N - 1;
+  SlabSrc<C> p;
+  p.a = op.A + plane * op.a_ps + (long long)(tt / S::CV) * op.lda + row;
+  p.b = op.B + plane * op.b_ps + (long long)col * op.ldb + (tt % S::TPC) * S::KB;
+  return p;
+}
+
+// Operands live in global memory; saying so keeps the loads off the flat path (whose
+// completion the LDS wait counter would then also track).
+template <typename V>
+__device__ inline V ld_global(const void* p) {
+  return *(const __attribute__((address_space(1))) V*)p;
+}
+
+template <typename C>
+__device__ inline void slab_fetch(const SlabSrc<C>& p, int lda, SlabRegs<C>& r) {
+  typedef typename Vec16<typename C::T>::type V;
+  typedef SlabShape<C> S;
+  const long long ai = (long long)(128 / S::CV) * lda;
 #pragma unroll
-  for (int i = 0; i < S::NA; ++i) {
-    const int f = tt + 128 * i;
-    const int kk = f / S::CV, row = op.row0 + (f % S::CV) * S::VEC;
-    if (row < op.M)
-      r.a[i] = *reinterpret_cast<const V*>(op.A + plane * op.a_ps + (long long)(k0 + kk) * op.lda + row);
-    else
-      r.a[i] = V{};
-  }
-  const int col = op.col0 + tt / S::TPC, kk = (tt % S::TPC) * S::KB;
-  const V* p = reinterpret_cast<const V*>(op.B + plane * op.b_ps + (long long)col * op.ldb + k0 + kk);
+  for (int i = 0; i < S::NA; ++i) r.a[i] = ld_global<V>(p.a + i * ai);
 #pragma unroll
-  for (int i = 0; i < S::NB; ++i) r.b[i] = col < op.N ? p[i] : V{};
+  for (int i = 0; i < S::NB; ++i) r.b[i] = ld_global<V>(p.b + i * S::VEC);
+}
+
+template <typename C>
+__device__ inline void slab_advance(SlabSrc<C>& p, int lda) {
+  p.a += (long long)TBK * lda;
+  p.b += TBK;
+}
+
+// Load slab 0 of a tile product into r.
+template <typename C>
+__device__ inline void tile_prime(const TileOperands<typename C::T>& op, SlabRegs<C>& r) {
+  slab_fetch<C>(slab_src<C>(op), op.lda, r);
 }
 
 template <typename C>
@@ -126,7 +164,7 @@ __device__ inline void tile_stash(TileLds<C>& s, int buf, const SlabRegs<C>& r) 
 #pragma unroll
   for (int i = 0; i < S::NA; ++i) {
     const int f = tt + 128 * i;
-    *reinterpret_cast<V*>(&s.a[buf][plane][f / S::CV][(f % S::CV) * S::VEC]) = r.a[i];
+    *static_cast<V*>(__builtin_assume_aligned(&s.a[buf][plane][f / S::CV][(f % S::CV) * S::VEC], 16)) = r.a[i];
   }
   const int jj = tt / S::TPC, kk = (tt % S::TPC) * S::KB;
 #pragma unroll
@@ -209,28 +247,60 @@ __device__ inline void tile_slab(const TileLds<C>& s, int buf, const bool (&rv)[
   }
 }
 
+// K loop of one tile.  On entry LDS buffer b0 holds slab 0 of op (stored by the previous
+// tile's loop, or by tile_start for the first tile).  While the last slab's MFMAs run,
+// slab 0 of `next` (when has_next) is loaded and then stored into the other buffer, so
+// the next tile's first loads overlap this tile's tail and epilogue.  Returns the buffer
+// that holds it.  Every slab ends with a barrier, after the LDS reads of the slab and the
+// store of the following one.
 template <typename C, bool FULL>
-__device__ inline void tile_kloop(const TileOperands<typename C::T>& op, TileLds<C>& s, const bool (&rv)[C::SM],
-                                  const bool (&cv)[C::SN], TileAcc<C>& acc) {
+__device__ inline int tile_kloop(const TileOperands<typename C::T>& op, TileLds<C>& s, const bool (&rv)[C::SM],
+                                 const bool (&cv)[C::SN], TileAcc<C>& acc, int b0, bool has_next,
+                                 const TileOperands<typename C::T>& next) {
   SlabRegs<C> r;
+  SlabSrc<C> p = slab_src<C>(op);
+  slab_advance<C>(p, op.lda);
   const int nk = op.K / TBK;
-  tile_fetch(op, 0, r);
-  __syncthreads();  // the previous tile's readers are done with both buffers
-  tile_stash(s, 0, r);
-  __syncthreads();
+  // after the last slab: the next tile's slab 0, or (no next tile) this tile's again,
+  // stored into the idle buffer and never read
+  const SlabSrc<C> pn = slab_src<C>(has_next ? next : op);
+  const int ldn = has_next ? next.lda : op.lda;
   for (int kb = 0; kb < nk; ++kb) {
-    const int buf = kb & 1;
-    if (kb + 1 < nk) tile_fetch(op, (kb + 1) * TBK, r);
+    const int buf = (b0 + kb) & 1;
+    const bool last = kb + 1 == nk;
+    SlabSrc<C> q;
+    q.a = last ? pn.a : p.a;
+    q.b = last ? pn.b : p.b;
+    slab_fetch<C>(q, last ? ldn : op.lda, r);
+    slab_advance<C>(p, op.lda);
+    __builtin_amdgcn_sched_barrier(0);  // issue the loads before the slab's MFMAs
     tile_slab<C, FULL>(s, buf, rv, cv, acc);
-    if (kb + 1 < nk) tile_stash(s, buf ^ 1, r);
+    // the store waits for this slab's loads: keep it after the MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+    tile_stash(s, buf ^ 1, r);
     __syncthreads();
   }
+  return (b0 + nk) & 1;
+}
+
+// Load the first tile's slab 0 into LDS buffer 0 (later tiles find theirs where the
+// previous tile_mma call left it).
+template <typename C>
+__device__ inline int tile_start(const TileOperands<typename C::T>& op, TileLds<C>& s) {
+  SlabRegs<C> r;
+  tile_prime<C>(op, r);
+  tile_stash(s, 0, r);
+  __syncthreads();
+  return 0;
 }
 
 // Full K loop for one output tile; acc is zeroed here.  Interior tiles run a copy of the
-// loop without the per-sub-tile range checks; every check is wave-uniform.
+// loop without the per-sub-tile range checks; every check is wave-uniform.  `buf` is the
+// LDS buffer holding slab 0 of op on entry and of next on return (see tile_kloop).  A
+// persistent loop calls tile_start for its first tile only.
 template <typename C>
-__device__ inline void tile_mma(const TileOperands<typename C::T>& op, TileLds<C>& s, TileAcc<C>& acc) {
+__device__ inline void tile_mma(const TileOperands<typename C::T>& op, TileLds<C>& s, TileAcc<C>& acc, int& buf,
+                                bool has_next, const TileOperands<typename C::T>& next) {
   typedef typename C::T T;
   constexpr int SM = C::SM, SN = C::SN;
 #pragma unroll
@@ -249,9 +319,9 @@ __device__ inline void tile_mma(const TileOperands<typename C::T>& op, TileLds<C
 #pragma unroll
   for (int q = 0; q < SN; ++q) cv[q] = op.col0 + wc * (C::BN / 2) + q * 16 < op.N;
   if (op.row0 + C::BM <= op.M && op.col0 + C::BN <= op.N)
-    tile_kloop<C, true>(op, s, rv, cv, acc);
+    buf = tile_kloop<C, true>(op, s, rv, cv, acc, buf, has_next, next);
   else
-    tile_kloop<C, false>(op, s, rv, cv, acc);
+    buf = tile_kloop<C, false>(op, s, rv, cv, acc, buf, has_next, next);
 #pragma unroll
   for (int ri = 0; ri < SM; ++ri)
 #pragma unroll
