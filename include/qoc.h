@@ -186,8 +186,9 @@ qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
  * variant in use, [16] slices per Taylor-scratch chunk.
  * Workspace: U and U^dag of every slice of a segment, Taylor scratch (Y..Y^r and two
  * ping-pong buffers) of one chunk of slices, states, gradient slots.  When the budget holds
- * everything, segment = chunk = N; otherwise the propagators of earlier segments are
- * recomputed during the backward sweep. */
+ * everything, segment = chunk = N; when it holds every propagator and the scratch of at
+ * least 8 slices, segment = N and the chunk is what the rest holds; otherwise the
+ * propagators of earlier segments are recomputed during the backward sweep. */
 qoc_status qoc_plan_info(qoc_plan plan, int64_t* info, int cap);
 
 /* GEMM tile variants.  The propagator and panel GEMMs are compiled for 3 work-group tile

@@ -1781,12 +1781,29 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     budget = std::min<size_t>((size_t)240 << 30, free_b / 20 * 17);
   }
   while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice + per_scratch > budget) chunk /= 2;
+  // a smaller gradient chunk (down to 128 slices) is preferred when it lets every
+  // propagator stay resident (no recompute in the backward sweep)
+  const long long ec_min = std::min(P->Nmax, 8);
+  auto resident = [&](int ch) {
+    return fixed + grad_bytes(ch) + (size_t)P->Nmax * per_slice + (size_t)ec_min * per_scratch <= budget;
+  };
+  if (!resident(chunk)) {
+    int ch = chunk;
+    while (ch > 128 && !resident(ch)) ch /= 2;
+    if (resident(ch)) chunk = ch;
+  }
   P->chunk = chunk;
   const size_t need = fixed + grad_bytes(chunk);
   const size_t avail = budget > need ? budget - need : 0;
   if ((size_t)P->Nmax * (per_slice + per_scratch) <= avail) {
     // everything resident: one segment formed in one pass
     P->seg_len = P->echunk = P->Nmax;
+  } else if ((size_t)P->Nmax * per_slice + (size_t)ec_min * per_scratch <= avail) {
+    // every propagator resident (no recompute in the backward sweep); the rest holds the
+    // Taylor scratch of as many slices as fit
+    P->seg_len = P->Nmax;
+    P->echunk = (int)std::min<long long>(P->Nmax, (long long)((avail - (size_t)P->Nmax * per_slice) /
+                                                              std::max<size_t>(per_scratch, 1)));
   } else {
     // Taylor scratch for a chunk of slices (at most an eighth of the budget, at least 8 slices
     // when they fit), U and U^dag of as many slices as the rest holds

@@ -82,7 +82,8 @@ template <> struct Vec16<double> { typedef d2v type; static constexpr int n = 2;
 //  A (BM x 16): vectors f = tt + 128 i (i < NA): k = f / CV, rows (f % CV) * VEC .. with
 //    CV = BM/VEC vectors per k row; a wave's stores to LDS cover whole k rows.  CV divides
 //    128, so a lane's NA vectors share their rows and sit 128/CV k rows apart;
-//  B (16 x BN): column tt/TPC, KB = BN/8 consecutive k from (tt%TPC)*KB (NB vectors).
+//  B (16 x BN): column tt%BN, KB = BN/8 consecutive k from (tt/BN)*KB (NB vectors); the
+//    lanes of a wave store to consecutive columns of one k row (no LDS bank conflicts).
 template <typename C>
 struct SlabShape {
   static constexpr int VEC = Vec16<typename C::T>::n;
@@ -117,11 +118,11 @@ __device__ inline SlabSrc<C> slab_src(const TileOperands<typename C::T>& op) {
   const int plane = t >> 7, tt = t & 127;
   int row = op.row0 + (tt % S::CV) * S::VEC;
   row = row < op.M ? row : op.M - S::VEC;
-  int col = op.col0 + tt / S::TPC;
+  int col = op.col0 + tt % C::BN;
   col = col < op.N ? col : op.N - 1;
   SlabSrc<C> p;
   p.a = op.A + plane * op.a_ps + (long long)(tt / S::CV) * op.lda + row;
-  p.b = op.B + plane * op.b_ps + (long long)col * op.ldb + (tt % S::TPC) * S::KB;
+  p.b = op.B + plane * op.b_ps + (long long)col * op.ldb + (tt / C::BN) * S::KB;
   return p;
 }
 
@@ -166,7 +167,7 @@ __device__ inline void tile_stash(TileLds<C>& s, int buf, const SlabRegs<C>& r) 
     const int f = tt + 128 * i;
     *static_cast<V*>(__builtin_assume_aligned(&s.a[buf][plane][f / S::CV][(f % S::CV) * S::VEC], 16)) = r.a[i];
   }
-  const int jj = tt / S::TPC, kk = (tt % S::TPC) * S::KB;
+  const int jj = tt % C::BN, kk = (tt / C::BN) * S::KB;
 #pragma unroll
   for (int i = 0; i < S::NB; ++i)
 #pragma unroll
@@ -220,11 +221,10 @@ __device__ inline void step_mfma(const StepOps<C>& o, const bool (&rv)[C::SM], c
 }
 
 // One 16-deep slab: the operands of step k+1 are read from LDS while the MFMAs of step k
-// run (two register stages); on interior tiles the scheduler is told to interleave them.
+// run (two register stages).
 template <typename C, bool FULL>
 __device__ inline void tile_slab(const TileLds<C>& s, int buf, const bool (&rv)[C::SM], const bool (&cv)[C::SN],
                                  TileAcc<C>& acc) {
-  constexpr int SM = C::SM, SN = C::SN;
   const int lane = threadIdx.x & 63, wave = tile_wave();
   const int r0 = (wave >> 1) * (C::BM / 2) + (lane & 15);
   const int c0 = (wave & 1) * (C::BN / 2) + (lane & 15);
@@ -235,15 +235,6 @@ __device__ inline void tile_slab(const TileLds<C>& s, int buf, const bool (&rv)[
   for (int k4 = 0; k4 < TBK / 4; ++k4) {
     if (k4 + 1 < TBK / 4) step_load(s, buf, (k4 + 1) * 4 + kl, r0, c0, o[(k4 + 1) & 1]);
     step_mfma<C, FULL>(o[k4 & 1], rv, cv, acc);
-    if (FULL && k4 + 1 < TBK / 4) {
-      // ds reads of the next step (merged in pairs) spread over this step's MFMAs
-      constexpr int NRD = SM + SN, NMF = 3 * SM * SN / NRD;
-#pragma unroll
-      for (int g = 0; g < NRD; ++g) {
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, NMF, 0);
-      }
-    }
   }
 }
 
