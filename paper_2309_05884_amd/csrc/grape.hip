@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
                 const int* ent_q, int mode, int step, int r, int seg_j0, int seg_len, int c0, int clen,
                 int skip_n) {
   typedef typename Shape::T T;
-  __shared__ TileLds<Shape> lds;
+  __shared__ TileSmem<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
   ItemCursor cur;
   // item -> tile product; false when this step has nothing to do for the item
@@ -422,14 +422,14 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   ExpmItem<T> x;
   while (it < rg.end && !prep(it, x)) it += rg.step;
   if (it >= rg.end) return;
-  int buf = tile_start<Shape>(x.op, lds);
+  TilePipe pipe = tile_start<Shape>(x.op, lds);
   for (;;) {
     long long nx = it + rg.step;
     ExpmItem<T> xn = x;
     while (nx < rg.end && !prep(nx, xn)) nx += rg.step;
     const bool more = nx < rg.end;
     TileAcc<Shape> acc;
-    tile_mma<Shape>(x.op, lds, acc, buf, more, xn.op);
+    tile_mma<Shape>(x.op, lds, acc, pipe, more, xn.op);
     const int se = x.se, qe = x.qe, ic = x.ic;
     const bool t12 = qe == 0;
     const bool final_op = (mode == STEP_SQUARE && step == se) || (mode == STEP_HORNER && se == 0 && step == qe - 1) ||
@@ -1009,7 +1009,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     k_panel_gemm(const JobDev* jobs, const PanelDesc* descs, int ndesc, long long total_items, char* ws,
                  size_t off_T, int vslot, int j0) {
   typedef typename Shape::T T;
-  __shared__ TileLds<Shape> lds;
+  __shared__ TileSmem<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
   ItemCursor cur;
   struct Item {
@@ -1046,14 +1046,14 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   Item x;
   while (it < rg.end && !prep(it, x)) it += rg.step;
   if (it >= rg.end) return;
-  int buf = tile_start<Shape>(x.op, lds);
+  TilePipe pipe = tile_start<Shape>(x.op, lds);
   for (;;) {
     long long nx = it + rg.step;
     Item xn = x;
     while (nx < rg.end && !prep(nx, xn)) nx += rg.step;
     const bool more = nx < rg.end;
     TileAcc<Shape> acc;
-    tile_mma<Shape>(x.op, lds, acc, buf, more, xn.op);
+    tile_mma<Shape>(x.op, lds, acc, pipe, more, xn.op);
     const int mp = x.op.M;
 #pragma unroll
     for (int ri = 0; ri < Shape::SM; ++ri)

@@ -274,54 +274,292 @@ __device__ inline int tile_kloop(const TileOperands<typename C::T>& op, TileLds<
   return (b0 + nk) & 1;
 }
 
-// Load the first tile's slab 0 into LDS buffer 0 (later tiles find theirs where the
-// previous tile_mma call left it).
+// State of a work-group's tile pipeline between tile products: the LDS stage that holds
+// (or will hold) slab 0 of the next product, and how many of its slabs are already being
+// loaded.
+struct TilePipe {
+  int stage, pre;
+};
+
+// Register-staged path (FP64): load the first tile's slab 0 into LDS buffer 0 (later
+// tiles find theirs where the previous tile_mma call left it).
 template <typename C>
-__device__ inline int tile_start(const TileOperands<typename C::T>& op, TileLds<C>& s) {
+__device__ inline TilePipe tile_start(const TileOperands<typename C::T>& op, TileLds<C>& s) {
   SlabRegs<C> r;
   tile_prime<C>(op, r);
   tile_stash(s, 0, r);
   __syncthreads();
-  return 0;
+  return TilePipe{0, 1};
 }
 
-// Full K loop for one output tile; acc is zeroed here.  Interior tiles run a copy of the
-// loop without the per-sub-tile range checks; every check is wave-uniform.  `buf` is the
-// LDS buffer holding slab 0 of op on entry and of next on return (see tile_kloop).  A
-// persistent loop calls tile_start for its first tile only.
 template <typename C>
-__device__ inline void tile_mma(const TileOperands<typename C::T>& op, TileLds<C>& s, TileAcc<C>& acc, int& buf,
-                                bool has_next, const TileOperands<typename C::T>& next) {
-  typedef typename C::T T;
-  constexpr int SM = C::SM, SN = C::SN;
+__device__ inline void tile_zero(TileAcc<C>& acc) {
 #pragma unroll
-  for (int ri = 0; ri < SM; ++ri)
+  for (int ri = 0; ri < C::SM; ++ri)
 #pragma unroll
-    for (int ci = 0; ci < SN; ++ci) {
-      acc.re[ri][ci] = typename Vec4<T>::type{0, 0, 0, 0};
-      acc.im[ri][ci] = typename Vec4<T>::type{0, 0, 0, 0};
-      acc.x[ri][ci] = typename Vec4<T>::type{0, 0, 0, 0};
+    for (int ci = 0; ci < C::SN; ++ci) {
+      acc.re[ri][ci] = typename Vec4<typename C::T>::type{0, 0, 0, 0};
+      acc.im[ri][ci] = typename Vec4<typename C::T>::type{0, 0, 0, 0};
+      acc.x[ri][ci] = typename Vec4<typename C::T>::type{0, 0, 0, 0};
     }
+}
+
+// Sub-tile validity of this wave (wave-uniform) and whether the whole tile is interior.
+template <typename C>
+__device__ inline bool tile_ranges(const TileOperands<typename C::T>& op, bool (&rv)[C::SM], bool (&cv)[C::SN]) {
   const int wave = tile_wave();
   const int wr = wave >> 1, wc = wave & 1;
-  bool rv[SM], cv[SN];
 #pragma unroll
-  for (int q = 0; q < SM; ++q) rv[q] = op.row0 + wr * (C::BM / 2) + q * 16 < op.M;
+  for (int q = 0; q < C::SM; ++q) rv[q] = op.row0 + wr * (C::BM / 2) + q * 16 < op.M;
 #pragma unroll
-  for (int q = 0; q < SN; ++q) cv[q] = op.col0 + wc * (C::BN / 2) + q * 16 < op.N;
-  if (op.row0 + C::BM <= op.M && op.col0 + C::BN <= op.N)
-    buf = tile_kloop<C, true>(op, s, rv, cv, acc, buf, has_next, next);
-  else
-    buf = tile_kloop<C, false>(op, s, rv, cv, acc, buf, has_next, next);
+  for (int q = 0; q < C::SN; ++q) cv[q] = op.col0 + wc * (C::BN / 2) + q * 16 < op.N;
+  return op.row0 + C::BM <= op.M && op.col0 + C::BN <= op.N;
+}
+
+// Gauss's 3M combination of the three real products (see TileAcc).
+template <typename C>
+__device__ inline void tile_finish(TileAcc<C>& acc) {
 #pragma unroll
-  for (int ri = 0; ri < SM; ++ri)
+  for (int ri = 0; ri < C::SM; ++ri)
 #pragma unroll
-    for (int ci = 0; ci < SN; ++ci) {
-      const typename Vec4<T>::type p1 = acc.re[ri][ci];
+    for (int ci = 0; ci < C::SN; ++ci) {
+      const typename Vec4<typename C::T>::type p1 = acc.re[ri][ci];
       acc.re[ri][ci] = p1 - acc.x[ri][ci];
       acc.im[ri][ci] = acc.im[ri][ci] - p1 - acc.x[ri][ci];
     }
 }
+
+// Full K loop for one output tile; acc is zeroed here.  Interior tiles run a copy of the
+// loop without the per-sub-tile range checks; every check is wave-uniform.  The pipe
+// state carries slab 0 of op in and of next out (see tile_kloop).  A persistent loop
+// calls tile_start for its first tile only.
+template <typename C>
+__device__ inline void tile_mma(const TileOperands<typename C::T>& op, TileLds<C>& s, TileAcc<C>& acc,
+                                TilePipe& tp, bool has_next, const TileOperands<typename C::T>& next) {
+  tile_zero<C>(acc);
+  bool rv[C::SM], cv[C::SN];
+  if (tile_ranges<C>(op, rv, cv))
+    tp.stage = tile_kloop<C, true>(op, s, rv, cv, acc, tp.stage, has_next, next);
+  else
+    tp.stage = tile_kloop<C, false>(op, s, rv, cv, acc, tp.stage, has_next, next);
+  tile_finish<C>(acc);
+}
+
+// ---------------------------------------------------------------------------------------
+// FP32 path: operands go from global memory straight into LDS (global_load_lds_dwordx4,
+// no registers, no LDS store instructions) through a ring of DLS stages, with slab kb + 2
+// in flight while slab kb is multiplied.  A wave's load instruction writes 64 lanes x 16
+// bytes contiguously, so each stage is laid out in 1 KB chunks:
+//  A [plane][k][BM]: a chunk holds KPC whole k rows; the row quads of k row k are stored
+//    XOR-permuted by ((k / 4) % 4) * 4 (bits 2-3 of the quad index);
+//  B [plane][col][16 k]: a chunk holds 16 columns; the k quads of column c are stored
+//    XOR-permuted by (c / 2) % 4.
+// The k index of MFMA step k4 for lane group kl = lane / 16 is 4 kl + k4 (any assignment
+// of the 16 k of a slab to (k4, kl) sums the same products), so a lane's four B values of
+// a slab are one 16-byte LDS read, and every LDS read below is free of bank conflicts.
+constexpr int DLS = 3;
+
+template <typename C>
+struct DlShape {
+  static constexpr int QPR = C::BM / 4;       // row quads per k row of A
+  static constexpr int KPC = 64 / QPR;        // k rows per A chunk
+  static constexpr int ACH = 2 * TBK / KPC;   // A chunks per stage (both planes)
+  static constexpr int BCH = 2 * C::BN / 16;  // B chunks per stage (16 columns each)
+  static constexpr int AW = ACH / 4, BW = BCH / 4;
+  static constexpr int NL = AW + BW;          // load instructions per wave per slab
+  static_assert(C::BM >= 64 && 64 % QPR == 0 && ACH % 4 == 0 && BCH % 4 == 0, "direct-to-LDS mapping");
+};
+
+template <typename C>
+struct alignas(16) DlLds {
+  float a[DLS][2][TBK][C::BM];
+  float b[DLS][2][C::BN][TBK];
+};
+
+// This lane's source address of each of its wave's chunks, at slab 0 of one product.
+template <typename C>
+struct DlSrc {
+  const float* a[DlShape<C>::AW];
+  const float* b[DlShape<C>::BW];
+};
+
+template <typename C>
+__device__ inline DlSrc<C> dl_src(const TileOperands<float>& op) {
+  typedef DlShape<C> S;
+  const int lane = threadIdx.x & 63, w = tile_wave();
+  DlSrc<C> p;
+#pragma unroll
+  for (int i = 0; i < S::AW; ++i) {
+    const int c = w * S::AW + i, plane = c / (S::ACH / 2);
+    const int k = (c % (S::ACH / 2)) * S::KPC + lane / S::QPR;
+    const int quad = (lane % S::QPR) ^ (((k >> 2) & 3) << 2);
+    int row = op.row0 + 4 * quad;
+    row = row < op.M ? row : op.M - 4;
+    p.a[i] = op.A + plane * op.a_ps + (long long)k * op.lda + row;
+  }
+#pragma unroll
+  for (int i = 0; i < S::BW; ++i) {
+    const int c = w * S::BW + i, plane = c / (S::BCH / 2);
+    const int col = (c % (S::BCH / 2)) * 16 + lane / 4;
+    const int kq = (lane & 3) ^ ((col >> 1) & 3);
+    int gc = op.col0 + col;
+    gc = gc < op.N ? gc : op.N - 1;
+    p.b[i] = op.B + plane * op.b_ps + (long long)gc * op.ldb + 4 * kq;
+  }
+  return p;
+}
+
+// One global_load_lds_dwordx4: every lane's 16 bytes at src land at dst + 16 * lane (dst
+// wave-uniform).
+__device__ inline void lds_dma16(const float* src, float* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
+// Start loading slab `slab` of a product (sources p, leading dimension lda) into a stage.
+template <typename C>
+__device__ inline void dl_issue(const DlSrc<C>& p, int slab, int lda, DlLds<C>& s, int stage) {
+  typedef DlShape<C> S;
+  const int w = tile_wave();
+  const long long ka = (long long)slab * TBK * lda;
+#pragma unroll
+  for (int i = 0; i < S::AW; ++i) {
+    const int c = w * S::AW + i, plane = c / (S::ACH / 2);
+    float* dst = &s.a[stage][plane][(c % (S::ACH / 2)) * S::KPC][0];
+    lds_dma16(p.a[i] + ka, dst);
+  }
+#pragma unroll
+  for (int i = 0; i < S::BW; ++i) {
+    const int c = w * S::BW + i, plane = c / (S::BCH / 2);
+    float* dst = &s.b[stage][plane][(c % (S::BCH / 2)) * 16][0];
+    lds_dma16(p.b[i] + slab * TBK, dst);
+  }
+}
+
+// Wait until at most n slabs of this wave's loads are still in flight (n <= 2).
+template <typename C>
+__device__ inline void dl_wait(int n) {
+  constexpr int NL = DlShape<C>::NL;
+  static_assert(2 * NL < 16, "vmcnt field");
+  // s_waitcnt: vmcnt in bits 3:0, expcnt (7: no wait) in 6:4, lgkmcnt (15: no wait) in 11:8
+  if (n >= 2)
+    __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * NL));
+  else if (n == 1)
+    __builtin_amdgcn_s_waitcnt(0x0F70 | NL);
+  else
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
+template <typename C, bool FULL>
+__device__ inline void dl_slab(const DlLds<C>& s, int st, const bool (&rv)[C::SM], const bool (&cv)[C::SN],
+                               TileAcc<C>& acc) {
+  constexpr int SM = C::SM, SN = C::SN;
+  const int lane = threadIdx.x & 63, wave = tile_wave();
+  const int rl = lane & 15, kl = lane >> 4;
+  const int wr = wave >> 1, wc = wave & 1;
+  f4v br[SN], bi[SN];
+#pragma unroll
+  for (int q = 0; q < SN; ++q) {
+    const int col = wc * (C::BN / 2) + q * 16 + rl;
+    const int off = col * TBK + 4 * (kl ^ ((col >> 1) & 3));
+    br[q] = *static_cast<const f4v*>(__builtin_assume_aligned(&s.b[st][0][0][0] + off, 16));
+    bi[q] = *static_cast<const f4v*>(__builtin_assume_aligned(&s.b[st][1][0][0] + off, 16));
+  }
+  int aoff[SM];
+#pragma unroll
+  for (int q = 0; q < SM; ++q) {
+    const int row = wr * (C::BM / 2) + q * 16 + rl;
+    aoff[q] = 4 * ((row >> 2) ^ (kl << 2)) + (row & 3);
+  }
+#pragma unroll
+  for (int k4 = 0; k4 < TBK / 4; ++k4) {
+    const int k = 4 * kl + k4;
+    StepOps<C> o;
+#pragma unroll
+    for (int q = 0; q < SM; ++q) {
+      o.ar[q] = s.a[st][0][k][aoff[q]];
+      o.ai[q] = s.a[st][1][k][aoff[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < SN; ++q) {
+      o.br[q] = br[q][k4];
+      o.bi[q] = bi[q][k4];
+    }
+    step_mfma<C, FULL>(o, rv, cv, acc);
+  }
+}
+
+// K loop of one product.  Slabs form one stream across the products of a work-group:
+// position p < nk is slab p of op, position nk + i slab i of next.  Before slab kb is
+// used, positions kb and kb + 1 have been issued; after the barrier that follows its
+// arrival, position kb + 2 is issued into the stage that slab kb - 1 used.
+template <typename C, bool FULL>
+__device__ inline void dl_kloop(const TileOperands<float>& op, DlLds<C>& s, const bool (&rv)[C::SM],
+                                const bool (&cv)[C::SN], TileAcc<C>& acc, TilePipe& tp, bool has_next,
+                                const TileOperands<float>& next) {
+  const int nk = op.K / TBK;
+  const int nkn = has_next ? next.K / TBK : 0;
+  const DlSrc<C> p = dl_src<C>(op);
+  const DlSrc<C> pn = dl_src<C>(next);  // next is a valid product even when !has_next
+  int npos = tp.pre;                     // positions issued so far
+#pragma unroll
+  for (int pos = 0; pos < 2; ++pos) {
+    if (npos != pos) continue;
+    if (pos < nk) {
+      dl_issue<C>(p, pos, op.lda, s, (tp.stage + pos) % DLS);
+      npos = pos + 1;
+    } else if (pos - nk < nkn) {
+      dl_issue<C>(pn, pos - nk, next.lda, s, (tp.stage + pos) % DLS);
+      npos = pos + 1;
+    }
+  }
+  for (int kb = 0; kb < nk; ++kb) {
+    dl_wait<C>(npos - 1 - kb);
+    __builtin_amdgcn_s_barrier();
+    if (npos == kb + 2) {
+      const int pos = kb + 2;
+      if (pos < nk) {
+        dl_issue<C>(p, pos, op.lda, s, (tp.stage + pos) % DLS);
+        npos = pos + 1;
+      } else if (pos - nk < nkn) {
+        dl_issue<C>(pn, pos - nk, next.lda, s, (tp.stage + pos) % DLS);
+        npos = pos + 1;
+      }
+    }
+    dl_slab<C, FULL>(s, (tp.stage + kb) % DLS, rv, cv, acc);
+  }
+  tp.stage = (tp.stage + nk) % DLS;
+  tp.pre = npos - nk > 0 ? npos - nk : 0;
+}
+
+template <typename C>
+__device__ inline TilePipe tile_start(const TileOperands<float>&, DlLds<C>&) {
+  return TilePipe{0, 0};
+}
+
+template <typename C>
+__device__ inline void tile_mma(const TileOperands<float>& op, DlLds<C>& s, TileAcc<C>& acc, TilePipe& tp,
+                                bool has_next, const TileOperands<float>& next) {
+  tile_zero<C>(acc);
+  bool rv[C::SM], cv[C::SN];
+  if (tile_ranges<C>(op, rv, cv))
+    dl_kloop<C, true>(op, s, rv, cv, acc, tp, has_next, next);
+  else
+    dl_kloop<C, false>(op, s, rv, cv, acc, tp, has_next, next);
+  tile_finish<C>(acc);
+}
+
+// The LDS of a work-group's tile pipeline: the direct-to-LDS ring for FP32, the
+// register-staged double buffer for FP64.
+template <typename C, typename T = typename C::T>
+struct TileSmemSel {
+  typedef TileLds<C> type;
+};
+template <typename C>
+struct TileSmemSel<C, float> {
+  typedef DlLds<C> type;
+};
+template <typename C>
+using TileSmem = typename TileSmemSel<C>::type;
 
 // First row of sub-tile ri of this wave, the row offset of accumulator element v, and
 // the column of sub-tile ci held by this lane.
