@@ -436,17 +436,20 @@ __device__ inline void dl_issue(const DlSrc<C>& p, int slab, int lda, DlLds<C>& 
 }
 
 // Wait until at most n slabs of this wave's loads are still in flight (n <= 2).
+// s_waitcnt operand that waits for vmcnt <= v only: vmcnt bits 3:0 and 15:14, expcnt
+// (7: no wait) bits 6:4, lgkmcnt (15: no wait) bits 11:8.
+constexpr int vmcnt_only(int v) { return (v & 15) | ((v >> 4) << 14) | 0x0F70; }
+
 template <typename C>
 __device__ inline void dl_wait(int n) {
   constexpr int NL = DlShape<C>::NL;
-  static_assert(2 * NL < 16, "vmcnt field");
-  // s_waitcnt: vmcnt in bits 3:0, expcnt (7: no wait) in 6:4, lgkmcnt (15: no wait) in 11:8
+  static_assert(2 * NL < 64, "vmcnt field");
   if (n >= 2)
-    __builtin_amdgcn_s_waitcnt(0x0F70 | (2 * NL));
+    __builtin_amdgcn_s_waitcnt(vmcnt_only(2 * NL));
   else if (n == 1)
-    __builtin_amdgcn_s_waitcnt(0x0F70 | NL);
+    __builtin_amdgcn_s_waitcnt(vmcnt_only(NL));
   else
-    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_s_waitcnt(vmcnt_only(0));
 }
 
 template <typename C, bool FULL>
