@@ -11,9 +11,10 @@ One step = one full hot-path call: all slice propagators (complex64 MFMA, FP64 n
 forward sweep, objective (FP64), backward sweep and exact gradient (FP64 accumulation).
 value = (slices x distinct blocks) per second of the timed steps.  The FP64 (complex128)
 path is timed beside it.  The roofline entry covers the dominant kernel, the propagator
-GEMM: algorithmic flops 8 m^3 per complex m x m product, with the products each slice
-needs for its (degree, squarings) choice, over its summed launch time measured with HIP
-events on the launch stream during the timed steps.
+GEMM: algorithmic flops 8 m^3 per complex m x m product (4 m^2 (m + 1) for the Hermitian
+powers of the generator, whose upper triangle is a mirror image), with the products each
+slice needs for its (degree, squarings) choice, over its summed launch time measured with
+HIP events on the launch stream during the timed steps.
 """
 import argparse
 import json
@@ -103,16 +104,24 @@ def timed_steps(q, torch, plan, dev, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall, prof, out, grad
 
 
+def _product_flops(m, qs, ss, r):
+    """Algorithmic flops of the propagator products of one block over its slices.  A
+    general complex m x m product is 8 m^3; the powers Y^2..Y^r of the skew-Hermitian
+    generator are (skew-)Hermitian, so only their lower triangle with the diagonal,
+    4 m^2 (m + 1), is work.  Degree-12 scheme (q = 0): 2 power products, then 2 + s general
+    ones; Paterson-Stockmeyer degree q r: r - 1 powers, then q - 1 + s general."""
+    herm = 4.0 * m * m * (m + 1)
+    full = 8.0 * m ** 3
+    npow = np.where(qs == 0, 2, r - 1)
+    ngen = np.where(qs == 0, 2 + ss, (qs - 1) + ss)
+    return float((npow * herm + ngen * full).sum())
+
+
 def gemm_flops(q, plan, dev, sizes):
-    """Algorithmic flops of the propagator GEMMs of one call (8 m^3 per complex product):
-    (r - 1) + (q - 1) + s products for Paterson-Stockmeyer degree q r, 4 + s for the
-    four-product degree-12 scheme (q = 0)."""
+    """Algorithmic flops of the propagator GEMMs of one call (see _product_flops)."""
     qs, ss, _ = q.slice_stats(plan, dev["u"])
     r = plan.info["taylor_step"]
-    tot = 0.0
-    for b, m in enumerate(sizes):
-        prods = np.where(qs[b] == 0, 4 + ss[b], (r - 1) + (qs[b] - 1) + ss[b])
-        tot += 8.0 * m ** 3 * float(prods.sum())
+    tot = sum(_product_flops(m, qs[b], ss[b], r) for b, m in enumerate(sizes))
     return tot, qs, ss
 
 
@@ -123,8 +132,7 @@ def gemm_flops_jobs(q, plan, u_flat, job_sizes):
     tot = 0.0
     for b, m in enumerate(job_sizes):
         valid = qs[b] >= 0
-        prods = np.where(qs[b] == 0, 4 + ss[b], (r - 1) + (qs[b] - 1) + ss[b])
-        tot += 8.0 * m ** 3 * float(prods[valid].sum())
+        tot += _product_flops(m, qs[b][valid], ss[b][valid], r)
     return tot
 
 
@@ -352,8 +360,9 @@ def main():
                      "alg_flops_per_launch": flops32 * args.steps / gemm_n,
                      "avg_launch_ms": gemm_ms / gemm_n, "kernel_ms_per_step": gemm_ms / args.steps,
                      "executed_mfma_frac": 0.75 * achieved / MFMA_PEAK["c64"],
-                     "note": "algorithmic flops 8 m^3 per complex m x m product; the kernel forms each with "
-                             "three real MFMA products (Gauss), 6 m^3 executed flops"},
+                     "note": "algorithmic flops 8 m^3 per complex m x m product, 4 m^2 (m + 1) for the "
+                             "(skew-)Hermitian powers of the generator (lower triangle; the upper is mirrored); "
+                             "the kernel forms each with three real MFMA products (Gauss): 3/4 of them executed"},
         "fp64": fp64,
         "fp32_vs_fp64": cmp,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},

@@ -382,6 +382,11 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     if (mode == STEP_POWER) {
       if (t12 && step > 3) return false;  // it needs Y^2 and Y^3 only
       ia = step - 2; ib = 0; ic = step - 1;
+      // Y is skew-Hermitian, so Y^step is Hermitian or skew-Hermitian: tiles wholly above
+      // the diagonal are written as mirrors by the tiles below it (except when this step
+      // also forms the entry's final propagator, which has no such symmetry)
+      const bool fin = !t12 && step == r && qe == 1 && se == 0;
+      if (!fin && ti * Shape::BM + Shape::BM <= tj * Shape::BN) return false;
     } else if (mode == STEP_T12) {
       if (!t12) return false;
       if (step == 1) {  // B4 B4 (B4 in buffer r) -> A6 = B3 + B4^2 in buffer r+1
@@ -445,6 +450,11 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     const bool init_T = mode == STEP_POWER && step == r && !t12;
     const bool init_final = init_T && qe == 1 && se == 0;
     const bool init_B4 = mode == STEP_POWER && step == 3 && t12;
+    // power steps (but a final one) keep the elements on and below the diagonal and write
+    // the mirror images of those strictly below; Y^step has the symmetry sign psign
+    // (M[c][r] = psign conj(M[r][c]))
+    const bool sym = mode == STEP_POWER && !init_final;
+    const T psign = (step & 1) ? T(-1) : T(1);
     if (mode == STEP_HORNER)
       for (int i = 0; i < r; ++i) coef[i] = kInvFact[lh * r + i];
     if (init_T) {
@@ -461,6 +471,34 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
         if (rbase >= mp || col >= mp) continue;
         const int row0 = rbase + acc_row_off<T>(0);  // this lane's first accumulator row
         const size_t at = (size_t)row0 + (size_t)col * mp;
+        const int cb = col - (int)(threadIdx.x & 15);  // first column of the sub-tile
+        if (sym && rbase + 16 <= cb) continue;        // above the diagonal: mirrored from below
+        const bool below = rbase >= cb + 16;           // every element strictly below
+        // direct store of the elements on or below the diagonal of a symmetric step, plus the
+        // conjugates of (mr, mi) at the transposed positions of those strictly below
+        auto put = [&](T* P, const V4& wr, const V4& wi, const V4& mr, const V4& mi) {
+          if (!sym || below) {
+            acc_store<T>(P + at, wr);
+            acc_store<T>(P + at + plane, wi);
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (row0 + v * AccRowStep<T>::value >= col) {
+                P[at + v * AccRowStep<T>::value] = wr[v];
+                P[at + plane + v * AccRowStep<T>::value] = wi[v];
+              }
+          }
+          if (!sym) return;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int rr = row0 + v * AccRowStep<T>::value;
+            if (below || rr > col) {
+              T* d = P + (size_t)col + (size_t)rr * mp;
+              d[0] = mr[v];
+              d[plane] = -mi[v];
+            }
+          }
+        };
         V4 vr = acc.re[ri][ci], vi = acc.im[ri][ci];
         if (mode == STEP_HORNER) {
           for (int i = 1; i < r; ++i) {
@@ -510,8 +548,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
             vi += y1i;
           }
         }
-        acc_store<T>(C + at, vr);
-        acc_store<T>(C + at + plane, vi);
+        put(C, vr, vi, psign * vr, psign * vi);
         if (init_B4) {
           // B4 = sum_k c[3][k] P_k (the product is Y^3) into buffer r: the degree-12 scheme's start
           const V4 y1r = acc_load<T>(base + at), y1i = acc_load<T>(base + at + plane);
@@ -519,27 +556,32 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
           V4 br = (T)kT12c[3][3] * vr, bi = (T)kT12c[3][3] * vi;
           br += (T)kT12c[3][1] * y1r + (T)kT12c[3][2] * y2r;
           bi += (T)kT12c[3][1] * y1i + (T)kT12c[3][2] * y2i;
+          // mirror: B4[c][r] = conj(-c1 Y + c2 Y^2 - c3 Y^3)[r][c] off the diagonal
+          const V4 mr = (T)kT12c[3][2] * y2r - (T)kT12c[3][1] * y1r - (T)kT12c[3][3] * vr;
+          const V4 mi = (T)kT12c[3][2] * y2i - (T)kT12c[3][1] * y1i - (T)kT12c[3][3] * vi;
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             if (row0 + v * AccRowStep<T>::value == col && col < x.m) br[v] += (T)kT12c[3][0];
-          T* B4 = base + (size_t)r * 2 * plane + at;
-          acc_store<T>(B4, br);
-          acc_store<T>(B4 + plane, bi);
+          put(base + (size_t)r * 2 * plane, br, bi, mr, mi);
         }
         if (init_T) {
-          // T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i at this tile (the Horner start)
+          // T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i at this tile (the Horner start); its
+          // mirror T0[c][r] = conj(sum_i (-1)^i c_i Y^i)[r][c] off the diagonal
           V4 tr = (T)ctop * vr, ti = (T)ctop * vi;
+          V4 mr = psign * tr, mi = psign * ti;
           for (int i = 1; i < r; ++i) {
             const T* Pp = base + (size_t)(i - 1) * 2 * plane + at;
-            tr += (T)coef[i] * acc_load<T>(Pp);
-            ti += (T)coef[i] * acc_load<T>(Pp + plane);
+            const V4 pr = acc_load<T>(Pp), pi = acc_load<T>(Pp + plane);
+            const T ci = (T)coef[i], cm = (i & 1) ? -ci : ci;
+            tr += ci * pr;
+            ti += ci * pi;
+            mr += cm * pr;
+            mi += cm * pi;
           }
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             if (row0 + v * AccRowStep<T>::value == col && col < x.m) tr[v] += (T)coef[0];
-          T* T0 = (init_final ? ubase : base + (size_t)r * 2 * plane) + at;
-          acc_store<T>(T0, tr);
-          acc_store<T>(T0 + plane, ti);
+          put(init_final ? ubase : base + (size_t)r * 2 * plane, tr, ti, mr, mi);
           if (init_final) {
             T* D = ubase + 2 * plane;
 #pragma unroll
