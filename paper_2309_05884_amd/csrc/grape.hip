@@ -55,6 +55,7 @@ struct JobDev {
   long long state_off;   // block offset in the batch's concatenated panels (complex entries)
   long long u_off;       // the problem's offset in the concatenated controls / gradients
   long long uout_off;    // offset of this job's propagators in qoc_propagate's output
+  long long xchg_off;    // co-operative sweep state exchange (64-bit words, per direction)
 };
 
 struct ProbDev {
@@ -147,7 +148,8 @@ struct qoc_plan_s {
   int nslots = 0;
   size_t elem = 8;
   // workspace layout (bytes)
-  size_t off_flags = 0, off_ent = 0, off_T = 0, off_gacc = 0, off_sync = 0, bytes = 0;
+  size_t off_flags = 0, off_ent = 0, off_T = 0, off_gacc = 0, off_sync = 0, off_xchg = 0, bytes = 0;
+  long long xchg_words = 0;  // per direction
   bool coop = false;      // co-operative sweeps (several work-groups per job)
   int coop_w = 1;         // largest number of work-groups of a job
   size_t coop_lds = 0;    // dynamic LDS of the co-operative sweep (bytes)
@@ -810,13 +812,17 @@ __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, c
 }
 
 // ---- co-operative sweep: the rows of a job are split over W = ceil(mp / RB) work-groups
-// (RB = 64 FP32 / 32 FP64 rows); after every slice each group publishes its rows of the
-// new state in the state panel and the groups meet on a per-job counter (agent-scope
-// release / acquire).  All waits are bounded.  Group 0 first waits (bounded) for the
-// other groups to arrive; if they are not all resident it runs the job alone
-// (sweep_solo) and the late groups leave, so the sweep never depends on co-residency.
-// Control words per job: [0] arrivals, [1] decision, [2] slice counter (zeroed before
-// the launch).
+// (RB = 64 FP32 / 32 FP64 rows).  After every slice each group publishes its rows of the
+// new state as tagged 64-bit words (a 32-bit half of a value and the slice number, one
+// single-copy-atomic store), into one of two buffers by slice parity; every group reads
+// the whole state back, spinning on each word until its tag is the slice it waits for.
+// Data and flag travel together, so no fences or counters sit on the per-slice path.  A
+// group overwrites the words of slice j - 2 only after reading every group's slice j - 1,
+// which each wrote after it had read slice j - 2.  All waits are bounded.  Group 0 first
+// waits (bounded) for the other groups to arrive; if they are not all resident it runs the
+// job alone (sweep_solo) and the late groups leave, so the sweep never depends on
+// co-residency.  Control words per job: [0] arrivals, [1] decision (zeroed before the
+// launch, with the exchange words).
 constexpr int kCoopGo = 1, kCoopSolo = 2;
 constexpr long kArriveSpins = 1L << 15;  // ~ms: group 0 waits this long for the others
 constexpr long kStepSpins = 1L << 20;    // a stalled hand-off (tens of ms) aborts the sweep
@@ -851,11 +857,56 @@ __device__ inline int coop_decide(int* ctl, int W, int* flags) {
   return decision;
 }
 
+// Tagged exchange words: a 32-bit half of a value in the low word, the tag in the high one.
+__device__ inline void xchg_put(unsigned long long* p, unsigned bits, unsigned tag) {
+  __hip_atomic_store(p, ((unsigned long long)tag << 32) | bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// spins (bounded) until the word carries tag; false on time-out
+__device__ inline bool xchg_get(const unsigned long long* p, unsigned tag, unsigned& bits) {
+  long s = 0;
+  for (;;) {
+    const unsigned long long w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((unsigned)(w >> 32) == tag) {
+      bits = (unsigned)w;
+      return true;
+    }
+    if (++s >= kStepSpins) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+template <typename T> struct XchgVal;
+template <> struct XchgVal<float> {
+  static constexpr int W = 1;
+  __device__ static void put(unsigned long long* p, float v, unsigned tag) { xchg_put(p, __float_as_uint(v), tag); }
+  __device__ static bool get(const unsigned long long* p, unsigned tag, float& v) {
+    unsigned b;
+    if (!xchg_get(p, tag, b)) return false;
+    v = __uint_as_float(b);
+    return true;
+  }
+};
+template <> struct XchgVal<double> {
+  static constexpr int W = 2;
+  __device__ static void put(unsigned long long* p, double v, unsigned tag) {
+    const unsigned long long b = __double_as_longlong(v);
+    xchg_put(p, (unsigned)b, tag);
+    xchg_put(p + 1, (unsigned)(b >> 32), tag);
+  }
+  __device__ static bool get(const unsigned long long* p, unsigned tag, double& v) {
+    unsigned lo, hi;
+    if (!xchg_get(p, tag, lo) || !xchg_get(p + 1, tag, hi)) return false;
+    v = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    return true;
+  }
+};
+
 template <typename T, int DIR>
 __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njobs, char* ws, size_t off_T,
                                                      const int* ent_s, const int* ent_q, int r, int seg_j0,
-                                                     int seg_len, int* ctl_all, int* flags) {
+                                                     int seg_len, int* ctl_all, int* flags,
+                                                     unsigned long long* xchg_all) {
   typedef typename Vec16<T>::type TV;
+  typedef XchgVal<T> XV;
   constexpr int RPL = Vec16<T>::n, RB = CoopRows<T>::value, UNR = 4;
   extern __shared__ __attribute__((aligned(16))) char smem_raw[];
   const int J = blockIdx.y;
@@ -882,38 +933,46 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
   const size_t ncol = DIR == 0 ? (size_t)(N + 1) * d : (size_t)N * d;
   const size_t ps = (size_t)mp * ncol;
   const size_t plane = (size_t)mp * mp;
+  // exchange words of this job: [parity][re, im][d][mp] values of XV::W words
+  unsigned long long* X = xchg_all + jb.xchg_off;
+  const size_t xplane = (size_t)d * mp * XV::W;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rv = lane & 15, kk = lane >> 4;
   const int r0 = blockIdx.x * RB, row = r0 + rv * RPL;  // this lane's rows row .. row + RPL - 1
   const int KC = ((m + 15) / 16 + 3) / 4 * 4;           // columns per wave (multiple of 4)
   const int kw0 = wave * KC, kw1 = min(m, kw0 + KC);
-  int col_prev = DIR == 0 ? seg_j0 : seg_j0 + len - 1;
-  for (int it = 0; it < len; ++it) {
-    const int jl = DIR == 0 ? it : len - 1 - it;
-    if (threadIdx.x == 0) {
-      abort_now = 0;
-      if (it > 0) {
-        long s = 0;
-        while (__hip_atomic_load(ctl + 2, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < W * it) {
-          if (++s >= kStepSpins) {
-            __hip_atomic_fetch_or(flags, kFlagSweepAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            abort_now = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-    }
-    __syncthreads();
-    if (abort_now) return;
-    // the input state (written by every group in the previous slice) into LDS
+  // the input state of the first slice (written before the launch)
+  {
+    const int col_in = DIR == 0 ? seg_j0 : seg_j0 + len - 1;
     for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
       const int c = idx / mp, i = idx % mp;
-      const size_t g = ((size_t)col_prev * d + c) * mp + i;
-      sre[idx] = __hip_atomic_load(S + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      sim[idx] = __hip_atomic_load(S + g + ps, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const size_t g = ((size_t)col_in * d + c) * mp + i;
+      sre[idx] = S[g];
+      sim[idx] = S[g + ps];
     }
+    if (threadIdx.x == 0) abort_now = 0;
     __syncthreads();
+  }
+  for (int it = 0; it < len; ++it) {
+    const int jl = DIR == 0 ? it : len - 1 - it;
+    if (it > 0) {
+      // the state after slice it - 1, published by every group with tag it
+      const unsigned long long* Xp = X + (size_t)((it - 1) & 1) * 2 * xplane;
+      bool ok = true;
+      for (int idx = threadIdx.x; idx < mp * d && ok; idx += blockDim.x) {
+        T vr = T(0), vi = T(0);
+        ok = XV::get(Xp + (size_t)idx * XV::W, (unsigned)it, vr) &&
+             XV::get(Xp + xplane + (size_t)idx * XV::W, (unsigned)it, vi);
+        sre[idx] = vr;
+        sim[idx] = vi;
+      }
+      if (!ok) {
+        abort_now = 1;
+        __hip_atomic_fetch_or(flags, kFlagSweepAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+      if (abort_now) return;
+    }
     const T* U = entry_U<T>(jb, ws, off_T, jl, DIR);
     T a[2][2][RPL];  // [copy][re, im][row]
 #pragma unroll
@@ -935,16 +994,14 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
         for (int u = 0; u < UNR; ++u) {
           const int k = kb + 4 * u + kk;
           if (k >= kw1) break;
-          const T* urq = reinterpret_cast<const T*>(&ur[u]);
-          const T* uiq = reinterpret_cast<const T*>(&ui[u]);
 #pragma unroll
           for (int c = 0; c < 2; ++c) {
             if (c >= d) break;
             const T pr = sre[c * mp + k], pi = sim[c * mp + k];
 #pragma unroll
             for (int t = 0; t < RPL; ++t) {
-              a[c][0][t] += urq[t] * pr - uiq[t] * pi;
-              a[c][1][t] += urq[t] * pi + uiq[t] * pr;
+              a[c][0][t] += ur[u][t] * pr - ui[u][t] * pi;
+              a[c][1][t] += ur[u][t] * pi + ui[u][t] * pr;
             }
           }
         }
@@ -979,15 +1036,21 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
         vi += pim[((size_t)w * d + c) * RB + i];
       }
       if (r0 + i >= m) vr = vi = T(0);
-      if (col_out >= 0 && r0 + i < mp) {
-        const size_t g = ((size_t)col_out * d + c) * mp + r0 + i;
-        S[g] = vr;
-        S[g + ps] = vi;
+      if (r0 + i < mp) {
+        if (it + 1 < len) {
+          unsigned long long* Xo = X + (size_t)(it & 1) * 2 * xplane + ((size_t)c * mp + r0 + i) * XV::W;
+          XV::put(Xo, vr, (unsigned)(it + 1));
+          XV::put(Xo + xplane, vi, (unsigned)(it + 1));
+        }
+        if (col_out >= 0) {
+          const size_t g = ((size_t)col_out * d + c) * mp + r0 + i;
+          S[g] = vr;
+          S[g + ps] = vi;
+        }
       }
     }
-    __syncthreads();  // this group's rows are written (and the partials consumed)
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctl + 2, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    col_prev = col_out;
+    // no barrier here: the next slice's state read ends with one before the partials are
+    // written again, and this slice's reads of the state in LDS are behind the one above
   }
 }
 
@@ -1531,13 +1594,16 @@ struct Driver {
       int* flags = reinterpret_cast<int*>(ws + P->off_flags);
       const dim3 grid(P->coop_w, njobs);
       timed(dir == 0 ? PK_SWEEP_FWD : PK_SWEEP_BWD, st, [&] {
+        unsigned long long* xg = reinterpret_cast<unsigned long long*>(ws + P->off_xchg) + (size_t)dir * P->xchg_words;
+        const int nz = (int)(2 * P->xchg_words);
         hipLaunchKernelGGL(k_zero_ints, dim3((4 * njobs + 255) / 256), dim3(256), 0, st, ctl, 4 * njobs);
+        hipLaunchKernelGGL(k_zero_ints, dim3((nz + 255) / 256), dim3(256), 0, st, reinterpret_cast<int*>(xg), nz);
         if (dir == 0)
           hipLaunchKernelGGL((k_sweep_coop<T, 0>), grid, dim3(1024), P->coop_lds, st, dj, njobs, ws, P->off_T,
-                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags);
+                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags, xg);
         else
           hipLaunchKernelGGL((k_sweep_coop<T, 1>), grid, dim3(1024), P->coop_lds, st, dj, njobs, ws, P->off_T,
-                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags);
+                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags, xg);
       });
       return;
     }
@@ -1874,6 +1940,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->off_ent = take((size_t)P->entries_per_seg * 16);
   long long tel = 0, ent_off = 0, gacc = 0, u_off = 0, state_base = 0, uout = 0;
   int max_cc = 0;
+  long long xw = 0;  // exchange words of the co-operative sweep, per direction
   for (size_t p = 0; p < probs.size(); ++p) {
     const auto& pr = probs[p];
     ProbDev pd{};
@@ -1914,6 +1981,8 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       gacc += (long long)j.cc * pr.sys->K;
       j.uout_off = uout;
       uout += (long long)pr.N * b.m * b.m;
+      j.xchg_off = xw;
+      xw += 2LL * 2 * b.mp * b.d * (f64 ? 2 : 1);
       P->jobs.push_back(j);
     }
     pd.job_end = (int)P->jobs.size();
@@ -1930,6 +1999,8 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->off_T = take((size_t)tel * P->elem);
   P->off_gacc = take((size_t)std::max<long long>(gacc, 1) * 16);
   P->off_sync = take((size_t)2 * 4 * sizeof(int) * P->jobs.size());  // co-operative sweep control words
+  P->xchg_words = xw;
+  P->off_xchg = take((size_t)2 * xw * 8);  // co-operative sweep state exchange, both directions
   P->bytes = off;
   // panel GEMM descriptors: (job, op) for op = 0..K_job (tiles set by apply_variant)
   for (size_t J = 0; J < P->jobs.size(); ++J)
