@@ -452,42 +452,48 @@ __device__ inline void dl_wait(int n) {
     __builtin_amdgcn_s_waitcnt(vmcnt_only(0));
 }
 
-template <typename C, bool FULL>
-__device__ inline void dl_slab(const DlLds<C>& s, int st, const bool (&rv)[C::SM], const bool (&cv)[C::SN],
-                               TileAcc<C>& acc) {
-  constexpr int SM = C::SM, SN = C::SN;
+// One slab of a wave whose first NR sub-tile rows and NC sub-tile columns lie inside the
+// product (compile-time counts: edge tiles run straight-line code for exactly their valid
+// sub-tiles).
+template <typename C, int NR, int NC>
+__device__ inline void dl_slab(const DlLds<C>& s, int st, TileAcc<C>& acc) {
   const int lane = threadIdx.x & 63, wave = tile_wave();
   const int rl = lane & 15, kl = lane >> 4;
   const int wr = wave >> 1, wc = wave & 1;
-  f4v br[SN], bi[SN];
+  f4v br[NC > 0 ? NC : 1], bi[NC > 0 ? NC : 1];
 #pragma unroll
-  for (int q = 0; q < SN; ++q) {
+  for (int q = 0; q < NC; ++q) {
     const int col = wc * (C::BN / 2) + q * 16 + rl;
     const int off = col * TBK + 4 * (kl ^ ((col >> 1) & 3));
     br[q] = *static_cast<const f4v*>(__builtin_assume_aligned(&s.b[st][0][0][0] + off, 16));
     bi[q] = *static_cast<const f4v*>(__builtin_assume_aligned(&s.b[st][1][0][0] + off, 16));
   }
-  int aoff[SM];
+  int aoff[NR > 0 ? NR : 1];
 #pragma unroll
-  for (int q = 0; q < SM; ++q) {
+  for (int q = 0; q < NR; ++q) {
     const int row = wr * (C::BM / 2) + q * 16 + rl;
     aoff[q] = 4 * ((row >> 2) ^ (kl << 2)) + (row & 3);
   }
 #pragma unroll
   for (int k4 = 0; k4 < TBK / 4; ++k4) {
     const int k = 4 * kl + k4;
-    StepOps<C> o;
+    float ar[NR > 0 ? NR : 1], ai[NR > 0 ? NR : 1], as[NR > 0 ? NR : 1], bs[NC > 0 ? NC : 1];
 #pragma unroll
-    for (int q = 0; q < SM; ++q) {
-      o.ar[q] = s.a[st][0][k][aoff[q]];
-      o.ai[q] = s.a[st][1][k][aoff[q]];
+    for (int q = 0; q < NR; ++q) {
+      ar[q] = s.a[st][0][k][aoff[q]];
+      ai[q] = s.a[st][1][k][aoff[q]];
+      as[q] = ar[q] + ai[q];
     }
 #pragma unroll
-    for (int q = 0; q < SN; ++q) {
-      o.br[q] = br[q][k4];
-      o.bi[q] = bi[q][k4];
-    }
-    step_mfma<C, FULL>(o, rv, cv, acc);
+    for (int q = 0; q < NC; ++q) bs[q] = br[q][k4] + bi[q][k4];
+#pragma unroll
+    for (int ri = 0; ri < NR; ++ri)
+#pragma unroll
+      for (int ci = 0; ci < NC; ++ci) {
+        acc.re[ri][ci] = mfma16(ar[ri], br[ci][k4], acc.re[ri][ci]);
+        acc.x[ri][ci] = mfma16(ai[ri], bi[ci][k4], acc.x[ri][ci]);
+        acc.im[ri][ci] = mfma16(as[ri], bs[ci], acc.im[ri][ci]);
+      }
   }
 }
 
@@ -495,10 +501,9 @@ __device__ inline void dl_slab(const DlLds<C>& s, int st, const bool (&rv)[C::SM
 // position p < nk is slab p of op, position nk + i slab i of next.  Before slab kb is
 // used, positions kb and kb + 1 have been issued; after the barrier that follows its
 // arrival, position kb + 2 is issued into the stage that slab kb - 1 used.
-template <typename C, bool FULL>
-__device__ inline void dl_kloop(const TileOperands<float>& op, DlLds<C>& s, const bool (&rv)[C::SM],
-                                const bool (&cv)[C::SN], TileAcc<C>& acc, TilePipe& tp, bool has_next,
-                                const TileOperands<float>& next) {
+template <typename C, int NR, int NC>
+__device__ inline void dl_kloop(const TileOperands<float>& op, DlLds<C>& s, TileAcc<C>& acc, TilePipe& tp,
+                                bool has_next, const TileOperands<float>& next) {
   const int nk = op.K / TBK;
   const int nkn = has_next ? next.K / TBK : 0;
   const DlSrc<C> p = dl_src<C>(op);
@@ -528,7 +533,7 @@ __device__ inline void dl_kloop(const TileOperands<float>& op, DlLds<C>& s, cons
         npos = pos + 1;
       }
     }
-    dl_slab<C, FULL>(s, (tp.stage + kb) % DLS, rv, cv, acc);
+    dl_slab<C, NR, NC>(s, (tp.stage + kb) % DLS, acc);
   }
   tp.stage = (tp.stage + nk) % DLS;
   tp.pre = npos - nk > 0 ? npos - nk : 0;
@@ -539,15 +544,37 @@ __device__ inline TilePipe tile_start(const TileOperands<float>&, DlLds<C>&) {
   return TilePipe{0, 0};
 }
 
+// Picks the K loop compiled for this wave's valid sub-tile counts (nr <= NR, nc <= NC).
+template <typename C, int NR, int NC>
+__device__ inline void dl_run(int nr, int nc, const TileOperands<float>& op, DlLds<C>& s, TileAcc<C>& acc,
+                              TilePipe& tp, bool has_next, const TileOperands<float>& next) {
+  if constexpr (NR > 0) {
+    if (nr < NR) {
+      dl_run<C, NR - 1, NC>(nr, nc, op, s, acc, tp, has_next, next);
+      return;
+    }
+  }
+  if constexpr (NC > 0) {
+    if (nc < NC) {
+      dl_run<C, NR, NC - 1>(nr, nc, op, s, acc, tp, has_next, next);
+      return;
+    }
+  }
+  dl_kloop<C, NR, NC>(op, s, acc, tp, has_next, next);
+}
+
 template <typename C>
 __device__ inline void tile_mma(const TileOperands<float>& op, DlLds<C>& s, TileAcc<C>& acc, TilePipe& tp,
                                 bool has_next, const TileOperands<float>& next) {
   tile_zero<C>(acc);
   bool rv[C::SM], cv[C::SN];
-  if (tile_ranges<C>(op, rv, cv))
-    dl_kloop<C, true>(op, s, rv, cv, acc, tp, has_next, next);
-  else
-    dl_kloop<C, false>(op, s, rv, cv, acc, tp, has_next, next);
+  tile_ranges<C>(op, rv, cv);
+  int nr = 0, nc = 0;  // valid sub-tiles come first along each direction
+#pragma unroll
+  for (int q = 0; q < C::SM; ++q) nr += rv[q];
+#pragma unroll
+  for (int q = 0; q < C::SN; ++q) nc += cv[q];
+  dl_run<C, C::SM, C::SN>(nr, nc, op, s, acc, tp, has_next, next);
   tile_finish<C>(acc);
 }
 
