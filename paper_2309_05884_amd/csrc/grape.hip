@@ -1249,11 +1249,14 @@ __global__ void k_series_combine(const JobDev* jobs, int njobs, char* ws, size_t
   }
 }
 
-// G[col][k] += sum_{i < nb} w_{i,t} <b_i | Z_k>, FP64; one wave per (job, column)
+// G[col][k] += sum_{i < nb} w_{i,t} <b_i | Z_k>, FP64; one wave per (job, column).  The
+// weights are real, so this is <sum_i w_i b_i | Z_k>: one pass over the rows forms the
+// combined bank vector and its products with up to KG controls at a time.
 template <typename T>
 __global__ void __launch_bounds__(256) k_series_dot(const JobDev* jobs, int njobs, char* ws, size_t off_T,
                                                     size_t off_gacc, int bank_slot, int nb, const double* w,
                                                     int zero_first, int j0) {
+  constexpr int KG = 8;
   for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];
   if (jb.N - j0 <= 0) continue;
@@ -1264,26 +1267,37 @@ __global__ void __launch_bounds__(256) k_series_dot(const JobDev* jobs, int njob
   const T* g = tplane<T>(ws, off_T, jb.gbase_off);
   const size_t vplane = (size_t)mp * jb.cc;
   double2* G = reinterpret_cast<double2*>(ws + off_gacc) + jb.gacc_off + (size_t)col * K;
-  for (int k = 1; k <= K; ++k) {
-    const T* Z = g + (size_t)k * jb.gslot + (size_t)col * mp;
-    double ar = 0.0, ai = 0.0;
-    for (int i = 0; i < nb; ++i) {
-      const T* Bv = g + (size_t)(bank_slot + i) * jb.gslot + (size_t)col * mp;
-      double pr = 0.0, pi = 0.0;
-      for (int row = lane; row < jb.m; row += 64) {
-        const double br = Bv[row], bi = Bv[row + vplane];
-        const double zr = Z[row], zi = Z[row + vplane];
-        pr += br * zr + bi * zi;
-        pi += br * zi - bi * zr;
+  const T* Bc = g + (size_t)bank_slot * jb.gslot + (size_t)col * mp;
+  for (int k0 = 1; k0 <= K; k0 += KG) {
+    const int nk = min(KG, K - k0 + 1);
+    double pr[KG], pi[KG];
+#pragma unroll
+    for (int q = 0; q < KG; ++q) pr[q] = pi[q] = 0.0;
+    for (int row = lane; row < jb.m; row += 64) {
+      double cr = 0.0, ci = 0.0;
+      for (int i = 0; i < nb; ++i) {
+        const T* Bv = Bc + (size_t)i * jb.gslot;
+        cr += w[i] * (double)Bv[row];
+        ci += w[i] * (double)Bv[row + vplane];
       }
-      ar += w[i] * pr;
-      ai += w[i] * pi;
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        if (q >= nk) break;
+        const T* Z = g + (size_t)(k0 + q) * jb.gslot + (size_t)col * mp;
+        const double zr = Z[row], zi = Z[row + vplane];
+        pr[q] += cr * zr + ci * zi;
+        pi[q] += cr * zi - ci * zr;
+      }
     }
-    ar = warp_sum(ar);
-    ai = warp_sum(ai);
-    if (lane == 0) {
-      double2 prev = zero_first ? make_double2(0.0, 0.0) : G[k - 1];
-      G[k - 1] = make_double2(prev.x + ar, prev.y + ai);
+#pragma unroll
+    for (int q = 0; q < KG; ++q) {
+      if (q >= nk) break;
+      const double ar = warp_sum(pr[q]), ai = warp_sum(pi[q]);
+      if (lane == 0) {
+        const int k = k0 + q;
+        double2 prev = zero_first ? make_double2(0.0, 0.0) : G[k - 1];
+        G[k - 1] = make_double2(prev.x + ar, prev.y + ai);
+      }
     }
   }
   }
@@ -1498,7 +1512,7 @@ GemmVariant make_variant(const char* name) {
 }
 static const GemmVariant kVariants32[] = {
     make_variant<TileShape<float, 4, 2, 2>>("fp32 128x64"),
-    make_variant<TileShape<float, 2, 2, 3>>("fp32 64x64"),
+    make_variant<TileShape<float, 2, 2, 2>>("fp32 64x64"),
     make_variant<TileShape<float, 2, 4, 2>>("fp32 64x128"),
 };
 static const GemmVariant kVariants64[] = {
