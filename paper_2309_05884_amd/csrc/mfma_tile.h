@@ -8,9 +8,11 @@
 // by default or by timing them on its own work (qoc_plan_autotune).
 // The complex product takes three real MFMAs per sub-tile and k step instead of four
 // (Gauss's 3M form, see TileAcc).
-// Operands are staged through double-buffered LDS in 16-deep slabs; the next slab is
-// loaded into registers while the current one feeds the MFMAs, and in a persistent loop
-// the next tile's first slab is loaded during the current tile's last one.
+// Operands are staged through LDS in 16-deep slabs.  FP32 tiles load them straight into
+// LDS (global_load_lds) through a ring of three stages, two slabs ahead of the MFMAs;
+// FP64 tiles load the next slab into registers while the current one feeds the MFMAs
+// and store it into the other half of a double buffer.  In a persistent loop the next
+// tile's first slab(s) load during the current tile's last one(s).
 // MFMA 16x16x4 operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16].  The
 // accumulator element v of lane l is D[4*(l/16)+v][l%16] for the FP32 instruction and
 // D[(l/16)+4v][l%16] for the FP64 one (measured on gfx950).
