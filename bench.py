@@ -31,13 +31,16 @@ if ROOT not in sys.path:
 MFMA_PEAK = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix TFLOP/s, MI355X
 
 # HBM-side bytes of k_expm_step<float> on this workload, from two rocprofv3 --pmc runs
-# (FETCH_SIZE, then WRITE_SIZE; mean KiB per dispatch over the 12 dispatches of
-# `bench.py --steps 1 --warmup 1 --fp64-steps 0 --copy-calibration 256`), each scaled
-# by what the same counter reads for the 256 MiB calibration copy (FETCH_SIZE reads
-# half of the bytes copied: x2.0; WRITE_SIZE all of them: x1.0).  Valid only for the
-# kernel sources they were taken with (sha1 of mfma_tile.h + grape.hip).
-TRAFFIC = {"sources_sha1": "41fbd9cb8eee9859c2ac0101860d4ec68fb67910", "variant": "fp32 128x64",
-           "fetch_kib": 20651052.7, "fetch_scale": 2.0, "write_kib": 7918390.7, "write_scale": 1.0}
+# (FETCH_SIZE, then WRITE_SIZE; mean KiB per dispatch over each tile variant's last 8
+# dispatches of `bench.py --steps 1 --warmup 1 --fp64-steps 0 --no-cpu-baseline
+# --copy-calibration 256 --sym-candidates 0 --ring14-slices 0 --batch-problems 0
+# --dense-slices 0`), each scaled by what the same counter reads for the 256 MiB
+# calibration copy (FETCH_SIZE reads half of the bytes copied: x2.0; WRITE_SIZE all of
+# them: x1.0).  Valid only for the kernel sources they were taken with (sha1 of
+# mfma_tile.h + grape.hip).
+TRAFFIC = {"sources_sha1": "a60379b0ddda13e6b4142a86493860d97636dd51", "fetch_scale": 2.0, "write_scale": 1.0,
+           "kib": {"fp32 128x64": (11802869.5, 6441000.3), "fp32 64x64": (14317875.6, 6454605.8),
+                   "fp32 64x128": (12721322.2, 6044278.7)}}
 
 
 def kernel_sources_sha1():
@@ -334,8 +337,9 @@ def main():
                "grad_rel_err": float((grad32.cpu() - g64).abs().max() / g64.abs().max()), "F64": out64[0].item()}
 
     traffic = None
-    if kernel_sources_sha1() == TRAFFIC["sources_sha1"] and var32 == TRAFFIC["variant"]:
-        traffic = 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+    if kernel_sources_sha1() == TRAFFIC["sources_sha1"] and var32 in TRAFFIC["kib"]:
+        fetch_kib, write_kib = TRAFFIC["kib"][var32]
+        traffic = 1024.0 * (fetch_kib * TRAFFIC["fetch_scale"] + write_kib * TRAFFIC["write_scale"])
     line = {
         "metric": "GRAPE slices*blocks/sec (fidelity+gradient), FP32-batched vs FP64, |dF|<=1e-6",
         "value": units / (ms32 * 1e-3),
