@@ -68,6 +68,9 @@ def parse():
                     help="problems of the 256-ring batched workload timed in one plan (0: skip)")
     ap.add_argument("--dense-slices", type=int, default=16,
                     help="slices of the same pulse timed on the dense 4096-dim space (0: skip)")
+    ap.add_argument("--paper-comparison", type=int, default=0, metavar="NMAX",
+                    help="also time the transfer all-up -> all-down for n = 3..NMAX qubits on the dense "
+                         "space, the first D_n block and (no coupling) the first S_n block (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -161,6 +164,96 @@ def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, p
             "gemm_tflops": tf, "gemm_frac": tf / MFMA_PEAK[precision], "gemm_ms_per_step": gemm_ms / steps,
             "gemm_variant": plan.variant_name, "steps": steps, "segments": plan.info["segments"],
             "workspace_gb": plan.workspace_bytes / 1e9}
+
+
+def paper_comparison(q, torch, W, nmax, N=100, dt=0.05, dense_max=12, steps=2):
+    """Milliseconds per fidelity+gradient step of the transfer all-up -> all-down (the
+    runtime comparison of the paper's Sec. III A): on the dense 2^n space (n <= dense_max),
+    on the first D_n block alone, and, without coupling, on the first S_n block alone.
+    Eq. (5) with B_z = 1 and c_cpl = 0 (no coupling) or 1 (nearest neighbours), and Eq. (7)
+    with B_z = 1 and c^(d) = 1/d for d = 1 .. floor(n/2) (full coupling, D_n only); global
+    controls of Eq. (6); N slices of dt; a resonant circular pi pulse (u_x, u_y) =
+    (pi / T)(cos t, sin t) at the slice midpoints t, T = N dt, which flips each free qubit,
+    plus seeded U[-0.05, 0.05] noise on both controls, so that F is far from 0 (about 0.995
+    at n = 14 without coupling); complex64 plans."""
+    def timed(B, h0, hk, u, blocks, psi, key, e):
+        """Eager step time under e[key + "_ms"]; for blocks of a few hundred or less, where
+        launch latency dominates, also the replay time of the step captured in a HIP graph
+        under e[key + "_graph_ms"].  Returns F."""
+        S = q.System(B, h0, hk)
+        P = q.Plan(S, "c64", N, dt, 1.0, blocks=blocks)
+        out, _ = q.fidelity_grad(P, u, psi[0], psi[1], check=False)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            out, _ = q.fidelity_grad(P, u, psi[0], psi[1], check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        q.check_flags(out)
+        e[key + "_ms"] = e0.elapsed_time(e1) / steps
+        F = out[0].item()
+        if e[key + "_m"] <= 512:
+            cap = q.CapturedStep(P, u, psi[0], psi[1])
+            reps = 20
+            cap.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                gout, _ = cap.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            q.check_flags(gout)
+            e[key + "_graph_ms"] = e0.elapsed_time(e1) / reps
+            assert abs(gout[0].item() - F) <= 1e-6, (key, gout[0].item(), F)
+        return F
+
+    def unit(n, i, length):
+        v = torch.zeros(length, dtype=torch.complex128, device="cuda")
+        v[i] = 1.0
+        return v
+
+    res = {"N": N, "dt": dt, "precision": "complex64", "no_coupling": [], "nn_coupling": [],
+           "full_coupling": []}
+    hk = W.global_controls(0.5)
+    t_mid = (np.arange(N) + 0.5) * dt
+    for case, h0_of in (("no_coupling", lambda n: [W.one_body(0.5, "z")]),
+                        ("nn_coupling", lambda n: W.ising_ring_terms(1.0, 1.0)),
+                        ("full_coupling", lambda n: W.full_coupling_terms(
+                            n, 1.0, [1.0 / dd for dd in range(1, n // 2 + 1)]))):
+        for n in range(3, nmax + 1):
+            rng = np.random.default_rng(1000 + n)
+            u_np = rng.uniform(-0.05, 0.05, (N, 2))
+            u_np[:, 0] += np.pi / (N * dt) * np.cos(t_mid)
+            u_np[:, 1] += np.pi / (N * dt) * np.sin(t_mid)
+            u = torch.tensor(u_np, device="cuda")
+            h0 = h0_of(n)
+            e = {"n": n}
+            Fs = []
+            if n <= dense_max:
+                Bd = q.Basis(n, "cyclic", n)
+                e["dense_m"] = 2 ** n
+                Fs.append(timed(Bd, h0, hk, u, None, (unit(n, 0, 2 ** n), unit(n, 2 ** n - 1, 2 ** n)),
+                                "dense", e))
+            Bs = q.Basis(n, "dihedral", 1)
+            up, dn = unit(n, 0, 2 ** n), unit(n, 2 ** n - 1, 2 ** n)
+            m0 = Bs.sizes[0]
+            pu, pd = Bs.to_blocks(up)[:m0].contiguous(), Bs.to_blocks(dn)[:m0].contiguous()
+            e["dn_a1_m"] = m0
+            Fs.append(timed(Bs, h0, hk, u, [0], (pu, pd), "dn_a1", e))
+            if case == "no_coupling":
+                Bj = q.Basis(n, "symmetric")
+                e["sn_m"] = n + 1
+                Fs.append(timed(Bj, h0, hk, u, [0], (unit(n, 0, n + 1), unit(n, n, n + 1)), "sn", e))
+            e["F"] = Fs[-1]
+            e["max_dF"] = max(Fs) - min(Fs)
+            if "dense_ms" in e:
+                e["speedup_dn"] = e["dense_ms"] / e["dn_a1_ms"]
+                if "sn_ms" in e:
+                    e["speedup_sn"] = e["dense_ms"] / e["sn_ms"]
+            res[case].append(e)
+            print(f"[bench] comparison {case} n={n}: {e}", file=sys.stderr, flush=True)
+    return res
 
 
 def cpu_baseline(w, v0, vf, nslices):
@@ -271,6 +364,11 @@ def main():
         del Ps, Ss, Bs
         torch.cuda.empty_cache()
 
+    comparison = None
+    if args.paper_comparison > 0:
+        comparison = paper_comparison(q, torch, W, args.paper_comparison)
+        torch.cuda.empty_cache()
+
     ring14 = None
     if args.ring14_slices > 0:
         # the 14-qubit ring with staggered controls under the two-site group (blocks 1300,
@@ -375,6 +473,8 @@ def main():
         "ring14_stagger": ring14,
         "batched_rings": batch,
     }
+    if comparison is not None:
+        line["paper_comparison"] = comparison
     if not args.no_cpu_baseline:
         print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, v0, vf, args.cpu_slices)

@@ -158,8 +158,9 @@ qoc_status qoc_system_block(qoc_system system, int block, int op, void* dst_dev,
  * when the whole pulse does not fit, propagators are recomputed segment by segment in
  * the backward sweep.  u_bound > 0 bounds |u[j,k]| for every
  * call that uses this plan; the plan uses it, with the exact 1-norms of the blocks, to
- * bound dt*||H0 + sum u_k H_k||_1 by the triangle inequality.  A slice whose control
- * exceeds u_bound makes the hot-path call report QOC_ERR_NUMERIC.
+ * bound dt*||H0 + sum u_k H_k||_1 by the triangle inequality.  A slice whose exact
+ * 1-norm exceeds that bound (possible only when some |u| exceeds u_bound) makes the
+ * hot-path call report QOC_ERR_NUMERIC.
  * Host-only apart from reading the free device memory and uploading small tables. */
 qoc_status qoc_plan_create(qoc_system system, int precision, int N, double dt, double u_bound,
                            size_t max_workspace_bytes, qoc_plan* out);
@@ -176,6 +177,16 @@ qoc_status qoc_plan_create(qoc_system system, int precision, int N, double dt, d
  * P: 1..65535.  Host-only. */
 qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* N, const double* dt, int precision,
                                    double u_bound, size_t max_workspace_bytes, qoc_plan* out);
+/* Execution plan over a subset of the system's blocks, in the order given (each index
+ * once, 0 <= blocks[i] < number of blocks): only those blocks' propagators, states and
+ * gradients are formed, and the caller's panels psi0 / psi_f hold only those blocks
+ * (length sum of m * copies over the subset, in the given order; qoc_plan_info [13]).
+ * The paper's runtime comparisons propagate the all-up and all-down states, which lie in
+ * the first block (Sec. III A: "only the first block ... necessary and sufficient"), so
+ * blocks = {0} is that computation.  Other arguments and errors as qoc_plan_create;
+ * QOC_ERR_INVALID_ARG for an empty, repeated or out-of-range block list.  Host-only. */
+qoc_status qoc_plan_create_blocks(qoc_system system, const int* blocks, int nblocks, int precision, int N,
+                                  double dt, double u_bound, size_t max_workspace_bytes, qoc_plan* out);
 void qoc_plan_free(qoc_plan plan);
 qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
 /* Plan facts: info[0] segment length, [1] number of segments, [2] Taylor degree step r,

@@ -119,9 +119,11 @@ class System:
 class Plan:
     """Execution plan (qoc_plan_create / qoc_plan_create_batched).
 
-    ``Plan(system, precision, N, dt, u_bound)`` plans one problem; ``Plan.batched(systems,
-    precision, Ns, dts, u_bound)`` plans several independent problems that share every
-    launch (systems may repeat, e.g. one Hamiltonian with many candidate pulses)."""
+    ``Plan(system, precision, N, dt, u_bound)`` plans one problem; ``blocks=[i, ...]`` limits
+    it to those blocks of the system (qoc_plan_create_blocks; panels then hold only them).
+    ``Plan.batched(systems, precision, Ns, dts, u_bound)`` plans several independent
+    problems that share every launch (systems may repeat, e.g. one Hamiltonian with many
+    candidate pulses)."""
 
     INFO_KEYS = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
                  "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid", "problems", "jobs",
@@ -129,10 +131,17 @@ class Plan:
     N_VARIANTS = 3
 
     def __init__(self, system: System, precision: str = "c128", N: int = 1, dt: float = 0.01,
-                 u_bound: float = 1.0, max_workspace_bytes: int = 0, _batch=None):
+                 u_bound: float = 1.0, max_workspace_bytes: int = 0, _batch=None, blocks=None):
         self.precision, self.u_bound = precision, float(u_bound)
         self._h = ctypes.c_void_p()
-        if _batch is None:
+        self.blocks = None if blocks is None else [int(b) for b in blocks]
+        if _batch is None and self.blocks is not None:
+            self.systems, self.Ns, self.dts = [system], [int(N)], [float(dt)]
+            arr = (ctypes.c_int * len(self.blocks))(*self.blocks)
+            C.check(C.lib().qoc_plan_create_blocks(system._h, arr, len(self.blocks), C.PRECISIONS[precision], int(N),
+                                                   float(dt), float(u_bound), int(max_workspace_bytes),
+                                                   ctypes.byref(self._h)))
+        elif _batch is None:
             self.systems, self.Ns, self.dts = [system], [int(N)], [float(dt)]
             C.check(C.lib().qoc_plan_create(system._h, C.PRECISIONS[precision], int(N), float(dt), float(u_bound),
                                             int(max_workspace_bytes), ctypes.byref(self._h)))
@@ -270,7 +279,7 @@ def fidelity_grad(plan: Plan, u, psi0, psif, workspace=None, check=True):
     assert u.shape == (plan.N, plan.K) and u.is_cuda
     psi0 = psi0.to(torch.complex128).contiguous()
     psif = psif.to(torch.complex128).contiguous()
-    D = plan.system.basis.dim
+    D = plan.info["total_panel"]
     assert psi0.numel() == D and psif.numel() == D
     out, grad = _run(plan, u.reshape(-1), psi0, psif, workspace, check)
     return out[0], grad.view(plan.N, plan.K)
@@ -305,7 +314,8 @@ def propagate(plan: Plan, u, workspace=None):
     per_problem, off = [], 0
     for sys_, N in zip(plan.systems, plan.Ns):
         outs = []
-        for m in sys_.basis.sizes:
+        sizes = sys_.basis.sizes if plan.blocks is None else [sys_.basis.sizes[b] for b in plan.blocks]
+        for m in sizes:
             outs.append(flat[off:off + N * m * m].view(N, m, m).transpose(1, 2))  # column-major
             off += N * m * m
         per_problem.append(outs)

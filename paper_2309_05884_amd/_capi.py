@@ -53,6 +53,9 @@ PROTOTYPES = {
     "qoc_plan_create_batched": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                                ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double,
                                                ctypes.c_size_t, ctypes.POINTER(vp)]),
+    "qoc_plan_create_blocks": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_size_t,
+                                              ctypes.POINTER(vp)]),
     "qoc_plan_free": (None, [vp]),
     "qoc_plan_workspace_size": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_size_t)]),
     "qoc_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),

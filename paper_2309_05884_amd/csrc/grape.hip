@@ -900,6 +900,112 @@ template <> struct XchgVal<double> {
   }
 };
 
+// A job whose rows fit one work-group (W = 1) needs no exchange: the new state goes straight
+// back into LDS, and the next slice's propagator entries (one column segment per lane, as
+// every column index k < m <= RB lands in the first column block of a wave) are loaded while
+// the current slice is applied, so the per-slice cost is two work-group barriers.
+template <typename T, int DIR>
+__device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j0, int len, char* smem_raw) {
+  typedef typename Vec16<T>::type TV;
+  constexpr int RPL = Vec16<T>::n, RB = CoopRows<T>::value;
+  const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
+  T* sre = reinterpret_cast<T*>(smem_raw);  // state [d][mp]
+  T* sim = sre + (size_t)d * mp;
+  T* pre = sim + (size_t)d * mp;             // wave partials [16][d][RB]
+  T* pim = pre + (size_t)16 * d * RB;
+  T* S = tplane<T>(ws, off_T, DIR == 0 ? jb.psi_off : jb.lam_off);
+  const size_t ncol = DIR == 0 ? (size_t)(N + 1) * d : (size_t)N * d;
+  const size_t ps = (size_t)mp * ncol;
+  const size_t plane = (size_t)mp * mp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rv = lane & 15, kk = lane >> 4;
+  const int row = rv * RPL, k = 4 * wave + kk;  // rows row .. row + RPL - 1 of column k
+  const bool act = row < m && k < m;
+  {
+    const int col_in = DIR == 0 ? seg_j0 : seg_j0 + len - 1;
+    for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
+      const int c = idx / mp, i = idx % mp;
+      const size_t g = ((size_t)col_in * d + c) * mp + i;
+      sre[idx] = S[g];
+      sim[idx] = S[g + ps];
+    }
+  }
+  TV ur = {}, ui = {};
+  if (act) {
+    const T* U = entry_U<T>(jb, ws, off_T, DIR == 0 ? 0 : len - 1, DIR) + row + (size_t)k * mp;
+    ur = *reinterpret_cast<const TV*>(U);
+    ui = *reinterpret_cast<const TV*>(U + plane);
+  }
+  __syncthreads();
+  for (int it = 0; it < len; ++it) {
+    const int jl = DIR == 0 ? it : len - 1 - it;
+    TV nr = {}, ni = {};
+    if (act && it + 1 < len) {
+      const T* U = entry_U<T>(jb, ws, off_T, DIR == 0 ? jl + 1 : jl - 1, DIR) + row + (size_t)k * mp;
+      nr = *reinterpret_cast<const TV*>(U);
+      ni = *reinterpret_cast<const TV*>(U + plane);
+    }
+    T a[2][2][RPL];  // [copy][re, im][row]
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) a[c][0][t] = a[c][1][t] = T(0);
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c >= d) break;
+        const T pr = sre[c * mp + k], pi = sim[c * mp + k];
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          a[c][0][t] = ur[t] * pr - ui[t] * pi;
+          a[c][1][t] = ur[t] * pi + ui[t] * pr;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          T v = a[c][h][t];
+          v += __shfl_xor(v, 16);
+          v += __shfl_xor(v, 32);
+          a[c][h][t] = v;
+        }
+    if (kk == 0)
+      for (int c = 0; c < d; ++c)
+#pragma unroll
+        for (int t = 0; t < RPL; ++t) {
+          pre[((size_t)wave * d + c) * RB + row + t] = a[c][0][t];
+          pim[((size_t)wave * d + c) * RB + row + t] = a[c][1][t];
+        }
+    __syncthreads();
+    const int col_out = DIR == 0 ? seg_j0 + jl + 1 : seg_j0 + jl - 1;
+    if ((int)threadIdx.x < RB * d) {
+      const int c = threadIdx.x / RB, i = threadIdx.x % RB;
+      T vr = T(0), vi = T(0);
+      for (int w = 0; w < 16; ++w) {
+        vr += pre[((size_t)w * d + c) * RB + i];
+        vi += pim[((size_t)w * d + c) * RB + i];
+      }
+      if (i >= m) vr = vi = T(0);
+      if (i < mp) {
+        sre[c * mp + i] = vr;
+        sim[c * mp + i] = vi;
+        if (col_out >= 0) {
+          const size_t g = ((size_t)col_out * d + c) * mp + i;
+          S[g] = vr;
+          S[g + ps] = vi;
+        }
+      }
+    }
+    __syncthreads();
+    ur = nr;
+    ui = ni;
+  }
+}
+
 template <typename T, int DIR>
 __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njobs, char* ws, size_t off_T,
                                                      const int* ent_s, const int* ent_q, int r, int seg_j0,
@@ -917,6 +1023,10 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
   const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
   const int W = (mp + RB - 1) / RB;
   if ((int)blockIdx.x >= W) return;
+  if (W == 1) {
+    sweep_single<T, DIR>(jb, ws, off_T, seg_j0, len, smem_raw);
+    return;
+  }
   int* ctl = ctl_all + 4 * J;
   const int mode = coop_decide(ctl, W, flags);
   if (mode == kCoopSolo) {
@@ -1785,7 +1895,15 @@ struct ProblemSpec {
   qoc_system_s* sys;
   int N;
   double dt;
+  // the blocks this problem carries (all of the system's, or a chosen subset); state_off
+  // is the block's offset in this problem's panel
+  std::vector<qoc_system_s::Block> blocks;
 };
+
+static ProblemSpec all_blocks(qoc_system_s* sys, int N, double dt) {
+  QOC_REQUIRE(sys, QOC_ERR_INVALID_ARG, "null system");
+  return ProblemSpec{sys, N, dt, sys->blocks};
+}
 
 static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precision, double u_bound, size_t max_ws) {
   QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
@@ -1814,7 +1932,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     P->Nmax = std::max(P->Nmax, pr.N);
     P->Kmax = std::max(P->Kmax, pr.sys->K);
     // norm bound by the triangle inequality on the exact block 1-norms
-    for (auto& b : pr.sys->blocks) {
+    for (auto& b : pr.blocks) {
       double v = b.norm1[0];
       for (int k = 1; k <= pr.sys->K; ++k) v += u_bound * b.norm1[k];
       nb = std::max(nb, pr.dt * v);
@@ -1868,7 +1986,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   QOC_REQUIRE(max_mp <= 4096, QOC_ERR_UNSUPPORTED, "blocks larger than 4096 are not supported by the sweep kernels");
   size_t lds_elems = 0;
   for (auto& pr : probs)
-    for (auto& b : pr.sys->blocks)
+    for (auto& b : pr.blocks)
       lds_elems = std::max(lds_elems, (size_t)2 * b.d * b.mp * (1 + sweep_kgroups(b.mp, (int)P->elem)));
   P->sweep_lds_elems = lds_elems;
   QOC_REQUIRE(lds_elems * P->elem <= 160 * 1024, QOC_ERR_UNSUPPORTED, "block panel too large for the LDS-resident sweep");
@@ -1879,7 +1997,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   // ping-pong buffers) for one chunk; fixed state bytes
   size_t per_slice = 0, per_scratch = 0, fixed = 0;
   for (auto& pr : probs)
-    for (auto& b : pr.sys->blocks) {
+    for (auto& b : pr.blocks) {
       per_slice += (size_t)2 * 2 * b.mp * b.mp * P->elem;
       per_scratch += (size_t)(P->r + 2) * 2 * b.mp * b.mp * P->elem;
       fixed += (size_t)2 * b.mp * ((size_t)(pr.N + 1) * b.d + (size_t)pr.N * b.d) * P->elem;
@@ -1888,7 +2006,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   auto grad_bytes = [&](int ch) {
     size_t g = 0;
     for (auto& pr : probs)
-      for (auto& b : pr.sys->blocks) {
+      for (auto& b : pr.blocks) {
         const int cc = (ch * b.d + 15) / 16 * 16;
         g += (size_t)nslots * 2 * b.mp * cc * P->elem + (size_t)cc * K * 16;
       }
@@ -1948,7 +2066,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   };
   P->off_flags = take(256);
   long long njobs_total = 0;
-  for (auto& pr : probs) njobs_total += (long long)pr.sys->blocks.size();
+  for (auto& pr : probs) njobs_total += (long long)pr.blocks.size();
   QOC_REQUIRE(njobs_total < (1LL << 30), QOC_ERR_INVALID_ARG, "too many (problem, block) pairs");
   P->entries_per_seg = (long long)P->seg_len * njobs_total;
   P->off_ent = take((size_t)P->entries_per_seg * 16);
@@ -1963,7 +2081,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     pd.K = pr.sys->K;
     pd.dt = pr.dt;
     pd.u_off = u_off;
-    for (auto& b : pr.sys->blocks) {
+    for (auto& b : pr.blocks) {
       JobDev j{};
       j.m = b.m;
       j.mp = b.mp;
@@ -2003,7 +2121,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     P->probs.push_back(pd);
     u_off += (long long)pr.N * pr.sys->K;
     long long D = 0;
-    for (auto& b : pr.sys->blocks) D += (long long)b.m * b.d;
+    for (auto& b : pr.blocks) D += (long long)b.m * b.d;
     state_base += D;
   }
   P->total_u = u_off;
@@ -2092,7 +2210,28 @@ qoc_status qoc_plan_create(qoc_system S, int precision, int N, double dt, double
   return guarded([&] {
     QOC_REQUIRE(S && out, QOC_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
-    *out = build_plan({ProblemSpec{S, N, dt}}, precision, u_bound, max_ws);
+    *out = build_plan({all_blocks(S, N, dt)}, precision, u_bound, max_ws);
+  });
+}
+
+qoc_status qoc_plan_create_blocks(qoc_system S, const int* blocks, int nblocks, int precision, int N, double dt,
+                                  double u_bound, size_t max_ws, qoc_plan* out) {
+  return guarded([&] {
+    QOC_REQUIRE(S && blocks && out, QOC_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    const int nb = (int)S->blocks.size();
+    QOC_REQUIRE(nblocks >= 1 && nblocks <= nb, QOC_ERR_INVALID_ARG, "nblocks must be in 1..number of blocks");
+    ProblemSpec pr{S, N, dt, {}};
+    int64_t off = 0;
+    for (int i = 0; i < nblocks; ++i) {
+      QOC_REQUIRE(blocks[i] >= 0 && blocks[i] < nb, QOC_ERR_INVALID_ARG, "block index out of range");
+      for (int k = 0; k < i; ++k) QOC_REQUIRE(blocks[k] != blocks[i], QOC_ERR_INVALID_ARG, "repeated block index");
+      qoc_system_s::Block b = S->blocks[blocks[i]];
+      b.state_off = off;
+      off += (int64_t)b.m * b.d;
+      pr.blocks.push_back(b);
+    }
+    *out = build_plan({pr}, precision, u_bound, max_ws);
   });
 }
 
@@ -2103,7 +2242,7 @@ qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* 
     *out = nullptr;
     QOC_REQUIRE(P >= 1 && P <= 65535, QOC_ERR_INVALID_ARG, "P must be in 1..65535");
     std::vector<ProblemSpec> probs;
-    for (int p = 0; p < P; ++p) probs.push_back(ProblemSpec{systems[p], N[p], dt[p]});
+    for (int p = 0; p < P; ++p) probs.push_back(all_blocks(systems[p], N[p], dt[p]));
     *out = build_plan(probs, precision, u_bound, max_ws);
   });
 }

@@ -56,6 +56,8 @@ def test_null_handles_rejected():
     out = ctypes.c_void_p()
     assert L.qoc_project(None, None, 0, None, None, 0, None, ctypes.byref(out)) == 1
     assert L.qoc_plan_create(None, 0, 10, 0.1, 1.0, 0, ctypes.byref(out)) == 1
+    blocks = (ctypes.c_int * 1)(0)
+    assert L.qoc_plan_create_blocks(None, blocks, 1, 0, 10, 0.1, 1.0, 0, ctypes.byref(out)) == 1
     assert L.qoc_fidelity_grad(None, None, None, None, None, None, None, 0, None) == 1
     assert L.qoc_propagate(None, None, None, None, 0, None) == 1
 
