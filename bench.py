@@ -68,9 +68,10 @@ def parse():
                     help="problems of the 256-ring batched workload timed in one plan (0: skip)")
     ap.add_argument("--dense-slices", type=int, default=16,
                     help="slices of the same pulse timed on the dense 4096-dim space (0: skip)")
-    ap.add_argument("--paper-comparison", type=int, default=0, metavar="NMAX",
+    ap.add_argument("--paper-comparison", type=int, default=14, metavar="NMAX",
                     help="also time the transfer all-up -> all-down for n = 3..NMAX qubits on the dense "
-                         "space, the first D_n block and (no coupling) the first S_n block (0: skip)")
+                         "space (n <= 12), the first D_n block and (no coupling) the first S_n block "
+                         "(0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -168,7 +169,7 @@ def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, p
 
 def paper_comparison(q, torch, W, nmax, N=100, dt=0.05, dense_max=12, steps=2):
     """Milliseconds per fidelity+gradient step of the transfer all-up -> all-down (the
-    runtime comparison of the paper's Sec. III A): on the dense 2^n space (n <= dense_max),
+    runtime comparison of the paper's Sec. II B, Fig. 3a/b): on the dense 2^n space (n <= dense_max),
     on the first D_n block alone, and, without coupling, on the first S_n block alone.
     Eq. (5) with B_z = 1 and c_cpl = 0 (no coupling) or 1 (nearest neighbours), and Eq. (7)
     with B_z = 1 and c^(d) = 1/d for d = 1 .. floor(n/2) (full coupling, D_n only); global

@@ -182,7 +182,8 @@ qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* 
  * gradients are formed, and the caller's panels psi0 / psi_f hold only those blocks
  * (length sum of m * copies over the subset, in the given order; qoc_plan_info [13]).
  * The paper's runtime comparisons propagate the all-up and all-down states, which lie in
- * the first block (Sec. III A: "only the first block ... necessary and sufficient"), so
+ * the first block (Sec. II B, Sec. III A: both states evolve inside the first subspace, so
+ * the first block of each transformed operator is all the computation needs), so
  * blocks = {0} is that computation.  Other arguments and errors as qoc_plan_create;
  * QOC_ERR_INVALID_ARG for an empty, repeated or out-of-range block list.  Host-only. */
 qoc_status qoc_plan_create_blocks(qoc_system system, const int* blocks, int nblocks, int precision, int N,

@@ -1,5 +1,5 @@
 """The paper's runtime comparison computes the transfer all-up -> all-down, which stays in
-the first block (Sec. III A): dense 2^n, the first D_n block (A1) and, without coupling,
+the first block (Sec. II B, Sec. III A): dense 2^n, the first D_n block (A1) and, without coupling,
 the first S_n block (J = n/2).  Plans over block subsets (qoc_plan_create_blocks) against
 the dense path and, without coupling, against the independent product-of-rotations closed
 form (the qubits evolve separately)."""
