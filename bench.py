@@ -72,6 +72,8 @@ def parse():
                     help="also time the transfer all-up -> all-down for n = 3..NMAX qubits on the dense "
                          "space (n <= 12), the first D_n block and (no coupling) the first S_n block "
                          "(0: skip)")
+    ap.add_argument("--optimizer", type=int, default=1,
+                    help="also run the L-BFGS GRAPE optimiser legs (1) or skip them (0)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -257,6 +259,70 @@ def paper_comparison(q, torch, W, nmax, N=100, dt=0.05, dense_max=12, steps=2):
     return res
 
 
+def optimizer_leg(q, torch, W, N=100, dt=0.05):
+    """GRAPE optimisation (qoc_optimize_lbfgs) of the transfer all-up -> all-down in the first
+    D_n block, nearest-neighbour (Eq. (5), c_cpl = 1) against full coupling (Eq. (7),
+    c^(d) = 1/d), n = 4..6 qubits (the convergence comparison of Fig. 4e), complex128,
+    seeded U[-0.1, 0.1] start, F target 0.999; and one larger run (12 qubits, first block of
+    224, 500 slices, complex64) that measures the optimiser's own overhead per evaluation
+    against a plain objective+gradient call."""
+    hk = W.global_controls(0.5)
+
+    def first_block(n, h0, prec, Nn, u_bound):
+        B = q.Basis(n, "dihedral", 1)
+        S = q.System(B, h0, hk)
+        P = q.Plan(S, prec, Nn, dt, u_bound, blocks=[0])
+        up = torch.zeros(2 ** n, dtype=torch.complex128, device="cuda")
+        dn = torch.zeros(2 ** n, dtype=torch.complex128, device="cuda")
+        up[0] = 1.0
+        dn[-1] = 1.0
+        m0 = B.sizes[0]
+        return P, B.to_blocks(up)[:m0].contiguous(), B.to_blocks(dn)[:m0].contiguous()
+
+    def run(P, u0, pu, pd, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = q.optimize_lbfgs(P, u0, pu, pd, **kw)
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    out = {"N": N, "dt": dt, "precision": "complex128", "f_target": 0.999, "runs": []}
+    for n in (4, 5, 6):
+        for case, h0 in (("nn_coupling", W.ising_ring_terms(1.0, 1.0)),
+                         ("full_coupling", W.full_coupling_terms(n, 1.0, [1.0 / d for d in range(1, n // 2 + 1)]))):
+            P, pu, pd = first_block(n, h0, "c128", N, 4.0)
+            rng = np.random.default_rng(500 + n)
+            u0 = torch.tensor(rng.uniform(-0.1, 0.1, (N, 2)), device="cuda")
+            r, ms = run(P, u0, pu, pd, max_iter=1000, memory=10, step0=0.2, f_target=0.999)
+            e = {"n": n, "case": case, "m": int(pu.numel()), "F0": float(r["hist"][0]), "F": r["F"],
+                 "iterations": r["iterations"], "evaluations": r["evaluations"], "reason": r["reason"],
+                 "ms": ms}
+            out["runs"].append(e)
+            print(f"[bench] optimizer {e}", file=sys.stderr, flush=True)
+    # overhead of the optimiser around its evaluations, on a larger block
+    n, Nn = 12, 500
+    P, pu, pd = first_block(n, W.ising_ring_terms(1.0, 1.0), "c64", Nn, 4.0)
+    rng = np.random.default_rng(512)
+    u0 = torch.tensor(rng.uniform(-0.1, 0.1, (Nn, 2)), device="cuda")
+    q.optimize_lbfgs(P, u0, pu, pd, max_iter=2)  # warm-up
+    r, ms = run(P, u0, pu, pd, max_iter=40, memory=10, step0=0.2, f_target=0.99)
+    ws = P.workspace()
+    q.fidelity_grad(P, u0, pu, pd, workspace=ws, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        q.fidelity_grad(P, u0, pu, pd, workspace=ws, check=False)
+    torch.cuda.synchronize()
+    eval_ms = (time.perf_counter() - t0) * 1e3 / 5
+    big = {"n": n, "m": int(pu.numel()), "N": Nn, "precision": "complex64", "F0": float(r["hist"][0]),
+           "F": r["F"], "iterations": r["iterations"], "evaluations": r["evaluations"], "reason": r["reason"],
+           "ms": ms, "ms_per_evaluation": ms / r["evaluations"], "plain_evaluation_ms": eval_ms,
+           "overhead_frac": 1.0 - r["evaluations"] * eval_ms / ms}
+    out["large"] = big
+    print(f"[bench] optimizer large {big}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(w, v0, vf, nslices):
     import numpy as np
     from threadpoolctl import threadpool_info
@@ -369,6 +435,7 @@ def main():
     if args.paper_comparison > 0:
         comparison = paper_comparison(q, torch, W, args.paper_comparison)
         torch.cuda.empty_cache()
+    optimizer = optimizer_leg(q, torch, W) if args.optimizer else None
 
     ring14 = None
     if args.ring14_slices > 0:
@@ -476,6 +543,8 @@ def main():
     }
     if comparison is not None:
         line["paper_comparison"] = comparison
+    if optimizer is not None:
+        line["optimizer"] = optimizer
     if not args.no_cpu_baseline:
         print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, v0, vf, args.cpu_slices)

@@ -263,6 +263,56 @@ qoc_status qoc_profile_end(double* ms, int64_t* launches, int cap);
 qoc_status qoc_plan_slice_stats(qoc_plan plan, const double* u_dev, int32_t* q, int32_t* s, double* norms,
                                 void* stream);
 
+/* GRAPE pulse optimisation: GRAPE raises the objective by gradient steps on every slice
+ * sample (Sec. I), with the gradient of App. B (here the exact one of qoc_fidelity_grad).
+ * The paper's update rule is in its Supplementary Material; this entry point uses
+ * limited-memory BFGS ascent on F(u) (Nocedal, Math. Comp. 1980) with a backtracking
+ * Armijo line search:
+ *   direction d = H g by the two-loop recursion over the last `memory` kept pairs
+ *   s = u_new - u_old, y = g_old - g_new (g = dF/du), H0 = (s.y / y.y) I from the newest
+ *   pair; with no pair d = (step0 / max|g|) g; a pair is kept when
+ *   s.y > 1e-10 sqrt(s.s y.y); the memory is cleared when g.d <= 0; trials u + alpha d
+ *   with alpha = 1, 1/2, ... (up to max_backtrack halvings) are accepted when the
+ *   evaluation's status word is 0 and F(u + alpha d) >= F(u) + c1 alpha g.d.
+ * Stops when F >= f_target (reason QOC_OPT_TARGET), max|g| <= gtol (QOC_OPT_GTOL), after
+ * max_iter accepted steps (QOC_OPT_MAX_ITER) or when a line search accepts no trial
+ * (QOC_OPT_LINE_SEARCH_FAILED).  memory: 1..64; c1 in (0, 1); step0 > 0;
+ * max_backtrack: 0..60; max_iter >= 0.
+ * plan: a one-problem plan (QOC_ERR_UNSUPPORTED otherwise).  u_dev: float64 [N][K] device
+ * controls, the start on entry and the last accepted point on return.  psi0_dev /
+ * psif_dev: as for qoc_fidelity_grad.  workspace: caller-owned device memory of at least
+ * qoc_optimize_workspace_size(plan, memory, &bytes) bytes; its first
+ * qoc_plan_workspace_size bytes serve the evaluations, the rest holds the pairs and
+ * vectors (about (2 memory + 6) N K doubles).  hist_host (host, hist_cap entries): F at
+ * the start and after every accepted step, as many as fit.  result: accepted steps,
+ * objective evaluations, stop reason and the final F.  The direction, trial point and pair
+ * updates run as FP64 kernels with fixed-order reductions; the line search decides on the
+ * host, so the call synchronises `stream` after every evaluation and cannot be captured.
+ * A trial outside the plan's norm bound (status bit 0) or with a non-finite value counts as
+ * rejected.  QOC_ERR_NUMERIC if the start is not a clean evaluation or a co-operative sweep
+ * stalls. */
+typedef struct qoc_lbfgs_options {
+  int max_iter;
+  int memory;
+  double step0;
+  double c1;
+  int max_backtrack;
+  double f_target;
+  double gtol;
+} qoc_lbfgs_options;
+typedef struct qoc_lbfgs_result {
+  int iterations;
+  int evaluations;
+  int reason;
+  double F;
+} qoc_lbfgs_result;
+enum { QOC_OPT_TARGET = 0, QOC_OPT_GTOL = 1, QOC_OPT_MAX_ITER = 2, QOC_OPT_LINE_SEARCH_FAILED = 3 };
+qoc_status qoc_optimize_workspace_size(qoc_plan plan, int memory, size_t* bytes);
+qoc_status qoc_optimize_lbfgs(qoc_plan plan, const qoc_lbfgs_options* options, double* u_dev,
+                              const void* psi0_dev, const void* psif_dev, void* workspace,
+                              size_t workspace_bytes, void* stream, double* hist_host, int hist_cap,
+                              qoc_lbfgs_result* result);
+
 /* Status text and the calling thread's last error detail. */
 const char* qoc_status_string(qoc_status status);
 const char* qoc_last_error(void);

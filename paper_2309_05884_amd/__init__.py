@@ -20,7 +20,8 @@ from . import _capi as C
 from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "propagate", "GrapeFidelity",
-           "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep"]
+           "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
+           "optimize_lbfgs"]
 
 library_path = C.LIB_PATH
 
@@ -320,6 +321,36 @@ def propagate(plan: Plan, u, workspace=None):
             off += N * m * m
         per_problem.append(outs)
     return per_problem[0] if plan.P == 1 else per_problem
+
+
+def optimize_lbfgs(plan: Plan, u, psi0, psif, max_iter=100, memory=10, step0=0.1, c1=1e-4,
+                   max_backtrack=20, f_target=1.0, gtol=0.0):
+    """GRAPE optimisation of a one-problem plan's controls by L-BFGS ascent with an Armijo
+    line search (qoc_optimize_lbfgs).  Returns a dict: u (the last accepted controls,
+    (N, K) on the device), F, hist (F at the start and after every accepted step),
+    iterations, evaluations and reason ("target", "gtol", "max_iter",
+    "line_search_failed")."""
+    torch = _torch()
+    assert plan.P == 1
+    u = u.to(torch.float64).contiguous().clone()
+    assert u.shape == (plan.N, plan.K) and u.is_cuda
+    psi0 = psi0.to(torch.complex128).contiguous()
+    psif = psif.to(torch.complex128).contiguous()
+    D = plan.info["total_panel"]
+    assert psi0.numel() == D and psif.numel() == D
+    L = C.lib()
+    nbytes = ctypes.c_size_t()
+    C.check(L.qoc_optimize_workspace_size(plan._h, int(memory), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=u.device)
+    opts = C.QocLbfgsOptions(int(max_iter), int(memory), float(step0), float(c1), int(max_backtrack),
+                             float(f_target), float(gtol))
+    hist = (ctypes.c_double * (int(max_iter) + 1))()
+    res = C.QocLbfgsResult()
+    C.check(L.qoc_optimize_lbfgs(plan._h, ctypes.byref(opts), _ptr(u), _ptr(psi0), _ptr(psif), _ptr(ws),
+                                 ctypes.c_size_t(ws.numel()), _stream(), hist, int(max_iter) + 1,
+                                 ctypes.byref(res)))
+    return {"u": u, "F": res.F, "hist": np.array(hist[:res.iterations + 1]), "iterations": res.iterations,
+            "evaluations": res.evaluations, "reason": C.OPT_REASONS[res.reason]}
 
 
 class CapturedStep:

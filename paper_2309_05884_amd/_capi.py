@@ -23,6 +23,20 @@ class QocTerm(ctypes.Structure):
                 ("z_mask", ctypes.c_uint64)]
 
 
+class QocLbfgsOptions(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("memory", ctypes.c_int), ("step0", ctypes.c_double),
+                ("c1", ctypes.c_double), ("max_backtrack", ctypes.c_int), ("f_target", ctypes.c_double),
+                ("gtol", ctypes.c_double)]
+
+
+class QocLbfgsResult(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("evaluations", ctypes.c_int), ("reason", ctypes.c_int),
+                ("F", ctypes.c_double)]
+
+
+OPT_REASONS = {0: "target", 1: "gtol", 2: "max_iter", 3: "line_search_failed"}
+
+
 class QocError(RuntimeError):
     def __init__(self, status, detail):
         self.status = status
@@ -72,6 +86,10 @@ PROTOTYPES = {
     "qoc_variant_name": (ctypes.c_char_p, [ctypes.c_int, ctypes.c_int]),
     "qoc_plan_autotune": (ctypes.c_int, [vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_double)]),
+    "qoc_optimize_workspace_size": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "qoc_optimize_lbfgs": (ctypes.c_int, [vp, ctypes.POINTER(QocLbfgsOptions), vp, vp, vp, vp, ctypes.c_size_t, vp,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                          ctypes.POINTER(QocLbfgsResult)]),
 }
 
 

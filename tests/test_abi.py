@@ -40,6 +40,15 @@ def test_term_struct_layout():
     assert C.QocTerm.coeff.offset == 16 and C.QocTerm.x_mask.offset == 32
 
 
+def test_optimizer_struct_layout():
+    """The ctypes mirrors of qoc_lbfgs_options / qoc_lbfgs_result match the C layout
+    (natural alignment on x86-64)."""
+    assert ctypes.sizeof(C.QocLbfgsOptions) == 48
+    assert C.QocLbfgsOptions.step0.offset == 8 and C.QocLbfgsOptions.max_backtrack.offset == 24
+    assert C.QocLbfgsOptions.f_target.offset == 32 and C.QocLbfgsOptions.gtol.offset == 40
+    assert ctypes.sizeof(C.QocLbfgsResult) == 24 and C.QocLbfgsResult.F.offset == 16
+
+
 @pytest.mark.parametrize("n,group,stride", [(0, 0, 1), (31, 0, 1), (6, 0, 4), (6, 7, 1), (5000, 2, 1), (6, 1, 0)])
 def test_build_basis_rejects_bad_arguments(n, group, stride):
     L = C.lib()
@@ -60,6 +69,12 @@ def test_null_handles_rejected():
     assert L.qoc_plan_create_blocks(None, blocks, 1, 0, 10, 0.1, 1.0, 0, ctypes.byref(out)) == 1
     assert L.qoc_fidelity_grad(None, None, None, None, None, None, None, 0, None) == 1
     assert L.qoc_propagate(None, None, None, None, 0, None) == 1
+    nbytes = ctypes.c_size_t()
+    assert L.qoc_optimize_workspace_size(None, 10, ctypes.byref(nbytes)) == 1
+    opts = C.QocLbfgsOptions(10, 10, 0.1, 1e-4, 20, 1.0, 0.0)
+    res = C.QocLbfgsResult()
+    assert L.qoc_optimize_lbfgs(None, ctypes.byref(opts), None, None, None, None, 0, None, None, 0,
+                                ctypes.byref(res)) == 1
 
 
 def test_symmetric_basis_is_host_only():
