@@ -29,7 +29,10 @@ def gate_unitaries(blocks, u, dt):
 
 def gate_fidelity(Ka, Kb, weights):
     """t = sum_theta w_theta Tr(Ka_theta^dag Kb_theta), D = sum_theta w_theta m_theta,
-    F = |t|^2 / D^2."""
+    F_paper = |t|^2 / D^2 and F = |t|^2 / (na nb) with na = sum_theta w_theta ||Ka_theta||_F^2
+    (nb likewise), which equals F_paper for unitaries and is what the library reports."""
     t = sum(w * np.trace(a.conj().T @ b) for a, b, w in zip(Ka, Kb, weights))
     D = float(sum(w * a.shape[0] for a, w in zip(Ka, weights)))
-    return {"F": abs(t) ** 2 / D ** 2, "t": t, "D": D}
+    na = float(sum(w * np.sum(np.abs(a) ** 2) for a, w in zip(Ka, weights)))
+    nb = float(sum(w * np.sum(np.abs(b) ** 2) for b, w in zip(Kb, weights)))
+    return {"F": abs(t) ** 2 / (na * nb), "F_paper": abs(t) ** 2 / D ** 2, "t": t, "D": D, "na": na, "nb": nb}

@@ -34,6 +34,8 @@ def test_block_route_equals_dense_route(n):
     assert abs(fd["t"] - np.trace(Kda.conj().T @ Kdb)) <= 1e-12 * 2 ** n
     assert abs(fb["t"] - fd["t"]) <= 1e-11 * 2 ** n
     assert abs(fb["F"] - fd["F"]) <= 1e-12 and fb["D"] == 2 ** n
+    # unitaries: the norm-normalised F is the paper's |Tr / 2^n|^2
+    assert abs(fb["na"] - 2 ** n) <= 1e-10 and abs(fb["F"] - fb["F_paper"]) <= 1e-12
 
 
 def test_single_slice_is_the_matrix_exponential():
@@ -77,5 +79,8 @@ def test_fidelity_invariances():
     f1 = gate.gate_fidelity(Ka, Kb, w)["F"]
     f2 = gate.gate_fidelity(Ka, [phase * K for K in Kb], w)["F"]
     assert abs(f1 - f2) <= 1e-14 and 0.0 <= f1 < 1.0
+    # a non-unitary scale drops out of F but not out of F_paper
+    f3 = gate.gate_fidelity(Ka, [1.01 * K for K in Ka], w)
+    assert abs(f3["F"] - 1.0) <= 1e-13 and abs(f3["F_paper"] - 1.01 ** 2) <= 1e-12
     for K in Ka:
         assert np.abs(K.conj().T @ K - np.eye(K.shape[0])).max() <= 1e-12
