@@ -72,6 +72,8 @@ def parse():
                     help="also time the transfer all-up -> all-down for n = 3..NMAX qubits on the dense "
                          "space (n <= 12), the first D_n block and (no coupling) the first S_n block "
                          "(0: skip)")
+    ap.add_argument("--gate", type=int, default=1,
+                    help="also time the unitary of the whole pulse and the gate fidelity (1) or skip (0)")
     ap.add_argument("--optimizer", type=int, default=1,
                     help="also run the L-BFGS GRAPE optimiser legs (1) or skip them (0)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -259,6 +261,43 @@ def paper_comparison(q, torch, W, nmax, N=100, dt=0.05, dense_max=12, steps=2):
     return res
 
 
+def gate_leg(q, torch, P, dev, B, w, reps=3):
+    """The unitary of the whole pulse for every block of the ring-12 workload
+    (qoc_gate_propagate: the slice propagators, then their time-ordered product as a tree
+    of batched complex GEMMs) and the gate fidelity of Sec. III B between the unitaries
+    of two nearby pulses.  The product tree's algorithmic flops are (N - 1) 8 m^3 per
+    block (complex products)."""
+    u = dev["u"]
+    u2 = (u + 0.01 * torch.sin(torch.arange(u.numel(), device="cuda", dtype=torch.float64)).view_as(u)).contiguous()
+    K = q.gate_propagate(P, u)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        K = q.gate_propagate(P, u)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    q.profile_begin(reps * 8192)
+    for _ in range(reps):
+        q.gate_propagate(P, u)
+    prof = q.profile_end()
+    chain_ms = prof["gate_chain"][0] / reps
+    flops = sum(8.0 * m ** 3 for m in B.sizes) * (w.N - 1)
+    K2 = q.gate_propagate(P, u2)
+    f_self = q.gate_fidelity(P, K, K).cpu().numpy()
+    f_pair = q.gate_fidelity(P, K, K2).cpu().numpy()
+    res = {"workload": "ring12_heisenberg_D12_gate", "slices": w.N, "blocks": list(B.sizes),
+           "precision": "complex64 MFMA", "ms": ms, "propagator_ms": prof["propagator_gemm"][0] / reps,
+           "chain_ms": chain_ms, "chain_launches": prof["gate_chain"][1] // reps,
+           "chain_tflops": flops / (chain_ms * 1e-3) / 1e12,
+           "chain_frac_of_fp32_peak": flops / (chain_ms * 1e-3) / 157.3e12,
+           "F_self": float(f_self[0]), "F_nearby_pulse": float(f_pair[0]), "D": float(f_pair[3]),
+           "unitarity_drift": float(f_self[4] / f_self[3] - 1.0)}
+    print(f"[bench] gate {res}", file=sys.stderr, flush=True)
+    return res
+
+
 def optimizer_leg(q, torch, W, N=100, dt=0.05):
     """GRAPE optimisation (qoc_optimize_lbfgs) of the transfer all-up -> all-down in the first
     D_n block, nearest-neighbour (Eq. (5), c_cpl = 1) against full coupling (Eq. (7),
@@ -380,6 +419,7 @@ def main():
     flops32, qs32, ss32 = gemm_flops(q, P32, dev, B.sizes)
     var32 = P32.variant_name
     print(f"[bench] c64 {ms32:.2f} ms/step  profile {prof32}", file=sys.stderr, flush=True)
+    gate = gate_leg(q, torch, P32, dev, B, w) if args.gate else None
     del P32
     torch.cuda.empty_cache()
 
@@ -545,6 +585,8 @@ def main():
         line["paper_comparison"] = comparison
     if optimizer is not None:
         line["optimizer"] = optimizer
+    if gate is not None:
+        line["gate"] = gate
     if not args.no_cpu_baseline:
         print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, v0, vf, args.cpu_slices)

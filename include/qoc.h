@@ -241,13 +241,39 @@ qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi
                              const void* psif_dev, double* out_dev, double* grad_dev,
                              void* workspace, size_t workspace_bytes, void* stream);
 
+/* Gate propagation: the unitary a pulse implements, K = U_{N-1} ... U_1 U_0 (Eq. (3)'s
+ * slice propagators in time order), for every block of a one-problem plan; Sec. III B
+ * compares two such products by the gate fidelity below.  The propagators are formed as
+ * in qoc_propagate and multiplied as a balanced tree of batched complex GEMMs on the MFMA
+ * units (log2 N levels, N - 1 products per block).  K_out_dev receives, block after
+ * block, column-major m x m interleaved complex128 matrices (length sum of m^2).
+ * Requires every propagator of the pulse to fit the plan's workspace (one segment,
+ * qoc_plan_info [1] == 1), else QOC_ERR_UNSUPPORTED; QOC_ERR_UNSUPPORTED for a batched
+ * plan.  Like qoc_propagate it reports no status word: qoc_plan_slice_stats or
+ * qoc_fidelity_grad flag controls beyond the plan's norm bound.  Asynchronous on
+ * `stream`; uses the workspace as qoc_fidelity_grad does. */
+qoc_status qoc_gate_propagate(qoc_plan plan, const double* u_dev, void* K_out_dev, void* workspace,
+                              size_t workspace_bytes, void* stream);
+/* Gate fidelity of two block-diagonal unitaries in the layout qoc_gate_propagate writes:
+ * t = sum_blocks d Tr(Ka^dag Kb) with d the block's copies (2 for E_m, 1 otherwise),
+ * na = sum_blocks d ||Ka||_F^2, nb likewise, D = sum_blocks d m, and F = |t|^2 / (na nb).
+ * For unitaries na = nb = D, so F is Sec. III B's |Tr(K_a^dag K_b) / 2^n|^2 when the plan
+ * covers every block of a ring group (D = 2^n); over a subset of blocks it is the same
+ * quantity restricted to their subspace; for S_n blocks each J carries weight 1.  The
+ * norms keep the drift of reduced-precision products (K slightly off unitary) out of F.
+ * out_dev (float64, 6 entries): [0] F, [1] Re t, [2] Im t, [3] D, [4] na, [5] nb.  FP64,
+ * fixed-order sums; the first 2 KB per block of the workspace hold partial sums.
+ * Asynchronous. */
+qoc_status qoc_gate_fidelity(qoc_plan plan, const void* Ka_dev, const void* Kb_dev, double* out_dev,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
 /* Benchmark instrumentation (process-wide, not thread-safe while enabled).
  * qoc_profile_begin pre-creates HIP events for up to max_launches kernel launches and
  * enables recording: every kernel the hot-path calls enqueue is bracketed by events on
  * the launch stream.  qoc_profile_end synchronises on them, disables recording and
  * writes, per kernel kind, the summed duration in milliseconds and the launch count:
  * [0] generator + norm, [1] propagator GEMM (powers, Horner or degree-12 steps,
- * squarings), [2] unused (the Horner start is formed inside the propagator GEMM),
+ * squarings), [2] gate product tree (qoc_gate_propagate),
  * [3] forward sweep, [4] backward sweep, [5] objective, [6] gradient GEMM, [7] gradient
  * vector kernels, [8] gradient reduction, [9] other. */
 qoc_status qoc_profile_begin(int max_launches);

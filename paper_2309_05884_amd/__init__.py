@@ -21,7 +21,7 @@ from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "propagate", "GrapeFidelity",
            "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
-           "optimize_lbfgs"]
+           "optimize_lbfgs", "gate_propagate", "gate_fidelity"]
 
 library_path = C.LIB_PATH
 
@@ -198,6 +198,11 @@ class Plan:
         return cls(None, precision, u_bound=u_bound, max_workspace_bytes=max_workspace_bytes,
                    _batch=(systems, [int(n) for n in Ns], [float(d) for d in dts]))
 
+    def block_sizes(self):
+        """Block sizes m of a one-problem plan, in plan order (the subset when blocks= was given)."""
+        sizes = self.systems[0].basis.sizes
+        return list(sizes) if self.blocks is None else [sizes[b] for b in self.blocks]
+
     def workspace(self):
         torch = _torch()
         if self._ws is None:
@@ -210,7 +215,7 @@ class Plan:
             self._h = None
 
 
-PROFILE_KINDS = ["generator", "propagator_gemm", "horner_init", "sweep_fwd", "sweep_bwd", "objective",
+PROFILE_KINDS = ["generator", "propagator_gemm", "gate_chain", "sweep_fwd", "sweep_bwd", "objective",
                  "gradient_gemm", "gradient_vector", "gradient_finish", "other"]
 
 
@@ -321,6 +326,44 @@ def propagate(plan: Plan, u, workspace=None):
             off += N * m * m
         per_problem.append(outs)
     return per_problem[0] if plan.P == 1 else per_problem
+
+
+def gate_propagate(plan: Plan, u, workspace=None):
+    """K = U_{N-1} ... U_0 of every block of a one-problem plan (qoc_gate_propagate): list of
+    (m, m) complex128 device tensors in block order."""
+    torch = _torch()
+    assert plan.P == 1
+    u = u.to(torch.float64).contiguous()
+    assert u.shape == (plan.N, plan.K) and u.is_cuda
+    ws = workspace if workspace is not None else plan.workspace()
+    sizes = plan.block_sizes()
+    flat = torch.empty(sum(m * m for m in sizes), dtype=torch.complex128, device=u.device)
+    C.check(C.lib().qoc_gate_propagate(plan._h, _ptr(u), _ptr(flat), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                       _stream()))
+    out, off = [], 0
+    for m in sizes:
+        out.append(flat[off:off + m * m].view(m, m).transpose(0, 1))  # column-major
+        off += m * m
+    return out
+
+
+def gate_fidelity(plan: Plan, Ka, Kb, workspace=None):
+    """Gate fidelity on the device (qoc_gate_fidelity) for block lists as gate_propagate
+    returns: out = [F, Re t, Im t, D, na, nb], t = sum_blocks d Tr(Ka^dag Kb),
+    F = |t|^2 / (na nb) with na, nb the weighted squared Frobenius norms (= D for
+    unitaries)."""
+    torch = _torch()
+
+    def flat(Ks):
+        return torch.cat([k.transpose(0, 1).contiguous().reshape(-1) for k in Ks]).to(torch.complex128).contiguous()
+
+    a, b = flat(Ka), flat(Kb)
+    assert a.numel() == b.numel() == sum(m * m for m in plan.block_sizes())
+    ws = workspace if workspace is not None else plan.workspace()
+    out = torch.empty(6, dtype=torch.float64, device=a.device)
+    C.check(C.lib().qoc_gate_fidelity(plan._h, _ptr(a), _ptr(b), _ptr(out), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                      _stream()))
+    return out
 
 
 def optimize_lbfgs(plan: Plan, u, psi0, psif, max_iter=100, memory=10, step0=0.1, c1=1e-4,

@@ -1441,6 +1441,186 @@ __global__ void k_grad_finish(const JobDev* jobs, const ProbDev* probs, const ch
   grad[pb.u_off + (size_t)(j0 + jj) * K + k] = 2.0 * re / (o[4] * o[5]);
 }
 
+// ===================================================================== gate propagation
+// The time-ordered product K = U_{N-1} ... U_1 U_0 of every block (the unitary a pulse
+// implements, Sec. III B), as a balanced tree of batched complex GEMMs: at each level,
+// factor pair p (slots 2p and 2p+1 of half `src` of the propagator store: half 0 holds U,
+// half 1 U^dag, which this path does not need) becomes U_{2p+1} U_{2p} in slot p of the
+// other half, and an odd last factor is carried over.  The level's items are laid out as
+// the propagator GEMM's (echunk pair slots x tiles per job); a launch covers pairs
+// c0 .. c0 + echunk - 1.  Reads and writes of one level touch different halves.
+template <typename Shape>
+__global__ void __launch_bounds__(256, Shape::WAVES)
+    k_chain_step(const JobDev* jobs, int njobs, long long total_items, char* ws, size_t off_T, int src, int c0,
+                 int npairs) {
+  typedef typename Shape::T T;
+  __shared__ TileSmem<Shape> lds;
+  const ItemRange rg = xcd_items(total_items);
+  ItemCursor cur;
+  struct Item {
+    TileOperands<T> op;
+    T* C;
+  };
+  auto prep = [&](long long it, Item& x) -> bool {
+    const int J = cursor_find(jobs, njobs, it, cur);
+    const JobDev jb = jobs[J];
+    const long long local = it - jb.item_off;
+    const int t2 = jb.tiles_m * jb.tiles_n;
+    const int p = c0 + (int)(local / t2);
+    if (p >= npairs) return false;
+    const int tile = (int)(local % t2);
+    const int ti = tile / jb.tiles_n, tj = tile % jb.tiles_n;
+    const int mp = jb.mp;
+    const size_t plane = (size_t)mp * mp;
+    T* ub = tplane<T>(ws, off_T, jb.ubuf_off);
+    x.op.A = ub + (size_t)(2 * p + 1) * 4 * plane + (size_t)src * 2 * plane;
+    x.op.a_ps = plane;
+    x.op.lda = mp;
+    x.op.B = ub + (size_t)(2 * p) * 4 * plane + (size_t)src * 2 * plane;
+    x.op.b_ps = plane;
+    x.op.ldb = mp;
+    x.op.M = mp;
+    x.op.N = mp;
+    x.op.K = mp;
+    x.op.row0 = ti * Shape::BM;
+    x.op.col0 = tj * Shape::BN;
+    x.C = ub + (size_t)p * 4 * plane + (size_t)(1 - src) * 2 * plane;
+    return true;
+  };
+  long long it = rg.begin;
+  Item x;
+  while (it < rg.end && !prep(it, x)) it += rg.step;
+  if (it >= rg.end) return;
+  TilePipe pipe = tile_start<Shape>(x.op, lds);
+  for (;;) {
+    long long nx = it + rg.step;
+    Item xn = x;
+    while (nx < rg.end && !prep(nx, xn)) nx += rg.step;
+    const bool more = nx < rg.end;
+    TileAcc<Shape> acc;
+    tile_mma<Shape>(x.op, lds, acc, pipe, more, xn.op);
+    const int mp = x.op.M;
+    const size_t plane = (size_t)mp * mp;
+#pragma unroll
+    for (int ri = 0; ri < Shape::SM; ++ri)
+#pragma unroll
+      for (int ci = 0; ci < Shape::SN; ++ci) {
+        const int rbase = acc_row_base<Shape>(x.op.row0, ri);
+        const int col = acc_col<Shape>(x.op.col0, ci);
+        if (rbase >= mp || col >= mp) continue;
+        T* cr = x.C + (size_t)(rbase + acc_row_off<T>(0)) + (size_t)col * mp;
+        acc_store<T>(cr, acc.re[ri][ci]);
+        acc_store<T>(cr + plane, acc.im[ri][ci]);
+      }
+    if (!more) break;
+    it = nx;
+    x = xn;
+  }
+}
+
+// the odd last factor of a level: slot `from` of half src -> slot `to` of the other half
+template <typename T>
+__global__ void k_chain_carry(const JobDev* jobs, int njobs, char* ws, size_t off_T, int src, int from, int to) {
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
+    const JobDev jb = jobs[J];
+    const size_t plane = (size_t)jb.mp * jb.mp;
+    T* ub = tplane<T>(ws, off_T, jb.ubuf_off);
+    const T* a = ub + (size_t)from * 4 * plane + (size_t)src * 2 * plane;
+    T* b = ub + (size_t)to * 4 * plane + (size_t)(1 - src) * 2 * plane;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * plane; i += (size_t)gridDim.x * blockDim.x)
+      b[i] = a[i];
+  }
+}
+
+// K (slot 0 of half `half`) of every block -> interleaved complex128, m x m column-major,
+// blocks back to back in job order
+template <typename T>
+__global__ void k_export_K(const JobDev* jobs, int njobs, char* ws, size_t off_T, int half, double2* out) {
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
+    const JobDev jb = jobs[J];
+    long long off = 0;
+    for (int q = 0; q < J; ++q) off += (long long)jobs[q].m * jobs[q].m;
+    const size_t plane = (size_t)jb.mp * jb.mp;
+    const T* K = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)half * 2 * plane;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < (long long)jb.m * jb.m;
+         idx += (long long)gridDim.x * blockDim.x) {
+      const int rr = (int)(idx % jb.m), cc = (int)(idx / jb.m);
+      const size_t s = (size_t)rr + (size_t)cc * jb.mp;
+      out[off + idx] = make_double2((double)K[s], (double)K[s + plane]);
+    }
+  }
+}
+
+// Gate overlap t = sum_blocks d Tr(Ka^dag Kb) and the weighted squared Frobenius norms
+// na = sum_blocks d ||Ka||^2, nb likewise (FP64): per job, kGateParts work-groups sum fixed
+// ranges of the entries; k_gate_finish adds the partials in a fixed order and writes
+// [F = |t|^2 / (na nb), Re t, Im t, D = sum_blocks d m, na, nb].  For unitaries na = nb = D,
+// so F = |t|^2 / D^2; dividing by the norms keeps the drift of FP32 products out of F.
+constexpr int kGateParts = 64;
+__global__ void __launch_bounds__(256) k_gate_partial(const JobDev* jobs, int njobs, const double2* Ka,
+                                                      const double2* Kb, double* part) {
+  __shared__ double rr[256], ri[256], ra[256], rb[256];
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
+    const JobDev jb = jobs[J];
+    long long off = 0;
+    for (int q = 0; q < J; ++q) off += (long long)jobs[q].m * jobs[q].m;
+    const long long n = (long long)jb.m * jb.m;
+    const long long per = (n + kGateParts - 1) / kGateParts;
+    const long long lo = (long long)blockIdx.x * per, hi = min(n, lo + per);
+    double sr = 0.0, si = 0.0, sa = 0.0, sb = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const double2 a = Ka[off + i], b = Kb[off + i];
+      sr += a.x * b.x + a.y * b.y;  // conj(a) b
+      si += a.x * b.y - a.y * b.x;
+      sa += a.x * a.x + a.y * a.y;
+      sb += b.x * b.x + b.y * b.y;
+    }
+    rr[threadIdx.x] = sr;
+    ri[threadIdx.x] = si;
+    ra[threadIdx.x] = sa;
+    rb[threadIdx.x] = sb;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        rr[threadIdx.x] += rr[threadIdx.x + h];
+        ri[threadIdx.x] += ri[threadIdx.x + h];
+        ra[threadIdx.x] += ra[threadIdx.x + h];
+        rb[threadIdx.x] += rb[threadIdx.x + h];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double* pp = part + 4 * ((size_t)J * kGateParts + blockIdx.x);
+      pp[0] = rr[0] * jb.d;
+      pp[1] = ri[0] * jb.d;
+      pp[2] = ra[0] * jb.d;
+      pp[3] = rb[0] * jb.d;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_gate_finish(const JobDev* jobs, int njobs, const double* part, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double tr = 0.0, ti = 0.0, na = 0.0, nb = 0.0, D = 0.0;
+  for (int J = 0; J < njobs; ++J) {
+    for (int b = 0; b < kGateParts; ++b) {
+      const double* pp = part + 4 * ((size_t)J * kGateParts + b);
+      tr += pp[0];
+      ti += pp[1];
+      na += pp[2];
+      nb += pp[3];
+    }
+    D += (double)jobs[J].d * jobs[J].m;
+  }
+  out[0] = (tr * tr + ti * ti) / (na * nb);
+  out[1] = tr;
+  out[2] = ti;
+  out[3] = D;
+  out[4] = na;
+  out[5] = nb;
+}
+
 // interleaved complex128 copy of U_j for qoc_propagate
 template <typename T>
 __global__ void k_export_U(const JobDev* jobs, int njobs, char* ws, size_t off_T, const int* ent_s, const int* ent_q,
@@ -1484,7 +1664,7 @@ __global__ void k_slot_sum(const JobDev* jobs, int njobs, char* ws, size_t off_T
 // Opt-in, process-wide launch timing for benchmarks: HIP events from a pre-created
 // pool are recorded on the launch stream around each kernel of the hot path.
 enum ProfKind {
-  PK_GENERATOR = 0, PK_EXPM_GEMM = 1, PK_HORNER_INIT = 2, PK_SWEEP_FWD = 3, PK_SWEEP_BWD = 4,
+  PK_GENERATOR = 0, PK_EXPM_GEMM = 1, PK_GATE_CHAIN = 2, PK_SWEEP_FWD = 3, PK_SWEEP_BWD = 4,
   PK_OVERLAP = 5, PK_GRAD_GEMM = 6, PK_GRAD_VECTOR = 7, PK_GRAD_FINISH = 8, PK_OTHER = 9, PK_COUNT = 10
 };
 
@@ -1597,11 +1777,13 @@ typedef void (*ExpmLaunch)(dim3, hipStream_t, const JobDev*, int, long long, cha
                            const int*, int, int, int, int, int, int, int, int);
 typedef void (*PanelLaunch)(dim3, hipStream_t, const JobDev*, const PanelDesc*, int, long long, char*, size_t, int,
                             int);
+typedef void (*ChainLaunch)(dim3, hipStream_t, const JobDev*, int, long long, char*, size_t, int, int, int);
 struct GemmVariant {
   const char* name;
   int bm, bn;
   ExpmLaunch expm;
   PanelLaunch panel;
+  ChainLaunch chain;
   const void* expm_fn;  // for occupancy queries
 };
 template <typename C>
@@ -1617,8 +1799,14 @@ void launch_panel(dim3 g, hipStream_t st, const JobDev* j, const PanelDesc* d, i
   hipLaunchKernelGGL(k_panel_gemm<C>, g, dim3(256), 0, st, j, d, nd, items, ws, offT, vslot, j0);
 }
 template <typename C>
+void launch_chain(dim3 g, hipStream_t st, const JobDev* j, int nj, long long items, char* ws, size_t offT, int src,
+                  int c0, int npairs) {
+  hipLaunchKernelGGL(k_chain_step<C>, g, dim3(256), 0, st, j, nj, items, ws, offT, src, c0, npairs);
+}
+template <typename C>
 GemmVariant make_variant(const char* name) {
-  return GemmVariant{name, C::BM, C::BN, launch_expm<C>, launch_panel<C>, (const void*)k_expm_step<C>};
+  return GemmVariant{name, C::BM, C::BN, launch_expm<C>, launch_panel<C>, launch_chain<C>,
+                     (const void*)k_expm_step<C>};
 }
 static const GemmVariant kVariants32[] = {
     make_variant<TileShape<float, 4, 2, 2>>("fp32 128x64"),
@@ -1750,6 +1938,34 @@ struct Driver {
     expm_segment(P, ws, u, 0, st);
     gemm_variant(P).panel(dim3(P->grid_gemm), st, P->d_jobs.as<JobDev>(), P->d_panels.as<PanelDesc>(),
                           (int)P->panels.size(), P->panel_items, ws, P->off_T, P->Kmax + 1, 0);
+  }
+
+  // K of every block: propagators of the (single) segment, then the product tree.
+  static void gate(qoc_plan_s* P, const double* u, double2* out, char* ws, hipStream_t st) {
+    const int njobs = (int)P->jobs.size();
+    const JobDev* dj = P->d_jobs.as<JobDev>();
+    int* flags = reinterpret_cast<int*>(ws + P->off_flags);
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);
+    expm_segment(P, ws, u, 0, st);
+    int cnt = P->Nmax, src = 0;
+    while (cnt > 1) {
+      const int npairs = cnt / 2;
+      for (int c0 = 0; c0 < npairs; c0 += P->echunk)
+        timed(PK_GATE_CHAIN, st, [&] {
+          gemm_variant(P).chain(dim3(P->grid_gemm), st, dj, njobs, P->expm_items, ws, P->off_T, src, c0, npairs);
+        });
+      if (cnt & 1)
+        timed(PK_OTHER, st, [&] {
+          hipLaunchKernelGGL(k_chain_carry<T>, dim3(64, (unsigned)njobs), dim3(256), 0, st, dj, njobs, ws, P->off_T,
+                             src, cnt - 1, npairs);
+        });
+      cnt = (cnt + 1) / 2;
+      src = 1 - src;
+    }
+    timed(PK_OTHER, st, [&] {
+      hipLaunchKernelGGL(k_export_K<T>, dim3(64, (unsigned)njobs), dim3(256), 0, st, dj, njobs, ws, P->off_T, src,
+                         out);
+    });
   }
 
   static void propagate(qoc_plan_s* P, const double* u, double2* out, char* ws, hipStream_t st) {
@@ -2350,6 +2566,41 @@ qoc_status qoc_fidelity_grad(qoc_plan P, const double* u_dev, const void* psi0_d
       Driver<double>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, st);
     else
       Driver<float>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, st);
+  });
+}
+
+qoc_status qoc_gate_propagate(qoc_plan P, const double* u_dev, void* K_out_dev, void* workspace, size_t ws_bytes,
+                              void* stream) {
+  return guarded([&] {
+    QOC_REQUIRE(P && u_dev && K_out_dev && workspace, QOC_ERR_INVALID_ARG, "null argument");
+    QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
+    QOC_REQUIRE(P->P == 1, QOC_ERR_UNSUPPORTED, "gate propagation takes a one-problem plan");
+    QOC_REQUIRE(P->nseg == 1, QOC_ERR_UNSUPPORTED,
+                "gate propagation needs every propagator of the pulse resident (one segment)");
+    hipStream_t st = (hipStream_t)stream;
+    if (P->prec == QOC_C128)
+      Driver<double>::gate(P, u_dev, static_cast<double2*>(K_out_dev), (char*)workspace, st);
+    else
+      Driver<float>::gate(P, u_dev, static_cast<double2*>(K_out_dev), (char*)workspace, st);
+    QOC_HIP(hipGetLastError());
+  });
+}
+
+qoc_status qoc_gate_fidelity(qoc_plan P, const void* Ka_dev, const void* Kb_dev, double* out_dev, void* workspace,
+                             size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    QOC_REQUIRE(P && Ka_dev && Kb_dev && out_dev && workspace, QOC_ERR_INVALID_ARG, "null argument");
+    const int njobs = (int)P->jobs.size();
+    QOC_REQUIRE(ws_bytes >= (size_t)njobs * kGateParts * 4 * sizeof(double), QOC_ERR_OUT_OF_MEMORY,
+                "workspace smaller than the partial sums");
+    QOC_REQUIRE(P->P == 1, QOC_ERR_UNSUPPORTED, "gate fidelity takes a one-problem plan");
+    hipStream_t st = (hipStream_t)stream;
+    double* part = static_cast<double*>(workspace);
+    const JobDev* dj = P->d_jobs.as<JobDev>();
+    hipLaunchKernelGGL(k_gate_partial, dim3(kGateParts, (unsigned)std::min(njobs, 65535)), dim3(256), 0, st, dj,
+                       njobs, static_cast<const double2*>(Ka_dev), static_cast<const double2*>(Kb_dev), part);
+    hipLaunchKernelGGL(k_gate_finish, dim3(1), dim3(64), 0, st, dj, njobs, part, out_dev);
+    QOC_HIP(hipGetLastError());
   });
 }
 

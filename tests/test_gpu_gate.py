@@ -1,0 +1,109 @@
+"""Gate propagation (qoc_gate_propagate: the product tree of batched MFMA GEMMs) and gate
+fidelity (qoc_gate_fidelity) against the oracle (oracle/gate.py), on every D_n block of
+6- and 5-qubit rings, for pulse lengths that exercise the tree's edge cases (one slice,
+a power of two, odd counts carried over at several levels); a first-block plan against the
+all-blocks plan; and, at the 12-qubit ring's full size, one block's K against the plain
+time-ordered product of the library's own propagators."""
+import numpy as np
+import pytest
+
+import qoc_workloads as W
+from oracle import gate, grape
+
+pytestmark = pytest.mark.gpu
+
+
+def _system(lib, n, h0, hk):
+    B = lib.Basis(n, "dihedral", 1)
+    return B, lib.System(B, h0, hk)
+
+
+@pytest.mark.parametrize("n,N", [(6, 1), (6, 2), (6, 37), (5, 64), (6, 45)])
+@pytest.mark.parametrize("prec,tk,tf", [("c128", 1e-11, 1e-12), ("c64", 3e-5, 2e-5)])
+def test_gate_unitaries_and_fidelity_match_the_oracle(lib, n, N, prec, tk, tf):
+    import torch
+    print(f"gate n={n} N={N} {prec}", flush=True)
+    dt = 0.1
+    h0 = W.full_coupling_terms(n, 1.0, [0.7, 0.3, 0.2][: n // 2])
+    hk = W.global_controls(0.5)
+    B, S = _system(lib, n, h0, hk)
+    P = lib.Plan(S, prec, N, dt, 1.0)
+    rng = np.random.default_rng(100 * n + N)
+    ua, ub = rng.uniform(-1, 1, (N, 2)), rng.uniform(-1, 1, (N, 2))
+    Ka = lib.gate_propagate(P, torch.tensor(ua, device="cuda"))
+    Kb = lib.gate_propagate(P, torch.tensor(ub, device="cuda"))
+    blocks = grape.block_system(n, h0, hk)
+    assert [b["m"] for b in blocks] == P.block_sizes()
+    Ra, Rb = gate.gate_unitaries(blocks, ua, dt), gate.gate_unitaries(blocks, ub, dt)
+    for K, R in zip(Ka, Ra):
+        assert np.abs(K.cpu().numpy() - R).max() <= tk
+    ref = gate.gate_fidelity(Ra, Rb, [b["d"] for b in blocks])
+    out = lib.gate_fidelity(P, Ka, Kb).cpu().numpy()
+    print(f"  F {out[0]:.14f} oracle {ref['F']:.14f}", flush=True)
+    assert out[3] == 2 ** n
+    assert abs(out[0] - ref["F"]) <= tf and abs(out[0] - ref["F_paper"]) <= tf
+    assert abs(out[4] - ref["na"]) <= (1e-9 if prec == "c128" else 2e-3)
+    # the fidelity kernel itself on the oracle's unitaries (FP64 throughout)
+    dev = [torch.tensor(R, device="cuda") for R in Ra], [torch.tensor(R, device="cuda") for R in Rb]
+    out2 = lib.gate_fidelity(P, *dev).cpu().numpy()
+    assert abs(out2[0] - ref["F"]) <= 1e-13 and abs(complex(out2[1], out2[2]) - ref["t"]) <= 1e-11
+
+
+def test_first_block_plan_equals_all_blocks_plan(lib):
+    import torch
+    print("gate subset plan", flush=True)
+    n, N, dt = 6, 21, 0.1
+    h0, hk = W.ising_ring_terms(1.0, 1.0), W.global_controls(0.5)
+    B, S = _system(lib, n, h0, hk)
+    u = torch.tensor(np.random.default_rng(9).uniform(-1, 1, (N, 2)), device="cuda")
+    Kall = lib.gate_propagate(lib.Plan(S, "c128", N, dt, 1.0), u)
+    P0 = lib.Plan(S, "c128", N, dt, 1.0, blocks=[0])
+    K0 = lib.gate_propagate(P0, u)
+    assert len(K0) == 1 and torch.equal(K0[0], Kall[0])
+    out = lib.gate_fidelity(P0, K0, K0).cpu().numpy()
+    assert abs(out[0] - 1.0) <= 1e-13 and out[3] == B.sizes[0]
+
+
+def test_gate_rejects_segmented_plans(lib):
+    import torch
+    from paper_2309_05884_amd._capi import QocError
+    n, N, dt = 6, 40, 0.1
+    h0, hk = W.ising_ring_terms(1.0, 1.0), W.global_controls(0.5)
+    B, S = _system(lib, n, h0, hk)
+    P = lib.Plan(S, "c128", N, dt, 1.0)
+    Pseg = None
+    for frac in (0.7, 0.5, 0.35, 0.25, 0.15):  # budgets that hold only part of the pulse's propagators
+        try:
+            cand = lib.Plan(S, "c128", N, dt, 1.0, max_workspace_bytes=int(P.workspace_bytes * frac))
+        except QocError:
+            break
+        if cand.info["segments"] > 1:
+            Pseg = cand
+            break
+    assert Pseg is not None and Pseg.info["segments"] > 1
+    u = torch.zeros((N, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(QocError, match="UNSUPPORTED"):
+        lib.gate_propagate(Pseg, u)
+
+
+def test_ring12_block_at_full_size_equals_the_time_ordered_product(lib):
+    """12-qubit ring (the benchmark's Heisenberg ring), 1000 slices, complex64: the tree's K
+    of the 128-wide A2 block against the product of the library's 1000 propagators taken
+    one by one on the host in complex128."""
+    import torch
+    print("gate ring12 A2 block, 1000 slices, c64", flush=True)
+    w = W.config2(seed=0, variant="all")
+    B = lib.Basis(12, "dihedral", 1)
+    S = lib.System(B, w.h0, w.hk)
+    assert B.sizes[1] == 128
+    P = lib.Plan(S, "c64", w.N, w.dt, 2.0, blocks=[1])
+    u = torch.tensor(w.u, device="cuda")
+    K = lib.gate_propagate(P, u)[0].cpu().numpy()
+    Us = lib.propagate(P, u)[0].cpu().numpy()
+    R = np.eye(128, dtype=complex)
+    for j in range(w.N):
+        R = Us[j] @ R
+    err = np.abs(K - R).max()
+    print(f"  max |K - prod U| = {err:.3e}", flush=True)
+    assert err <= 2e-4
+    assert np.abs(K.conj().T @ K - np.eye(128)).max() <= 2e-4
