@@ -75,6 +75,8 @@ def parse():
                          "(0: skip)")
     ap.add_argument("--gate", type=int, default=1,
                     help="also time the unitary of the whole pulse and the gate fidelity (1) or skip (0)")
+    ap.add_argument("--lts", type=int, default=1,
+                    help="also run the Trotterised per-qubit-control legs (1) or skip them (0)")
     ap.add_argument("--optimizer", type=int, default=1,
                     help="also run the L-BFGS GRAPE optimiser legs (1) or skip them (0)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -299,6 +301,79 @@ def gate_leg(q, torch, P, dev, B, w, reps=3):
     return res
 
 
+def lts_leg(q, torch, nmax=13, dt=0.05, Bz=1.0, c_cpl=1.0, dense_max=12, fid_n=11, fid_N=2000):
+    """The Trotterised per-qubit-control propagator of Sec. III B (Eqs. (8)-(11)) on the
+    Ising ring with B_z = 1, c_cpl = 1, tau = 0.05 and seeded U[-1, 1] per-qubit pulses:
+    (a) the runtime per time step of the unitary, K^LTS by qoc_lts_apply (FP64, all 2^n
+    columns) against the untrotterised dense propagator (the dense plan with 2n per-qubit
+    controls, complex64 MFMA, qoc_gate_propagate), n = 3..nmax (dense up to dense_max), the
+    comparison of Fig. 5b; (b) the gate fidelity of K^LTS against the dense unitary for
+    fid_n qubits after fid_N steps (Fig. 5a; the dense reference holds every propagator of
+    the pulse, which bounds fid_N)."""
+    def per_qubit_system(n):
+        B = q.Basis(n, "cyclic", n)
+        h0 = [{"kind": "one_body", "coeff": 0.5 * Bz, "op": "z", "sites": "all", "stagger": False},
+              {"kind": "ring_pair", "coeff": 0.25 * c_cpl, "op": "zz", "distance": 1}]
+        hk = []
+        for i in range(1, n + 1):
+            for a in "XY":
+                st = ["I"] * n
+                st[i - 1] = a
+                hk.append([{"kind": "pauli", "coeff": 0.5, "string": "".join(st)}])
+        return B, q.System(B, h0, hk)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            r = fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, r
+
+    res = {"Bz": Bz, "c_cpl": c_cpl, "dt": dt, "per_step": []}
+    for n in range(3, nmax + 1):
+        rng = np.random.default_rng(700 + n)
+        Nl = 200
+        u = torch.tensor(rng.uniform(-1, 1, (Nl, 2 * n)), device="cuda")
+        ms_l, _ = timed(lambda: q.lts_apply(n, Bz, c_cpl, u, dt), 2)
+        e = {"n": n, "lts_ms_per_step": ms_l / Nl}
+        if n <= dense_max:
+            Nd = 20 if n <= 10 else 8
+            B, S = per_qubit_system(n)
+            P = q.Plan(S, "c64", Nd, dt, 1.0)
+            ud = u[:Nd].contiguous()
+            ms_d, _ = timed(lambda: q.gate_propagate(P, ud), 2)
+            e["dense_ms_per_step"] = ms_d / Nd
+            e["speedup"] = e["dense_ms_per_step"] / e["lts_ms_per_step"]
+            del P, S, B
+            torch.cuda.empty_cache()
+        res["per_step"].append(e)
+        print(f"[bench] lts {e}", file=sys.stderr, flush=True)
+    # gate fidelity of the Trotterised unitary after fid_N steps
+    rng = np.random.default_rng(711)
+    u = torch.tensor(rng.uniform(-1, 1, (fid_N, 2 * fid_n)), device="cuda")
+    B, S = per_qubit_system(fid_n)
+    P = q.Plan(S, "c64", fid_N, dt, 1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Kd = q.gate_propagate(P, u)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Kl = q.lts_apply(fid_n, Bz, c_cpl, u, dt)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f = q.gate_fidelity(P, [Kl], Kd).cpu().numpy()
+    res["fidelity"] = {"n": fid_n, "steps": fid_N, "F": float(f[0]), "F_paper_form": float(f[1] ** 2 + f[2] ** 2) / f[3] ** 2,
+                       "dense_complex64_s": t1 - t0, "lts_fp64_s": t2 - t1}
+    print(f"[bench] lts fidelity {res['fidelity']}", file=sys.stderr, flush=True)
+    del P, S, B, Kd, Kl
+    torch.cuda.empty_cache()
+    return res
+
+
 def optimizer_leg(q, torch, W, N=100, dt=0.05):
     """GRAPE optimisation (qoc_optimize_lbfgs) of the transfer all-up -> all-down in the first
     D_n block, nearest-neighbour (Eq. (5), c_cpl = 1) against full coupling (Eq. (7),
@@ -477,6 +552,7 @@ def main():
         comparison = paper_comparison(q, torch, W, args.paper_comparison)
         torch.cuda.empty_cache()
     optimizer = optimizer_leg(q, torch, W) if args.optimizer else None
+    lts = lts_leg(q, torch) if args.lts else None
 
     ring14 = None
     if args.ring14_slices > 0:
@@ -588,6 +664,8 @@ def main():
         line["optimizer"] = optimizer
     if gate is not None:
         line["gate"] = gate
+    if lts is not None:
+        line["lts"] = lts
     if not args.no_cpu_baseline:
         print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, v0, vf, args.cpu_slices)

@@ -133,7 +133,7 @@ qoc_status qoc_state_from_blocks(qoc_basis basis, const void* blocks_dev, void* 
  * of H_1..H_K back to back, n_hk[k] of them for H_k.  Every term is first checked for
  * exact invariance under the group generators on its integer bit masks; a term that
  * breaks the symmetry returns QOC_ERR_SYMMETRY before device work.  The system keeps
- * complex128 and complex64 copies of every block on the device.  K: 0..16.
+ * complex128 and complex64 copies of every block on the device.  K: 0..32.
  * Synchronises `stream` before returning. */
 qoc_status qoc_project(qoc_basis basis, const qoc_term* h0, int n_h0, const qoc_term* hk,
                        const int* n_hk, int K, void* stream, qoc_system* out);
@@ -266,6 +266,26 @@ qoc_status qoc_gate_propagate(qoc_plan plan, const double* u_dev, void* K_out_de
  * Asynchronous. */
 qoc_status qoc_gate_fidelity(qoc_plan plan, const void* Ka_dev, const void* Kb_dev, double* out_dev,
                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Trotterised propagator for per-qubit controls (Sec. III B, Eqs. (8)-(11)) on the Ising
+ * ring H_j = sum_i [(B_z/2) sz_i + (Bx_i[j] sx_i + By_i[j] sy_i)/2]
+ *          + (c_cpl/4) sum_i sz_i sz_{i+1}  (qubit n+1 = qubit 1):
+ *   U_j^LTS = prod_{i=1..n} [exp(-i dt (H_0^(i) + H_c'^(i)[j])) exp(-i (dt/n) H_cpl)],
+ * the product written i = 1 leftmost, so qubit n's bracket acts first and, inside a
+ * bracket, the coupling factor first.  qoc_lts_apply computes
+ * psi_out = U_{N-1}^LTS ... U_0^LTS psi_in for ncols state columns.
+ * n: 1..13 (each column is held in LDS; QOC_ERR_UNSUPPORTED beyond).  u_dev: float64
+ * [N][2n] device controls, u[j][2(i-1)] = Bx_i, u[j][2(i-1)+1] = By_i.  psi_in_dev:
+ * column-major 2^n x ncols interleaved complex128 in the computational basis (qubit q at
+ * bit n - q, bit 0 = spin up), or NULL for the identity columns 0 .. ncols - 1 (ncols <=
+ * 2^n), which yields those columns of K^LTS = U_{N-1}^LTS ... U_0^LTS.  psi_out_dev: the
+ * same layout (2^n x ncols).  workspace: caller-owned device memory of at least
+ * qoc_lts_workspace_size(n, N) bytes (the 2 x 2 factors of every slice and qubit).  FP64;
+ * one work-group per column; asynchronous on `stream`. */
+qoc_status qoc_lts_workspace_size(int n, int N, size_t* bytes);
+qoc_status qoc_lts_apply(int n, double Bz, double c_cpl, const double* u_dev, int N, double dt,
+                         const void* psi_in_dev, int ncols, void* psi_out_dev, void* workspace,
+                         size_t workspace_bytes, void* stream);
 
 /* Benchmark instrumentation (process-wide, not thread-safe while enabled).
  * qoc_profile_begin pre-creates HIP events for up to max_launches kernel launches and

@@ -21,7 +21,7 @@ from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "propagate", "GrapeFidelity",
            "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
-           "optimize_lbfgs", "gate_propagate", "gate_fidelity"]
+           "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply"]
 
 library_path = C.LIB_PATH
 
@@ -364,6 +364,37 @@ def gate_fidelity(plan: Plan, Ka, Kb, workspace=None):
     C.check(C.lib().qoc_gate_fidelity(plan._h, _ptr(a), _ptr(b), _ptr(out), _ptr(ws), ctypes.c_size_t(ws.numel()),
                                       _stream()))
     return out
+
+
+def lts_apply(n: int, Bz: float, c_cpl: float, u, dt: float, psi=None, ncols=None):
+    """Trotterised per-qubit-control propagation (qoc_lts_apply): U_{N-1}^LTS ... U_0^LTS
+    applied to the columns of psi (2^n x k complex128, computational basis), or, with
+    psi=None, to the identity columns 0 .. ncols-1 (default all: K^LTS).  u: (N, 2n) with
+    u[j, 2(i-1)] = Bx_i, u[j, 2(i-1)+1] = By_i.  Returns a (2^n, k) device tensor."""
+    torch = _torch()
+    u = u.to(torch.float64).contiguous()
+    N = u.shape[0]
+    assert u.shape == (N, 2 * n) and u.is_cuda
+    D = 1 << n
+    if psi is not None:
+        psi = psi.to(torch.complex128)
+        if psi.dim() == 1:
+            psi = psi[:, None]
+        assert psi.shape[0] == D
+        k = psi.shape[1]
+        src = psi.transpose(0, 1).contiguous()  # column-major
+    else:
+        k = D if ncols is None else int(ncols)
+        src = None
+    L = C.lib()
+    nbytes = ctypes.c_size_t()
+    C.check(L.qoc_lts_workspace_size(int(n), int(N), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=u.device)
+    out = torch.empty((k, D), dtype=torch.complex128, device=u.device)
+    C.check(L.qoc_lts_apply(int(n), float(Bz), float(c_cpl), _ptr(u), int(N), float(dt),
+                            None if src is None else _ptr(src), int(k), _ptr(out), _ptr(ws),
+                            ctypes.c_size_t(ws.numel()), _stream()))
+    return out.transpose(0, 1)
 
 
 def optimize_lbfgs(plan: Plan, u, psi0, psif, max_iter=100, memory=10, step0=0.1, c1=1e-4,

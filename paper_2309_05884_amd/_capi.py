@@ -86,6 +86,9 @@ PROTOTYPES = {
     "qoc_variant_name": (ctypes.c_char_p, [ctypes.c_int, ctypes.c_int]),
     "qoc_plan_autotune": (ctypes.c_int, [vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_double)]),
+    "qoc_lts_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "qoc_lts_apply": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, ctypes.c_int, ctypes.c_double,
+                                     vp, ctypes.c_int, vp, vp, ctypes.c_size_t, vp]),
     "qoc_gate_propagate": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_gate_fidelity": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_optimize_workspace_size": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),

@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqoc_gfx950.so")
-SOURCES = ["basis.hip", "project.hip", "grape.hip", "optimize.hip"]
+SOURCES = ["basis.hip", "project.hip", "grape.hip", "optimize.hip", "lts.hip"]
 # -disable-promote-alloca-to-lds: the tile kernels keep the next slab of operands in
 # registers across the K loop; the compiler would otherwise move that array into spare
 # LDS, adding a store and a reload (and a wait on the global loads) before every slab.

@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
                                                    int r, int qmax, int t12, int smax, double norm_bound,
                                                    int skip_n) {
   __shared__ double red[GEN_SG][256];
-  __shared__ double us[GEN_SG][17];
+  __shared__ double us[GEN_SG][kMaxControls + 1];
   __shared__ double scale[GEN_SG];
   const int J = blockIdx.x / groups, g = blockIdx.x % groups;
   if (J >= njobs) return;
@@ -1697,7 +1697,7 @@ __global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njo
                                                      const double* theta, int r, int qmax, int t12, int* q_out, int* s_out,
                                                      double* n_out) {
   __shared__ double red[256];
-  __shared__ double ujs[17];
+  __shared__ double ujs[kMaxControls + 1];
   const int j = blockIdx.x;
   for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];

@@ -261,7 +261,7 @@ qoc_status qoc_project(qoc_basis B, const qoc_term* h0, int n_h0, const qoc_term
   return guarded([&] {
     QOC_REQUIRE(B && out, QOC_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
-    QOC_REQUIRE(K >= 0 && K <= 16, QOC_ERR_INVALID_ARG, "K must be in 0..16");
+    QOC_REQUIRE(K >= 0 && K <= kMaxControls, QOC_ERR_INVALID_ARG, "K must be in 0..32");
     QOC_REQUIRE(n_h0 >= 0 && (n_h0 == 0 || h0), QOC_ERR_INVALID_ARG, "bad H0 term list");
     QOC_REQUIRE(K == 0 || n_hk, QOC_ERR_INVALID_ARG, "n_hk is null");
     int total_hk = 0;

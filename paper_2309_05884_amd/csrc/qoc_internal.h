@@ -13,6 +13,9 @@
 
 namespace qoc {
 
+// control operators per system (per-qubit x and y fields of up to 16 qubits)
+constexpr int kMaxControls = 32;
+
 // ---------------------------------------------------------------------------------------
 // error plumbing
 void set_error(const std::string& msg);

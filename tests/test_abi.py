@@ -75,6 +75,19 @@ def test_null_handles_rejected():
     res = C.QocLbfgsResult()
     assert L.qoc_optimize_lbfgs(None, ctypes.byref(opts), None, None, None, None, 0, None, None, 0,
                                 ctypes.byref(res)) == 1
+    assert L.qoc_gate_propagate(None, None, None, None, 0, None) == 1
+    assert L.qoc_gate_fidelity(None, None, None, None, None, 0, None) == 1
+    assert L.qoc_lts_apply(4, 1.0, 1.0, None, 10, 0.1, None, 1, None, None, 0, None) == 1
+
+
+def test_lts_sizes_host_only():
+    """The Trotterised path keeps a column of 2^n amplitudes in LDS: n <= 13."""
+    L = C.lib()
+    nbytes = ctypes.c_size_t()
+    assert L.qoc_lts_workspace_size(11, 100, ctypes.byref(nbytes)) == 0 and nbytes.value == 100 * 11 * 4 * 16
+    assert L.qoc_lts_workspace_size(14, 100, ctypes.byref(nbytes)) == 3
+    assert L.qoc_lts_workspace_size(0, 100, ctypes.byref(nbytes)) == 3
+    assert L.qoc_lts_workspace_size(5, 0, ctypes.byref(nbytes)) == 1
 
 
 def test_symmetric_basis_is_host_only():

@@ -1,0 +1,112 @@
+"""The Trotterised per-qubit-control propagator on the GPU (qoc_lts_apply, Sec. III B,
+Eqs. (8)-(11)) against the oracle (oracle/lts.py): the whole unitary K^LTS for small
+rings, state columns up to the 13-qubit limit, partial identity columns, and, without
+coupling, where the split is exact, against the library's dense gate path with 2n
+per-qubit control operators."""
+import numpy as np
+import pytest
+
+from oracle import lts
+
+pytestmark = pytest.mark.gpu
+
+
+def _u(seed, N, n):
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, (N, 2 * n))
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 6])
+def test_lts_unitary_matches_the_oracle(lib, n):
+    import torch
+    print(f"lts K n={n}", flush=True)
+    N, dt, Bz, c = 5, 0.1, 1.0, 0.8
+    u = _u(n, N, n)
+    K = lib.lts_apply(n, Bz, c, torch.tensor(u, device="cuda"), dt).cpu().numpy()
+    ref = lts.lts_gate(n, Bz, c, u, dt)
+    assert np.abs(K - ref).max() <= 1e-12
+    # the first three identity columns alone
+    if n >= 2:
+        K3 = lib.lts_apply(n, Bz, c, torch.tensor(u, device="cuda"), dt, ncols=3).cpu().numpy()
+        assert np.array_equal(K3, K[:, :3])
+
+
+@pytest.mark.parametrize("n", [10, 13])
+def test_lts_states_match_the_oracle_up_to_13_qubits(lib, n):
+    import torch
+    print(f"lts states n={n}", flush=True)
+    N, dt, Bz, c = 3, 0.05, 1.0, 1.0
+    u = _u(20 + n, N, n)
+    rng = np.random.default_rng(30 + n)
+    psi = rng.standard_normal((2 ** n, 2)) + 1j * rng.standard_normal((2 ** n, 2))
+    psi /= np.linalg.norm(psi, axis=0)
+    out = lib.lts_apply(n, Bz, c, torch.tensor(u, device="cuda"), dt, psi=torch.tensor(psi, device="cuda"))
+    ref = lts.apply_state(n, Bz, c, u, dt, psi)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-12
+
+
+def test_no_coupling_equals_the_dense_gate_path(lib):
+    """c_cpl = 0: U^LTS = exp(-i dt H_j) exactly, so K^LTS equals the unitary of the dense
+    plan (trivial group) whose 2n controls are the per-qubit sx_i / 2 and sy_i / 2."""
+    import torch
+    print("lts vs dense gate path", flush=True)
+    n, N, dt, Bz = 5, 9, 0.1, 1.0
+    u = _u(40, N, n)
+    B = lib.Basis(n, "cyclic", n)
+    h0 = [{"kind": "one_body", "coeff": 0.5 * Bz, "op": "z", "sites": "all", "stagger": False}]
+    hk = []
+    for i in range(1, n + 1):
+        for a in "XY":
+            s = ["I"] * n
+            s[i - 1] = a
+            hk.append([{"kind": "pauli", "coeff": 0.5, "string": "".join(s)}])
+    S = lib.System(B, h0, hk)
+    P = lib.Plan(S, "c128", N, dt, 1.0)
+    ud = torch.tensor(u, device="cuda")
+    Kd = lib.gate_propagate(P, ud)[0].cpu().numpy()
+    Kl = lib.lts_apply(n, Bz, 0.0, ud, dt).cpu().numpy()
+    assert np.abs(Kd - Kl).max() <= 1e-11
+
+
+def test_lts_argument_errors(lib):
+    import torch
+    from paper_2309_05884_amd._capi import QocError
+    u = torch.zeros((4, 28), dtype=torch.float64, device="cuda")
+    with pytest.raises(QocError, match="UNSUPPORTED"):
+        lib.lts_apply(14, 1.0, 1.0, u, 0.1, ncols=1)
+    u4 = torch.zeros((4, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(QocError, match="INVALID_ARG"):
+        lib.lts_apply(4, 1.0, 1.0, u4, 0.1, ncols=17)
+    with pytest.raises(QocError, match="INVALID_ARG"):
+        lib.lts_apply(4, 1.0, 1.0, u4, -0.1)
+
+
+def test_eighteen_per_qubit_controls_gradient_matches_the_oracle(lib):
+    """More than 16 control operators (9 qubits, x and y on each): the exact gradient of the
+    dense plan against the oracle's."""
+    import torch
+    from oracle import grape
+    print("18 per-qubit controls, dense 512", flush=True)
+    n, N, dt = 9, 3, 0.05
+    h0 = [{"kind": "one_body", "coeff": 0.5, "op": "z", "sites": "all", "stagger": False},
+          {"kind": "ring_pair", "coeff": 0.25, "op": "zz", "distance": 1}]
+    hk = []
+    for i in range(1, n + 1):
+        for a in "XY":
+            s = ["I"] * n
+            s[i - 1] = a
+            hk.append([{"kind": "pauli", "coeff": 0.5, "string": "".join(s)}])
+    B = lib.Basis(n, "cyclic", n)
+    S = lib.System(B, h0, hk)
+    P = lib.Plan(S, "c128", N, dt, 1.0)
+    u = _u(50, N, n)
+    rng = np.random.default_rng(51)
+    p0 = rng.standard_normal(2 ** n) + 1j * rng.standard_normal(2 ** n)
+    pf = rng.standard_normal(2 ** n) + 1j * rng.standard_normal(2 ** n)
+    p0 /= np.linalg.norm(p0)
+    pf /= np.linalg.norm(pf)
+    out, g = lib.fidelity_grad(P, torch.tensor(u, device="cuda"), torch.tensor(p0, device="cuda"),
+                               torch.tensor(pf, device="cuda"))
+    dense = grape.dense_system(n, h0, hk)
+    ref = grape.fidelity_grad(dense, u, dt, [p0[:, None]], [pf[:, None]])
+    assert abs(out[0].item() - ref["F"]) <= 1e-12
+    assert np.abs(g.cpu().numpy() - np.asarray(ref["grad"])).max() <= 1e-12
