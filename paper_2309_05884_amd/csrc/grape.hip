@@ -155,6 +155,7 @@ struct qoc_plan_s {
   size_t coop_lds = 0;    // dynamic LDS of the co-operative sweep (bytes)
   long long expm_items = 0, panel_items = 0;
   long long entries_per_seg = 0;
+  int max_mp = 0;         // largest padded block
   size_t sweep_lds_elems = 0;
   int max_cc = 0;
   long long total_u = 0, total_D = 0, total_U = 0;
@@ -327,6 +328,168 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
       }
     }
     // -i * scale * (hr + i hi) = scale * hi - i scale * hr
+#pragma unroll
+    for (int t = 0; t < GEN_SG; ++t) {
+      if (t < ns) {
+        T* Y = Y0 + (size_t)t * ent_stride;
+        Y[idx] = (T)(scale[t] * hi[t]);
+        Y[idx + plane] = (T)(-scale[t] * hr[t]);
+      }
+    }
+  }
+}
+
+// The same generator split over column ranges, for chunks with too few (job, slice group)
+// pairs to fill the GPU (short pulses on large blocks): k_gen_norms takes the largest
+// column sum of |H_j| over csplit column ranges (atomic maximum on the bit pattern of a
+// non-negative double, ent_norm zeroed first), k_gen_pick turns it into each slice's
+// (q, s) and flags, k_gen_form writes Y over csplit element ranges.  Same arithmetic as
+// k_generator, element by element.
+__device__ inline void gen_load_controls(const JobDev& jb, const double* u, int seg_j0, int jl0, int ns,
+                                         double (*us)[kMaxControls + 1]) {
+  const int K = jb.K;
+  const double* uj = u + jb.u_off;
+  for (int idx = threadIdx.x; idx < GEN_SG * (K + 1); idx += blockDim.x) {
+    const int t = idx / (K + 1), o = idx % (K + 1);
+    double v = 0.0;
+    if (t < ns) v = o == 0 ? 1.0 : uj[(size_t)(seg_j0 + jl0 + t) * K + (o - 1)];
+    us[t][o] = v;
+  }
+}
+
+// zero the chunk's entries c0 .. c0 + clen - 1 of every job (the maxima of k_gen_norms)
+__global__ void k_gen_zero(const JobDev* jobs, int njobs, int c0, int clen, double* ent_norm) {
+  for (int J = blockIdx.y; J < njobs; J += gridDim.y)
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < clen; t += gridDim.x * blockDim.x)
+      ent_norm[jobs[J].ent_off + c0 + t] = 0.0;
+}
+
+__global__ void __launch_bounds__(256) k_gen_norms(const JobDev* jobs, int njobs, const double* u, int seg_j0,
+                                                   int seg_len, int c0, int clen, int groups, int csplit,
+                                                   double* ent_norm, int skip_n) {
+  __shared__ double red[GEN_SG][256];
+  __shared__ double us[GEN_SG][kMaxControls + 1];
+  const int J = blockIdx.x / (groups * csplit), g = (blockIdx.x / csplit) % groups, cs = blockIdx.x % csplit;
+  if (J >= njobs) return;
+  const JobDev jb = jobs[J];
+  if (jb.N <= skip_n) return;
+  const int jl0 = c0 + g * GEN_SG;
+  const int len = min(job_len(jb, seg_j0, seg_len), c0 + clen);
+  if (jl0 >= len) return;
+  const int ns = min(GEN_SG, len - jl0);
+  const int m = jb.m, mp = jb.mp, K = jb.K;
+  const int cw = (m + csplit - 1) / csplit, clo = cs * cw, chi = min(m, clo + cw);
+  const size_t plane = (size_t)mp * mp;
+  const double* H = jb.h64;
+  gen_load_controls(jb, u, seg_j0, jl0, ns, us);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double cmax[GEN_SG];
+#pragma unroll
+  for (int t = 0; t < GEN_SG; ++t) cmax[t] = 0.0;
+  for (int c = clo + wave; c < chi; c += nw) {
+    double cs_[GEN_SG];
+#pragma unroll
+    for (int t = 0; t < GEN_SG; ++t) cs_[t] = 0.0;
+    for (int rr = lane; rr < m; rr += 64) {
+      const size_t idx = (size_t)rr + (size_t)c * mp;
+      double hr[GEN_SG], hi[GEN_SG];
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
+      for (int o = 0; o <= K; ++o) {
+        const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
+#pragma unroll
+        for (int t = 0; t < GEN_SG; ++t) {
+          hr[t] += us[t][o] * ar;
+          hi[t] += us[t][o] * ai;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) cs_[t] += hypot(hr[t], hi[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < GEN_SG; ++t) cmax[t] = fmax(cmax[t], warp_sum(cs_[t]));
+  }
+#pragma unroll
+  for (int t = 0; t < GEN_SG; ++t) red[t][threadIdx.x] = cmax[t];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) red[t][threadIdx.x] = fmax(red[t][threadIdx.x], red[t][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < ns)
+    atomicMax(reinterpret_cast<unsigned long long*>(ent_norm + jb.ent_off + jl0 + threadIdx.x),
+              (unsigned long long)__double_as_longlong(red[threadIdx.x][0]));
+}
+
+__global__ void k_gen_pick(const JobDev* jobs, int njobs, const double* u, int seg_j0, int seg_len, int c0, int clen,
+                           int groups, int* ent_s, int* ent_q, double* ent_norm, int* flags, const double* theta, int r,
+                           int qmax, int t12, int smax, double norm_bound, int skip_n) {
+  const int J = blockIdx.x / groups, g = blockIdx.x % groups;
+  if (J >= njobs) return;
+  const JobDev jb = jobs[J];
+  if (jb.N <= skip_n) return;
+  const int jl0 = c0 + g * GEN_SG;
+  const int len = min(job_len(jb, seg_j0, seg_len), c0 + clen);
+  const int t = threadIdx.x;
+  if (t >= GEN_SG || jl0 + t >= len) return;
+  const long long e = jb.ent_off + jl0 + t;
+  const double nx = jb.dt * ent_norm[e];
+  bool finite = isfinite(nx);
+  for (int o = 0; o < jb.K; ++o) finite = finite && isfinite(u[jb.u_off + (size_t)(seg_j0 + jl0 + t) * jb.K + o]);
+  int flag = 0;
+  if (!finite) flag |= 2;
+  if (nx > norm_bound * (1.0 + 1e-12)) flag |= 1;
+  int best_q, best_s;
+  pick_degree(nx, theta, r, qmax, t12, &best_q, &best_s);
+  if (best_s > smax) { flag |= 1; best_s = smax; }
+  if (flag) atomicOr(flags, flag);
+  atomicMax(flags + 1, best_s);
+  ent_s[e] = best_s;
+  ent_q[e] = best_q;
+  ent_norm[e] = nx;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gen_form(const JobDev* jobs, int njobs, const double* u, int seg_j0,
+                                                  int seg_len, int c0, int clen, int groups, int csplit, char* ws,
+                                                  size_t off_T, const int* ent_s, int r, int skip_n) {
+  __shared__ double us[GEN_SG][kMaxControls + 1];
+  __shared__ double scale[GEN_SG];
+  const int J = blockIdx.x / (groups * csplit), g = (blockIdx.x / csplit) % groups, cs = blockIdx.x % csplit;
+  if (J >= njobs) return;
+  const JobDev jb = jobs[J];
+  if (jb.N <= skip_n) return;
+  const int jl0 = c0 + g * GEN_SG;
+  const int len = min(job_len(jb, seg_j0, seg_len), c0 + clen);
+  if (jl0 >= len) return;
+  const int ns = min(GEN_SG, len - jl0);
+  const int m = jb.m, mp = jb.mp, K = jb.K;
+  const size_t plane = (size_t)mp * mp;
+  const size_t ew = (plane + csplit - 1) / csplit, lo = cs * ew, hi_ = min(plane, lo + ew);
+  const double* H = jb.h64;
+  gen_load_controls(jb, u, seg_j0, jl0, ns, us);
+  if ((int)threadIdx.x < ns) scale[threadIdx.x] = ldexp(jb.dt, -ent_s[jb.ent_off + jl0 + threadIdx.x]);
+  __syncthreads();
+  const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
+  T* Y0 = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)(jl0 - c0) * ent_stride;
+  for (size_t idx = lo + threadIdx.x; idx < hi_; idx += blockDim.x) {
+    const int rr = (int)(idx % mp), c = (int)(idx / mp);
+    double hr[GEN_SG], hi[GEN_SG];
+#pragma unroll
+    for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
+    if (rr < m && c < m) {
+      for (int o = 0; o <= K; ++o) {
+        const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
+#pragma unroll
+        for (int t = 0; t < GEN_SG; ++t) {
+          hr[t] += us[t][o] * ar;
+          hi[t] += us[t][o] * ai;
+        }
+      }
+    }
 #pragma unroll
     for (int t = 0; t < GEN_SG; ++t) {
       if (t < ns) {
@@ -1877,11 +2040,31 @@ struct Driver {
     for (int c0 = 0; c0 < L; c0 += P->echunk) {
       const int clen = std::min(P->echunk, L - c0);
       const int groups = (clen + GEN_SG - 1) / GEN_SG;
-      timed(PK_GENERATOR, st, [&] {
-        hipLaunchKernelGGL(k_generator<T>, dim3(njobs * groups), dim3(256), 0, st, dj, njobs, u, seg_j0, L, c0, clen,
-                           groups, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags,
-                           P->d_theta.as<double>(), P->r, P->qmax, P->t12, P->smax, P->norm_bound, skip_n);
-      });
+      // too few (job, slice group) work-groups to fill the GPU: split each over columns
+      const long long wgs = (long long)njobs * groups;
+      const int csplit = wgs >= P->ncu ? 1
+                                       : (int)std::min<long long>((2LL * P->ncu + wgs - 1) / wgs,
+                                                                  std::max(1, P->max_mp / 16));
+      if (csplit == 1) {
+        timed(PK_GENERATOR, st, [&] {
+          hipLaunchKernelGGL(k_generator<T>, dim3(njobs * groups), dim3(256), 0, st, dj, njobs, u, seg_j0, L, c0,
+                             clen, groups, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags,
+                             P->d_theta.as<double>(), P->r, P->qmax, P->t12, P->smax, P->norm_bound, skip_n);
+        });
+      } else {
+        timed(PK_GENERATOR, st, [&] {
+          // the chunk's entries of ent_norm collect maxima: zero them first
+          hipLaunchKernelGGL(k_gen_zero, dim3((clen + 255) / 256, (unsigned)std::min(njobs, 65535)), dim3(256), 0, st,
+                             dj, njobs, c0, clen, ent_norm(P, ws));
+          hipLaunchKernelGGL(k_gen_norms, dim3((unsigned)(wgs * csplit)), dim3(256), 0, st, dj, njobs, u, seg_j0, L,
+                             c0, clen, groups, csplit, ent_norm(P, ws), skip_n);
+          hipLaunchKernelGGL(k_gen_pick, dim3((unsigned)wgs), dim3(64), 0, st, dj, njobs, u, seg_j0, L, c0, clen,
+                             groups, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags, P->d_theta.as<double>(),
+                             P->r, P->qmax, P->t12, P->smax, P->norm_bound, skip_n);
+          hipLaunchKernelGGL(k_gen_form<T>, dim3((unsigned)(wgs * csplit)), dim3(256), 0, st, dj, njobs, u, seg_j0,
+                             L, c0, clen, groups, csplit, ws, P->off_T, ent_s(P, ws), P->r, skip_n);
+        });
+      }
       auto step = [&](int mode, int s) {
         timed(PK_EXPM_GEMM, st, [&] {
           gemm_variant(P).expm(grid, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), mode, s,
@@ -2200,6 +2383,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     P->Q = bestQ;
   }
   QOC_REQUIRE(max_mp <= 4096, QOC_ERR_UNSUPPORTED, "blocks larger than 4096 are not supported by the sweep kernels");
+  P->max_mp = max_mp;
   size_t lds_elems = 0;
   for (auto& pr : probs)
     for (auto& b : pr.blocks)
