@@ -34,14 +34,14 @@ MFMA_PEAK = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix TFLOP/s, MI
 # (FETCH_SIZE, then WRITE_SIZE; mean KiB per dispatch over each tile variant's last 8
 # dispatches of `bench.py --steps 1 --warmup 1 --fp64-steps 0 --no-cpu-baseline
 # --copy-calibration 256 --sym-candidates 0 --ring14-slices 0 --batch-problems 0
-# --dense-slices 0 --paper-comparison 0 --optimizer 0 --gate 0`), each scaled by what the
-# same counter reads for the 256 MiB
+# --dense-slices 0 --paper-comparison 0 --optimizer 0 --gate 0 --lts 0`), each scaled by
+# what the same counter reads for the 256 MiB
 # calibration copy (FETCH_SIZE reads half of the bytes copied: x2.0; WRITE_SIZE all of
 # them: x1.0).  Valid only for the kernel sources they were taken with (sha1 of
 # mfma_tile.h + grape.hip).
-TRAFFIC = {"sources_sha1": "50ef65a5ff8af103e200421ccfcf7c10e70cbc06", "fetch_scale": 2.0, "write_scale": 1.0,
-           "kib": {"fp32 128x64": (11802002.5, 6447285.9), "fp32 64x64": (14315133.0, 6457807.4),
-                   "fp32 64x128": (12735038.9, 6044822.9)}}
+TRAFFIC = {"sources_sha1": "b5a6eb3e7bd88640a9dfdd0e0960ffbb2d735f4e", "fetch_scale": 2.0, "write_scale": 1.0,
+           "kib": {"fp32 128x64": (11782054.7, 6448232.2), "fp32 64x64": (14311744.0, 6465908.5),
+                   "fp32 64x128": (12710347.8, 6046942.3)}}
 
 
 def kernel_sources_sha1():
