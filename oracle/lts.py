@@ -22,7 +22,7 @@ not fit), ``exact_slice`` (Eq. (3) of the untrotterised H_j).
 from __future__ import annotations
 
 import numpy as np
-from scipy.linalg import expm
+from scipy.linalg import expm, expm_frechet
 
 from . import basis, counts, pauli
 
@@ -127,3 +127,50 @@ def exact_gate(n, Bz, c, u, dt):
     for j in range(np.asarray(u).shape[0]):
         K = exact_slice(n, Bz, c, u[j], dt) @ K
     return K
+
+
+def qubit_factor(Bz, ux, uy, dt):
+    """The 2 x 2 factor exp(-i dt h.sigma) of one qubit, h = (ux, uy, Bz) / 2."""
+    return expm(-1j * dt * (0.5 * Bz * SZ + 0.5 * ux * SX + 0.5 * uy * SY))
+
+
+def fidelity_grad(n, Bz, c, u, dt, psi0, psif):
+    """State transfer through the Trotterised propagator (Eq. (10)) and its exact gradient.
+
+    o = <psi_f| U_{N-1}^LTS ... U_0^LTS |psi_0>, F = |o|^2 / (||psi_N||^2 ||psi_f||^2) (the
+    objective of Eq. (4)).  The control u[j, 2(i-1)+a] enters only qubit i's factor g of
+    slice j, so do/du = <lambda| (dg/du on qubit i) |psi> with psi the state just before
+    that factor and lambda the costate just after it (psi_f carried back through the
+    adjoints of every later factor); dg/du is the Frechet derivative of the 2 x 2
+    exponential in the direction -i dt sigma_a / 2 (scipy's expm_frechet).  Returns F, o,
+    the norms and the gradient (N, 2n).  States are stored at every factor: small n only."""
+    u = np.asarray(u, dtype=float)
+    N = u.shape[0]
+    zs = np.array([[1.0 if ((x >> (n - q)) & 1) == 0 else -1.0 for q in range(1, n + 1)] for x in range(2 ** n)])
+    ecpl = 0.25 * c * sum(zs[:, q - 1] * zs[:, q % n] for q in range(1, n + 1))
+    phase = np.exp(-1j * (dt / n) * ecpl)
+    # forward: the sequence of factors, and the state before each qubit factor
+    ops, before = [], []
+    psi = np.array(psi0, dtype=complex).reshape(-1)
+    for j in range(N):
+        for i in range(n, 0, -1):
+            psi = phase * psi
+            before.append(psi)
+            g = qubit_factor(Bz, u[j, 2 * (i - 1)], u[j, 2 * (i - 1) + 1], dt)
+            ops.append((j, i, g))
+            psi = _apply_qubit(psi[:, None], n, i, g)[:, 0]
+    psif = np.array(psif, dtype=complex).reshape(-1)
+    o = np.vdot(psif, psi)
+    nN, nf = float(np.vdot(psi, psi).real), float(np.vdot(psif, psif).real)
+    grad = np.zeros((N, 2 * n))
+    lam = psif.copy()
+    for (j, i, g), pb in zip(reversed(ops), reversed(before)):
+        # lam is the costate just after factor (j, i)
+        h = 0.5 * Bz * SZ + 0.5 * u[j, 2 * (i - 1)] * SX + 0.5 * u[j, 2 * (i - 1) + 1] * SY
+        for a, s in enumerate((SX, SY)):
+            _, dg = expm_frechet(-1j * dt * h, -1j * dt * 0.5 * s)
+            do = np.vdot(lam, _apply_qubit(pb[:, None], n, i, dg)[:, 0])
+            grad[j, 2 * (i - 1) + a] = 2.0 * (np.conj(o) * do).real / (nN * nf)
+        lam = _apply_qubit(lam[:, None], n, i, g.conj().T)[:, 0]
+        lam = np.conj(phase) * lam
+    return {"F": abs(o) ** 2 / (nN * nf), "o": o, "nN": nN, "nf": nf, "grad": grad, "psiN": psi}

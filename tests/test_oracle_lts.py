@@ -73,3 +73,47 @@ def test_lts_gate_fidelity_close_to_exact_for_small_steps():
                                            [1])["F"])
     assert 0.0 < fs[1] < fs[0] < 1e-2
     assert 2.5 < fs[0] / fs[1] < 6.0
+
+
+def _states(seed, n):
+    rng = np.random.default_rng(seed)
+    p0 = rng.standard_normal(2 ** n) + 1j * rng.standard_normal(2 ** n)
+    pf = rng.standard_normal(2 ** n) + 1j * rng.standard_normal(2 ** n)
+    return p0 / np.linalg.norm(p0), pf / np.linalg.norm(pf)
+
+
+def test_trotterised_gradient_matches_central_differences():
+    n, N, dt, h = 4, 3, 0.1, 1e-5
+    u = _u(60, N, n)
+    p0, pf = _states(61, n)
+    r = lts.fidelity_grad(n, 1.0, 0.8, u, dt, p0, pf)
+    assert abs(r["F"] - abs(np.vdot(pf, lts.lts_gate(n, 1.0, 0.8, u, dt) @ p0)) ** 2) <= 1e-13
+    fd = np.zeros_like(u)
+    for j in range(N):
+        for k in range(2 * n):
+            up, um = u.copy(), u.copy()
+            up[j, k] += h
+            um[j, k] -= h
+            fd[j, k] = (lts.fidelity_grad(n, 1.0, 0.8, up, dt, p0, pf)["F"]
+                        - lts.fidelity_grad(n, 1.0, 0.8, um, dt, p0, pf)["F"]) / (2 * h)
+    assert np.abs(fd - r["grad"]).max() <= 1e-9 * max(1.0, np.abs(r["grad"]).max()) + 1e-10
+
+
+def test_without_coupling_the_gradient_is_the_exact_grape_gradient():
+    """c_cpl = 0: the split is exact, so objective and gradient equal those of the exact
+    propagators (the dense GRAPE oracle with 2n per-qubit control operators)."""
+    from oracle import grape
+    n, N, dt = 3, 4, 0.1
+    u = _u(62, N, n)
+    p0, pf = _states(63, n)
+    h0 = [{"kind": "one_body", "coeff": 0.5, "op": "z", "sites": "all", "stagger": False}]
+    hk = []
+    for i in range(1, n + 1):
+        for a in "XY":
+            s = ["I"] * n
+            s[i - 1] = a
+            hk.append([{"kind": "pauli", "coeff": 0.5, "string": "".join(s)}])
+    ref = grape.fidelity_grad(grape.dense_system(n, h0, hk), u, dt, [p0[:, None]], [pf[:, None]])
+    r = lts.fidelity_grad(n, 1.0, 0.0, u, dt, p0, pf)
+    assert abs(r["F"] - ref["F"]) <= 1e-13
+    assert np.abs(r["grad"] - np.asarray(ref["grad"])).max() <= 1e-12
