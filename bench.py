@@ -371,6 +371,27 @@ def lts_leg(q, torch, nmax=13, dt=0.05, Bz=1.0, c_cpl=1.0, dense_max=12, fid_n=1
     print(f"[bench] lts fidelity {res['fidelity']}", file=sys.stderr, flush=True)
     del P, S, B, Kd, Kl
     torch.cuda.empty_cache()
+    # objective and exact gradient: Pg candidate pulses through the Trotterised propagator
+    # (one work-group each) against the dense exact path of one pulse
+    n, Ng, Pg = fid_n, fid_N, 64
+    rng = np.random.default_rng(712)
+    ug = torch.tensor(rng.uniform(-1, 1, (Pg, Ng, 2 * n)), device="cuda")
+    p0 = torch.zeros((Pg, 2 ** n), dtype=torch.complex128, device="cuda")
+    p0[:, 0] = 1.0
+    pf = torch.zeros((Pg, 2 ** n), dtype=torch.complex128, device="cuda")
+    pf[:, -1] = 1.0
+    ms_g, _ = timed(lambda: q.lts_fidelity_grad(n, Bz, c_cpl, ug, dt, p0, pf), 2)
+    Nd = 20
+    B, S = per_qubit_system(n)
+    P = q.Plan(S, "c64", Nd, dt, 1.0)
+    ud = ug[0, :Nd].contiguous()
+    ms_d, _ = timed(lambda: q.fidelity_grad(P, ud, p0[0], pf[0], check=False), 2)
+    res["gradient"] = {"n": n, "slices": Ng, "candidates": Pg, "lts_ms": ms_g,
+                       "lts_us_per_slice_per_candidate": ms_g * 1e3 / (Ng * Pg),
+                       "dense_exact_ms_per_slice": ms_d / Nd, "dense_slices": Nd, "dense_precision": "complex64 MFMA"}
+    print(f"[bench] lts gradient {res['gradient']}", file=sys.stderr, flush=True)
+    del P, S, B
+    torch.cuda.empty_cache()
     return res
 
 

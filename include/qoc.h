@@ -286,6 +286,23 @@ qoc_status qoc_lts_workspace_size(int n, int N, size_t* bytes);
 qoc_status qoc_lts_apply(int n, double Bz, double c_cpl, const double* u_dev, int N, double dt,
                          const void* psi_in_dev, int ncols, void* psi_out_dev, void* workspace,
                          size_t workspace_bytes, void* stream);
+/* State transfer through the same Trotterised propagator and its exact gradient, for P
+ * independent problems (App. B: the transformed propagator serves gradient-based methods;
+ * here each qubit factor is differentiated exactly, not to first order).  Problem p has
+ * controls u_dev[p] (float64 [N][2n], problems back to back), psi0_dev[p] and psif_dev[p]
+ * (2^n interleaved complex128 each, back to back).  out_dev (float64 [P][8]): F =
+ * |o|^2 / (||psi_N||^2 ||psi_f||^2), |o|^2, Re o, Im o, ||psi_N||^2, ||psi_f||^2, 0, status
+ * (bit 1: non-finite), o = <psi_f|psi_N>.  grad_dev (float64 [P][N][2n]): dF/du =
+ * 2 Re(conj(o) <lambda| dg/du |psi>) / norms, psi the state just before the factor g of
+ * that control and lambda the costate just after it.  n: 1..12 (state and costate in LDS;
+ * QOC_ERR_UNSUPPORTED beyond).  workspace: qoc_lts_grad_workspace_size(n, N, P) bytes (the
+ * factors and their derivatives).  FP64; one work-group per problem; the backward pass
+ * recovers the states by undoing each factor, so nothing is stored per slice.
+ * Asynchronous on `stream`. */
+qoc_status qoc_lts_grad_workspace_size(int n, int N, int P, size_t* bytes);
+qoc_status qoc_lts_fidelity_grad(int n, double Bz, double c_cpl, const double* u_dev, int N, double dt,
+                                 int P, const void* psi0_dev, const void* psif_dev, double* out_dev,
+                                 double* grad_dev, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Benchmark instrumentation (process-wide, not thread-safe while enabled).
  * qoc_profile_begin pre-creates HIP events for up to max_launches kernel launches and

@@ -21,7 +21,8 @@ from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "propagate", "GrapeFidelity",
            "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
-           "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply"]
+           "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply",
+           "lts_fidelity_grad"]
 
 library_path = C.LIB_PATH
 
@@ -395,6 +396,32 @@ def lts_apply(n: int, Bz: float, c_cpl: float, u, dt: float, psi=None, ncols=Non
                             None if src is None else _ptr(src), int(k), _ptr(out), _ptr(ws),
                             ctypes.c_size_t(ws.numel()), _stream()))
     return out.transpose(0, 1)
+
+
+def lts_fidelity_grad(n: int, Bz: float, c_cpl: float, u, dt: float, psi0, psif):
+    """Objective and exact gradient through the Trotterised per-qubit-control propagator
+    (qoc_lts_fidelity_grad).  u: (N, 2n) or (P, N, 2n); psi0, psif: (2^n,) or (P, 2^n)
+    complex128.  Returns (out (P, 8) or (8,), grad shaped like u) on the device."""
+    torch = _torch()
+    u = u.to(torch.float64).contiguous()
+    single = u.dim() == 2
+    if single:
+        u = u[None]
+    P, N = u.shape[0], u.shape[1]
+    assert u.shape[2] == 2 * n and u.is_cuda
+    D = 1 << n
+    p0 = psi0.to(torch.complex128).reshape(P, D).contiguous()
+    pf = psif.to(torch.complex128).reshape(P, D).contiguous()
+    L = C.lib()
+    nbytes = ctypes.c_size_t()
+    C.check(L.qoc_lts_grad_workspace_size(int(n), int(N), int(P), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=u.device)
+    out = torch.empty((P, 8), dtype=torch.float64, device=u.device)
+    grad = torch.empty_like(u)
+    C.check(L.qoc_lts_fidelity_grad(int(n), float(Bz), float(c_cpl), _ptr(u), int(N), float(dt), int(P), _ptr(p0),
+                                    _ptr(pf), _ptr(out), _ptr(grad), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                    _stream()))
+    return (out[0], grad[0]) if single else (out, grad)
 
 
 def optimize_lbfgs(plan: Plan, u, psi0, psif, max_iter=100, memory=10, step0=0.1, c1=1e-4,

@@ -89,6 +89,10 @@ PROTOTYPES = {
     "qoc_lts_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "qoc_lts_apply": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, ctypes.c_int, ctypes.c_double,
                                      vp, ctypes.c_int, vp, vp, ctypes.c_size_t, vp]),
+    "qoc_lts_grad_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_size_t)]),
+    "qoc_lts_fidelity_grad": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, vp, ctypes.c_int,
+                                             ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_gate_propagate": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_gate_fidelity": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_optimize_workspace_size": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),

@@ -82,6 +82,181 @@ __global__ void __launch_bounds__(1024) k_lts_apply(int n, const double2* g, Lts
   for (int x = threadIdx.x; x < D; x += blockDim.x) out[(long long)col * D + x] = st[x];
 }
 
+// The factor and its derivatives for the gradient: per (problem, slice, qubit) twelve
+// entries, g then dg/dBx then dg/dBy (row-major 2 x 2 each).  With h = (Bx, By, B_z) / 2,
+// r = |h|, s = sin(t r) / r: g = cos(t r) I - i s h.sigma and
+//   dg/dh_a = -t sin(t r) (h_a / r) I - i s'(r) (h_a / r) h.sigma - i s sigma_a,
+//   s'(r) = (t r cos(t r) - sin(t r)) / r^2,  dg/dB_a = dg/dh_a / 2.
+__global__ void k_lts_factors_grad(int n, double Bz, const double* u, long long NP, double dt, double2* g) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < NP * n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long j = e / n;  // slice index over all problems (problem-major)
+    const int i = (int)(e % n);
+    const double hx = 0.5 * u[j * 2 * n + 2 * i], hy = 0.5 * u[j * 2 * n + 2 * i + 1], hz = 0.5 * Bz;
+    const double r = sqrt(hx * hx + hy * hy + hz * hz);
+    const double tr = dt * r, c = cos(tr), sn = sin(tr);
+    const double s = r > 0.0 ? sn / r : dt;
+    // s'(r) / r, with its series where t r is small
+    const double spr = tr > 1e-3 ? (tr * c - sn) / (r * r * r) : -dt * dt * dt / 3.0 * (1.0 - tr * tr / 10.0);
+    double2* o = g + 12 * e;
+    o[0] = make_double2(c, -s * hz);
+    o[1] = make_double2(-s * hy, -s * hx);
+    o[2] = make_double2(s * hy, -s * hx);
+    o[3] = make_double2(c, s * hz);
+    const double hs[2] = {hx, hy};
+    for (int a = 0; a < 2; ++a) {
+      const double A = r > 0.0 ? -dt * sn * hs[a] / r : 0.0, B = spr * hs[a];
+      // -i s sigma_a: sigma_x -> (0,1), (1,0) = -i s; sigma_y -> (0,1) = -s, (1,0) = +s
+      const double2 sx01 = a == 0 ? make_double2(0.0, -s) : make_double2(-s, 0.0);
+      const double2 sx10 = a == 0 ? make_double2(0.0, -s) : make_double2(s, 0.0);
+      double2* d = o + 4 + 4 * a;
+      d[0] = make_double2(0.5 * A, -0.5 * B * hz);
+      d[1] = make_double2(0.5 * (-B * hy + sx01.x), 0.5 * (-B * hx + sx01.y));
+      d[2] = make_double2(0.5 * (B * hy + sx10.x), 0.5 * (-B * hx + sx10.y));
+      d[3] = make_double2(0.5 * A, 0.5 * B * hz);
+    }
+  }
+}
+
+__device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// One work-group per problem, state and costate in LDS (n <= 12).  Forward: the pulse on
+// psi_0.  Then o, the norms, and backward, factor by factor in reverse: the gate is undone
+// on psi (giving the state just before it) and applied adjoint to lambda (the costate
+// just after it becomes the one just before it) while the pass accumulates
+// <lambda_after| dg/dB_a |psi_before> for a = x, y; the coupling phase is then undone on
+// both.  The wave partials of a factor go to one of two LDS slots by parity, so one barrier
+// per factor suffices; wave 0 adds them up after that barrier.
+__global__ void __launch_bounds__(1024) k_lts_grad(int n, const double2* fac, LtsPhases ph, int N,
+                                                   const double2* psi0, const double2* psif, double* out,
+                                                   double* grad) {
+  extern __shared__ double2 sm[];
+  __shared__ double part[2][16][4];
+  __shared__ double ored[16][4];
+  __shared__ double osum[4];
+  const int D = 1 << n, half = D >> 1;
+  const unsigned mask = (unsigned)D - 1u;
+  const int p = blockIdx.x;
+  double2* ps = sm;
+  double2* lm = sm + D;
+  const double2* F = fac + (size_t)p * N * n * 12;
+  for (int x = threadIdx.x; x < D; x += blockDim.x) ps[x] = psi0[(size_t)p * D + x];
+  __syncthreads();
+  for (int j = 0; j < N; ++j)
+    for (int i = n; i >= 1; --i) {
+      const int b = n - i;
+      const double2* f = F + 12 * ((size_t)j * n + (i - 1));
+      const double2 g00 = f[0], g01 = f[1], g10 = f[2], g11 = f[3];
+      for (int t = threadIdx.x; t < half; t += blockDim.x) {
+        const unsigned lo = (unsigned)t & ((1u << b) - 1u);
+        const unsigned a0 = (((unsigned)t >> b) << (b + 1)) | lo, a1 = a0 | (1u << b);
+        const unsigned r0 = ((a0 << 1) | (a0 >> (n - 1))) & mask, r1 = ((a1 << 1) | (a1 >> (n - 1))) & mask;
+        const double2 v0 = cmul(ps[a0], ph.v[__popc(a0 ^ r0)]), v1 = cmul(ps[a1], ph.v[__popc(a1 ^ r1)]);
+        const double2 n0 = cmul(g00, v0), n1 = cmul(g01, v1), m0 = cmul(g10, v0), m1 = cmul(g11, v1);
+        ps[a0] = make_double2(n0.x + n1.x, n0.y + n1.y);
+        ps[a1] = make_double2(m0.x + m1.x, m0.y + m1.y);
+      }
+      __syncthreads();
+    }
+  // o = <psi_f|psi_N>, norms
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  {
+    double orr = 0.0, oii = 0.0, nN = 0.0, nf = 0.0;
+    for (int x = threadIdx.x; x < D; x += blockDim.x) {
+      const double2 l = psif[(size_t)p * D + x], v = ps[x];
+      lm[x] = l;
+      const double2 c = cconjmul(l, v);
+      orr += c.x;
+      oii += c.y;
+      nN += v.x * v.x + v.y * v.y;
+      nf += l.x * l.x + l.y * l.y;
+    }
+    double vals[4] = {orr, oii, nN, nf};
+    for (int q = 0; q < 4; ++q) {
+      double v = vals[q];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) ored[wave][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      double v = 0.0;
+      for (int w = 0; w < nw; ++w) v += ored[w][threadIdx.x];
+      osum[threadIdx.x] = v;
+    }
+    __syncthreads();
+  }
+  const double o_r = osum[0], o_i = osum[1], nN = osum[2], nf = osum[3];
+  if (threadIdx.x == 0) {
+    double* o = out + (size_t)p * 8;
+    const double raw = o_r * o_r + o_i * o_i;
+    o[0] = raw / (nN * nf);
+    o[1] = raw;
+    o[2] = o_r;
+    o[3] = o_i;
+    o[4] = nN;
+    o[5] = nf;
+    o[6] = 0.0;
+    o[7] = isfinite(o[0]) ? 0.0 : 2.0;
+  }
+  const double scale = 2.0 / (nN * nf);
+  double* G = grad + (size_t)p * N * 2 * n;
+  int step = 0;
+  for (int j = N - 1; j >= 0; --j)
+    for (int i = 1; i <= n; ++i, ++step) {
+      const int b = n - i;
+      const double2* f = F + 12 * ((size_t)j * n + (i - 1));
+      const double2 g00 = f[0], g01 = f[1], g10 = f[2], g11 = f[3];
+      const double2 x00 = f[4], x01 = f[5], x10 = f[6], x11 = f[7];
+      const double2 y00 = f[8], y01 = f[9], y10 = f[10], y11 = f[11];
+      double dxr = 0.0, dxi = 0.0, dyr = 0.0, dyi = 0.0;
+      for (int t = threadIdx.x; t < half; t += blockDim.x) {
+        const unsigned lo = (unsigned)t & ((1u << b) - 1u);
+        const unsigned a0 = (((unsigned)t >> b) << (b + 1)) | lo, a1 = a0 | (1u << b);
+        const double2 p0 = ps[a0], p1 = ps[a1], l0 = lm[a0], l1 = lm[a1];
+        // psi before the gate: g^dag psi
+        const double2 q0 = make_double2(cconjmul(g00, p0).x + cconjmul(g10, p1).x, cconjmul(g00, p0).y + cconjmul(g10, p1).y);
+        const double2 q1 = make_double2(cconjmul(g01, p0).x + cconjmul(g11, p1).x, cconjmul(g01, p0).y + cconjmul(g11, p1).y);
+        // <lambda_after| dg |psi_before>
+        const double2 ax0 = make_double2(cmul(x00, q0).x + cmul(x01, q1).x, cmul(x00, q0).y + cmul(x01, q1).y);
+        const double2 ax1 = make_double2(cmul(x10, q0).x + cmul(x11, q1).x, cmul(x10, q0).y + cmul(x11, q1).y);
+        const double2 ay0 = make_double2(cmul(y00, q0).x + cmul(y01, q1).x, cmul(y00, q0).y + cmul(y01, q1).y);
+        const double2 ay1 = make_double2(cmul(y10, q0).x + cmul(y11, q1).x, cmul(y10, q0).y + cmul(y11, q1).y);
+        const double2 cx0 = cconjmul(l0, ax0), cx1 = cconjmul(l1, ax1), cy0 = cconjmul(l0, ay0), cy1 = cconjmul(l1, ay1);
+        dxr += cx0.x + cx1.x;
+        dxi += cx0.y + cx1.y;
+        dyr += cy0.x + cy1.x;
+        dyi += cy0.y + cy1.y;
+        // lambda before the gate: g^dag lambda
+        const double2 k0 = make_double2(cconjmul(g00, l0).x + cconjmul(g10, l1).x, cconjmul(g00, l0).y + cconjmul(g10, l1).y);
+        const double2 k1 = make_double2(cconjmul(g01, l0).x + cconjmul(g11, l1).x, cconjmul(g01, l0).y + cconjmul(g11, l1).y);
+        // undo the coupling phase on both
+        const unsigned r0 = ((a0 << 1) | (a0 >> (n - 1))) & mask, r1 = ((a1 << 1) | (a1 >> (n - 1))) & mask;
+        const double2 e0 = ph.v[__popc(a0 ^ r0)], e1 = ph.v[__popc(a1 ^ r1)];
+        ps[a0] = cconjmul(e0, q0);
+        ps[a1] = cconjmul(e1, q1);
+        lm[a0] = cconjmul(e0, k0);
+        lm[a1] = cconjmul(e1, k1);
+      }
+      double vals[4] = {dxr, dxi, dyr, dyi};
+      for (int q = 0; q < 4; ++q) {
+        double v = vals[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) part[step & 1][wave][q] = v;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < nw; ++w)
+          for (int q = 0; q < 4; ++q) s4[q] += part[step & 1][w][q];
+        // 2 Re(conj(o) d) / norms
+        G[(size_t)j * 2 * n + 2 * (i - 1)] = scale * (o_r * s4[0] + o_i * s4[1]);
+        G[(size_t)j * 2 * n + 2 * (i - 1) + 1] = scale * (o_r * s4[2] + o_i * s4[3]);
+      }
+    }
+}
+
 }  // namespace
 }  // namespace qoc
 
@@ -126,6 +301,52 @@ qoc_status qoc_lts_apply(int n, double Bz, double c_cpl, const double* u_dev, in
     const int threads = std::min(1024, std::max(64, (D / 2 + 63) / 64 * 64));
     hipLaunchKernelGGL(k_lts_apply, dim3((unsigned)ncols), dim3(threads), lds, st, n, g, ph, N,
                        static_cast<const double2*>(psi_in_dev), (long long)D, static_cast<double2*>(psi_out_dev));
+    QOC_HIP(hipGetLastError());
+  });
+}
+
+qoc_status qoc_lts_grad_workspace_size(int n, int N, int P, size_t* bytes) {
+  return guarded([&] {
+    QOC_REQUIRE(bytes, QOC_ERR_INVALID_ARG, "null argument");
+    QOC_REQUIRE(n >= 1 && n <= kLtsMaxQubits - 1, QOC_ERR_UNSUPPORTED,
+                "n must be in 1..12 (state and costate live in LDS)");
+    QOC_REQUIRE(N >= 1 && P >= 1, QOC_ERR_INVALID_ARG, "N and P must be >= 1");
+    *bytes = (size_t)P * N * n * 12 * sizeof(double2);
+  });
+}
+
+qoc_status qoc_lts_fidelity_grad(int n, double Bz, double c_cpl, const double* u_dev, int N, double dt, int P,
+                                 const void* psi0_dev, const void* psif_dev, double* out_dev, double* grad_dev,
+                                 void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    QOC_REQUIRE(u_dev && psi0_dev && psif_dev && out_dev && grad_dev && workspace, QOC_ERR_INVALID_ARG,
+                "null argument");
+    QOC_REQUIRE(n >= 1 && n <= kLtsMaxQubits - 1, QOC_ERR_UNSUPPORTED,
+                "n must be in 1..12 (state and costate live in LDS)");
+    QOC_REQUIRE(N >= 1 && N <= (1 << 26) && P >= 1 && P <= 65535, QOC_ERR_INVALID_ARG,
+                "N must be in 1..2^26 and P in 1..65535");
+    QOC_REQUIRE(std::isfinite(Bz) && std::isfinite(c_cpl) && std::isfinite(dt) && dt > 0.0, QOC_ERR_INVALID_ARG,
+                "B_z, c_cpl and dt must be finite, dt > 0");
+    QOC_REQUIRE(ws_bytes >= (size_t)P * N * n * 12 * sizeof(double2), QOC_ERR_OUT_OF_MEMORY,
+                "workspace smaller than qoc_lts_grad_workspace_size");
+    hipStream_t st = (hipStream_t)stream;
+    double2* g = static_cast<double2*>(workspace);
+    const long long NP = (long long)N * P;
+    hipLaunchKernelGGL(k_lts_factors_grad, dim3((unsigned)std::min<long long>((NP * n + 255) / 256, 4096)),
+                       dim3(256), 0, st, n, Bz, u_dev, NP, dt, g);
+    QOC_HIP(hipGetLastError());
+    LtsPhases ph{};
+    for (int k = 0; k <= n; ++k) {
+      const double a = -(dt / n) * 0.25 * c_cpl * (double)(n - 2 * k);
+      ph.v[k] = make_double2(std::cos(a), std::sin(a));
+    }
+    const int D = 1 << n;
+    const int lds = 2 * D * (int)sizeof(double2);
+    QOC_HIP(hipFuncSetAttribute((const void*)k_lts_grad, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    const int threads = std::min(1024, std::max(64, (D / 2 + 63) / 64 * 64));
+    hipLaunchKernelGGL(k_lts_grad, dim3((unsigned)P), dim3(threads), lds, st, n, g, ph, N,
+                       static_cast<const double2*>(psi0_dev), static_cast<const double2*>(psif_dev), out_dev,
+                       grad_dev);
     QOC_HIP(hipGetLastError());
   });
 }

@@ -88,6 +88,9 @@ def test_lts_sizes_host_only():
     assert L.qoc_lts_workspace_size(14, 100, ctypes.byref(nbytes)) == 3
     assert L.qoc_lts_workspace_size(0, 100, ctypes.byref(nbytes)) == 3
     assert L.qoc_lts_workspace_size(5, 0, ctypes.byref(nbytes)) == 1
+    assert L.qoc_lts_grad_workspace_size(12, 10, 2, ctypes.byref(nbytes)) == 0 and nbytes.value == 2 * 10 * 12 * 12 * 16
+    assert L.qoc_lts_grad_workspace_size(13, 10, 1, ctypes.byref(nbytes)) == 3
+    assert L.qoc_lts_fidelity_grad(4, 1.0, 1.0, None, 10, 0.1, 1, None, None, None, None, None, 0, None) == 1
 
 
 def test_symmetric_basis_is_host_only():

@@ -110,3 +110,24 @@ def test_eighteen_per_qubit_controls_gradient_matches_the_oracle(lib):
     ref = grape.fidelity_grad(dense, u, dt, [p0[:, None]], [pf[:, None]])
     assert abs(out[0].item() - ref["F"]) <= 1e-12
     assert np.abs(g.cpu().numpy() - np.asarray(ref["grad"])).max() <= 1e-12
+
+
+@pytest.mark.parametrize("n,N,P", [(1, 3, 1), (4, 5, 3), (7, 4, 2), (12, 2, 1)])
+def test_trotterised_gradient_matches_the_oracle(lib, n, N, P):
+    import torch
+    print(f"lts gradient n={n} N={N} P={P}", flush=True)
+    dt, Bz, c = 0.1, 1.0, 0.8
+    rng = np.random.default_rng(70 + n)
+    u = rng.uniform(-1, 1, (P, N, 2 * n))
+    p0 = rng.standard_normal((P, 2 ** n)) + 1j * rng.standard_normal((P, 2 ** n))
+    pf = rng.standard_normal((P, 2 ** n)) + 1j * rng.standard_normal((P, 2 ** n))
+    p0 /= np.linalg.norm(p0, axis=1, keepdims=True)
+    pf /= np.linalg.norm(pf, axis=1, keepdims=True)
+    out, g = lib.lts_fidelity_grad(n, Bz, c, torch.tensor(u, device="cuda"), dt, torch.tensor(p0, device="cuda"),
+                                   torch.tensor(pf, device="cuda"))
+    out, g = out.cpu().numpy(), g.cpu().numpy()
+    for p in range(P):
+        ref = lts.fidelity_grad(n, Bz, c, u[p], dt, p0[p], pf[p])
+        assert abs(out[p, 0] - ref["F"]) <= 1e-12 and out[p, 7] == 0.0
+        assert abs(complex(out[p, 2], out[p, 3]) - ref["o"]) <= 1e-12
+        assert np.abs(g[p] - ref["grad"]).max() <= 1e-12 * max(1.0, np.abs(ref["grad"]).max())
