@@ -11,8 +11,9 @@
 // unequal neighbour pairs on the ring, sum_i z_i z_{i+1} = n - 2k.
 //
 // One work-group owns one column (2^n amplitudes in LDS, n <= 13) for the whole pulse:
-// per slice and qubit (n down to 1, the rightmost factor acting first) one pass multiplies
-// by the coupling phase and applies the qubit's 2 x 2 factor, then a barrier.  The 2 x 2
+// per slice and qubit (n down to 1, the rightmost factor acting first) the column is
+// multiplied by the coupling phase and the qubit's 2 x 2 factor is applied; three qubits
+// share one pass over LDS (their 8 amplitudes in registers), then a barrier.  The 2 x 2
 // factors of every (slice, qubit) are formed first, in closed form
 // exp(-i t h.sigma) = cos(t|h|) I - i sin(t|h|)/|h| h.sigma, by k_lts_factors.  All
 // arithmetic is FP64.  Qubit q sits at bit n - q; bit 0 is spin up (z = +1).
@@ -52,33 +53,80 @@ __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// One LDS pass over Q consecutive qubit bits p .. p + Q - 1 (qubits n - p, n - p - 1, ...,
+// applied in that order): each thread takes the 2^Q amplitudes that differ only in those
+// bits into registers and applies, per bit, the coupling phase and that qubit's 2 x 2
+// factor, so a slice needs ceil(n / 3) passes and barriers instead of n.
+template <int Q>
+__device__ inline void lts_pass(double2* st, int n, int p, const double2* gj, int es, const LtsPhases& ph) {
+  constexpr int M = 1 << Q;
+  const int D = 1 << n;
+  const unsigned mask = (unsigned)D - 1u;
+  double2 g[Q][4];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double2* f = gj + es * (n - (p + k) - 1);  // qubit n - (p + k); es entries per factor
+#pragma unroll
+    for (int e = 0; e < 4; ++e) g[k][e] = f[e];
+  }
+  for (int t = threadIdx.x; t < (D >> Q); t += blockDim.x) {
+    const unsigned lo = (unsigned)t & ((1u << p) - 1u);
+    const unsigned base = (((unsigned)t >> p) << (p + Q)) | lo;
+    double2 v[M], e[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const unsigned a = base | ((unsigned)m << p);
+      const unsigned ra = ((a << 1) | (a >> (n - 1))) & mask;
+      v[m] = st[a];
+      e[m] = ph.v[__popc(a ^ ra)];
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) v[m] = cmul(v[m], e[m]);
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if (m & (1 << k)) continue;
+        const int m1 = m | (1 << k);
+        const double2 x0 = v[m], x1 = v[m1];
+        const double2 n0 = cmul(g[k][0], x0), n1 = cmul(g[k][1], x1), q0 = cmul(g[k][2], x0), q1 = cmul(g[k][3], x1);
+        v[m] = make_double2(n0.x + n1.x, n0.y + n1.y);
+        v[m1] = make_double2(q0.x + q1.x, q0.y + q1.y);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) st[base | ((unsigned)m << p)] = v[m];
+  }
+}
+
+// the slices j of the pulse on the column in st, three qubits per pass; the factors hold
+// es entries per (slice, qubit), the 2 x 2 factor first
+__device__ inline void lts_forward(double2* st, int n, const double2* g, int N, const LtsPhases& ph, int es) {
+  for (int j = 0; j < N; ++j) {
+    const double2* gj = g + (long long)es * j * n;
+    for (int p = 0; p < n;) {
+      const int Q = n - p >= 3 ? 3 : n - p;
+      if (Q == 3)
+        lts_pass<3>(st, n, p, gj, es, ph);
+      else if (Q == 2)
+        lts_pass<2>(st, n, p, gj, es, ph);
+      else
+        lts_pass<1>(st, n, p, gj, es, ph);
+      p += Q;
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_lts_apply(int n, const double2* g, LtsPhases ph, int N,
                                                     const double2* in, long long ldin, double2* out) {
   extern __shared__ double2 st[];
   const int D = 1 << n;
-  const unsigned mask = (unsigned)D - 1u;
   const int col = blockIdx.x;
   for (int x = threadIdx.x; x < D; x += blockDim.x)
     st[x] = in ? in[(long long)col * ldin + x] : make_double2(x == col ? 1.0 : 0.0, 0.0);
   __syncthreads();
-  const int half = D >> 1;
-  for (int j = 0; j < N; ++j) {
-    for (int i = n; i >= 1; --i) {
-      const int p = n - i;
-      const double2* f = g + 4 * ((long long)j * n + (i - 1));
-      const double2 g00 = f[0], g01 = f[1], g10 = f[2], g11 = f[3];
-      for (int t = threadIdx.x; t < half; t += blockDim.x) {
-        const unsigned lo = (unsigned)t & ((1u << p) - 1u);
-        const unsigned a = (((unsigned)t >> p) << (p + 1)) | lo, b = a | (1u << p);
-        const unsigned ra = ((a << 1) | (a >> (n - 1))) & mask, rb = ((b << 1) | (b >> (n - 1))) & mask;
-        const double2 va = cmul(st[a], ph.v[__popc(a ^ ra)]), vb = cmul(st[b], ph.v[__popc(b ^ rb)]);
-        const double2 na = cmul(g00, va), nb = cmul(g01, vb), ma = cmul(g10, va), mb = cmul(g11, vb);
-        st[a] = make_double2(na.x + nb.x, na.y + nb.y);
-        st[b] = make_double2(ma.x + mb.x, ma.y + mb.y);
-      }
-      __syncthreads();
-    }
-  }
+  lts_forward(st, n, g, N, ph, 4);
   for (int x = threadIdx.x; x < D; x += blockDim.x) out[(long long)col * D + x] = st[x];
 }
 
@@ -144,22 +192,7 @@ __global__ void __launch_bounds__(1024) k_lts_grad(int n, const double2* fac, Lt
   const double2* F = fac + (size_t)p * N * n * 12;
   for (int x = threadIdx.x; x < D; x += blockDim.x) ps[x] = psi0[(size_t)p * D + x];
   __syncthreads();
-  for (int j = 0; j < N; ++j)
-    for (int i = n; i >= 1; --i) {
-      const int b = n - i;
-      const double2* f = F + 12 * ((size_t)j * n + (i - 1));
-      const double2 g00 = f[0], g01 = f[1], g10 = f[2], g11 = f[3];
-      for (int t = threadIdx.x; t < half; t += blockDim.x) {
-        const unsigned lo = (unsigned)t & ((1u << b) - 1u);
-        const unsigned a0 = (((unsigned)t >> b) << (b + 1)) | lo, a1 = a0 | (1u << b);
-        const unsigned r0 = ((a0 << 1) | (a0 >> (n - 1))) & mask, r1 = ((a1 << 1) | (a1 >> (n - 1))) & mask;
-        const double2 v0 = cmul(ps[a0], ph.v[__popc(a0 ^ r0)]), v1 = cmul(ps[a1], ph.v[__popc(a1 ^ r1)]);
-        const double2 n0 = cmul(g00, v0), n1 = cmul(g01, v1), m0 = cmul(g10, v0), m1 = cmul(g11, v1);
-        ps[a0] = make_double2(n0.x + n1.x, n0.y + n1.y);
-        ps[a1] = make_double2(m0.x + m1.x, m0.y + m1.y);
-      }
-      __syncthreads();
-    }
+  lts_forward(ps, n, F, N, ph, 12);
   // o = <psi_f|psi_N>, norms
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   {
@@ -298,7 +331,7 @@ qoc_status qoc_lts_apply(int n, double Bz, double c_cpl, const double* u_dev, in
     }
     const int lds = D * (int)sizeof(double2);
     QOC_HIP(hipFuncSetAttribute((const void*)k_lts_apply, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    const int threads = std::min(1024, std::max(64, (D / 2 + 63) / 64 * 64));
+    const int threads = std::min(1024, std::max(64, (D / 8 + 63) / 64 * 64));
     hipLaunchKernelGGL(k_lts_apply, dim3((unsigned)ncols), dim3(threads), lds, st, n, g, ph, N,
                        static_cast<const double2*>(psi_in_dev), (long long)D, static_cast<double2*>(psi_out_dev));
     QOC_HIP(hipGetLastError());
