@@ -339,7 +339,10 @@ def lts_leg(q, torch, nmax=13, dt=0.05, Bz=1.0, c_cpl=1.0, dense_max=12, fid_n=1
         Nl = 200
         u = torch.tensor(rng.uniform(-1, 1, (Nl, 2 * n)), device="cuda")
         ms_l, _ = timed(lambda: q.lts_apply(n, Bz, c_cpl, u, dt), 2)
-        e = {"n": n, "lts_ms_per_step": ms_l / Nl}
+        # FP64 vector work per step: 2^n columns x n qubits x 2^(n-1) amplitude pairs, each a
+        # 2 x 2 complex product (28 flops) and two phase products (12 flops)
+        tflops = (2 ** n) * n * 2 ** (n - 1) * 40.0 / (ms_l / Nl * 1e-3) / 1e12
+        e = {"n": n, "lts_ms_per_step": ms_l / Nl, "lts_fp64_tflops": tflops, "lts_frac_of_fp64_vector_peak": tflops / 78.6}
         if n <= dense_max:
             Nd = 20 if n <= 10 else 8
             B, S = per_qubit_system(n)
