@@ -156,6 +156,7 @@ struct qoc_plan_s {
   long long expm_items = 0, panel_items = 0;
   long long entries_per_seg = 0;
   int max_mp = 0;         // largest padded block
+  bool small_grad = false;  // every block <= 64 wide: the one-wave gradient series
   size_t sweep_lds_elems = 0;
   int max_cc = 0;
   long long total_u = 0, total_D = 0, total_U = 0;
@@ -1577,6 +1578,151 @@ __global__ void __launch_bounds__(256) k_series_dot(const JobDev* jobs, int njob
   }
 }
 
+// The whole Frechet series of one (job, slice, copy) in one wave, for plans whose blocks
+// are at most 32 wide: lane = row, vectors broadcast through LDS, the operators read
+// from the working-precision planes (L2-resident, shared by every slice of a job).  It
+// computes what the panel-GEMM route computes term by term: the b-series
+// b_0 = lambda^(r), b_{i+1} = +i (dt/R) H_j b_i / (i+1), lambda^(r-1) = sum_i b_i, folded
+// at once into c_t^(r) = sum_{i <= Q-1-t} w(t, i) b_i (w = i! t! / (i+t+1)!); then the
+// a-series a_0 = psi^(r), a_{t+1} = -i (dt/R) H_j a_t / (t+1), psi^(r+1) = sum_t a_t, with
+// G[k] += <c_t^(r)| H_k a_t> in FP64.  One launch replaces the 4 R Q launches of that
+// route, which dominate the step for small blocks.
+constexpr int kSmallGradRows = 64;
+constexpr int kSmallGradMaxRQ = 48;
+// up to this width the one-wave series beats the panel-GEMM route (each lane walks m
+// columns per product, so the wave's latency grows with m)
+constexpr int kSmallGradMaxWidth = 32;
+
+template <typename T>
+__device__ inline double2 small_hv(const T* H, size_t hplane, int mp, int m, int row, int o, const T* vr,
+                                   const T* vi) {
+  T ar = T(0), ai = T(0);
+  if (row < m) {
+    const T* hr = H + (size_t)(2 * o) * hplane + row;
+    const T* hi = H + (size_t)(2 * o + 1) * hplane + row;
+    for (int c = 0; c < m; ++c) {
+      const T xr = hr[(size_t)c * mp], xi = hi[(size_t)c * mp], yr = vr[c], yi = vi[c];
+      ar += xr * yr - xi * yi;
+      ai += xr * yi + xi * yr;
+    }
+  }
+  return make_double2((double)ar, (double)ai);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_grad_small(const JobDev* jobs, int njobs, char* ws, size_t off_T,
+                                                   size_t off_gacc, const double* u, const double* w, int R, int Q,
+                                                   int j0, int chunk) {
+  extern __shared__ double cbuf[];  // c_t^(r): [R][Q][64] complex (re, im)
+  __shared__ T vr[kSmallGradRows], vi[kSmallGradRows];
+  const int J = blockIdx.y;
+  if (J >= njobs) return;
+  const JobDev jb = jobs[J];
+  const int nsl = min(chunk, jb.N - j0);
+  const int col = blockIdx.x;  // chunk column: slice jj, copy c
+  if (nsl <= 0 || col >= nsl * jb.d) return;
+  const int jj = col / jb.d, cp = col % jb.d;
+  const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N, K = jb.K;
+  const int row = threadIdx.x;
+  const size_t hplane = (size_t)mp * mp;
+  const T* H = static_cast<const T*>(jb.hT);
+  const double* uj = u + jb.u_off + (size_t)(j0 + jj) * K;
+  const T cdt = (T)(jb.dt / R);
+  // H_j v for the vector in (vr, vi), this lane's row, in the working precision
+  auto hjv = [&](T& outr, T& outi) {
+    T ar = T(0), ai = T(0);
+    for (int o = 0; o <= K; ++o) {
+      const double2 z = small_hv<T>(H, hplane, mp, m, row, o, vr, vi);
+      const T uo = o == 0 ? T(1) : (T)uj[o - 1];
+      ar += uo * (T)z.x;
+      ai += uo * (T)z.y;
+    }
+    outr = ar;
+    outi = ai;
+  };
+  // costate lambda_{j+1} and state psi_j of this column
+  const T* Lm = tplane<T>(ws, off_T, jb.lam_off);
+  const size_t lps = (size_t)mp * N * d;
+  const T* Ps = tplane<T>(ws, off_T, jb.psi_off);
+  const size_t pps = (size_t)mp * (N + 1) * d;
+  const size_t gcol = ((size_t)(j0 + jj) * d + cp) * mp;
+  T br = row < m ? Lm[gcol + row] : T(0), bi = row < m ? Lm[gcol + row + lps] : T(0);
+  double* C = cbuf;  // index ((r * Q + t) * 64 + row) * 2
+  for (int r = R - 1; r >= 0; --r) {
+    T sr = br, si = bi;
+    for (int t = 0; t < Q; ++t) {
+      double* ct = C + ((size_t)(r * Q + t) * kSmallGradRows + row) * 2;
+      ct[0] = w[(size_t)t * Q] * (double)br;
+      ct[1] = w[(size_t)t * Q] * (double)bi;
+    }
+    for (int i = 0; i + 1 < Q; ++i) {
+      vr[row] = br;
+      vi[row] = bi;
+      __syncthreads();
+      T hr, hi;
+      hjv(hr, hi);
+      __syncthreads();
+      const T cf = cdt / (T)(i + 1);
+      br = -cf * hi;  // (+i cf)(hr + i hi)
+      bi = cf * hr;
+      if (row >= m) br = bi = T(0);
+      sr += br;
+      si += bi;
+      for (int t = 0; t + i + 1 < Q; ++t) {
+        double* ct = C + ((size_t)(r * Q + t) * kSmallGradRows + row) * 2;
+        const double wt = w[(size_t)t * Q + i + 1];
+        ct[0] += wt * (double)br;
+        ct[1] += wt * (double)bi;
+      }
+    }
+    br = sr;
+    bi = si;
+  }
+  // a-series and the dots (wave sums; lane 0 keeps the totals in LDS)
+  __shared__ double gsum[2 * kMaxControls];
+  if (row < 2 * K) gsum[row] = 0.0;
+  T ar_ = row < m ? Ps[gcol + row] : T(0), ai_ = row < m ? Ps[gcol + row + pps] : T(0);
+  for (int r = 0; r < R; ++r) {
+    const bool next_state = r + 1 < R;
+    T sr = ar_, si = ai_;
+    for (int t = 0; t < Q; ++t) {
+      vr[row] = ar_;
+      vi[row] = ai_;
+      __syncthreads();
+      const double* ct = C + ((size_t)(r * Q + t) * kSmallGradRows + row) * 2;
+      const double cr = row < m ? ct[0] : 0.0, ci = row < m ? ct[1] : 0.0;
+      T hr = T(0), hi = T(0);
+      for (int o = 0; o <= K; ++o) {
+        const double2 z = small_hv<T>(H, hplane, mp, m, row, o, vr, vi);
+        const T uo = o == 0 ? T(1) : (T)uj[o - 1];
+        hr += uo * (T)z.x;
+        hi += uo * (T)z.y;
+        if (o > 0) {
+          const double dr = warp_sum(cr * z.x + ci * z.y), di = warp_sum(cr * z.y - ci * z.x);
+          if (row == 0) {
+            gsum[2 * (o - 1)] += dr;
+            gsum[2 * (o - 1) + 1] += di;
+          }
+        }
+      }
+      __syncthreads();
+      if (t + 1 < Q || next_state) {
+        const T cf = cdt / (T)(t + 1);
+        ar_ = cf * hi;  // (-i cf)(hr + i hi)
+        ai_ = -cf * hr;
+        if (row >= m) ar_ = ai_ = T(0);
+        sr += ar_;
+        si += ai_;
+      }
+    }
+    ar_ = sr;
+    ai_ = si;
+  }
+  __syncthreads();
+  double2* G = reinterpret_cast<double2*>(ws + off_gacc) + jb.gacc_off + (size_t)col * K;
+  if (row < K) G[row] = make_double2(gsum[2 * row], gsum[2 * row + 1]);
+}
+
 // grad[j][k] = 2 Re(conj(o) (-i dt/R) sum_{jobs,copies} G) / (||psi_N||^2 ||psi_f||^2), per problem
 __global__ void k_grad_finish(const JobDev* jobs, const ProbDev* probs, const char* ws, size_t off_gacc, int j0,
                               int chunk, int R, const double* out, double* grad) {
@@ -2223,6 +2369,20 @@ struct Driver {
     const PanelDesc* dp = P->d_panels.as<PanelDesc>();
     const int npanel = (int)P->panels.size();
     const int C = P->chunk;
+    if (P->small_grad && njobs <= 65535) {
+      const size_t lds = (size_t)R * Q * kSmallGradRows * 2 * sizeof(double);
+      for (int j0 = 0; j0 < P->Nmax; j0 += C) {
+        timed(PK_GRAD_VECTOR, st, [&] {
+          hipLaunchKernelGGL(k_grad_small<T>, dim3((unsigned)P->max_cc, (unsigned)njobs), dim3(kSmallGradRows), lds, st,
+                             dj, njobs, ws, P->off_T, P->off_gacc, u, P->d_w.as<double>(), R, Q, j0, C);
+        });
+        timed(PK_GRAD_FINISH, st, [&] {
+          hipLaunchKernelGGL(k_grad_finish, dim3((C * K + 255) / 256, P->P), dim3(256), 0, st, dj, dpr, ws,
+                             P->off_gacc, j0, C, R, out, grad);
+        });
+      }
+      return;
+    }
     for (int j0 = 0; j0 < P->Nmax; j0 += C) {
       auto gemm = [&](int vslot) {
         timed(PK_GRAD_GEMM, st, [&] {
@@ -2382,6 +2542,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     P->R = bestR;
     P->Q = bestQ;
   }
+  P->small_grad = max_mp <= kSmallGradMaxWidth && P->R * P->Q <= kSmallGradMaxRQ;
   QOC_REQUIRE(max_mp <= 4096, QOC_ERR_UNSUPPORTED, "blocks larger than 4096 are not supported by the sweep kernels");
   P->max_mp = max_mp;
   size_t lds_elems = 0;
