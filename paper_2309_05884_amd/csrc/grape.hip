@@ -2186,9 +2186,10 @@ struct Driver {
     for (int c0 = 0; c0 < L; c0 += P->echunk) {
       const int clen = std::min(P->echunk, L - c0);
       const int groups = (clen + GEN_SG - 1) / GEN_SG;
-      // too few (job, slice group) work-groups to fill the GPU: split each over columns
+      // too few (job, slice group) work-groups to fill the GPU, each reading large operator
+      // planes: split each over columns
       const long long wgs = (long long)njobs * groups;
-      const int csplit = wgs >= P->ncu ? 1
+      const int csplit = wgs >= P->ncu || P->max_mp < 64 ? 1
                                        : (int)std::min<long long>((2LL * P->ncu + wgs - 1) / wgs,
                                                                   std::max(1, P->max_mp / 16));
       if (csplit == 1) {
