@@ -305,6 +305,7 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
     if (best_s > smax) { flag |= 1; best_s = smax; }
     if (flag) atomicOr(flags, flag);
     atomicMax(flags + 1, best_s);
+    atomicMax(flags + 2, best_q);
     ent_s[e] = best_s;
     ent_q[e] = best_q;
     ent_norm[e] = nx;
@@ -448,6 +449,7 @@ __global__ void k_gen_pick(const JobDev* jobs, int njobs, const double* u, int s
   if (best_s > smax) { flag |= 1; best_s = smax; }
   if (flag) atomicOr(flags, flag);
   atomicMax(flags + 1, best_s);
+  atomicMax(flags + 2, best_q);
   ent_s[e] = best_s;
   ent_q[e] = best_q;
   ent_norm[e] = nx;
@@ -525,9 +527,12 @@ template <typename Shape>
 __global__ void __launch_bounds__(256, Shape::WAVES)
     k_expm_step(const JobDev* jobs, int njobs, long long total_items, char* ws, size_t off_T, const int* ent_s,
                 const int* ent_q, int mode, int step, int r, int seg_j0, int seg_len, int c0, int clen,
-                int skip_n) {
+                int skip_n, const int* flags) {
   typedef typename Shape::T T;
   __shared__ TileSmem<Shape> lds;
+  // a Horner or squaring step no entry needs (flags[2] is the largest q, flags[1] the
+  // largest s the generator picked so far) exits at once instead of walking every item
+  if ((mode == STEP_HORNER && step > flags[2] - 1) || (mode == STEP_SQUARE && step > flags[1])) return;
   const ItemRange rg = xcd_items(total_items);
   ItemCursor cur;
   // item -> tile product; false when this step has nothing to do for the item
@@ -2083,7 +2088,7 @@ static void upload_factorials() {
 // work.  Every shape accumulates each output element over k in the same order, so the
 // choice does not change any result bit.
 typedef void (*ExpmLaunch)(dim3, hipStream_t, const JobDev*, int, long long, char*, size_t, const int*,
-                           const int*, int, int, int, int, int, int, int, int);
+                           const int*, int, int, int, int, int, int, int, int, const int*);
 typedef void (*PanelLaunch)(dim3, hipStream_t, const JobDev*, const PanelDesc*, int, long long, char*, size_t, int,
                             int);
 typedef void (*ChainLaunch)(dim3, hipStream_t, const JobDev*, int, long long, char*, size_t, int, int, int);
@@ -2098,9 +2103,9 @@ struct GemmVariant {
 template <typename C>
 void launch_expm(dim3 g, hipStream_t st, const JobDev* j, int nj, long long items, char* ws, size_t offT,
                  const int* es, const int* eq, int mode, int step, int r, int j0, int len, int c0, int clen,
-                 int skip_n) {
+                 int skip_n, const int* flags) {
   hipLaunchKernelGGL(k_expm_step<C>, g, dim3(256), 0, st, j, nj, items, ws, offT, es, eq, mode, step, r, j0, len, c0,
-                     clen, skip_n);
+                     clen, skip_n, flags);
 }
 template <typename C>
 void launch_panel(dim3 g, hipStream_t st, const JobDev* j, const PanelDesc* d, int nd, long long items, char* ws,
@@ -2215,7 +2220,7 @@ struct Driver {
       auto step = [&](int mode, int s) {
         timed(PK_EXPM_GEMM, st, [&] {
           gemm_variant(P).expm(grid, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), mode, s,
-                               P->r, seg_j0, L, c0, clen, skip_n);
+                               P->r, seg_j0, L, c0, clen, skip_n, flags);
         });
       };
       for (int i = 2; i <= P->r; ++i) step(STEP_POWER, i);
