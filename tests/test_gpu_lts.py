@@ -15,7 +15,7 @@ def _u(seed, N, n):
     return np.random.default_rng(seed).uniform(-1.0, 1.0, (N, 2 * n))
 
 
-@pytest.mark.parametrize("n", [1, 3, 4, 6])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6])
 def test_lts_unitary_matches_the_oracle(lib, n):
     import torch
     print(f"lts K n={n}", flush=True)

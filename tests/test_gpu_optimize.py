@@ -106,3 +106,28 @@ def test_optimiser_argument_errors(lib):
     assert np.array_equal(r["u"].cpu().numpy(), u0)
     F0 = grape.fidelity_grad(b0, u0, DT, p0, pf)["F"]
     assert abs(r["F"] - F0) <= 1e-12
+
+
+def test_optimiser_on_a_segmented_plan_takes_the_same_steps(lib):
+    """A workspace budget that holds only part of the propagators makes the plan recompute
+    segments in the backward sweep; the optimiser's steps are unchanged (the recomputed
+    propagators are the same arithmetic)."""
+    import torch
+    print("optimiser segmented plan", flush=True)
+    h0, hk, b0, p0, pf, u0 = _problem(24)
+    P = _gpu_plan(lib, h0, hk, "c128", 3.0)
+    Pseg = None
+    for frac in (0.6, 0.45, 0.3, 0.2):
+        B = lib.Basis(N_QUBITS, "dihedral", 1)
+        S = lib.System(B, h0, hk)
+        cand = lib.Plan(S, "c128", N, DT, 3.0, max_workspace_bytes=int(P.workspace_bytes * frac), blocks=[0])
+        if cand.info["segments"] > 1:
+            Pseg = cand
+            break
+    assert Pseg is not None
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), device="cuda")
+    kw = dict(memory=5, step0=0.3, max_iter=10, f_target=1.0)
+    a = lib.optimize_lbfgs(P, dev(u0), dev(p0[0].ravel()), dev(pf[0].ravel()), **kw)
+    b = lib.optimize_lbfgs(Pseg, dev(u0), dev(p0[0].ravel()), dev(pf[0].ravel()), **kw)
+    assert a["evaluations"] == b["evaluations"] and np.array_equal(a["hist"], b["hist"])
+    assert torch.equal(a["u"], b["u"])
