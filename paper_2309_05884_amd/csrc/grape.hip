@@ -1617,8 +1617,8 @@ __device__ inline double2 small_hv(const T* H, size_t hplane, int mp, int m, int
 template <typename T>
 __global__ void __launch_bounds__(64) k_grad_small(const JobDev* jobs, int njobs, char* ws, size_t off_T,
                                                    size_t off_gacc, const double* u, const double* w, int R, int Q,
-                                                   int j0, int chunk) {
-  extern __shared__ double cbuf[];  // c_t^(r): [R][Q][64] complex (re, im)
+                                                   int j0, int chunk, int hstage) {
+  extern __shared__ double cbuf[];  // c_t^(r): [R][Q][64] complex (re, im), then the staged operators
   __shared__ T vr[kSmallGradRows], vi[kSmallGradRows];
   const int J = blockIdx.y;
   if (J >= njobs) return;
@@ -1631,6 +1631,12 @@ __global__ void __launch_bounds__(64) k_grad_small(const JobDev* jobs, int njobs
   const int row = threadIdx.x;
   const size_t hplane = (size_t)mp * mp;
   const T* H = static_cast<const T*>(jb.hT);
+  if (hstage) {  // the block's operator planes fit in LDS: every product reads them there
+    T* Hs = reinterpret_cast<T*>(cbuf + (size_t)R * Q * kSmallGradRows * 2);
+    for (size_t e = row; e < (size_t)(K + 1) * 2 * hplane; e += kSmallGradRows) Hs[e] = H[e];
+    H = Hs;
+    __syncthreads();
+  }
   const double* uj = u + jb.u_off + (size_t)(j0 + jj) * K;
   const T cdt = (T)(jb.dt / R);
   // H_j v for the vector in (vr, vi), this lane's row, in the working precision
@@ -2376,11 +2382,13 @@ struct Driver {
     const int npanel = (int)P->panels.size();
     const int C = P->chunk;
     if (P->small_grad && njobs <= 65535) {
-      const size_t lds = (size_t)R * Q * kSmallGradRows * 2 * sizeof(double);
+      const size_t hbytes = (size_t)(K + 1) * 2 * P->max_mp * P->max_mp * sizeof(T);
+      const int hstage = hbytes <= 32768 ? 1 : 0;
+      const size_t lds = (size_t)R * Q * kSmallGradRows * 2 * sizeof(double) + (hstage ? hbytes : 0);
       for (int j0 = 0; j0 < P->Nmax; j0 += C) {
         timed(PK_GRAD_VECTOR, st, [&] {
           hipLaunchKernelGGL(k_grad_small<T>, dim3((unsigned)P->max_cc, (unsigned)njobs), dim3(kSmallGradRows), lds, st,
-                             dj, njobs, ws, P->off_T, P->off_gacc, u, P->d_w.as<double>(), R, Q, j0, C);
+                             dj, njobs, ws, P->off_T, P->off_gacc, u, P->d_w.as<double>(), R, Q, j0, C, hstage);
         });
         timed(PK_GRAD_FINISH, st, [&] {
           hipLaunchKernelGGL(k_grad_finish, dim3((C * K + 255) / 256, P->P), dim3(256), 0, st, dj, dpr, ws,
@@ -2753,11 +2761,15 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_coop<double, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, clds));
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_coop<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, clds));
+    QOC_HIP(hipFuncSetAttribute((const void*)k_grad_small<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                96 * 1024));
   } else {
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_coop<float, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, clds));
     QOC_HIP(hipFuncSetAttribute((const void*)k_sweep_coop<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, clds));
+    QOC_HIP(hipFuncSetAttribute((const void*)k_grad_small<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                96 * 1024));
   }
   // second stream (default priority) for the backward sweep, and fork/join events
   QOC_HIP(hipStreamCreateWithFlags(&P->st2, hipStreamNonBlocking));
