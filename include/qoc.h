@@ -371,6 +371,17 @@ typedef struct qoc_lbfgs_result {
 } qoc_lbfgs_result;
 enum { QOC_OPT_TARGET = 0, QOC_OPT_GTOL = 1, QOC_OPT_MAX_ITER = 2, QOC_OPT_LINE_SEARCH_FAILED = 3 };
 qoc_status qoc_optimize_workspace_size(qoc_plan plan, int memory, size_t* bytes);
+/* The same L-BFGS iterations on the Trotterised per-qubit-control objective of
+ * qoc_lts_fidelity_grad (one problem: n, B_z, c_cpl, N, dt, u_dev [N][2n], psi0_dev /
+ * psif_dev of 2^n amplitudes as there).  There is no plan norm bound: a trial is
+ * rejected only when its evaluation is not finite.  workspace: at least
+ * qoc_optimize_lts_workspace_size(n, N, memory) bytes.  Options, history, result, errors
+ * and synchronisation as qoc_optimize_lbfgs. */
+qoc_status qoc_optimize_lts_workspace_size(int n, int N, int memory, size_t* bytes);
+qoc_status qoc_optimize_lbfgs_lts(int n, double Bz, double c_cpl, int N, double dt,
+                                  const qoc_lbfgs_options* options, double* u_dev, const void* psi0_dev,
+                                  const void* psif_dev, void* workspace, size_t workspace_bytes, void* stream,
+                                  double* hist_host, int hist_cap, qoc_lbfgs_result* result);
 qoc_status qoc_optimize_lbfgs(qoc_plan plan, const qoc_lbfgs_options* options, double* u_dev,
                               const void* psi0_dev, const void* psif_dev, void* workspace,
                               size_t workspace_bytes, void* stream, double* hist_host, int hist_cap,

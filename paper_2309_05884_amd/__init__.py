@@ -22,7 +22,7 @@ from ._capi import QocError
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "propagate", "GrapeFidelity",
            "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
            "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply",
-           "lts_fidelity_grad"]
+           "lts_fidelity_grad", "optimize_lbfgs_lts"]
 
 library_path = C.LIB_PATH
 
@@ -450,6 +450,32 @@ def optimize_lbfgs(plan: Plan, u, psi0, psif, max_iter=100, memory=10, step0=0.1
     C.check(L.qoc_optimize_lbfgs(plan._h, ctypes.byref(opts), _ptr(u), _ptr(psi0), _ptr(psif), _ptr(ws),
                                  ctypes.c_size_t(ws.numel()), _stream(), hist, int(max_iter) + 1,
                                  ctypes.byref(res)))
+    return {"u": u, "F": res.F, "hist": np.array(hist[:res.iterations + 1]), "iterations": res.iterations,
+            "evaluations": res.evaluations, "reason": C.OPT_REASONS[res.reason]}
+
+
+def optimize_lbfgs_lts(n: int, Bz: float, c_cpl: float, u, dt: float, psi0, psif, max_iter=100, memory=10,
+                       step0=0.1, c1=1e-4, max_backtrack=20, f_target=1.0, gtol=0.0):
+    """GRAPE through the Trotterised per-qubit-control propagator (qoc_optimize_lbfgs_lts):
+    L-BFGS ascent on F(u), u of shape (N, 2n).  Returns a dict as optimize_lbfgs."""
+    torch = _torch()
+    u = u.to(torch.float64).contiguous().clone()
+    N = u.shape[0]
+    assert u.shape == (N, 2 * n) and u.is_cuda
+    D = 1 << n
+    psi0 = psi0.to(torch.complex128).reshape(D).contiguous()
+    psif = psif.to(torch.complex128).reshape(D).contiguous()
+    L = C.lib()
+    nbytes = ctypes.c_size_t()
+    C.check(L.qoc_optimize_lts_workspace_size(int(n), int(N), int(memory), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=u.device)
+    opts = C.QocLbfgsOptions(int(max_iter), int(memory), float(step0), float(c1), int(max_backtrack),
+                             float(f_target), float(gtol))
+    hist = (ctypes.c_double * (int(max_iter) + 1))()
+    res = C.QocLbfgsResult()
+    C.check(L.qoc_optimize_lbfgs_lts(int(n), float(Bz), float(c_cpl), int(N), float(dt), ctypes.byref(opts), _ptr(u),
+                                     _ptr(psi0), _ptr(psif), _ptr(ws), ctypes.c_size_t(ws.numel()), _stream(), hist,
+                                     int(max_iter) + 1, ctypes.byref(res)))
     return {"u": u, "F": res.F, "hist": np.array(hist[:res.iterations + 1]), "iterations": res.iterations,
             "evaluations": res.evaluations, "reason": C.OPT_REASONS[res.reason]}
 

@@ -95,6 +95,12 @@ PROTOTYPES = {
                                              ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_gate_propagate": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_gate_fidelity": (ctypes.c_int, [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "qoc_optimize_lts_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                       ctypes.POINTER(ctypes.c_size_t)]),
+    "qoc_optimize_lbfgs_lts": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_double, ctypes.POINTER(QocLbfgsOptions), vp, vp, vp, vp,
+                                              ctypes.c_size_t, vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                              ctypes.POINTER(QocLbfgsResult)]),
     "qoc_optimize_workspace_size": (ctypes.c_int, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "qoc_optimize_lbfgs": (ctypes.c_int, [vp, ctypes.POINTER(QocLbfgsOptions), vp, vp, vp, vp, ctypes.c_size_t, vp,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int,

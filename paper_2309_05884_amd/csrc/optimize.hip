@@ -138,17 +138,14 @@ struct OptLayout {
   size_t o_ut, o_g, o_gt, o_d, o_S, o_Y, o_pst, o_scal, o_out;
 };
 
-OptLayout opt_layout(qoc_plan plan, int memory) {
+// the optimiser's vectors after `base` bytes that the objective uses
+OptLayout layout_after(size_t base, long long L, int memory) {
   OptLayout Lo;
-  int64_t info[17] = {};
-  if (qoc_plan_info(plan, info, 17) != QOC_OK) throw Failure{QOC_ERR_INVALID_ARG, "qoc_plan_info failed"};
-  QOC_REQUIRE(info[10] == 1, QOC_ERR_UNSUPPORTED, "the optimiser takes a one-problem plan");
-  if (qoc_plan_workspace_size(plan, &Lo.plan_bytes) != QOC_OK)
-    throw Failure{QOC_ERR_INVALID_ARG, "qoc_plan_workspace_size failed"};
-  Lo.L = info[12];
+  Lo.plan_bytes = base;
+  Lo.L = L;
   Lo.slots = memory + 1;
   const size_t vec = align256((size_t)Lo.L * sizeof(double));
-  size_t o = align256(Lo.plan_bytes);
+  size_t o = align256(base);
   Lo.off = o;
   Lo.o_ut = o; o += vec;
   Lo.o_g = o; o += vec;
@@ -161,6 +158,22 @@ OptLayout opt_layout(qoc_plan plan, int memory) {
   Lo.o_out = o; o += 256;  // objective words of the current point [0..7] and of the trial [8..15]
   Lo.total = o;
   return Lo;
+}
+
+OptLayout opt_layout(qoc_plan plan, int memory) {
+  int64_t info[17] = {};
+  if (qoc_plan_info(plan, info, 17) != QOC_OK) throw Failure{QOC_ERR_INVALID_ARG, "qoc_plan_info failed"};
+  QOC_REQUIRE(info[10] == 1, QOC_ERR_UNSUPPORTED, "the optimiser takes a one-problem plan");
+  size_t pb = 0;
+  if (qoc_plan_workspace_size(plan, &pb) != QOC_OK) throw Failure{QOC_ERR_INVALID_ARG, "qoc_plan_workspace_size failed"};
+  return layout_after(pb, info[12], memory);
+}
+
+OptLayout lts_opt_layout(int n, int N, int memory) {
+  size_t lb = 0;
+  const qoc_status s = qoc_lts_grad_workspace_size(n, N, 1, &lb);
+  if (s != QOC_OK) throw Failure{s, std::string("qoc_lts_grad_workspace_size: ") + qoc_last_error()};
+  return layout_after(lb, (long long)N * 2 * n, memory);
 }
 
 void check_options(const qoc_lbfgs_options* opt) {
@@ -186,6 +199,114 @@ qoc_status qoc_optimize_workspace_size(qoc_plan plan, int memory, size_t* bytes)
   });
 }
 
+// The L-BFGS iterations of the header, on the controls u_dev (L doubles), with the
+// objective and gradient from objective(u, out_dev[8], grad_dev[L]) (asynchronous on
+// `stream`); the optimiser's vectors live in `workspace` at the offsets of Lo.
+template <class Objective>
+void run_lbfgs(const qoc_lbfgs_options* opt, double* u_dev, void* workspace, const OptLayout& Lo, void* stream,
+               double* hist_host, int hist_cap, qoc_lbfgs_result* result, Objective&& objective) {
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = static_cast<char*>(workspace);
+  double* ut = reinterpret_cast<double*>(ws + Lo.o_ut);
+  double* g = reinterpret_cast<double*>(ws + Lo.o_g);
+  double* gt = reinterpret_cast<double*>(ws + Lo.o_gt);
+  double* d = reinterpret_cast<double*>(ws + Lo.o_d);
+  double* S = reinterpret_cast<double*>(ws + Lo.o_S);
+  double* Y = reinterpret_cast<double*>(ws + Lo.o_Y);
+  double* pst = reinterpret_cast<double*>(ws + Lo.o_pst);
+  double* scal = reinterpret_cast<double*>(ws + Lo.o_scal);
+  double* out = reinterpret_cast<double*>(ws + Lo.o_out);
+  const long long L = Lo.L;
+  const int tgrid = (int)std::min<long long>((L + 255) / 256, 1024);
+
+  // objective words of one evaluation, copied to the host
+  auto evaluate = [&](const double* u, double* o_dev, double* grad, double* o_host) {
+    objective(u, o_dev, grad);
+    QOC_HIP(hipMemcpyAsync(o_host, o_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    QOC_HIP(hipStreamSynchronize(st));
+    const int flags = (int)o_host[7];
+    QOC_REQUIRE(!(flags & 4), QOC_ERR_NUMERIC, "a co-operative sweep stalled during the optimisation");
+    return flags == 0 && std::isfinite(o_host[0]);
+  };
+  auto fetch_scal = [&](double* h, int n) {
+    QOC_HIP(hipMemcpyAsync(h, scal, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    QOC_HIP(hipStreamSynchronize(st));
+  };
+
+  double cur[8], trial[8], sc[4];
+  QOC_REQUIRE(evaluate(u_dev, out, g, cur), QOC_ERR_NUMERIC,
+              "the starting controls give a flagged evaluation (outside the plan's norm bound or non-finite)");
+  double F = cur[0];
+  int nh = 0, evals = 1, iters = 0, reason = QOC_OPT_MAX_ITER;
+  if (nh < hist_cap) hist_host[nh++] = F;
+  int count = 0, newest = 0;
+  bool stopped = false;
+  for (int it = 0; it < opt->max_iter; ++it) {
+    if (F >= opt->f_target) {
+      reason = QOC_OPT_TARGET;
+      stopped = true;
+      break;
+    }
+    hipLaunchKernelGGL(k_opt_direction, dim3(1), dim3(kOptThreads), 0, st, g, S, Y, pst, L, Lo.slots, count,
+                       newest, opt->step0, d, scal);
+    QOC_HIP(hipGetLastError());
+    fetch_scal(sc, 2);
+    if (sc[1] <= opt->gtol) {
+      reason = QOC_OPT_GTOL;
+      stopped = true;
+      break;
+    }
+    if (!(sc[0] > 0.0) && count > 0) {  // not an ascent direction: clear the memory
+      count = 0;
+      hipLaunchKernelGGL(k_opt_direction, dim3(1), dim3(kOptThreads), 0, st, g, S, Y, pst, L, Lo.slots, 0,
+                         newest, opt->step0, d, scal);
+      QOC_HIP(hipGetLastError());
+      fetch_scal(sc, 2);
+    }
+    const double gd = sc[0];
+    double alpha = 1.0;
+    bool accepted = false;
+    for (int b = 0; b <= opt->max_backtrack; ++b) {
+      hipLaunchKernelGGL(k_opt_trial, dim3(tgrid), dim3(256), 0, st, u_dev, d, alpha, L, ut);
+      QOC_HIP(hipGetLastError());
+      const bool ok = evaluate(ut, out + 8, gt, trial);
+      ++evals;
+      if (ok && trial[0] >= F + opt->c1 * alpha * gd) {
+        accepted = true;
+        break;
+      }
+      alpha *= 0.5;
+    }
+    if (!accepted) {
+      reason = QOC_OPT_LINE_SEARCH_FAILED;
+      stopped = true;
+      break;
+    }
+    const int slot = count == 0 ? 0 : (newest + 1) % Lo.slots;
+    hipLaunchKernelGGL(k_opt_accept, dim3(1), dim3(kOptThreads), 0, st, u_dev, g, ut, gt, L, S, Y, pst, slot);
+    QOC_HIP(hipGetLastError());
+    double ps[3];
+    QOC_HIP(hipMemcpyAsync(ps, pst + 3 * slot, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    QOC_HIP(hipStreamSynchronize(st));
+    if (ps[0] > kCurvatureEps * std::sqrt(ps[2] * ps[1])) {
+      newest = slot;
+      count = std::min(count + 1, opt->memory);
+    }
+    F = trial[0];
+    ++iters;
+    if (nh < hist_cap) hist_host[nh++] = F;
+  }
+  if (!stopped && F >= opt->f_target) reason = QOC_OPT_TARGET;
+  result->iterations = iters;
+  result->evaluations = evals;
+  result->reason = reason;
+  result->F = F;
+  result->iterations = iters;
+  result->evaluations = evals;
+  result->reason = reason;
+  result->F = F;
+}
+
 qoc_status qoc_optimize_lbfgs(qoc_plan plan, const qoc_lbfgs_options* opt, double* u_dev, const void* psi0_dev,
                               const void* psif_dev, void* workspace, size_t ws_bytes, void* stream,
                               double* hist_host, int hist_cap, qoc_lbfgs_result* result) {
@@ -196,102 +317,38 @@ qoc_status qoc_optimize_lbfgs(qoc_plan plan, const qoc_lbfgs_options* opt, doubl
     QOC_REQUIRE(hist_cap >= 0 && (hist_cap == 0 || hist_host), QOC_ERR_INVALID_ARG, "bad history buffer");
     const OptLayout Lo = opt_layout(plan, opt->memory);
     QOC_REQUIRE(ws_bytes >= Lo.total, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than qoc_optimize_workspace_size");
-    hipStream_t st = (hipStream_t)stream;
-    char* ws = static_cast<char*>(workspace);
-    double* ut = reinterpret_cast<double*>(ws + Lo.o_ut);
-    double* g = reinterpret_cast<double*>(ws + Lo.o_g);
-    double* gt = reinterpret_cast<double*>(ws + Lo.o_gt);
-    double* d = reinterpret_cast<double*>(ws + Lo.o_d);
-    double* S = reinterpret_cast<double*>(ws + Lo.o_S);
-    double* Y = reinterpret_cast<double*>(ws + Lo.o_Y);
-    double* pst = reinterpret_cast<double*>(ws + Lo.o_pst);
-    double* scal = reinterpret_cast<double*>(ws + Lo.o_scal);
-    double* out = reinterpret_cast<double*>(ws + Lo.o_out);
-    const long long L = Lo.L;
-    const int tgrid = (int)std::min<long long>((L + 255) / 256, 1024);
+    run_lbfgs(opt, u_dev, workspace, Lo, stream, hist_host, hist_cap, result,
+              [&](const double* u, double* o_dev, double* grad) {
+                const qoc_status s = qoc_fidelity_grad(plan, u, psi0_dev, psif_dev, o_dev, grad, workspace,
+                                                       Lo.plan_bytes, stream);
+                if (s != QOC_OK) throw Failure{s, std::string("qoc_fidelity_grad: ") + qoc_last_error()};
+              });
+  });
+}
 
-    // objective words of one evaluation, copied to the host
-    auto evaluate = [&](const double* u, double* o_dev, double* grad, double* o_host) {
-      const qoc_status s = qoc_fidelity_grad(plan, u, psi0_dev, psif_dev, o_dev, grad, workspace, Lo.plan_bytes, stream);
-      if (s != QOC_OK) throw Failure{s, std::string("qoc_fidelity_grad: ") + qoc_last_error()};
-      QOC_HIP(hipMemcpyAsync(o_host, o_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-      QOC_HIP(hipStreamSynchronize(st));
-      const int flags = (int)o_host[7];
-      QOC_REQUIRE(!(flags & 4), QOC_ERR_NUMERIC, "a co-operative sweep stalled during the optimisation");
-      return flags == 0 && std::isfinite(o_host[0]);
-    };
-    auto fetch_scal = [&](double* h, int n) {
-      QOC_HIP(hipMemcpyAsync(h, scal, n * sizeof(double), hipMemcpyDeviceToHost, st));
-      QOC_HIP(hipStreamSynchronize(st));
-    };
+qoc_status qoc_optimize_lts_workspace_size(int n, int N, int memory, size_t* bytes) {
+  return guarded([&] {
+    QOC_REQUIRE(bytes, QOC_ERR_INVALID_ARG, "null argument");
+    QOC_REQUIRE(memory >= 1 && memory <= 64, QOC_ERR_INVALID_ARG, "memory must be in 1..64");
+    *bytes = lts_opt_layout(n, N, memory).total;
+  });
+}
 
-    double cur[8], trial[8], sc[4];
-    QOC_REQUIRE(evaluate(u_dev, out, g, cur), QOC_ERR_NUMERIC,
-                "the starting controls are outside the plan's norm bound or give a non-finite objective");
-    double F = cur[0];
-    int nh = 0, evals = 1, iters = 0, reason = QOC_OPT_MAX_ITER;
-    if (nh < hist_cap) hist_host[nh++] = F;
-    int count = 0, newest = 0;
-    bool stopped = false;
-    for (int it = 0; it < opt->max_iter; ++it) {
-      if (F >= opt->f_target) {
-        reason = QOC_OPT_TARGET;
-        stopped = true;
-        break;
-      }
-      hipLaunchKernelGGL(k_opt_direction, dim3(1), dim3(kOptThreads), 0, st, g, S, Y, pst, L, Lo.slots, count,
-                         newest, opt->step0, d, scal);
-      QOC_HIP(hipGetLastError());
-      fetch_scal(sc, 2);
-      if (sc[1] <= opt->gtol) {
-        reason = QOC_OPT_GTOL;
-        stopped = true;
-        break;
-      }
-      if (!(sc[0] > 0.0) && count > 0) {  // not an ascent direction: clear the memory
-        count = 0;
-        hipLaunchKernelGGL(k_opt_direction, dim3(1), dim3(kOptThreads), 0, st, g, S, Y, pst, L, Lo.slots, 0,
-                           newest, opt->step0, d, scal);
-        QOC_HIP(hipGetLastError());
-        fetch_scal(sc, 2);
-      }
-      const double gd = sc[0];
-      double alpha = 1.0;
-      bool accepted = false;
-      for (int b = 0; b <= opt->max_backtrack; ++b) {
-        hipLaunchKernelGGL(k_opt_trial, dim3(tgrid), dim3(256), 0, st, u_dev, d, alpha, L, ut);
-        QOC_HIP(hipGetLastError());
-        const bool ok = evaluate(ut, out + 8, gt, trial);
-        ++evals;
-        if (ok && trial[0] >= F + opt->c1 * alpha * gd) {
-          accepted = true;
-          break;
-        }
-        alpha *= 0.5;
-      }
-      if (!accepted) {
-        reason = QOC_OPT_LINE_SEARCH_FAILED;
-        stopped = true;
-        break;
-      }
-      const int slot = count == 0 ? 0 : (newest + 1) % Lo.slots;
-      hipLaunchKernelGGL(k_opt_accept, dim3(1), dim3(kOptThreads), 0, st, u_dev, g, ut, gt, L, S, Y, pst, slot);
-      QOC_HIP(hipGetLastError());
-      double ps[3];
-      QOC_HIP(hipMemcpyAsync(ps, pst + 3 * slot, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-      QOC_HIP(hipStreamSynchronize(st));
-      if (ps[0] > kCurvatureEps * std::sqrt(ps[2] * ps[1])) {
-        newest = slot;
-        count = std::min(count + 1, opt->memory);
-      }
-      F = trial[0];
-      ++iters;
-      if (nh < hist_cap) hist_host[nh++] = F;
-    }
-    if (!stopped && F >= opt->f_target) reason = QOC_OPT_TARGET;
-    result->iterations = iters;
-    result->evaluations = evals;
-    result->reason = reason;
-    result->F = F;
+qoc_status qoc_optimize_lbfgs_lts(int n, double Bz, double c_cpl, int N, double dt, const qoc_lbfgs_options* opt,
+                                  double* u_dev, const void* psi0_dev, const void* psif_dev, void* workspace,
+                                  size_t ws_bytes, void* stream, double* hist_host, int hist_cap,
+                                  qoc_lbfgs_result* result) {
+  return guarded([&] {
+    QOC_REQUIRE(opt && u_dev && psi0_dev && psif_dev && workspace && result, QOC_ERR_INVALID_ARG, "null argument");
+    check_options(opt);
+    QOC_REQUIRE(hist_cap >= 0 && (hist_cap == 0 || hist_host), QOC_ERR_INVALID_ARG, "bad history buffer");
+    const OptLayout Lo = lts_opt_layout(n, N, opt->memory);
+    QOC_REQUIRE(ws_bytes >= Lo.total, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than qoc_optimize_lts_workspace_size");
+    run_lbfgs(opt, u_dev, workspace, Lo, stream, hist_host, hist_cap, result,
+              [&](const double* u, double* o_dev, double* grad) {
+                const qoc_status s = qoc_lts_fidelity_grad(n, Bz, c_cpl, u, N, dt, 1, psi0_dev, psif_dev, o_dev, grad,
+                                                           workspace, Lo.plan_bytes, stream);
+                if (s != QOC_OK) throw Failure{s, std::string("qoc_lts_fidelity_grad: ") + qoc_last_error()};
+              });
   });
 }

@@ -131,3 +131,34 @@ def test_optimiser_on_a_segmented_plan_takes_the_same_steps(lib):
     b = lib.optimize_lbfgs(Pseg, dev(u0), dev(p0[0].ravel()), dev(pf[0].ravel()), **kw)
     assert a["evaluations"] == b["evaluations"] and np.array_equal(a["hist"], b["hist"])
     assert torch.equal(a["u"], b["u"])
+
+
+def test_trotterised_optimiser_follows_the_oracle(lib):
+    """GRAPE with per-qubit controls through the Trotterised propagator
+    (qoc_optimize_lbfgs_lts) takes the oracle's L-BFGS steps on the oracle's Trotterised
+    objective and gradient (oracle/lts.py)."""
+    import torch
+    from oracle import lts
+    print("optimiser, Trotterised per-qubit controls", flush=True)
+    n, Nn, dt, Bz, c = 4, 20, 0.1, 1.0, 1.0
+    rng = np.random.default_rng(25)
+    u0 = rng.uniform(-0.3, 0.3, (Nn, 2 * n))
+    p0 = np.zeros(2 ** n, complex)
+    p0[0] = 1.0
+    pf = np.zeros(2 ** n, complex)
+    pf[-1] = 1.0
+
+    def fun(uf):
+        r = lts.fidelity_grad(n, Bz, c, uf.reshape(Nn, 2 * n), dt, p0, pf)
+        return r["F"], r["grad"].reshape(-1), bool(np.isfinite(r["F"]))
+
+    kw = dict(memory=6, step0=0.5, c1=1e-4, max_backtrack=12, max_iter=15, f_target=1.0, gtol=0.0)
+    ref = opt.lbfgs_ascent(fun, u0.reshape(-1), **kw)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), device="cuda")
+    got = lib.optimize_lbfgs_lts(n, Bz, c, dev(u0), dt, dev(p0), dev(pf), **kw)
+    print(f"  oracle F {ref['F']:.12f} ({ref['evals']} evals); library F {got['F']:.12f} "
+          f"({got['evaluations']} evals)", flush=True)
+    assert ref["hist"][-1] > 10 * ref["hist"][0]
+    assert got["evaluations"] == ref["evals"] and got["reason"] == REASON[ref["reason"]]
+    assert np.abs(got["hist"] - ref["hist"]).max() <= 1e-10
+    assert np.abs(got["u"].cpu().numpy().reshape(-1) - ref["u"]).max() <= 1e-8 * max(1.0, np.abs(ref["u"]).max())
