@@ -170,6 +170,73 @@ __device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
+// The backward step over Q consecutive qubit bits low .. low + Q - 1, taken from the highest
+// bit down (the reverse of the forward order): per bit, the gate is undone on psi, the
+// derivative products <lambda| dg/dB_a |psi> are accumulated into d[bit - low], the adjoint
+// gate is applied to lambda, then the coupling phase is undone on both; each thread holds
+// the 2^Q amplitudes of psi and lambda that differ in those bits.
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+template <int Q>
+__device__ inline void lts_back_pass(double2* ps, double2* lm, int n, int low, const double2* Fj,
+                                     const LtsPhases& ph, double (&d)[3][4]) {
+  constexpr int M = 1 << Q;
+  const int D = 1 << n;
+  const unsigned mask = (unsigned)D - 1u;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[k][q] = 0.0;
+  for (int t = threadIdx.x; t < (D >> Q); t += blockDim.x) {
+    const unsigned lo = (unsigned)t & ((1u << low) - 1u);
+    const unsigned base = (((unsigned)t >> low) << (low + Q)) | lo;
+    double2 v[M], l[M], e[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const unsigned a = base | ((unsigned)m << low);
+      const unsigned ra = ((a << 1) | (a >> (n - 1))) & mask;
+      v[m] = ps[a];
+      l[m] = lm[a];
+      e[m] = ph.v[__popc(a ^ ra)];
+    }
+#pragma unroll
+    for (int k = Q - 1; k >= 0; --k) {
+      const double2* f = Fj + 12 * (n - (low + k) - 1);  // qubit n - (low + k)
+      const double2 g00 = f[0], g01 = f[1], g10 = f[2], g11 = f[3];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if (m & (1 << k)) continue;
+        const int m1 = m | (1 << k);
+        const double2 p0 = v[m], p1 = v[m1], l0 = l[m], l1 = l[m1];
+        const double2 q0 = cadd(cconjmul(g00, p0), cconjmul(g10, p1));
+        const double2 q1 = cadd(cconjmul(g01, p0), cconjmul(g11, p1));
+        const double2 ax0 = cadd(cmul(f[4], q0), cmul(f[5], q1)), ax1 = cadd(cmul(f[6], q0), cmul(f[7], q1));
+        const double2 ay0 = cadd(cmul(f[8], q0), cmul(f[9], q1)), ay1 = cadd(cmul(f[10], q0), cmul(f[11], q1));
+        const double2 cx = cadd(cconjmul(l0, ax0), cconjmul(l1, ax1)), cy = cadd(cconjmul(l0, ay0), cconjmul(l1, ay1));
+        d[k][0] += cx.x;
+        d[k][1] += cx.y;
+        d[k][2] += cy.x;
+        d[k][3] += cy.y;
+        v[m] = q0;
+        v[m1] = q1;
+        l[m] = cadd(cconjmul(g00, l0), cconjmul(g10, l1));
+        l[m1] = cadd(cconjmul(g01, l0), cconjmul(g11, l1));
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        v[m] = cconjmul(e[m], v[m]);
+        l[m] = cconjmul(e[m], l[m]);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const unsigned a = base | ((unsigned)m << low);
+      ps[a] = v[m];
+      lm[a] = l[m];
+    }
+  }
+}
+
 // One work-group per problem, state and costate in LDS (n <= 12).  Forward: the pulse on
 // psi_0.  Then o, the norms, and backward, factor by factor in reverse: the gate is undone
 // on psi (giving the state just before it) and applied adjoint to lambda (the costate
@@ -177,15 +244,14 @@ __device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) b
 // <lambda_after| dg/dB_a |psi_before> for a = x, y; the coupling phase is then undone on
 // both.  The wave partials of a factor go to one of two LDS slots by parity, so one barrier
 // per factor suffices; wave 0 adds them up after that barrier.
-__global__ void __launch_bounds__(1024) k_lts_grad(int n, const double2* fac, LtsPhases ph, int N,
+__global__ void __launch_bounds__(512) k_lts_grad(int n, const double2* fac, LtsPhases ph, int N,
                                                    const double2* psi0, const double2* psif, double* out,
                                                    double* grad) {
   extern __shared__ double2 sm[];
-  __shared__ double part[2][16][4];
+  __shared__ double part[2][16][12];
   __shared__ double ored[16][4];
   __shared__ double osum[4];
-  const int D = 1 << n, half = D >> 1;
-  const unsigned mask = (unsigned)D - 1u;
+  const int D = 1 << n;
   const int p = blockIdx.x;
   double2* ps = sm;
   double2* lm = sm + D;
@@ -237,56 +303,37 @@ __global__ void __launch_bounds__(1024) k_lts_grad(int n, const double2* fac, Lt
   double* G = grad + (size_t)p * N * 2 * n;
   int step = 0;
   for (int j = N - 1; j >= 0; --j)
-    for (int i = 1; i <= n; ++i, ++step) {
-      const int b = n - i;
-      const double2* f = F + 12 * ((size_t)j * n + (i - 1));
-      const double2 g00 = f[0], g01 = f[1], g10 = f[2], g11 = f[3];
-      const double2 x00 = f[4], x01 = f[5], x10 = f[6], x11 = f[7];
-      const double2 y00 = f[8], y01 = f[9], y10 = f[10], y11 = f[11];
-      double dxr = 0.0, dxi = 0.0, dyr = 0.0, dyi = 0.0;
-      for (int t = threadIdx.x; t < half; t += blockDim.x) {
-        const unsigned lo = (unsigned)t & ((1u << b) - 1u);
-        const unsigned a0 = (((unsigned)t >> b) << (b + 1)) | lo, a1 = a0 | (1u << b);
-        const double2 p0 = ps[a0], p1 = ps[a1], l0 = lm[a0], l1 = lm[a1];
-        // psi before the gate: g^dag psi
-        const double2 q0 = make_double2(cconjmul(g00, p0).x + cconjmul(g10, p1).x, cconjmul(g00, p0).y + cconjmul(g10, p1).y);
-        const double2 q1 = make_double2(cconjmul(g01, p0).x + cconjmul(g11, p1).x, cconjmul(g01, p0).y + cconjmul(g11, p1).y);
-        // <lambda_after| dg |psi_before>
-        const double2 ax0 = make_double2(cmul(x00, q0).x + cmul(x01, q1).x, cmul(x00, q0).y + cmul(x01, q1).y);
-        const double2 ax1 = make_double2(cmul(x10, q0).x + cmul(x11, q1).x, cmul(x10, q0).y + cmul(x11, q1).y);
-        const double2 ay0 = make_double2(cmul(y00, q0).x + cmul(y01, q1).x, cmul(y00, q0).y + cmul(y01, q1).y);
-        const double2 ay1 = make_double2(cmul(y10, q0).x + cmul(y11, q1).x, cmul(y10, q0).y + cmul(y11, q1).y);
-        const double2 cx0 = cconjmul(l0, ax0), cx1 = cconjmul(l1, ax1), cy0 = cconjmul(l0, ay0), cy1 = cconjmul(l1, ay1);
-        dxr += cx0.x + cx1.x;
-        dxi += cx0.y + cx1.y;
-        dyr += cy0.x + cy1.x;
-        dyi += cy0.y + cy1.y;
-        // lambda before the gate: g^dag lambda
-        const double2 k0 = make_double2(cconjmul(g00, l0).x + cconjmul(g10, l1).x, cconjmul(g00, l0).y + cconjmul(g10, l1).y);
-        const double2 k1 = make_double2(cconjmul(g01, l0).x + cconjmul(g11, l1).x, cconjmul(g01, l0).y + cconjmul(g11, l1).y);
-        // undo the coupling phase on both
-        const unsigned r0 = ((a0 << 1) | (a0 >> (n - 1))) & mask, r1 = ((a1 << 1) | (a1 >> (n - 1))) & mask;
-        const double2 e0 = ph.v[__popc(a0 ^ r0)], e1 = ph.v[__popc(a1 ^ r1)];
-        ps[a0] = cconjmul(e0, q0);
-        ps[a1] = cconjmul(e1, q1);
-        lm[a0] = cconjmul(e0, k0);
-        lm[a1] = cconjmul(e1, k1);
-      }
-      double vals[4] = {dxr, dxi, dyr, dyi};
-      for (int q = 0; q < 4; ++q) {
-        double v = vals[q];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) part[step & 1][wave][q] = v;
+    for (int top = n - 1; top >= 0;) {  // bits top, top - 1, ... (qubits 1, 2, ...), two per pass
+      const int Q = top >= 1 ? 2 : 1;
+      const int low = top - Q + 1;
+      double d[3][4];
+      if (Q == 2)
+        lts_back_pass<2>(ps, lm, n, low, F + 12 * (size_t)j * n, ph, d);
+      else
+        lts_back_pass<1>(ps, lm, n, low, F + 12 * (size_t)j * n, ph, d);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        if (k >= Q) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double v = d[k][q];
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+          if (lane == 0) part[step & 1][wave][4 * k + q] = v;
+        }
       }
       __syncthreads();
-      if (threadIdx.x == 0) {
-        double s4[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int w = 0; w < nw; ++w)
-          for (int q = 0; q < 4; ++q) s4[q] += part[step & 1][w][q];
-        // 2 Re(conj(o) d) / norms
-        G[(size_t)j * 2 * n + 2 * (i - 1)] = scale * (o_r * s4[0] + o_i * s4[1]);
-        G[(size_t)j * 2 * n + 2 * (i - 1) + 1] = scale * (o_r * s4[2] + o_i * s4[3]);
-      }
+      if (threadIdx.x == 0)
+        for (int k = 0; k < Q; ++k) {
+          double s4[4] = {0.0, 0.0, 0.0, 0.0};
+          for (int w = 0; w < nw; ++w)
+            for (int q = 0; q < 4; ++q) s4[q] += part[step & 1][w][4 * k + q];
+          const int i = n - (low + k);  // qubit of bit low + k
+          // 2 Re(conj(o) d) / norms
+          G[(size_t)j * 2 * n + 2 * (i - 1)] = scale * (o_r * s4[0] + o_i * s4[1]);
+          G[(size_t)j * 2 * n + 2 * (i - 1) + 1] = scale * (o_r * s4[2] + o_i * s4[3]);
+        }
+      ++step;
+      top -= Q;
     }
 }
 
@@ -376,7 +423,7 @@ qoc_status qoc_lts_fidelity_grad(int n, double Bz, double c_cpl, const double* u
     const int D = 1 << n;
     const int lds = 2 * D * (int)sizeof(double2);
     QOC_HIP(hipFuncSetAttribute((const void*)k_lts_grad, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    const int threads = std::min(1024, std::max(64, (D / 2 + 63) / 64 * 64));
+    const int threads = std::min(512, std::max(64, (D / 4 + 63) / 64 * 64));
     hipLaunchKernelGGL(k_lts_grad, dim3((unsigned)P), dim3(threads), lds, st, n, g, ph, N,
                        static_cast<const double2*>(psi0_dev), static_cast<const double2*>(psif_dev), out_dev,
                        grad_dev);
