@@ -238,12 +238,13 @@ __device__ inline void lts_back_pass(double2* ps, double2* lm, int n, int low, c
 }
 
 // One work-group per problem, state and costate in LDS (n <= 12).  Forward: the pulse on
-// psi_0.  Then o, the norms, and backward, factor by factor in reverse: the gate is undone
-// on psi (giving the state just before it) and applied adjoint to lambda (the costate
-// just after it becomes the one just before it) while the pass accumulates
-// <lambda_after| dg/dB_a |psi_before> for a = x, y; the coupling phase is then undone on
-// both.  The wave partials of a factor go to one of two LDS slots by parity, so one barrier
-// per factor suffices; wave 0 adds them up after that barrier.
+// psi_0 (three qubits per pass).  Then o, the norms, and backward, factor by factor in
+// reverse, two qubits per pass (lts_back_pass): the gate is undone on psi (giving the
+// state just before it) and applied adjoint to lambda (the costate just after it becomes
+// the one just before it) while the pass accumulates <lambda_after| dg/dB_a |psi_before>
+// for a = x, y; the coupling phase is then undone on both.  The wave partials of a pass go
+// to one of two LDS slots by parity, so one barrier per pass suffices; thread 0 adds them
+// up after that barrier.
 __global__ void __launch_bounds__(512) k_lts_grad(int n, const double2* fac, LtsPhases ph, int N,
                                                    const double2* psi0, const double2* psif, double* out,
                                                    double* grad) {
