@@ -1072,7 +1072,9 @@ template <> struct XchgVal<double> {
 // A job whose rows fit one work-group (W = 1) needs no exchange: the new state goes straight
 // back into LDS, and the next slice's propagator entries (one column segment per lane, as
 // every column index k < m <= RB lands in the first column block of a wave) are loaded while
-// the current slice is applied, so the per-slice cost is two work-group barriers.
+// the current slice is applied, so the per-slice cost is two work-group barriers.  When every
+// job of a plan fits one group, the sweep is launched with only the waves the widest block
+// needs (4 columns per wave), so the barriers span fewer waves.
 template <typename T, int DIR>
 __device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j0, int len, char* smem_raw) {
   typedef typename Vec16<T>::type TV;
@@ -1086,9 +1088,9 @@ __device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j
   const size_t ncol = DIR == 0 ? (size_t)(N + 1) * d : (size_t)N * d;
   const size_t ps = (size_t)mp * ncol;
   const size_t plane = (size_t)mp * mp;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int rv = lane & 15, kk = lane >> 4;
-  const int row = rv * RPL, k = 4 * wave + kk;  // rows row .. row + RPL - 1 of column k
+  const int row = rv * RPL, k = 4 * wave + kk;  // rows row .. row + RPL - 1 of column k (4 nw >= m)
   const bool act = row < m && k < m;
   {
     const int col_in = DIR == 0 ? seg_j0 : seg_j0 + len - 1;
@@ -1154,7 +1156,7 @@ __device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j
     if ((int)threadIdx.x < RB * d) {
       const int c = threadIdx.x / RB, i = threadIdx.x % RB;
       T vr = T(0), vi = T(0);
-      for (int w = 0; w < 16; ++w) {
+      for (int w = 0; w < nw; ++w) {
         vr += pre[((size_t)w * d + c) * RB + i];
         vi += pim[((size_t)w * d + c) * RB + i];
       }
@@ -2246,16 +2248,18 @@ struct Driver {
       int* ctl = reinterpret_cast<int*>(ws + P->off_sync) + (size_t)dir * 4 * njobs;
       int* flags = reinterpret_cast<int*>(ws + P->off_flags);
       const dim3 grid(P->coop_w, njobs);
+      // one group per job: 4 columns per wave, at least the 128 threads of the reduction
+      const int threads = P->coop_w == 1 ? std::min(1024, std::max(256, 16 * P->max_mp)) : 1024;
       timed(dir == 0 ? PK_SWEEP_FWD : PK_SWEEP_BWD, st, [&] {
         unsigned long long* xg = reinterpret_cast<unsigned long long*>(ws + P->off_xchg) + (size_t)dir * P->xchg_words;
         const int nz = (int)(2 * P->xchg_words);
         hipLaunchKernelGGL(k_zero_ints, dim3((4 * njobs + 255) / 256), dim3(256), 0, st, ctl, 4 * njobs);
         hipLaunchKernelGGL(k_zero_ints, dim3((nz + 255) / 256), dim3(256), 0, st, reinterpret_cast<int*>(xg), nz);
         if (dir == 0)
-          hipLaunchKernelGGL((k_sweep_coop<T, 0>), grid, dim3(1024), P->coop_lds, st, dj, njobs, ws, P->off_T,
+          hipLaunchKernelGGL((k_sweep_coop<T, 0>), grid, dim3(threads), P->coop_lds, st, dj, njobs, ws, P->off_T,
                              ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags, xg);
         else
-          hipLaunchKernelGGL((k_sweep_coop<T, 1>), grid, dim3(1024), P->coop_lds, st, dj, njobs, ws, P->off_T,
+          hipLaunchKernelGGL((k_sweep_coop<T, 1>), grid, dim3(threads), P->coop_lds, st, dj, njobs, ws, P->off_T,
                              ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags, xg);
       });
       return;
