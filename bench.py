@@ -39,9 +39,9 @@ MFMA_PEAK = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix TFLOP/s, MI
 # calibration copy (FETCH_SIZE reads half of the bytes copied: x2.0; WRITE_SIZE all of
 # them: x1.0).  Valid only for the kernel sources they were taken with (sha1 of
 # mfma_tile.h + grape.hip).
-TRAFFIC = {"sources_sha1": "1b5e2024a84695b99c1b4b7358be346fe99f5b34", "fetch_scale": 2.0, "write_scale": 1.0,
-           "kib": {"fp32 128x64": (11795144.8, 6443670.1), "fp32 64x64": (14336184.7, 6458852.7),
-                   "fp32 64x128": (12730628.0, 6044866.5)}}
+TRAFFIC = {"sources_sha1": "4a811cb297e287d05a6934d579339bf3be25d755", "fetch_scale": 2.0, "write_scale": 1.0,
+           "kib": {"fp32 128x64": (11787138.4, 6446834.2), "fp32 64x64": (14336225.4, 6460062.7),
+                   "fp32 64x128": (12721752.3, 6045069.4)}}
 
 
 def kernel_sources_sha1():
