@@ -195,7 +195,8 @@ qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
  * bytes per slice, [7] largest squaring count, [8] gradient chunk (slices), [9] GEMM
  * grid, [10] problems P, [11] (problem, block) jobs, [12] total controls (sum N_p K_p),
  * [13] total panel length (sum D_p), [14] total propagator entries, [15] GEMM tile
- * variant in use, [16] slices per Taylor-scratch chunk.
+ * variant in use, [16] slices per Taylor-scratch chunk, [17] largest number of work-groups
+ * sharing one block's sweep (1: one work-group per block).
  * Workspace: U and U^dag of every slice of a segment, Taylor scratch (Y..Y^r and two
  * ping-pong buffers) of one chunk of slices, states, gradient slots.  When the budget holds
  * everything, segment = chunk = N; when it holds every propagator and the scratch of at
@@ -240,6 +241,36 @@ qoc_status qoc_propagate(qoc_plan plan, const double* u_dev, void* U_out_dev, vo
 qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi0_dev,
                              const void* psif_dev, double* out_dev, double* grad_dev,
                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Objective only (Eqs. (3)-(4)): the propagators and the forward sweep, segment by
+ * segment, then o = <psi_f|psi_N> and F, with no backward sweep and no gradient.  Each
+ * propagator is used once, so a plan with several segments recomputes nothing here.
+ * Arguments, out_dev layout (8 float64 per problem, status bits 0-2 as for
+ * qoc_fidelity_grad), batching and asynchrony as qoc_fidelity_grad. */
+qoc_status qoc_fidelity(qoc_plan plan, const double* u_dev, const void* psi0_dev, const void* psif_dev,
+                        double* out_dev, void* workspace, size_t workspace_bytes, void* stream);
+
+/* One state of the sweeps of the last qoc_fidelity_grad (or, for which = 0, qoc_fidelity)
+ * call that used `workspace` with this plan (Eq. (3): psi_{j+1} = U_j psi_j; App. B:
+ * lambda_j = U_j^dag lambda_{j+1}, lambda_N = psi_f): which = 0 the forward state psi_j,
+ * 0 <= j <= N; which = 1 the costate lambda_j, 1 <= j <= N.  Then o = <lambda_j|psi_j>
+ * for every j, and changing u[j-1, k] alone changes o to <lambda_j| U_{j-1}(u') |psi_{j-1}>.
+ * out_dev receives problem `problem`'s block panels (interleaved complex128, length D_p,
+ * the layout of psi0_dev), in the working precision of the plan converted to FP64.
+ * QOC_ERR_INVALID_ARG for an index out of range.  Asynchronous on `stream`. */
+qoc_status qoc_plan_read_state(qoc_plan plan, int problem, int which, int j, const void* workspace,
+                               size_t workspace_bytes, void* out_dev, void* stream);
+
+/* Co-operative sweep switches, for tests of its fallback and failure handling (0 in
+ * normal use).  QOC_SWEEP_SOLO: every block whose rows span several work-groups is swept
+ * by one work-group alone (the path the sweep takes by itself when its groups are not all
+ * resident); results are unchanged.  QOC_SWEEP_TEST_STALL_FWD / _BWD: the forward or
+ * backward sweep's hand-offs wait for tags that are never written, so each bounded wait
+ * times out (tens of milliseconds per group) and the call reports status bit 2 (outputs
+ * invalid), as after a real stall.  They act only on plans whose sweeps run co-operatively.
+ * Host call. */
+enum { QOC_SWEEP_SOLO = 1, QOC_SWEEP_TEST_STALL_FWD = 2, QOC_SWEEP_TEST_STALL_BWD = 4 };
+qoc_status qoc_plan_set_sweep_mode(qoc_plan plan, int mode);
 
 /* Gate propagation: the unitary a pulse implements, K = U_{N-1} ... U_1 U_0 (Eq. (3)'s
  * slice propagators in time order), for every block of a one-problem plan; Sec. III B

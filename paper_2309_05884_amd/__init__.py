@@ -19,12 +19,17 @@ import numpy as np
 from . import _capi as C
 from ._capi import QocError
 
-__all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "propagate", "GrapeFidelity",
+__all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "fidelity", "fidelity_batched",
+           "read_state", "check_flags", "propagate", "GrapeFidelity", "SWEEP_SOLO", "SWEEP_TEST_STALL_FWD", "SWEEP_TEST_STALL_BWD",
            "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
            "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply",
            "lts_fidelity_grad", "optimize_lbfgs_lts"]
 
 library_path = C.LIB_PATH
+
+# co-operative sweep switches of qoc_plan_set_sweep_mode (tests of the fallback and of the
+# stall handling; 0 in normal use)
+SWEEP_SOLO, SWEEP_TEST_STALL_FWD, SWEEP_TEST_STALL_BWD = 1, 2, 4
 
 
 def _torch():
@@ -129,7 +134,7 @@ class Plan:
 
     INFO_KEYS = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
                  "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid", "problems", "jobs",
-                 "total_controls", "total_panel", "total_propagator", "gemm_variant", "expm_chunk"]
+                 "total_controls", "total_panel", "total_propagator", "gemm_variant", "expm_chunk", "sweep_groups"]
     N_VARIANTS = 3
 
     def __init__(self, system: System, precision: str = "c128", N: int = 1, dt: float = 0.01,
@@ -203,6 +208,10 @@ class Plan:
         """Block sizes m of a one-problem plan, in plan order (the subset when blocks= was given)."""
         sizes = self.systems[0].basis.sizes
         return list(sizes) if self.blocks is None else [sizes[b] for b in self.blocks]
+
+    def set_sweep_mode(self, mode: int):
+        """Co-operative sweep switches (SWEEP_SOLO, SWEEP_TEST_STALL_FWD / _BWD bits; 0 = normal)."""
+        C.check(C.lib().qoc_plan_set_sweep_mode(self._h, int(mode)))
 
     def workspace(self):
         torch = _torch()
@@ -290,6 +299,60 @@ def fidelity_grad(plan: Plan, u, psi0, psif, workspace=None, check=True):
     assert psi0.numel() == D and psif.numel() == D
     out, grad = _run(plan, u.reshape(-1), psi0, psif, workspace, check)
     return out[0], grad.view(plan.N, plan.K)
+
+
+def _run_objective(plan, u_flat, psi0_flat, psif_flat, workspace, check):
+    torch = _torch()
+    ws = workspace if workspace is not None else plan.workspace()
+    out = torch.empty((plan.P, 8), dtype=torch.float64, device=u_flat.device)
+    C.check(C.lib().qoc_fidelity(plan._h, _ptr(u_flat), _ptr(psi0_flat), _ptr(psif_flat), _ptr(out), _ptr(ws),
+                                 ctypes.c_size_t(ws.numel()), _stream()))
+    if check:
+        for p in range(plan.P):
+            check_flags(out[p])
+    return out
+
+
+def fidelity(plan: Plan, u, psi0, psif, workspace=None, check=True):
+    """Objective only (qoc_fidelity: propagators, forward sweep, overlap; no gradient) for a
+    one-problem plan: out[8] as fidelity_grad returns it."""
+    torch = _torch()
+    assert plan.P == 1
+    u = u.to(torch.float64).contiguous()
+    assert u.shape == (plan.N, plan.K) and u.is_cuda
+    psi0 = psi0.to(torch.complex128).contiguous()
+    psif = psif.to(torch.complex128).contiguous()
+    D = plan.info["total_panel"]
+    assert psi0.numel() == D and psif.numel() == D
+    return _run_objective(plan, u.reshape(-1), psi0, psif, workspace, check)[0]
+
+
+def fidelity_batched(plan: Plan, us, psi0s, psifs, workspace=None, check=True):
+    """Objective only for a batched plan: out[P, 8]."""
+    torch = _torch()
+    assert len(us) == plan.P == len(psi0s) == len(psifs)
+    u_flat = torch.cat([u.to(torch.float64).reshape(-1) for u in us]).contiguous()
+    p0 = torch.cat([v.to(torch.complex128).reshape(-1) for v in psi0s]).contiguous()
+    pf = torch.cat([v.to(torch.complex128).reshape(-1) for v in psifs]).contiguous()
+    assert u_flat.numel() == plan.info["total_controls"] and p0.numel() == plan.info["total_panel"]
+    return _run_objective(plan, u_flat, p0, pf, workspace, check)
+
+
+def read_state(plan: Plan, which: str, j: int, problem: int = 0, workspace=None):
+    """A state of the last call's sweeps (qoc_plan_read_state): which = "psi" for psi_j
+    (0 <= j <= N) or "lambda" for the costate lambda_j (1 <= j <= N), as block panels of
+    problem `problem` (complex128 device tensor).  The workspace must be the one that call
+    used (default: the plan's own)."""
+    torch = _torch()
+    ws = workspace if workspace is not None else plan.workspace()
+    sizes = plan.systems[problem].basis.sizes
+    copies = plan.systems[problem].basis.copies
+    idx = range(len(sizes)) if plan.blocks is None else plan.blocks
+    D = sum(sizes[b] * copies[b] for b in idx)
+    out = torch.empty(D, dtype=torch.complex128, device="cuda")
+    C.check(C.lib().qoc_plan_read_state(plan._h, int(problem), {"psi": 0, "lambda": 1}[which], int(j), _ptr(ws),
+                                        ctypes.c_size_t(ws.numel()), _ptr(out), _stream()))
+    return out
 
 
 def fidelity_grad_batched(plan: Plan, us, psi0s, psifs, workspace=None, check=True):
@@ -515,7 +578,10 @@ def _autograd_function():
     torch = _torch()
 
     class GrapeFidelity(torch.autograd.Function):
-        """F(u) with the library's exact adjoint gradient (segment recompute inside the plan)."""
+        """F(u) with the library's exact adjoint gradient (segment recompute inside the plan):
+        the forward pass computes F and dF/du in one call and the backward pass scales the
+        stored gradient.  (GrapeFidelity.apply evaluates the objective alone, without this
+        Function, when no gradient can be asked for.)"""
 
         @staticmethod
         def forward(ctx, u, plan, psi0, psif):
@@ -534,10 +600,16 @@ def _autograd_function():
 class _Lazy:
     _fn = None
 
-    def apply(self, *a):
+    def apply(self, u, plan, psi0, psif):
+        """F(u) as a 0-d tensor; differentiable in u through the library's exact gradient.
+        With grad mode off or u not requiring a gradient, only the objective is evaluated
+        (qoc_fidelity: no backward sweep, no gradient)."""
+        torch = _torch()
+        if not (torch.is_grad_enabled() and u.requires_grad):
+            return fidelity(plan, u.detach(), psi0, psif)[0].clone()
         if _Lazy._fn is None:
             _Lazy._fn = _autograd_function()
-        return _Lazy._fn.apply(*a)
+        return _Lazy._fn.apply(u, plan, psi0, psif)
 
 
 GrapeFidelity = _Lazy()

@@ -11,7 +11,10 @@
 //   Horner products in Y^r);  U_j = T^(2^s_j).
 // All products are complex GEMMs on the matrix cores (FP64 or FP32 MFMA).
 // Sweeps: psi_{j+1} = U_j psi_j (forward), lambda_j = U_j^dag lambda_{j+1} (backward),
-// one work-group per block with the state in LDS.  Objective o = <psi_f|psi_N> in FP64.
+// sequential in j; a block's rows are split over ceil(m / 64) (FP32) or ceil(m / 32)
+// (FP64) work-groups that hand the new state to each other after every slice, and a
+// block that fits one work-group keeps its state in LDS.  Objective o = <psi_f|psi_N>
+// in FP64.
 // Gradient: do/du[j,k] = <lambda_{j+1}| L(X_j, -i dt H_k) |psi_j>, with L the Frechet
 // derivative of exp, through the vector series
 //   <lambda|L(Y,E)|psi> = sum_{i+t<Q} i! t!/(i+t+1)! <b_i|E|a_t>,
@@ -167,6 +170,7 @@ struct qoc_plan_s {
   qoc::DeviceBuffer d_theta, d_w;
   int grid_gemm = 512;
   int variant = 0;        // GEMM tile variant (index into the precision's table)
+  int sweep_mode = 0;     // QOC_SWEEP_* bits (qoc_plan_set_sweep_mode)
   int ncu = 256;
   hipStream_t st2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -828,6 +832,27 @@ __global__ void k_fold_flags(const int* flags, int nprob, double* out) {
   }
 }
 
+// One state of problem p's sweeps as block panels (interleaved complex128): which = 0 the
+// forward state psi_j (store column j, 0 <= j <= N), which = 1 the costate lambda_j (store
+// column j - 1, 1 <= j <= N).
+template <typename T>
+__global__ void k_export_state(const JobDev* jobs, int job_begin, int job_end, const char* ws, size_t off_T,
+                               int which, int j, double2* out) {
+  for (int J = job_begin + blockIdx.y; J < job_end; J += gridDim.y) {
+    const JobDev jb = jobs[J];
+    const T* S = reinterpret_cast<const T*>(ws + off_T) + (which == 0 ? jb.psi_off : jb.lam_off);
+    const size_t ncol = which == 0 ? (size_t)(jb.N + 1) * jb.d : (size_t)jb.N * jb.d;
+    const size_t ps = (size_t)jb.mp * ncol;
+    const size_t col = which == 0 ? (size_t)j : (size_t)(j - 1);
+    const long long base = jb.state_off - jobs[job_begin].state_off;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < jb.m * jb.d; idx += gridDim.x * blockDim.x) {
+      const int c = idx / jb.m, i = idx % jb.m;
+      const size_t g = (col * jb.d + c) * jb.mp + i;
+      out[base + (long long)c * jb.m + i] = make_double2((double)S[g], (double)S[g + ps]);
+    }
+  }
+}
+
 // ===================================================================== sweeps
 // Sweep through one segment, one work-group (16 waves) per job, the state in LDS.
 // DIR 0: psi_{j+1} = U_j psi_j from the forward store; DIR 1: lambda_j = U_j^dag
@@ -999,16 +1024,17 @@ constexpr int kFlagSweepAbort = 4;       // status bit 2: a co-operative sweep g
 
 template <typename T> struct CoopRows { static constexpr int value = 16 * Vec16<T>::n; };
 
-__device__ inline int coop_decide(int* ctl, int W, int* flags) {
+__device__ inline int coop_decide(int* ctl, int W, int* flags, int force_solo) {
   __shared__ int decision;
   if (threadIdx.x == 0) {
     if (W == 1) {
       decision = kCoopGo;
     } else if (blockIdx.x == 0) {
       long s = 0;
-      while (__hip_atomic_load(ctl + 0, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < W - 1 && ++s < kArriveSpins)
+      while (!force_solo && __hip_atomic_load(ctl + 0, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < W - 1 &&
+             ++s < kArriveSpins)
         __builtin_amdgcn_s_sleep(2);
-      const int all = __hip_atomic_load(ctl + 0, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= W - 1;
+      const int all = !force_solo && __hip_atomic_load(ctl + 0, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= W - 1;
       // the others read the decision; once written it never changes
       decision = all ? kCoopGo : kCoopSolo;
       __hip_atomic_store(ctl + 1, decision, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1177,11 +1203,15 @@ __device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j
   }
 }
 
+// mode (host test switches, 0 in normal use): bit 0 -- group 0 runs every multi-group job
+// alone without waiting for the others (sweep_solo); bit 1 -- the groups wait for hand-off
+// tags that are never written, so every bounded wait times out and the sweep gives up with
+// status bit 2, as it would on a real stall.
 template <typename T, int DIR>
 __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njobs, char* ws, size_t off_T,
                                                      const int* ent_s, const int* ent_q, int r, int seg_j0,
                                                      int seg_len, int* ctl_all, int* flags,
-                                                     unsigned long long* xchg_all) {
+                                                     unsigned long long* xchg_all, int mode) {
   typedef typename Vec16<T>::type TV;
   typedef XchgVal<T> XV;
   constexpr int RPL = Vec16<T>::n, RB = CoopRows<T>::value, UNR = 4;
@@ -1199,12 +1229,14 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
     return;
   }
   int* ctl = ctl_all + 4 * J;
-  const int mode = coop_decide(ctl, W, flags);
-  if (mode == kCoopSolo) {
+  const int decision = coop_decide(ctl, W, flags, mode & 1);
+  if (decision == kCoopSolo) {
     sweep_solo<T, DIR>(jb, ws, off_T, ent_s, ent_q, r, seg_j0, seg_len);
     return;
   }
-  if (mode != kCoopGo) return;
+  if (decision != kCoopGo) return;
+  // tags run 1 .. len - 1 < 2^24 (N <= 2^24): the skewed tag is never written
+  const unsigned tag_skew = (mode & 2) ? (1u << 30) : 0u;
   T* sre = reinterpret_cast<T*>(smem_raw);  // state [d][mp]
   T* sim = sre + (size_t)d * mp;
   T* pre = sim + (size_t)d * mp;             // wave partials [16][d][RB]
@@ -1242,8 +1274,8 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
       bool ok = true;
       for (int idx = threadIdx.x; idx < mp * d && ok; idx += blockDim.x) {
         T vr = T(0), vi = T(0);
-        ok = XV::get(Xp + (size_t)idx * XV::W, (unsigned)it, vr) &&
-             XV::get(Xp + xplane + (size_t)idx * XV::W, (unsigned)it, vi);
+        ok = XV::get(Xp + (size_t)idx * XV::W, (unsigned)it + tag_skew, vr) &&
+             XV::get(Xp + xplane + (size_t)idx * XV::W, (unsigned)it + tag_skew, vi);
         sre[idx] = vr;
         sim[idx] = vi;
       }
@@ -2255,12 +2287,14 @@ struct Driver {
         const int nz = (int)(2 * P->xchg_words);
         hipLaunchKernelGGL(k_zero_ints, dim3((4 * njobs + 255) / 256), dim3(256), 0, st, ctl, 4 * njobs);
         hipLaunchKernelGGL(k_zero_ints, dim3((nz + 255) / 256), dim3(256), 0, st, reinterpret_cast<int*>(xg), nz);
+        const int mode = (P->sweep_mode & QOC_SWEEP_SOLO ? 1 : 0) |
+                         (P->sweep_mode & (dir == 0 ? QOC_SWEEP_TEST_STALL_FWD : QOC_SWEEP_TEST_STALL_BWD) ? 2 : 0);
         if (dir == 0)
           hipLaunchKernelGGL((k_sweep_coop<T, 0>), grid, dim3(threads), P->coop_lds, st, dj, njobs, ws, P->off_T,
-                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags, xg);
+                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags, xg, mode);
         else
           hipLaunchKernelGGL((k_sweep_coop<T, 1>), grid, dim3(threads), P->coop_lds, st, dj, njobs, ws, P->off_T,
-                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags, xg);
+                             ent_s(P, ws), ent_q(P, ws), P->r, seg_j0, P->seg_len, ctl, flags, xg, mode);
       });
       return;
     }
@@ -2369,8 +2403,33 @@ struct Driver {
         if (sg != P->nseg - 1) expm_segment(P, ws, u, sg * P->seg_len, st, (sg + 1) * P->seg_len);
         sweep(P, ws, 1, sg * P->seg_len, st);
       }
+      // status bits raised by the backward sweeps and recomputed slices after the objective
+      // was written
+      hipLaunchKernelGGL(k_fold_flags, dim3(1), dim3(64), 0, st, flags, P->P, out);
     }
     gradient(P, u, out, grad, ws, st);
+  }
+
+  // Objective only: propagators and the forward sweep, segment by segment (nothing is
+  // recomputed: each segment's propagators are used once), then the overlap.
+  static void objective_only(qoc_plan_s* P, const double* u, const void* psi0, const void* psif, double* out,
+                             char* ws, hipStream_t st) {
+    const int njobs = (int)P->jobs.size();
+    const JobDev* dj = P->d_jobs.as<JobDev>();
+    const ProbDev* dpr = P->d_probs.as<ProbDev>();
+    int* flags = reinterpret_cast<int*>(ws + P->off_flags);
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);
+    timed(PK_OTHER, st, [&] {
+      hipLaunchKernelGGL(k_states_in<T>, dim3(std::max(1, std::min(64, 8192 / njobs)), std::min(njobs, 32768)),
+                         dim3(256), 0, st, dj, njobs, (const double2*)psi0, (const double2*)psif, ws, P->off_T, flags);
+    });
+    for (int sg = 0; sg < P->nseg; ++sg) {
+      expm_segment(P, ws, u, sg * P->seg_len, st);
+      sweep(P, ws, 0, sg * P->seg_len, st);
+    }
+    timed(PK_OVERLAP, st, [&] {
+      hipLaunchKernelGGL(k_overlap<T>, dim3(P->P), dim3(1024), 0, st, dj, dpr, ws, P->off_T, flags, out);
+    });
   }
 
   // Exact gradient by the Frechet series over R sub-steps (see the file header).
@@ -2557,6 +2616,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       if (best < 0 || (long)R * Q < best) { best = (long)R * Q; bestR = R; bestQ = Q; }
       if (th < 0.5) break;
     }
+    QOC_REQUIRE(bestQ > 0, QOC_ERR_NUMERIC, "dt * ||H|| bound too large for the gradient series");
     P->R = bestR;
     P->Q = bestQ;
   }
@@ -2844,10 +2904,10 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
     QOC_REQUIRE(P && info, QOC_ERR_INVALID_ARG, "null argument");
     size_t per_slice = 0;
     for (auto& j : P->jobs) per_slice += (size_t)(2 + P->r + 2) * 2 * j.mp * j.mp * P->elem;
-    int64_t v[17] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
+    int64_t v[18] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
                      P->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U,
-                     P->variant, P->echunk};
-    for (int i = 0; i < cap && i < 17; ++i) info[i] = v[i];
+                     P->variant, P->echunk, P->coop ? P->coop_w : 1};
+    for (int i = 0; i < cap && i < 18; ++i) info[i] = v[i];
   });
 }
 
@@ -2933,6 +2993,51 @@ qoc_status qoc_fidelity_grad(qoc_plan P, const double* u_dev, const void* psi0_d
       Driver<double>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, st);
     else
       Driver<float>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, st);
+  });
+}
+
+qoc_status qoc_fidelity(qoc_plan P, const double* u_dev, const void* psi0_dev, const void* psif_dev,
+                        double* out_dev, void* workspace, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    QOC_REQUIRE(P && u_dev && psi0_dev && psif_dev && out_dev && workspace, QOC_ERR_INVALID_ARG, "null argument");
+    QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
+    hipStream_t st = (hipStream_t)stream;
+    if (P->prec == QOC_C128)
+      Driver<double>::objective_only(P, u_dev, psi0_dev, psif_dev, out_dev, (char*)workspace, st);
+    else
+      Driver<float>::objective_only(P, u_dev, psi0_dev, psif_dev, out_dev, (char*)workspace, st);
+  });
+}
+
+qoc_status qoc_plan_read_state(qoc_plan P, int problem, int which, int j, const void* workspace, size_t ws_bytes,
+                               void* out_dev, void* stream) {
+  return guarded([&] {
+    QOC_REQUIRE(P && workspace && out_dev, QOC_ERR_INVALID_ARG, "null argument");
+    QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
+    QOC_REQUIRE(problem >= 0 && problem < P->P, QOC_ERR_INVALID_ARG, "problem out of range");
+    QOC_REQUIRE(which == 0 || which == 1, QOC_ERR_INVALID_ARG, "which must be 0 (state) or 1 (costate)");
+    const ProbDev& pb = P->probs[problem];
+    QOC_REQUIRE(which == 0 ? (j >= 0 && j <= pb.N) : (j >= 1 && j <= pb.N), QOC_ERR_INVALID_ARG,
+                "slice index out of range (states 0..N, costates 1..N)");
+    hipStream_t st = (hipStream_t)stream;
+    const int nj = pb.job_end - pb.job_begin;
+    const dim3 grid(16, (unsigned)std::min(nj, 65535));
+    if (P->prec == QOC_C128)
+      hipLaunchKernelGGL(k_export_state<double>, grid, dim3(256), 0, st, P->d_jobs.as<JobDev>(), pb.job_begin,
+                         pb.job_end, (const char*)workspace, P->off_T, which, j, (double2*)out_dev);
+    else
+      hipLaunchKernelGGL(k_export_state<float>, grid, dim3(256), 0, st, P->d_jobs.as<JobDev>(), pb.job_begin,
+                         pb.job_end, (const char*)workspace, P->off_T, which, j, (double2*)out_dev);
+    QOC_HIP(hipGetLastError());
+  });
+}
+
+qoc_status qoc_plan_set_sweep_mode(qoc_plan P, int mode) {
+  return guarded([&] {
+    QOC_REQUIRE(P, QOC_ERR_INVALID_ARG, "null plan");
+    QOC_REQUIRE(mode >= 0 && mode <= (QOC_SWEEP_SOLO | QOC_SWEEP_TEST_STALL_FWD | QOC_SWEEP_TEST_STALL_BWD),
+                QOC_ERR_INVALID_ARG, "unknown sweep mode bits");
+    P->sweep_mode = mode;
   });
 }
 

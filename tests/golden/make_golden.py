@@ -4,6 +4,9 @@ Calls only the FP64 CPU oracle and the seeded input generators.  Usage:
     python tests/golden/make_golden.py ring12       # 12-qubit ring, D12, all blocks, N=1000
     python tests/golden/make_golden.py ring14       # 14-qubit ring, two-site group, first 8 slices
     python tests/golden/make_golden.py sym128       # S_128, 8 candidates, candidates 0 and 5
+    python tests/golden/make_golden.py sym128 1024  # S_128, 1024 candidates, candidates 0, 5, 1023
+    python tests/golden/make_golden.py ring14 64    # 14-qubit ring, first 64 slices
+    python tests/golden/make_golden.py batch 0 1 2 4   # problems of the 256-ring batch
 The output files hold F, o, ||psi_N||^2 and the full gradient, one value per line.
 """
 import os
@@ -27,6 +30,15 @@ def panels(blocks, v):
         out.append(v[off:off + s].reshape(b["d"], b["m"]).T)
         off += s
     return out
+
+
+def _write(path, header, r, N):
+    with open(path, "w") as fh:
+        fh.write(header + "\n")
+        fh.write(f"F {float(r['F'])!r}\nF_raw {float(r['F_raw'])!r}\no_re {float(r['o'].real)!r}\n")
+        fh.write(f"o_im {float(r['o'].imag)!r}\nnormN2 {float(r['normN2'])!r}\n")
+        for j in range(N):
+            fh.write("g " + " ".join(repr(float(v)) for v in r["grad"][j]) + "\n")
 
 
 def ring12():
@@ -61,7 +73,7 @@ def ring14(nslices=8):
     D = sum(b["m"] * b["d"] for b in ob)
     vf = W.gaussian_panel(rng, D)
     v0 = W.gaussian_panel(rng, D)
-    r = og.fidelity_grad(ob, w.u[:nslices], w.dt, panels(ob, v0), panels(ob, vf))
+    r = og.fidelity_grad(ob, w.u[:nslices], w.dt, panels(ob, v0), panels(ob, vf), keep_states=True)
     path = os.path.join(HERE, f"ring14_T2R_allblocks_N{nslices}.txt")
     with open(path, "w") as fh:
         fh.write("# oracle (FP64, eigendecomposition + Daleckii-Krein) for qoc_workloads.config4(seed=0, "
@@ -74,12 +86,14 @@ def ring14(nslices=8):
     print(path, f"{time.time() - t:.1f} s", r["F"])
 
 
-def sym128(C=8, which=(0, 5)):
+def sym128(C=8, which=None):
     """The all-to-all S_128 workload with C candidate pulses (500 slices each); states are
     drawn after the pulses, psi_f then psi0 per candidate.  Candidates `which` are written."""
     w = W.config5(seed=0, C=C)
     rng = w.notes["rng"]
     uc = w.notes["u_candidates"]
+    if which is None:
+        which = (0, 5) if C == 8 else (0, 5, C - 1)
     t = time.time()
     ob = og.block_system(128, w.h0, w.hk, "symmetric")
     D = sum(b["m"] * b["d"] for b in ob)
@@ -102,5 +116,35 @@ def sym128(C=8, which=(0, 5)):
         print(path, f"{time.time() - t:.1f} s", r["F"], flush=True)
 
 
+def batch(problems):
+    """Problems of the 256-ring batched workload (qoc_workloads.config3_list(seed=0)):
+    after the list is drawn, each problem in list order draws psi_f then psi0 (2^n
+    amplitudes each, Gaussian panels over every block) from the list's generator, so a
+    problem's states do not depend on how many problems follow it."""
+    ws, rng = W.config3_list(seed=0)
+    states = []
+    for w in ws[:max(problems) + 1]:
+        vf = W.gaussian_panel(rng, 2 ** w.n)
+        v0 = W.gaussian_panel(rng, 2 ** w.n)
+        states.append((v0, vf))
+    for p in problems:
+        w = ws[p]
+        t = time.time()
+        ob = og.block_system(w.n, w.h0, w.hk, "dihedral", w.stride)
+        v0, vf = states[p]
+        r = og.fidelity_grad(ob, w.u, w.dt, panels(ob, v0), panels(ob, vf), keep_states=True)
+        path = os.path.join(HERE, f"batch256_p{p}_n{w.n}_N{w.N}.txt")
+        _write(path, f"# oracle (FP64, eigendecomposition + Daleckii-Krein) for problem {p} of "
+                     f"qoc_workloads.config3_list(seed=0) (n={w.n}, N={w.N}, J={w.J!r}), "
+                     "states psi_f then psi0 per problem in list order; written by make_golden.py", r, w.N)
+        print(path, f"{time.time() - t:.1f} s", r["F"], flush=True)
+
+
 if __name__ == "__main__":
-    {"ring12": ring12, "ring14": ring14, "sym128": sym128}[sys.argv[1]]()
+    cmd, rest = sys.argv[1], [int(a) for a in sys.argv[2:]]
+    if cmd == "batch":
+        batch(rest)
+    elif cmd in ("ring14", "sym128"):
+        {"ring14": ring14, "sym128": sym128}[cmd](*rest)
+    else:
+        {"ring12": ring12}[cmd]()
