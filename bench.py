@@ -59,14 +59,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=3)
-    ap.add_argument("--cpu-slices", type=int, default=32, help="oracle sample size (slices, all blocks)")
+    ap.add_argument("--cpu-slices", type=int, default=128,
+                    help="oracle sample size on all host cores (slices, all blocks)")
+    ap.add_argument("--cpu-slices-1t", type=int, default=16, help="oracle sample size on one host thread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sym-candidates", type=int, default=64,
-                    help="S_128 candidate pulses timed in one batched plan (0: skip)")
-    ap.add_argument("--ring14-slices", type=int, default=64,
-                    help="slices of the 14-qubit staggered-control ring timed (0: skip)")
-    ap.add_argument("--batch-problems", type=int, default=8,
-                    help="problems of the 256-ring batched workload timed in one plan (0: skip)")
+    ap.add_argument("--sym-candidates", type=int, default=1024,
+                    help="S_128 candidate pulses timed in one batched plan (0: skip; 1024 = the full workload)")
+    ap.add_argument("--ring14-slices", type=int, default=4000,
+                    help="slices of the 14-qubit staggered-control ring timed (0: skip; 4000 = the full pulse)")
+    ap.add_argument("--batch-problems", type=int, default=32,
+                    help="problems of the 256-ring batched workload timed in one plan (0: skip; 256 = all)")
     ap.add_argument("--dense-slices", type=int, default=16,
                     help="slices of the same pulse timed on the dense 4096-dim space (0: skip)")
     ap.add_argument("--paper-comparison", type=int, default=14, metavar="NMAX",
@@ -150,6 +152,69 @@ def gemm_flops_jobs(q, plan, u_flat, job_sizes):
     return tot
 
 
+def executed_flops_jobs(q, plan, u_flat, job_sizes):
+    """(algorithmic, executed) propagator GEMM flops of one fidelity+gradient call: the
+    executed count adds the slices recomputed in the backward sweep of a segmented plan (a
+    job recomputes every segment before its own last one)."""
+    qs, ss, _ = q.slice_stats(plan, u_flat)
+    r = plan.info["taylor_step"]
+    L = plan.info["segment"]
+    alg = ex = 0.0
+    for b, m in enumerate(job_sizes):
+        valid = np.where(qs[b] >= 0)[0]
+        if valid.size == 0:
+            continue
+        f = _product_flops(m, qs[b][valid], ss[b][valid], r)
+        nj = int(valid.size)
+        last_start = ((nj - 1) // L) * L
+        alg += f
+        ex += f + (_product_flops(m, qs[b][:last_start], ss[b][:last_start], r) if last_start > 0 else 0.0)
+    return alg, ex
+
+
+def golden_values(name):
+    """(scalars, gradient) stored by tests/golden/make_golden.py (FP64 oracle), or None."""
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    vals, grad = {}, []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        k, *v = line.split()
+        # values are Python float reprs (older files: numpy scalar reprs)
+        num = [float(x.replace("np.float64(", "").rstrip(")")) for x in v]
+        if k == "g":
+            grad.append(num)
+        else:
+            vals[k] = num[0]
+    return vals, np.array(grad)
+
+
+def parity(name, F, grad):
+    """|dF| and gradient error of one result against the stored oracle values `name`."""
+    gv = golden_values(name)
+    if gv is None:
+        return None
+    vals, gref = gv
+    g = np.asarray(grad)
+    gmax = float(np.abs(gref).max())
+    dg = float(np.abs(g - gref).max())
+    return {"oracle": name, "dF": abs(float(F) - vals["F"]), "max_grad_err": dg,
+            "grad_err_rel_to_max": dg / gmax if gmax > 0 else None}
+
+
+def one_step(torch, run):
+    """Milliseconds of one call of run(), HIP events on the current stream."""
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    res = run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1), res
+
+
 def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, precision="c64"):
     """Time `steps` calls of run() after `warmup`, with the library's per-kernel events;
     returns throughput and the propagator GEMM's fraction of the MFMA peak."""
@@ -165,13 +230,17 @@ def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, p
     torch.cuda.synchronize()
     prof = q.profile_end()
     ms = e0.elapsed_time(e1) / steps
-    flops = gemm_flops_jobs(q, plan, u_flat, job_sizes)
+    flops, ex_flops = executed_flops_jobs(q, plan, u_flat, job_sizes)
     gemm_ms, gemm_n = prof["propagator_gemm"]
     tf = flops * steps / (gemm_ms * 1e-3) / 1e12
+    tfx = ex_flops * steps / (gemm_ms * 1e-3) / 1e12
     return {"ms_per_step": ms, "value": units / (ms * 1e-3), "unit": "slices*blocks/s",
-            "gemm_tflops": tf, "gemm_frac": tf / MFMA_PEAK[precision], "gemm_ms_per_step": gemm_ms / steps,
-            "gemm_variant": plan.variant_name, "steps": steps, "segments": plan.info["segments"],
-            "workspace_gb": plan.workspace_bytes / 1e9}
+            "gemm_tflops": tf, "gemm_frac": tf / MFMA_PEAK[precision],
+            "gemm_tflops_with_recompute": tfx, "gemm_frac_with_recompute": tfx / MFMA_PEAK[precision],
+            "gemm_ms_per_step": gemm_ms / steps, "gemm_launches_per_step": gemm_n / steps,
+            "gemm_variant": plan.variant_name, "steps": steps, "warmup": warmup, "segments": plan.info["segments"],
+            "segment_slices": plan.info["segment"], "workspace_gb": plan.workspace_bytes / 1e9,
+            "kernel_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]}}
 
 
 def paper_comparison(q, torch, W, nmax, N=100, dt=0.05, dense_max=12, steps=2):
@@ -468,9 +537,21 @@ def optimizer_leg(q, torch, W, N=100, dt=0.05):
     return out
 
 
-def cpu_baseline(w, v0, vf, nslices):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, v0, vf, nslices, nslices_1t):
+    """The FP64 oracle (eigendecomposition propagators, Daleckii-Krein gradient) on the host,
+    on the first slices of the same workload (all blocks): on every BLAS thread, and on one."""
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import grape as og
     ob = og.block_system(12, w.h0, w.hk)
@@ -487,9 +568,198 @@ def cpu_baseline(w, v0, vf, nslices):
     og.fidelity_grad(ob, w.u[:nslices], w.dt, panels(v0), panels(vf))
     el = time.perf_counter() - t0
     threads = max([i["num_threads"] for i in threadpool_info()] or [1])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        og.fidelity_grad(ob, w.u[:nslices_1t], w.dt, panels(v0), panels(vf))
+        el1 = time.perf_counter() - t0
     return {"value": nslices * len(ob) / el, "unit": "slices*blocks/s", "cores": int(threads), "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"first {nslices} of {w.N} slices, all {len(ob)} blocks, FP64 eigendecomposition "
-                      f"propagators and Daleckii-Krein gradient ({el:.1f} s)"}
+                      f"propagators and Daleckii-Krein gradient ({el:.1f} s on {threads} BLAS threads)",
+            "single_thread": {"value": nslices_1t * len(ob) / el1, "unit": "slices*blocks/s", "cores": 1,
+                              "sample": f"first {nslices_1t} slices, all blocks ({el1:.1f} s)"}}
+
+
+def _fp64_subset(q, torch, make_plan, run, reps=1):
+    """ms per step of the same work in complex64 and complex128 (one warm-up each)."""
+    res = {}
+    for prec in ("c64", "c128"):
+        P = make_plan(prec)
+        run(P)
+        ms, _ = one_step(torch, lambda: run(P))
+        for _ in range(reps - 1):
+            ms = min(ms, one_step(torch, lambda: run(P))[0])
+        res[prec] = ms
+        del P
+        torch.cuda.empty_cache()
+    return {"c64_ms": res["c64"], "c128_ms": res["c128"], "speedup": res["c128"] / res["c64"]}
+
+
+def sym_leg(q, torch, W, C):
+    """All-to-all S_128 register: C candidate pulses (500 slices of 0.01 each, 65 blocks of
+    129..1 states) in one batched plan, complex64, every block of every candidate carrying
+    state.  One timed step (the kernels are warmed up and the tile variant chosen by the
+    autotuner on a 32-candidate plan of the same blocks).  Parity: candidates 0, 5 and C - 1
+    against stored oracle values when C = 1024 (the full workload).  FP32 vs FP64: the
+    first 16 candidates in both precisions."""
+    ws = W.config5(seed=0, C=C)
+    uc = ws.notes["u_candidates"]
+    rs = ws.notes["rng"]
+    Bs = q.Basis(128, "symmetric")
+    Ss = q.System(Bs, ws.h0, ws.hk)
+    states = []
+    for _ in range(C):  # psi_f then psi0 per candidate, after the pulses
+        vf = W.gaussian_panel(rs, Bs.dim)
+        v0 = W.gaussian_panel(rs, Bs.dim)
+        states.append((v0, vf))
+    us = [torch.tensor(x, device="cuda") for x in uc]
+    p0 = [torch.tensor(st[0], device="cuda") for st in states]
+    pf = [torch.tensor(st[1], device="cuda") for st in states]
+    sub = min(32, C)
+    Pt = q.Plan.batched([Ss] * sub, "c64", [ws.N] * sub, [ws.dt] * sub, 1.0)
+    chosen, tune_ms = Pt.autotune(torch.cat([x.reshape(-1) for x in us[:sub]]))
+    q.fidelity_grad_batched(Pt, us[:sub], p0[:sub], pf[:sub], check=False)
+    del Pt
+    torch.cuda.empty_cache()
+    Ps = q.Plan.batched([Ss] * C, "c64", [ws.N] * C, [ws.dt] * C, 1.0)
+    Ps.set_variant(chosen)
+    uflat = torch.cat([x.reshape(-1) for x in us])
+    res = {}
+
+    def run():
+        res["out"], res["grads"] = q.fidelity_grad_batched(Ps, us, p0, pf, check=False)
+
+    sym = profiled_leg(q, torch, Ps, run, 1, 0, uflat, list(Bs.sizes) * C, C * len(Bs.sizes) * ws.N)
+    out = res["out"]
+    for c in range(C):
+        q.check_flags(out[c])
+    sym.update({"workload": "allpairs128_S128_candidates", "full_size": C == 1024, "candidates": C,
+                "slices": ws.N, "blocks": len(Bs.sizes), "autotune_ms": tune_ms})
+    if C == 1024:
+        sym["parity"] = [parity(f"sym128_C1024_cand{c}_N{ws.N}.txt", out[c, 0].item(), res["grads"][c].cpu().numpy())
+                         for c in (0, 5, C - 1)]
+    del Ps, res
+    torch.cuda.empty_cache()
+    k = min(16, C)
+    sym["fp32_vs_fp64"] = _fp64_subset(
+        q, torch, lambda prec: q.Plan.batched([Ss] * k, prec, [ws.N] * k, [ws.dt] * k, 1.0),
+        lambda P: q.fidelity_grad_batched(P, us[:k], p0[:k], pf[:k], check=False))
+    sym["fp32_vs_fp64"]["subset"] = f"first {k} candidates"
+    print(f"[bench] S_128 x {C}: {sym}", file=sys.stderr, flush=True)
+    return sym
+
+
+def ring14_leg(q, torch, W, N):
+    """The 14-qubit ring with staggered controls under the two-site group (blocks 1300,
+    1044, 3 x 2340; 4 controls; slices of 0.01): the first N slices of its 4000-slice pulse
+    (N = 4000: the full workload), all blocks, complex64, the default workspace budget
+    (propagators recomputed segment by segment in the backward sweep).  One timed step after
+    the kernels are warmed up and the tile variant chosen on the 64-slice prefix plan.
+    Parity and FP32 vs FP64: the 64-slice prefix in both precisions against stored oracle
+    values (the oracle takes about 35 s per slice of this workload)."""
+    w4 = W.config4(seed=0, variant="all")
+    r4 = w4.notes["rng"]
+    B4 = q.Basis(14, "dihedral", 2)
+    S4 = q.System(B4, w4.h0, w4.hk)
+    f4 = torch.tensor(W.gaussian_panel(r4, B4.dim), device="cuda")
+    z4 = torch.tensor(W.gaussian_panel(r4, B4.dim), device="cuda")
+    u_all = torch.tensor(w4.u, device="cuda")
+    # prefix: parity in both precisions, FP32 vs FP64 timing, autotune
+    Np = min(64, N)
+    gname = f"ring14_T2R_allblocks_N{Np}.txt"
+    if golden_values(gname) is None:
+        Np = min(8, N)
+        gname = f"ring14_T2R_allblocks_N{Np}.txt"
+    up = u_all[:Np].contiguous()
+    prefix = {"slices": Np}
+    chosen = 0
+    for prec in ("c64", "c128"):
+        P = q.Plan(S4, prec, Np, w4.dt, 2.0)
+        if prec == "c64":
+            chosen, prefix["autotune_ms"] = P.autotune(up)
+        q.fidelity_grad(P, up, z4, f4)
+        ms, (o, g) = one_step(torch, lambda: q.fidelity_grad(P, up, z4, f4))
+        q.check_flags(o)
+        prefix[prec + "_ms"] = ms
+        prefix["parity_" + prec] = parity(gname, o[0].item(), g.cpu().numpy())
+        del P
+        torch.cuda.empty_cache()
+    prefix["speedup"] = prefix["c128_ms"] / prefix["c64_ms"]
+    u4 = u_all[:N].contiguous()
+    P4 = q.Plan(S4, "c64", N, w4.dt, 2.0)
+    P4.set_variant(chosen)
+    res = {}
+
+    def run():
+        res["out"], res["grad"] = q.fidelity_grad(P4, u4, z4, f4, check=False)
+
+    ring14 = profiled_leg(q, torch, P4, run, 1, 0, u4, list(B4.sizes), len(B4.sizes) * N)
+    q.check_flags(res["out"])
+    ring14.update({"workload": "ring14_stagger_T2R_allblocks", "full_size": N == 4000, "slices": N,
+                   "blocks": list(B4.sizes), "F": res["out"][0].item(), "prefix": prefix})
+    print(f"[bench] ring14: {ring14}", file=sys.stderr, flush=True)
+    del P4, res
+    torch.cuda.empty_cache()
+    return ring14
+
+
+def batch_leg(q, torch, W, Pn):
+    """The first Pn problems of the 256-ring batched workload (n in {8, 10, 12, 14}, 200-2000
+    slices of 0.02, J ~ U[0.5, 1.5], all blocks carrying state) in one complex64 plan with
+    the default workspace budget; Pn = 256 is the full workload.  One timed step after the
+    kernels are warmed up and the tile variant chosen on a plan of the first 4 problems.
+    Parity: every problem with stored oracle values; FP32 vs FP64: the first 4 problems in
+    both precisions."""
+    wl, rb = W.config3_list(seed=0)
+    wl = wl[:Pn]
+    states = []
+    for x in wl:  # psi_f then psi0 per problem, in list order
+        vf = W.gaussian_panel(rb, 2 ** x.n)
+        v0 = W.gaussian_panel(rb, 2 ** x.n)
+        states.append((v0, vf))
+    bases = {n: q.Basis(n) for n in sorted({x.n for x in wl})}
+    systems = [q.System(bases[x.n], x.h0, x.hk) for x in wl]
+    ub = [torch.tensor(x.u, device="cuda") for x in wl]
+    p0 = [torch.tensor(st[0], device="cuda") for st in states]
+    pf = [torch.tensor(st[1], device="cuda") for st in states]
+    k = min(4, Pn)
+
+    def subset_plan(prec):
+        return q.Plan.batched(systems[:k], prec, [x.N for x in wl[:k]], [x.dt for x in wl[:k]], 1.0)
+
+    Pt = subset_plan("c64")
+    chosen, tune_ms = Pt.autotune(torch.cat([x.reshape(-1) for x in ub[:k]]))
+    del Pt
+    torch.cuda.empty_cache()
+    fp = _fp64_subset(q, torch, subset_plan, lambda P: q.fidelity_grad_batched(P, ub[:k], p0[:k], pf[:k], check=False))
+    fp["subset"] = f"first {k} problems"
+    Pb = q.Plan.batched(systems, "c64", [x.N for x in wl], [x.dt for x in wl], 1.0)
+    Pb.set_variant(chosen)
+    uflat = torch.cat([x.reshape(-1) for x in ub])
+    sizes = [m for x in wl for m in bases[x.n].sizes]
+    units_b = sum(len(bases[x.n].sizes) * x.N for x in wl)
+    res = {}
+
+    def run():
+        res["out"], res["grads"] = q.fidelity_grad_batched(Pb, ub, p0, pf, check=False)
+
+    batch = profiled_leg(q, torch, Pb, run, 1, 0, uflat, sizes, units_b)
+    out = res["out"]
+    for p in range(len(wl)):
+        q.check_flags(out[p])
+    par = []
+    for p, x in enumerate(wl):
+        r = parity(f"batch256_p{p}_n{x.n}_N{x.N}.txt", out[p, 0].item(), res["grads"][p].cpu().numpy())
+        if r is not None:
+            r["problem"] = p
+            par.append(r)
+    batch.update({"workload": "batch_rings", "full_size": Pn == 256, "problems": len(wl),
+                  "n": [x.n for x in wl], "slices": [x.N for x in wl], "block_slices": units_b,
+                  "autotune_ms": tune_ms, "parity": par, "fp32_vs_fp64": fp})
+    print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
+    del Pb, res, systems, bases
+    torch.cuda.empty_cache()
+    return batch
 
 
 def main():
@@ -553,30 +823,7 @@ def main():
         del Pd, Sd, Bd
         torch.cuda.empty_cache()
 
-    sym = None
-    if args.sym_candidates > 0:
-        # batched: C candidate pulses of the all-to-all S_128 register in one plan (65 blocks
-        # of 129..1 states, 500 slices each); every block of every candidate carries state
-        ws = W.config5(seed=0, C=args.sym_candidates)
-        uc = ws.notes["u_candidates"]
-        rs = ws.notes["rng"]
-        Bs = q.Basis(128, "symmetric")
-        Ss = q.System(Bs, ws.h0, ws.hk)
-        C = uc.shape[0]
-        Ps = q.Plan.batched([Ss] * C, "c64", [ws.N] * C, [ws.dt] * C, 1.0)
-        us = [torch.tensor(x, device="cuda") for x in uc]
-        p0 = [torch.tensor(W.gaussian_panel(rs, Bs.dim), device="cuda") for _ in range(C)]
-        pf = [torch.tensor(W.gaussian_panel(rs, Bs.dim), device="cuda") for _ in range(C)]
-        uflat = torch.cat([x.reshape(-1) for x in us])
-        Ps.autotune(uflat)
-        sym = profiled_leg(q, torch, Ps, lambda: q.fidelity_grad_batched(Ps, us, p0, pf, check=False), 2, 1, uflat,
-                           list(Bs.sizes) * C, C * len(Bs.sizes) * ws.N)
-        sym.update({"workload": "allpairs128_S128_candidates", "candidates": C, "slices": ws.N,
-                    "blocks": len(Bs.sizes)})
-        print(f"[bench] S_128 x {C}: {sym}", file=sys.stderr, flush=True)
-        del Ps, Ss, Bs
-        torch.cuda.empty_cache()
-
+    sym = sym_leg(q, torch, W, args.sym_candidates) if args.sym_candidates > 0 else None
     comparison = None
     if args.paper_comparison > 0:
         comparison = paper_comparison(q, torch, W, args.paper_comparison)
@@ -584,54 +831,13 @@ def main():
     optimizer = optimizer_leg(q, torch, W) if args.optimizer else None
     lts = lts_leg(q, torch) if args.lts else None
 
-    ring14 = None
-    if args.ring14_slices > 0:
-        # the 14-qubit ring with staggered controls under the two-site group (blocks 1300,
-        # 1044, 3 x 2340, 4 controls), first slices of its 4000-slice pulse, all blocks
-        w4 = W.config4(seed=0, variant="all")
-        r4 = w4.notes["rng"]
-        B4 = q.Basis(14, "dihedral", 2)
-        S4 = q.System(B4, w4.h0, w4.hk)
-        N4 = args.ring14_slices
-        P4 = q.Plan(S4, "c64", N4, w4.dt, 2.0)
-        u4 = torch.tensor(w4.u[:N4], device="cuda")
-        f4 = torch.tensor(W.gaussian_panel(r4, B4.dim), device="cuda")
-        z4 = torch.tensor(W.gaussian_panel(r4, B4.dim), device="cuda")
-        P4.autotune(u4)
-        ring14 = profiled_leg(q, torch, P4, lambda: q.fidelity_grad(P4, u4, z4, f4, check=False), 2, 1, u4,
-                              list(B4.sizes), len(B4.sizes) * N4)
-        ring14.update({"workload": "ring14_stagger_T2R_allblocks", "slices": N4, "blocks": list(B4.sizes)})
-        print(f"[bench] ring14: {ring14}", file=sys.stderr, flush=True)
-        del P4, S4, B4
-        torch.cuda.empty_cache()
-
-    batch = None
-    if args.batch_problems > 0:
-        # the first problems of the 256-ring batched workload (ragged n and N) in one plan
-        wl, rb = W.config3_list(seed=0)
-        wl = wl[:args.batch_problems]
-        states = [(W.gaussian_panel(rb, 2 ** x.n), W.gaussian_panel(rb, 2 ** x.n)) for x in wl]
-        bases = {x.n: q.Basis(x.n) for x in wl}
-        systems = [q.System(bases[x.n], x.h0, x.hk) for x in wl]
-        Pb = q.Plan.batched(systems, "c64", [x.N for x in wl], [x.dt for x in wl], 1.0)
-        ub = [torch.tensor(x.u, device="cuda") for x in wl]
-        p0 = [torch.tensor(st[0], device="cuda") for st in states]
-        pf = [torch.tensor(st[1], device="cuda") for st in states]
-        uflat = torch.cat([x.reshape(-1) for x in ub])
-        Pb.autotune(uflat)
-        sizes = [m for x in wl for m in bases[x.n].sizes]
-        units_b = sum(len(bases[x.n].sizes) * x.N for x in wl)
-        batch = profiled_leg(q, torch, Pb, lambda: q.fidelity_grad_batched(Pb, ub, p0, pf, check=False), 2, 1, uflat,
-                             sizes, units_b)
-        batch.update({"workload": "batch_rings_prefix", "problems": len(wl), "n": [x.n for x in wl],
-                      "slices": [x.N for x in wl]})
-        print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
-        del Pb, systems, bases
-        torch.cuda.empty_cache()
+    ring14 = ring14_leg(q, torch, W, args.ring14_slices) if args.ring14_slices > 0 else None
+    batch = batch_leg(q, torch, W, args.batch_problems) if args.batch_problems > 0 else None
 
     gemm_ms, gemm_n = prof32["propagator_gemm"]
     achieved = flops32 * args.steps / (gemm_ms * 1e-3) / 1e12
-    fp64 = cmp = None
+    fp64 = cmp = par64 = None
+    par32 = parity("ring12_D12_allblocks_N1000.txt", out32[0].item(), grad32.cpu().numpy())
     if args.fp64_steps > 0:
         P64 = q.Plan(S, "c128", w.N, w.dt, 2.0)
         tune64 = P64.autotune(dev["u"])
@@ -648,6 +854,7 @@ def main():
                 "gemm_variant": var64, "autotune_ms": tune64[1]}
         cmp = {"speedup": ms64 / ms32, "dF": abs(out32[0].item() - out64[0].item()),
                "grad_rel_err": float((grad32.cpu() - g64).abs().max() / g64.abs().max()), "F64": out64[0].item()}
+        par64 = parity("ring12_D12_allblocks_N1000.txt", out64[0].item(), g64.numpy())
 
     traffic = None
     if kernel_sources_sha1() == TRAFFIC["sources_sha1"] and var32 in TRAFFIC["kib"]:
@@ -680,6 +887,8 @@ def main():
                      "note": "algorithmic flops 8 m^3 per complex m x m product, 4 m^2 (m + 1) for the "
                              "(skew-)Hermitian powers of the generator (lower triangle; the upper is mirrored); "
                              "the kernel forms each with three real MFMA products (Gauss): 3/4 of them executed"},
+        "parity": {"c64": par32, "c128": par64,
+                   "bounds": "c64: |dF| <= 1e-6; c128: |dF| and max grad error <= 1e-12 (FP64 oracle)"},
         "fp64": fp64,
         "fp32_vs_fp64": cmp,
         "kernel_ms_per_step": {k: v[0] / args.steps for k, v in prof32.items()},
@@ -698,7 +907,7 @@ def main():
         line["lts"] = lts
     if not args.no_cpu_baseline:
         print("[bench] oracle sample on the host ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w, v0, vf, args.cpu_slices)
+        line["cpu_baseline"] = cpu_baseline(w, v0, vf, args.cpu_slices, args.cpu_slices_1t)
     print(json.dumps(line), flush=True)
 
 

@@ -20,7 +20,7 @@ from . import _capi as C
 from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "fidelity", "fidelity_batched",
-           "read_state", "check_flags", "propagate", "GrapeFidelity", "SWEEP_SOLO", "SWEEP_TEST_STALL_FWD", "SWEEP_TEST_STALL_BWD",
+           "read_state", "check_flags",  "propagate", "GrapeFidelity", "SWEEP_SOLO", "SWEEP_TEST_STALL_FWD", "SWEEP_TEST_STALL_BWD",
            "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
            "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply",
            "lts_fidelity_grad", "optimize_lbfgs_lts"]

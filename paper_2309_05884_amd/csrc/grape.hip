@@ -2660,16 +2660,23 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     budget = std::min<size_t>((size_t)240 << 30, free_b / 20 * 17);
   }
   while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice + per_scratch > budget) chunk /= 2;
-  // a smaller gradient chunk (down to 128 slices) is preferred when it lets every
-  // propagator stay resident (no recompute in the backward sweep)
+  // A smaller gradient chunk (down to 16 slices: more, narrower gradient launches, the same
+  // work) is preferred when it lets every propagator stay resident (no recompute in the
+  // backward sweep).  When the propagators must be segmented anyway, the gradient slots
+  // take at most an eighth of the budget, so that the segments stay long: each segment
+  // costs a round of launches and every segment but the last is formed twice.
   const long long ec_min = std::min(P->Nmax, 8);
   auto resident = [&](int ch) {
     return fixed + grad_bytes(ch) + (size_t)P->Nmax * per_slice + (size_t)ec_min * per_scratch <= budget;
   };
   if (!resident(chunk)) {
     int ch = chunk;
-    while (ch > 128 && !resident(ch)) ch /= 2;
-    if (resident(ch)) chunk = ch;
+    while (ch > 16 && !resident(ch)) ch /= 2;
+    if (resident(ch)) {
+      chunk = ch;
+    } else {
+      while (chunk > 16 && grad_bytes(chunk) > budget / 8) chunk /= 2;
+    }
   }
   P->chunk = chunk;
   const size_t need = fixed + grad_bytes(chunk);

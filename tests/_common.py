@@ -42,6 +42,20 @@ def oracle_blocks(n, h0, hk, group="dihedral", stride=1):
     return grape.block_system(n, h0, hk, group, stride, "convention")
 
 
+# FP32 (complex64) gradient bound relative to max|g|.  Each complex64 propagator carries a
+# relative rounding error of about u32 sqrt(m) per product (u32 = 6e-8) over ~4 products;
+# the states accumulate it over N slices like a random walk, sqrt(N) * 4e-7 ~ 1e-5 at
+# N = 1000 in the worst block, and the gradient inherits it relative to its own size.
+# Measured on the 12-qubit ring (1000 slices, blocks up to 346): 4.1e-6 max|g|; on the
+# 500-slice S_128 candidates and the ragged ring batch: at most 6e-6.  The bound leaves a
+# factor ~3-5 over the measured errors.
+FP32_GRAD_REL = 2e-5
+
+
+def fp32_grad_tol(gmax):
+    return FP32_GRAD_REL * gmax + 1e-9
+
+
 GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 

@@ -7,7 +7,7 @@ import pytest
 import qoc_workloads as W
 from oracle import counts
 from oracle import grape as og
-from tests._common import panels_from_flat, read_golden
+from tests._common import fp32_grad_tol, panels_from_flat, read_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,10 @@ def _oracle(w, v0, vf):
 
 
 def test_ring_batch_prefix(lib):
-    """Problems 0..8 of the 256-ring workload (n = 14, 12, 12, 10, 10, 8, 8, 8, 8), FP32."""
+    """Problems 0..8 of the 256-ring workload (n = 14, 12, 12, 10, 10, 8, 8, 8, 8; 424-1745
+    slices) in one FP32 plan, every problem against the FP64 oracle: problems 0, 1, 2 and 4
+    against values stored by tests/golden/make_golden.py (their oracle runs take minutes to an
+    hour), the others against the oracle run here."""
     import torch
     print("ring batch prefix", flush=True)
     ws, rng = W.config3_list(seed=0)
@@ -47,24 +50,18 @@ def test_ring_batch_prefix(lib):
     for p, w in enumerate(ws):
         g = grads[p].cpu().numpy()
         assert out[p, 7] == 0
-        if w.n <= 10 and w.N < 1000:
-            ref = _oracle(w, *states[p])
-        elif w.n <= 8:
-            ref = _oracle(w, *states[p])
+        if p in (0, 1, 2, 4):
+            vals, gref = read_golden(f"batch256_p{p}_n{w.n}_N{w.N}.txt")
+            ref = {"F": vals["F"], "grad": gref}
         else:
-            # larger rings: the FP64 single-problem path (itself checked against the oracle)
-            S1 = systems[p]
-            P1 = lib.Plan(S1, "c128", w.N, w.dt, 1.0, max_workspace_bytes=60 << 30)
-            o1, g1 = lib.fidelity_grad(P1, torch.tensor(w.u, device="cuda"), torch.tensor(states[p][0], device="cuda"),
-                                       torch.tensor(states[p][1], device="cuda"))
-            ref = {"F": o1[0].item(), "grad": g1.cpu().numpy()}
-            del P1
-            torch.cuda.empty_cache()
+            ref = _oracle(w, *states[p])
         dF = abs(out[p, 0] - ref["F"])
         dg = np.abs(g - ref["grad"]).max()
-        print(f"  problem {p} n={w.n} N={w.N}: |dF|={dF:.2e} max|dg|={dg:.2e}", flush=True)
+        gmax = np.abs(ref["grad"]).max()
+        print(f"  problem {p} n={w.n} N={w.N}: |dF|={dF:.2e} max|dg|={dg:.2e} ({dg / gmax:.2e} of max|g|)",
+              flush=True)
         assert dF <= 1e-6
-        assert dg <= 2e-4 * np.abs(ref["grad"]).max() + 1e-7
+        assert dg <= fp32_grad_tol(gmax)
 
 
 def test_small_batch_fp64_exact(lib):
@@ -120,7 +117,7 @@ def test_symmetric_candidates(lib, prec):
     for c in (0, 5):
         vals, gref = read_golden(f"sym128_C8_cand{c}_N{w.N}.txt")
         g = grads[c].cpu().numpy()
-        tg = 1e-12 if prec == "c128" else 2e-4 * np.abs(gref).max() + 1e-7
+        tg = 1e-12 if prec == "c128" else fp32_grad_tol(np.abs(gref).max())
         print(f"  candidate {c}: |dF|={abs(out[c, 0].item() - vals['F']):.2e} "
               f"max|dg|={np.abs(g - gref).max():.2e}", flush=True)
         assert abs(out[c, 0].item() - vals["F"]) <= tf

@@ -6,11 +6,13 @@ import numpy as np
 import pytest
 
 import qoc_workloads as W
+from oracle import grape as og
+from tests._common import FP32_GRAD_REL, oracle_blocks, panels_from_flat
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec,tf,tg", [("c128", 1e-12, 1e-12), ("c64", 1e-6, 2e-4)])
+@pytest.mark.parametrize("prec,tf,tg", [("c128", 1e-12, 1e-12), ("c64", 1e-6, FP32_GRAD_REL)])
 def test_dense_equals_blocks(lib, prec, tf, tg):
     import torch
     n, N, dt = 10, 8, 0.02
@@ -36,4 +38,12 @@ def test_dense_equals_blocks(lib, prec, tf, tg):
     dg = (gd - gb).abs().max().item()
     print(f"  F {ob[0].item():.12f}  |dF| {dF:.2e}  max|dg| {dg:.2e}", flush=True)
     assert dF <= tf
-    assert dg <= tg * (gb.abs().max().item() if prec == "c64" else 1.0) + (1e-7 if prec == "c64" else 0.0)
+    assert dg <= tg * (gb.abs().max().item() if prec == "c64" else 1.0) + (1e-9 if prec == "c64" else 0.0)
+    # both against the oracle's block route
+    blocks = oracle_blocks(n, h0, hk)
+    ref = og.fidelity_grad(blocks, u.cpu().numpy(), dt, panels_from_flat(blocks, p0.cpu().numpy()),
+                           panels_from_flat(blocks, pf.cpu().numpy()))
+    gmax = np.abs(ref["grad"]).max()
+    for o, g in ((ob, gb), (od, gd)):
+        assert abs(o[0].item() - ref["F"]) <= tf
+        assert np.abs(g.cpu().numpy() - ref["grad"]).max() <= (tg * gmax + 1e-9 if prec == "c64" else tg)

@@ -1,14 +1,15 @@
 """Objective and exact gradient on the device (Eqs. (3)-(4); App. B) against the FP64 oracle.
 
 Tolerances: FP64 |dF| <= 1e-12 and gradient error <= 1e-12 (absolute; gradients are
-O(1e-2)); FP32: |dF| <= 1e-6 and gradient error <= 2e-4 * max|g| + 1e-7, from FP32
-rounding of U_j (relative ~1e-7 per slice, growing like sqrt(N)) entering the costates."""
+O(1e-2)); FP32: |dF| <= 1e-6 and gradient error <= 2e-5 * max|g| (tests/_common.py gives the
+derivation), from FP32 rounding of U_j (relative ~1e-7 per slice, growing like sqrt(N))
+entering the costates."""
 import numpy as np
 import pytest
 
 import qoc_workloads as W
 from oracle import grape as og
-from tests._common import all_states, flat_from_panels, oracle_blocks, plain_states
+from tests._common import all_states, flat_from_panels, fp32_grad_tol, oracle_blocks, plain_states
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +30,7 @@ def _device(lib, n, group, stride, h0, hk, u, dt, psi0, psif, prec, max_ws=0, u_
 def _tol(prec, g):
     if prec == "c128":
         return 1e-12, 1e-12
-    return 1e-6, 2e-4 * np.abs(g).max() + 1e-7
+    return 1e-6, fp32_grad_tol(np.abs(g).max())
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
