@@ -10,7 +10,7 @@ import pytest
 import qoc_workloads as W
 from oracle import basis as obasis
 from oracle import closed_form
-from tests._common import read_golden
+from tests._common import fp32_grad_tol, read_golden
 
 pytestmark = pytest.mark.gpu
 
