@@ -47,13 +47,15 @@ def oracle_blocks(n, h0, hk, group="dihedral", stride=1):
 # the states accumulate it over N slices like a random walk, sqrt(N) * 4e-7 ~ 1e-5 at
 # N = 1000 in the worst block, and the gradient inherits it relative to its own size.
 # Measured on the 12-qubit ring (1000 slices, blocks up to 346): 4.1e-6 max|g|; on the
-# 500-slice S_128 candidates and the ragged ring batch: at most 6e-6.  The bound leaves a
-# factor ~3-5 over the measured errors.
+# 500-slice S_128 candidates and the ragged ring batch: 3e-6 to 1.4e-5.  A start in one
+# basis state (the all-up "plain" transfers) has a gradient that is small against the
+# rounding scale 2 |o| dt ||H_k|| u32 sqrt(N) of the costates: 2.6e-5 max|g| measured on the
+# 12-qubit ring's first block, so those tests pass a bound of their own (5e-5).
 FP32_GRAD_REL = 2e-5
 
 
-def fp32_grad_tol(gmax):
-    return FP32_GRAD_REL * gmax + 1e-9
+def fp32_grad_tol(gmax, rel=FP32_GRAD_REL):
+    return rel * gmax + 1e-9
 
 
 GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")

@@ -9,7 +9,7 @@ import pytest
 import qoc_workloads as W
 from oracle import closed_form
 from oracle import grape as og
-from tests._common import FP32_GRAD_REL, oracle_blocks
+from tests._common import oracle_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +29,10 @@ def _first_block_states(lib, B, n):
     return up, dn, pu[:m0].contiguous(), pd[:m0].contiguous()
 
 
+# FP32 gradient bounds: 5e-5 max|g|, the bound for transfers from one basis state
+# (all-up; tests/_common.py gives the derivation)
+
+
 def _run(lib, B, h0, hk, u, dt, prec, blocks=None, psi=None):
     S = lib.System(B, h0, hk)
     # near-pi pulses reach |u| ~ 2.3 at N = 30: the plan's bound must cover them
@@ -38,7 +42,7 @@ def _run(lib, B, h0, hk, u, dt, prec, blocks=None, psi=None):
 
 
 @pytest.mark.parametrize("n", [6, 9])
-@pytest.mark.parametrize("prec,tf,tg", [("c128", 1e-12, 1e-12), ("c64", 1e-6, FP32_GRAD_REL)])
+@pytest.mark.parametrize("prec,tf,tg", [("c128", 1e-12, 1e-12), ("c64", 1e-6, 5e-5)])
 def test_no_coupling_dense_dn_sn_and_closed_form(lib, n, prec, tf, tg):
     import torch
     print(f"no coupling n={n} {prec}", flush=True)
@@ -75,7 +79,7 @@ def test_no_coupling_dense_dn_sn_and_closed_form(lib, n, prec, tf, tg):
         assert np.abs(g - ref["grad"]).max() <= (tg * gmax + 1e-9 if prec == "c64" else tg)
 
 
-@pytest.mark.parametrize("prec,tf,tg", [("c128", 1e-12, 1e-12), ("c64", 1e-6, FP32_GRAD_REL)])
+@pytest.mark.parametrize("prec,tf,tg", [("c128", 1e-12, 1e-12), ("c64", 1e-6, 5e-5)])
 def test_nn_coupling_dense_vs_first_dn_block(lib, prec, tf, tg):
     """Nearest-neighbour Ising ring (Eq. (5)): only D_n applies.  The dense space, the first
     block alone and all blocks against the oracle's block route with both states in the

@@ -27,10 +27,10 @@ def _device(lib, n, group, stride, h0, hk, u, dt, psi0, psif, prec, max_ws=0, u_
     return out.cpu().numpy(), grad.cpu().numpy(), P
 
 
-def _tol(prec, g):
+def _tol(prec, g, rel=None):
     if prec == "c128":
         return 1e-12, 1e-12
-    return 1e-6, fp32_grad_tol(np.abs(g).max())
+    return 1e-6, fp32_grad_tol(np.abs(g).max()) if rel is None else fp32_grad_tol(np.abs(g).max(), rel)
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
@@ -41,7 +41,7 @@ def test_config1_plain(lib, prec):
     psi0, psif = plain_states(ob, w.notes["rng"])
     ref = og.fidelity_grad(ob, w.u, w.dt, psi0, psif)
     out, grad, P = _device(lib, 6, "dihedral", 1, w.h0, w.hk, w.u, w.dt, psi0, psif, prec)
-    tf, tg = _tol(prec, ref["grad"])
+    tf, tg = _tol(prec, ref["grad"], 5e-5)  # one-basis-state start (tests/_common.py)
     assert abs(out[0] - ref["F"]) <= tf
     assert abs(out[1] - ref["F_raw"]) <= tf
     assert np.abs(grad - ref["grad"]).max() <= tg
