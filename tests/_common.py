@@ -58,6 +58,19 @@ def fp32_grad_tol(gmax, rel=FP32_GRAD_REL):
     return rel * gmax + 1e-9
 
 
+def plan_with_segments(lib, S, prec, N, dt, u_bound, min_segments=2, budget_frac=0.3):
+    """A plan whose workspace budget forces at least min_segments segments (propagators
+    of earlier segments recomputed in the backward sweep)."""
+    full = lib.Plan(S, prec, N, dt, u_bound).workspace_bytes
+    frac = budget_frac
+    while True:
+        P = lib.Plan(S, prec, N, dt, u_bound, int(full * frac))
+        if P.info["segments"] >= min_segments:
+            return P
+        frac *= 0.7
+        assert frac > 1e-4
+
+
 GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 

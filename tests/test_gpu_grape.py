@@ -9,7 +9,7 @@ import pytest
 
 import qoc_workloads as W
 from oracle import grape as og
-from tests._common import all_states, flat_from_panels, fp32_grad_tol, oracle_blocks, plain_states
+from tests._common import all_states, flat_from_panels, fp32_grad_tol, oracle_blocks, plain_states, plan_with_segments
 
 pytestmark = pytest.mark.gpu
 
@@ -119,7 +119,7 @@ def test_segmented_recompute_matches(lib):
     psi0, psif = all_states(ob, np.random.default_rng(4))
     ref = og.fidelity_grad(ob, w.u, w.dt, psi0, psif)
     out1, g1, P1 = _device(lib, 6, "dihedral", 1, w.h0, w.hk, w.u, w.dt, psi0, psif, "c128")
-    small = P1.workspace_bytes - 40 * P1.info["bytes_per_slice"]
+    small = plan_with_segments(lib, P1.system, "c128", w.N, w.dt, float(np.abs(w.u).max())).workspace_bytes
     out2, g2, P2 = _device(lib, 6, "dihedral", 1, w.h0, w.hk, w.u, w.dt, psi0, psif, "c128", max_ws=small)
     assert P2.info["segments"] > 1
     assert abs(out2[0] - ref["F"]) <= 1e-12

@@ -14,7 +14,7 @@ import pytest
 
 import qoc_workloads as W
 from oracle import grape as og
-from tests._common import all_states, flat_from_panels, oracle_blocks
+from tests._common import all_states, flat_from_panels, oracle_blocks, plan_with_segments
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +41,7 @@ def test_objective_only_equals_full_call(lib, prec):
     out_obj = lib.fidelity(P, u, p0, pf)
     assert torch.equal(out_full[:6], out_obj[:6]) and out_obj[7].item() == 0
     # a segmented plan: the forward pass forms each segment once
-    Ps = lib.Plan(S, prec, w.N, w.dt, 2.0, int(P.workspace_bytes * 0.3))
-    assert Ps.info["segments"] > 1
+    Ps = plan_with_segments(lib, S, prec, w.N, w.dt, 2.0)
     out_seg = lib.fidelity(Ps, u, p0, pf)
     assert torch.equal(out_seg[:6], out_full[:6])
     if prec == "c128":
@@ -80,8 +79,7 @@ def test_state_invariants_and_slice_local_differences(lib, prec, segmented):
     n, N = 8, 30
     w, ob, psi0, psif, B, S, P, (u, p0, pf) = _ring(lib, n, N, 2, prec)
     if segmented:
-        P = lib.Plan(S, prec, N, w.dt, 2.0, int(P.workspace_bytes * 0.3))
-        assert P.info["segments"] > 1
+        P = plan_with_segments(lib, S, prec, N, w.dt, 2.0)
     out, grad = lib.fidelity_grad(P, u, p0, pf)
     o = complex(out[2].item(), out[3].item())
     tol = 1e-12 if prec == "c128" else 2e-5

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import qoc_workloads as W
-from tests._common import read_golden
+from tests._common import plan_with_segments, read_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -37,20 +37,6 @@ def _ring14(lib, N):
     return w, B, S, dev
 
 
-def _plan_with_segments(lib, S, prec, N, dt, u_bound, min_segments, budget_frac=0.3):
-    """A plan whose workspace budget forces at least min_segments segments."""
-    P1 = lib.Plan(S, prec, N, dt, u_bound)
-    full = P1.workspace_bytes
-    del P1
-    frac = budget_frac
-    while True:
-        P = lib.Plan(S, prec, N, dt, u_bound, int(full * frac))
-        if P.info["segments"] >= min_segments:
-            return P
-        frac *= 0.7
-        assert frac > 1e-4
-
-
 def _check(prec, out, grad, vals, gref):
     dF = abs(out[0] - vals["F"])
     dg = np.abs(grad - gref).max()
@@ -76,7 +62,7 @@ def test_ring12_segmented_cooperative_matches_oracle(lib):
     o1, g1 = o1.cpu().numpy(), g1.cpu().numpy()
     del P1
     torch.cuda.empty_cache()
-    P = _plan_with_segments(lib, S, "c64", w.N, w.dt, 2.0, 3)
+    P = plan_with_segments(lib, S, "c64", w.N, w.dt, 2.0, 3)
     print(f"  plan {P.info}", flush=True)
     assert P.info["sweep_groups"] > 1
     o, g = lib.fidelity_grad(P, u, v0, vf)
@@ -97,7 +83,7 @@ def test_ring14_two_site_group_segmented(lib, prec):
     N = 8
     w, B, S, (u, v0, vf) = _ring14(lib, N)
     vals, gref = read_golden(f"ring14_T2R_allblocks_N{N}.txt")
-    P = _plan_with_segments(lib, S, prec, N, w.dt, 2.0, 3, budget_frac=0.4)
+    P = plan_with_segments(lib, S, prec, N, w.dt, 2.0, 3, budget_frac=0.4)
     print(f"  plan {P.info}", flush=True)
     o, g = lib.fidelity_grad(P, u, v0, vf)
     _check(prec, o.cpu().numpy(), g.cpu().numpy(), vals, gref)
@@ -150,7 +136,7 @@ def test_sweep_stall_is_reported(lib, stall, segmented):
     w, B, S, (u, v0, vf) = _ring12(lib)
     N = 64
     u = u[:N].contiguous()
-    P = _plan_with_segments(lib, S, "c64", N, w.dt, 2.0, 3) if segmented else lib.Plan(S, "c64", N, w.dt, 2.0)
+    P = plan_with_segments(lib, S, "c64", N, w.dt, 2.0, 3) if segmented else lib.Plan(S, "c64", N, w.dt, 2.0)
     assert P.info["sweep_groups"] > 1
     P.set_sweep_mode(lib.SWEEP_TEST_STALL_FWD if stall == "fwd" else lib.SWEEP_TEST_STALL_BWD)
     out, _ = lib.fidelity_grad(P, u, v0, vf, check=False)
