@@ -250,6 +250,22 @@ qoc_status qoc_fidelity_grad(qoc_plan plan, const double* u_dev, const void* psi
 qoc_status qoc_fidelity(qoc_plan plan, const double* u_dev, const void* psi0_dev, const void* psif_dev,
                         double* out_dev, void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, hosts that forbid hipMalloc): qoc_fidelity_grad with its workspace taken
+ * from a static device array of QOC_STATIC_SCRATCH_BYTES (64 MiB) that the library's code
+ * object holds on every GPU it runs on until the process ends.  The call allocates nothing
+ * (no hipMalloc / hipFree or allocating library routine); the caller still passes the
+ * inputs and outputs, laid out as for qoc_fidelity_grad, with the same results.  The plan's
+ * workspace must fit (create it with max_workspace_bytes <= QOC_STATIC_SCRATCH_BYTES; a
+ * smaller budget only means more segments), else QOC_ERR_OUT_OF_MEMORY before any device
+ * work.  Every call on one GPU shares that GPU's array and leaves its contents behind;
+ * what a call needs zeroed it clears itself.  Calls that overlap on one GPU (two streams,
+ * two threads, or this call beside a qoc_fidelity_grad_noalloc of another plan) race on
+ * the array: serialise them.  Asynchronous on `stream`, like qoc_fidelity_grad. */
+#define QOC_STATIC_SCRATCH_BYTES (64ull << 20)
+qoc_status qoc_fidelity_grad_noalloc(qoc_plan plan, const double* u_dev, const void* psi0_dev, const void* psif_dev,
+                                     double* out_dev, double* grad_dev, void* stream);
+
 /* One state of the sweeps of the last qoc_fidelity_grad (or, for which = 0, qoc_fidelity)
  * call that used `workspace` with this plan (Eq. (3): psi_{j+1} = U_j psi_j; App. B:
  * lambda_j = U_j^dag lambda_{j+1}, lambda_N = psi_f): which = 0 the forward state psi_j,

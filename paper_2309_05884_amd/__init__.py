@@ -20,7 +20,7 @@ from . import _capi as C
 from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "fidelity", "fidelity_batched",
-           "read_state", "check_flags",  "propagate", "GrapeFidelity", "SWEEP_SOLO", "SWEEP_TEST_STALL_FWD", "SWEEP_TEST_STALL_BWD",
+           "read_state", "check_flags", "fidelity_grad_noalloc", "STATIC_SCRATCH_BYTES", "propagate", "GrapeFidelity", "SWEEP_SOLO", "SWEEP_TEST_STALL_FWD", "SWEEP_TEST_STALL_BWD",
            "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
            "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply",
            "lts_fidelity_grad", "optimize_lbfgs_lts"]
@@ -30,6 +30,9 @@ library_path = C.LIB_PATH
 # co-operative sweep switches of qoc_plan_set_sweep_mode (tests of the fallback and of the
 # stall handling; 0 in normal use)
 SWEEP_SOLO, SWEEP_TEST_STALL_FWD, SWEEP_TEST_STALL_BWD = 1, 2, 4
+# size of the library's static device scratch (QOC_STATIC_SCRATCH_BYTES): the largest plan
+# workspace qoc_fidelity_grad_noalloc accepts
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def _torch():
@@ -353,6 +356,24 @@ def read_state(plan: Plan, which: str, j: int, problem: int = 0, workspace=None)
     C.check(C.lib().qoc_plan_read_state(plan._h, int(problem), {"psi": 0, "lambda": 1}[which], int(j), _ptr(ws),
                                         ctypes.c_size_t(ws.numel()), _ptr(out), _stream()))
     return out
+
+
+def fidelity_grad_noalloc(plan: Plan, u, psi0, psif, out, grad):
+    """qoc_fidelity_grad_noalloc: objective and gradient of a one-problem plan with the
+    library's static device scratch as workspace (the call allocates nothing).  out (8
+    float64) and grad (N, K float64) are caller-allocated device tensors, written in place;
+    u, psi0 and psif must already be contiguous device tensors of the right dtype."""
+    torch = _torch()
+    assert plan.P == 1
+    assert u.dtype == torch.float64 and u.is_contiguous() and u.shape == (plan.N, plan.K)
+    assert psi0.dtype == torch.complex128 and psif.dtype == torch.complex128
+    assert psi0.is_contiguous() and psif.is_contiguous()
+    assert psi0.numel() == plan.info["total_panel"] == psif.numel()
+    assert out.dtype == torch.float64 and out.numel() >= 8 and out.is_contiguous()
+    assert grad.dtype == torch.float64 and grad.numel() == plan.N * plan.K and grad.is_contiguous()
+    C.check(C.lib().qoc_fidelity_grad_noalloc(plan._h, _ptr(u), _ptr(psi0), _ptr(psif), _ptr(out), _ptr(grad),
+                                              _stream()))
+    return out, grad
 
 
 def fidelity_grad_batched(plan: Plan, us, psi0s, psifs, workspace=None, check=True):

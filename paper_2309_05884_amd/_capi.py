@@ -76,6 +76,7 @@ PROTOTYPES = {
     "qoc_propagate": (ctypes.c_int, [vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_fidelity_grad": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
     "qoc_fidelity": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]),
+    "qoc_fidelity_grad_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
     "qoc_plan_read_state": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp,
                                            vp]),
     "qoc_plan_set_sweep_mode": (ctypes.c_int, [vp, ctypes.c_int]),

@@ -3016,6 +3016,52 @@ qoc_status qoc_fidelity(qoc_plan P, const double* u_dev, const void* psi0_dev, c
   });
 }
 
+}  // extern "C"
+
+namespace qoc {
+// Device memory of qoc_fidelity_grad_noalloc: a file-scope array that the code object
+// brings with it, so the call itself allocates nothing.  Its host-side name is not a device
+// address: host code uses only the per-device address from hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[QOC_STATIC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[256] = {};
+
+// The calling thread's current device's copy of `scratch`, looked up once per device.
+static char* static_scratch() {
+  int dev = 0;
+  QOC_HIP(hipGetDevice(&dev));
+  QOC_REQUIRE(dev >= 0 && dev < 256, QOC_ERR_DEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    QOC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    QOC_REQUIRE(ptr != nullptr, QOC_ERR_DEVICE, "no device address for the static scratch array");
+    g_scratch_ptr[dev] = static_cast<char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace qoc
+
+extern "C" {
+
+qoc_status qoc_fidelity_grad_noalloc(qoc_plan P, const double* u_dev, const void* psi0_dev, const void* psif_dev,
+                                     double* out_dev, double* grad_dev, void* stream) {
+  return guarded([&] {
+    QOC_REQUIRE(P && u_dev && psi0_dev && psif_dev && out_dev && grad_dev, QOC_ERR_INVALID_ARG, "null argument");
+    QOC_REQUIRE(P->bytes <= (size_t)QOC_STATIC_SCRATCH_BYTES, QOC_ERR_OUT_OF_MEMORY,
+                "the plan's workspace (" + std::to_string(P->bytes) + " bytes) exceeds the library's static " +
+                    "scratch of " + std::to_string((size_t)QOC_STATIC_SCRATCH_BYTES) +
+                    " bytes: create the plan with max_workspace_bytes <= QOC_STATIC_SCRATCH_BYTES");
+    char* ws = static_scratch();
+    hipStream_t st = (hipStream_t)stream;
+    if (P->prec == QOC_C128)
+      Driver<double>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, ws, st);
+    else
+      Driver<float>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, ws, st);
+  });
+}
+
 qoc_status qoc_plan_read_state(qoc_plan P, int problem, int which, int j, const void* workspace, size_t ws_bytes,
                                void* out_dev, void* stream) {
   return guarded([&] {
