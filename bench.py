@@ -152,15 +152,18 @@ def gemm_flops_jobs(q, plan, u_flat, job_sizes):
     return tot
 
 
-def executed_flops_jobs(q, plan, u_flat, job_sizes):
+def executed_flops_jobs(q, plan, u_flat, job_sizes, job_problem=None):
     """(algorithmic, executed) propagator GEMM flops of one fidelity+gradient call: the
-    executed count adds the slices recomputed in the backward sweep of a segmented plan (a
-    job recomputes every segment before its own last one)."""
+    executed count adds the slices recomputed in the backward sweep of a segmented plan or
+    problem group (a job recomputes every segment of its group before its own last one).
+    job_problem: the problem of each job (batched plans)."""
     qs, ss, _ = q.slice_stats(plan, u_flat)
     r = plan.info["taylor_step"]
-    L = plan.info["segment"]
+    groups = plan.groups()
     alg = ex = 0.0
     for b, m in enumerate(job_sizes):
+        p = 0 if job_problem is None else job_problem[b]
+        L = [sl for (p0, sl, _) in groups if p0 <= p][-1]
         valid = np.where(qs[b] >= 0)[0]
         if valid.size == 0:
             continue
@@ -215,7 +218,7 @@ def one_step(torch, run):
     return e0.elapsed_time(e1), res
 
 
-def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, precision="c64"):
+def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, precision="c64", job_problem=None):
     """Time `steps` calls of run() after `warmup`, with the library's per-kernel events;
     returns throughput and the propagator GEMM's fraction of the MFMA peak."""
     for _ in range(warmup):
@@ -230,7 +233,7 @@ def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, p
     torch.cuda.synchronize()
     prof = q.profile_end()
     ms = e0.elapsed_time(e1) / steps
-    flops, ex_flops = executed_flops_jobs(q, plan, u_flat, job_sizes)
+    flops, ex_flops = executed_flops_jobs(q, plan, u_flat, job_sizes, job_problem)
     gemm_ms, gemm_n = prof["propagator_gemm"]
     tf = flops * steps / (gemm_ms * 1e-3) / 1e12
     tfx = ex_flops * steps / (gemm_ms * 1e-3) / 1e12
@@ -239,7 +242,8 @@ def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, p
             "gemm_tflops_with_recompute": tfx, "gemm_frac_with_recompute": tfx / MFMA_PEAK[precision],
             "gemm_ms_per_step": gemm_ms / steps, "gemm_launches_per_step": gemm_n / steps,
             "gemm_variant": plan.variant_name, "steps": steps, "warmup": warmup, "segments": plan.info["segments"],
-            "segment_slices": plan.info["segment"], "workspace_gb": plan.workspace_bytes / 1e9,
+            "segment_slices": plan.info["segment"], "problem_groups": plan.info["problem_groups"],
+            "groups_segmented": sum(1 for g in plan.groups() if g[2] > 1), "workspace_gb": plan.workspace_bytes / 1e9,
             "kernel_ms_per_step": {k: v[0] / steps for k, v in prof.items() if v[1]}}
 
 
@@ -629,7 +633,9 @@ def sym_leg(q, torch, W, C):
     def run():
         res["out"], res["grads"] = q.fidelity_grad_batched(Ps, us, p0, pf, check=False)
 
-    sym = profiled_leg(q, torch, Ps, run, 1, 0, uflat, list(Bs.sizes) * C, C * len(Bs.sizes) * ws.N)
+    nb = len(Bs.sizes)
+    sym = profiled_leg(q, torch, Ps, run, 1, 0, uflat, list(Bs.sizes) * C, C * nb * ws.N,
+                       job_problem=[c for c in range(C) for _ in range(nb)])
     out = res["out"]
     for c in range(C):
         q.check_flags(out[c])
@@ -743,7 +749,8 @@ def batch_leg(q, torch, W, Pn):
     def run():
         res["out"], res["grads"] = q.fidelity_grad_batched(Pb, ub, p0, pf, check=False)
 
-    batch = profiled_leg(q, torch, Pb, run, 1, 0, uflat, sizes, units_b)
+    jp = [p for p, x in enumerate(wl) for _ in bases[x.n].sizes]
+    batch = profiled_leg(q, torch, Pb, run, 1, 0, uflat, sizes, units_b, job_problem=jp)
     out = res["out"]
     for p in range(len(wl)):
         q.check_flags(out[p])

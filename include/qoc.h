@@ -196,13 +196,22 @@ qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
  * grid, [10] problems P, [11] (problem, block) jobs, [12] total controls (sum N_p K_p),
  * [13] total panel length (sum D_p), [14] total propagator entries, [15] GEMM tile
  * variant in use, [16] slices per Taylor-scratch chunk, [17] largest number of work-groups
- * sharing one block's sweep (1: one work-group per block).
+ * sharing one block's sweep (1: one work-group per block), [18] problem groups.
  * Workspace: U and U^dag of every slice of a segment, Taylor scratch (Y..Y^r and two
  * ping-pong buffers) of one chunk of slices, states, gradient slots.  When the budget holds
  * everything, segment = chunk = N; when it holds every propagator and the scratch of at
  * least 8 slices, segment = N and the chunk is what the rest holds; otherwise the
- * propagators of earlier segments are recomputed during the backward sweep. */
+ * propagators of earlier segments are recomputed during the backward sweep.
+ * Batched plans: when the propagators of all problems do not fit the budget at once, the
+ * problems are split into groups of consecutive problems whose propagators do fit, run one
+ * after another in the same workspace (nothing is recomputed for them); a problem too large
+ * on its own forms a group that segments.  [0], [1], [8] and [16] then describe the group
+ * with the most segments; qoc_plan_groups lists every group. */
 qoc_status qoc_plan_info(qoc_plan plan, int64_t* info, int cap);
+/* Problem groups of a plan (see qoc_plan_info): *count groups (1 for a plan without
+ * groups); for each of the first `cap`, its first problem, segment length and number of
+ * segments (host arrays; any may be NULL).  Host-only. */
+qoc_status qoc_plan_groups(qoc_plan plan, int* count, int32_t* prob_begin, int32_t* seg_len, int32_t* nseg, int cap);
 
 /* GEMM tile variants.  The propagator and panel GEMMs are compiled for 3 work-group tile
  * shapes per precision (qoc_variant_name: e.g. "fp32 128x64"); every shape accumulates
@@ -229,7 +238,8 @@ qoc_status qoc_propagate(qoc_plan plan, const double* u_dev, void* U_out_dev, vo
  * psi0_dev, psif_dev: block panels (interleaved complex128, length D).
  * out_dev (float64, 8 entries): [0] F = |o|^2 / (||psi_N||^2 ||psi_f||^2),
  * [1] |o|^2, [2] Re o, [3] Im o with o = <psi_f|psi_N>, [4] ||psi_N||^2,
- * [5] ||psi_f||^2, [6] largest squaring count used, [7] status flags (0 = clean;
+ * [5] ||psi_f||^2, [6] largest squaring count used (by all problems of the call, or of the
+ * problem's group when a batched plan has problem groups), [7] status flags (0 = clean;
  * bit 0: a slice exceeded the plan's norm bound; bit 1: non-finite value; bit 2: a
  * co-operative sweep's hand-off between work-groups stalled and the sweep gave up, so
  * the outputs are invalid).

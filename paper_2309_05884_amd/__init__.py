@@ -137,7 +137,8 @@ class Plan:
 
     INFO_KEYS = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
                  "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid", "problems", "jobs",
-                 "total_controls", "total_panel", "total_propagator", "gemm_variant", "expm_chunk", "sweep_groups"]
+                 "total_controls", "total_panel", "total_propagator", "gemm_variant", "expm_chunk", "sweep_groups",
+                 "problem_groups"]
     N_VARIANTS = 3
 
     def __init__(self, system: System, precision: str = "c128", N: int = 1, dt: float = 0.01,
@@ -211,6 +212,17 @@ class Plan:
         """Block sizes m of a one-problem plan, in plan order (the subset when blocks= was given)."""
         sizes = self.systems[0].basis.sizes
         return list(sizes) if self.blocks is None else [sizes[b] for b in self.blocks]
+
+    def groups(self):
+        """Problem groups (qoc_plan_groups): [(first problem, segment length, segments)]."""
+        L = C.lib()
+        n = ctypes.c_int()
+        C.check(L.qoc_plan_groups(self._h, ctypes.byref(n), None, None, None, 0))
+        b0 = (ctypes.c_int32 * n.value)()
+        sl = (ctypes.c_int32 * n.value)()
+        ns = (ctypes.c_int32 * n.value)()
+        C.check(L.qoc_plan_groups(self._h, ctypes.byref(n), b0, sl, ns, n.value))
+        return [(int(b0[g]), int(sl[g]), int(ns[g])) for g in range(n.value)]
 
     def set_sweep_mode(self, mode: int):
         """Co-operative sweep switches (SWEEP_SOLO, SWEEP_TEST_STALL_FWD / _BWD bits; 0 = normal)."""

@@ -174,7 +174,14 @@ struct qoc_plan_s {
   int ncu = 256;
   hipStream_t st2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // A batched plan whose propagators do not all fit the budget at once is run as groups of
+  // consecutive problems, each a plan of its own whose propagators fit (no recompute), one
+  // after another in the same workspace; a problem too large on its own is a group that
+  // segments.  This plan's own tables still describe every job (slice statistics, sizes).
+  std::vector<qoc_plan_s*> groups;
+  std::vector<int> grp_prob0;  // first problem of each group
   ~qoc_plan_s() {
+    for (auto* g : groups) delete g;
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (st2) (void)hipStreamDestroy(st2);
@@ -2541,6 +2548,14 @@ static ProblemSpec all_blocks(qoc_system_s* sys, int N, double dt) {
   return ProblemSpec{sys, N, dt, sys->blocks};
 }
 
+// Default workspace budget: 85 % of the free device memory (the rest for the caller's
+// tensors and the allocator), at most 240 GiB of the 288 GB part.
+static size_t default_budget() {
+  size_t free_b = 0, total_b = 0;
+  QOC_HIP(hipMemGetInfo(&free_b, &total_b));
+  return std::min<size_t>((size_t)240 << 30, free_b / 20 * 17);
+}
+
 static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precision, double u_bound, size_t max_ws) {
   QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
   QOC_REQUIRE(std::isfinite(u_bound) && u_bound >= 0.0, QOC_ERR_INVALID_ARG, "u_bound must be finite and >= 0");
@@ -2651,14 +2666,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       }
     return g;
   };
-  size_t budget = max_ws;
-  if (!budget) {
-    // default: 85 % of the free device memory (the rest for the caller's tensors and the
-    // allocator), at most 240 GiB of the 288 GB part
-    size_t free_b = 0, total_b = 0;
-    QOC_HIP(hipMemGetInfo(&free_b, &total_b));
-    budget = std::min<size_t>((size_t)240 << 30, free_b / 20 * 17);
-  }
+  const size_t budget = max_ws ? max_ws : default_budget();
   while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice + per_scratch > budget) chunk /= 2;
   // A smaller gradient chunk (down to 16 slices: more, narrower gradient launches, the same
   // work) is preferred when it lets every propagator stay resident (no recompute in the
@@ -2849,6 +2857,126 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   return P.release();
 }
 
+// Bytes a group of problems needs with every propagator resident: states, gradient slots
+// for a chunk of `chunk` slices, U and U^dag of every slice, and the Taylor scratch of 8
+// slices (the layout build_plan makes, without the alignment of its regions).
+static size_t resident_bytes(const std::vector<ProblemSpec>& probs, size_t b0, size_t b1, size_t elem, int r,
+                             int nslots, int chunk) {
+  size_t fixed = 0, grad = 0, props = 0, scratch = 0;
+  int nmax = 0;
+  for (size_t p = b0; p < b1; ++p) nmax = std::max(nmax, probs[p].N);
+  for (size_t p = b0; p < b1; ++p) {
+    const auto& pr = probs[p];
+    for (auto& b : pr.blocks) {
+      const size_t mp = (size_t)b.mp;
+      fixed += 2 * mp * ((size_t)(pr.N + 1) * b.d + (size_t)pr.N * b.d) * elem;
+      const size_t cc = (size_t)(std::min(chunk, nmax) * b.d + 15) / 16 * 16;
+      grad += (size_t)nslots * 2 * mp * cc * elem + cc * pr.sys->K * 16;
+      props += (size_t)pr.N * 4 * mp * mp * elem;
+      scratch += (size_t)(r + 2) * 2 * mp * mp * elem;
+    }
+  }
+  return fixed + grad + props + (size_t)std::min(nmax, 8) * scratch;
+}
+
+// Split a batched plan whose propagators do not all fit into groups of consecutive problems
+// that do (see qoc_plan_s::groups).  Greedy in problem order by the estimate above; a group
+// whose plan still segments is halved, down to single problems, which may segment.
+static void group_problems(qoc_plan_s* full, const std::vector<ProblemSpec>& probs, int precision, double u_bound,
+                           size_t budget) {
+  const int nslots = full->Kmax + 4 + full->R * full->Q;  // the whole batch's series: an upper bound
+  const size_t limit = budget / 100 * 97;                  // room for the regions' alignment
+  std::vector<std::pair<size_t, size_t>> todo;
+  for (size_t b0 = 0; b0 < probs.size();) {
+    size_t b1 = b0 + 1;
+    while (b1 < probs.size() &&
+           resident_bytes(probs, b0, b1 + 1, full->elem, full->r, nslots, std::min(full->Nmax, 2048)) <= limit)
+      ++b1;
+    todo.push_back({b0, b1});
+    b0 = b1;
+  }
+  std::vector<std::pair<size_t, qoc_plan_s*>> made;
+  while (!todo.empty()) {
+    const auto [b0, b1] = todo.front();
+    todo.erase(todo.begin());
+    std::vector<ProblemSpec> sub(probs.begin() + b0, probs.begin() + b1);
+    std::unique_ptr<qoc_plan_s> g(build_plan(sub, precision, u_bound, budget));
+    if (g->nseg > 1 && b1 - b0 > 1) {
+      const size_t mid = b0 + (b1 - b0) / 2;
+      todo.insert(todo.begin(), {{b0, mid}, {mid, b1}});
+      continue;
+    }
+    made.push_back({b0, g.release()});
+  }
+  std::sort(made.begin(), made.end());
+  size_t bytes = 0;
+  for (auto& [b0, g] : made) {
+    full->groups.push_back(g);
+    full->grp_prob0.push_back((int)b0);
+    bytes = std::max(bytes, g->bytes);
+  }
+  full->bytes = bytes;
+}
+
+// Group g's share of a batched call's concatenated arrays: controls and gradients, panels,
+// objective outputs and propagators start at its first problem.
+struct GroupOffsets {
+  long long u, D, out, U;
+};
+static GroupOffsets group_offsets(const qoc_plan_s* P, size_t g) {
+  const int p0 = P->grp_prob0[g];
+  const ProbDev& pb = P->probs[p0];
+  const JobDev& jb = P->jobs[pb.job_begin];
+  return {pb.u_off, jb.state_off, 8LL * p0, jb.uout_off};
+}
+
+// The hot-path calls on a plan, group by group when the plan has problem groups.
+static void exec_run(qoc_plan_s* P, const double* u, const void* psi0, const void* psif, double* out, double* grad,
+                     char* ws, hipStream_t st) {
+  if (!P->groups.empty()) {
+    for (size_t g = 0; g < P->groups.size(); ++g) {
+      const GroupOffsets o = group_offsets(P, g);
+      exec_run(P->groups[g], u + o.u, static_cast<const double2*>(psi0) + o.D, static_cast<const double2*>(psif) + o.D,
+               out + o.out, grad + o.u, ws, st);
+    }
+    return;
+  }
+  if (P->prec == QOC_C128)
+    Driver<double>::run(P, u, psi0, psif, out, grad, ws, st);
+  else
+    Driver<float>::run(P, u, psi0, psif, out, grad, ws, st);
+}
+
+static void exec_objective(qoc_plan_s* P, const double* u, const void* psi0, const void* psif, double* out, char* ws,
+                           hipStream_t st) {
+  if (!P->groups.empty()) {
+    for (size_t g = 0; g < P->groups.size(); ++g) {
+      const GroupOffsets o = group_offsets(P, g);
+      exec_objective(P->groups[g], u + o.u, static_cast<const double2*>(psi0) + o.D,
+                     static_cast<const double2*>(psif) + o.D, out + o.out, ws, st);
+    }
+    return;
+  }
+  if (P->prec == QOC_C128)
+    Driver<double>::objective_only(P, u, psi0, psif, out, ws, st);
+  else
+    Driver<float>::objective_only(P, u, psi0, psif, out, ws, st);
+}
+
+static void exec_propagate(qoc_plan_s* P, const double* u, double2* U_out, char* ws, hipStream_t st) {
+  if (!P->groups.empty()) {
+    for (size_t g = 0; g < P->groups.size(); ++g) {
+      const GroupOffsets o = group_offsets(P, g);
+      exec_propagate(P->groups[g], u + o.u, U_out + o.U, ws, st);
+    }
+    return;
+  }
+  if (P->prec == QOC_C128)
+    Driver<double>::propagate(P, u, U_out, ws, st);
+  else
+    Driver<float>::propagate(P, u, U_out, ws, st);
+}
+
 }  // namespace qoc
 
 using namespace qoc;
@@ -2893,7 +3021,10 @@ qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* 
     QOC_REQUIRE(P >= 1 && P <= 65535, QOC_ERR_INVALID_ARG, "P must be in 1..65535");
     std::vector<ProblemSpec> probs;
     for (int p = 0; p < P; ++p) probs.push_back(all_blocks(systems[p], N[p], dt[p]));
-    *out = build_plan(probs, precision, u_bound, max_ws);
+    const size_t budget = max_ws ? max_ws : default_budget();
+    std::unique_ptr<qoc_plan_s> full(build_plan(probs, precision, u_bound, budget));
+    if (full->nseg > 1 && P > 1) group_problems(full.get(), probs, precision, u_bound, budget);
+    *out = full.release();
   });
 }
 
@@ -2911,10 +3042,17 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
     QOC_REQUIRE(P && info, QOC_ERR_INVALID_ARG, "null argument");
     size_t per_slice = 0;
     for (auto& j : P->jobs) per_slice += (size_t)(2 + P->r + 2) * 2 * j.mp * j.mp * P->elem;
-    int64_t v[18] = {P->seg_len, P->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
-                     P->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U,
-                     P->variant, P->echunk, P->coop ? P->coop_w : 1};
-    for (int i = 0; i < cap && i < 18; ++i) info[i] = v[i];
+    // a plan with problem groups reports the execution of the group with the most segments
+    const qoc_plan_s* E = P;
+    int sweep_groups = P->coop ? P->coop_w : 1;
+    for (auto* g : P->groups) {
+      if (E == P || g->nseg > E->nseg) E = g;
+      sweep_groups = std::max(sweep_groups, g->coop ? g->coop_w : 1);
+    }
+    int64_t v[19] = {E->seg_len, E->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
+                     E->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U,
+                     P->variant, E->echunk, sweep_groups, (int64_t)std::max<size_t>(1, P->groups.size())};
+    for (int i = 0; i < cap && i < 19; ++i) info[i] = v[i];
   });
 }
 
@@ -2924,6 +3062,7 @@ qoc_status qoc_plan_set_variant(qoc_plan P, int variant) {
     QOC_REQUIRE(variant >= 0 && variant < kNumVariants, QOC_ERR_INVALID_ARG, "variant out of range");
     QOC_HIP(hipDeviceSynchronize());
     apply_variant(P, variant);
+    for (auto* g : P->groups) apply_variant(g, variant);
   });
 }
 
@@ -2942,16 +3081,18 @@ qoc_status qoc_plan_autotune(qoc_plan P, const double* u_dev, void* workspace, s
     hipEvent_t e0, e1;
     QOC_HIP(hipEventCreate(&e0));
     QOC_HIP(hipEventCreate(&e1));
+    // a plan with problem groups is timed on its first group (controls from offset 0)
+    qoc_plan_s* T = P->groups.empty() ? P : P->groups[0];
     auto run = [&] {
       if (P->prec == QOC_C128)
-        Driver<double>::tune_pass(P, u_dev, (char*)workspace, st);
+        Driver<double>::tune_pass(T, u_dev, (char*)workspace, st);
       else
-        Driver<float>::tune_pass(P, u_dev, (char*)workspace, st);
+        Driver<float>::tune_pass(T, u_dev, (char*)workspace, st);
     };
     int best = 0;
     double best_ms = 0.0;
     for (int v = 0; v < kNumVariants; ++v) {
-      apply_variant(P, v);
+      apply_variant(T, v);
       run();  // warm-up
       double t = 1e300;
       for (int rep = 0; rep < 2; ++rep) {
@@ -2972,6 +3113,7 @@ qoc_status qoc_plan_autotune(qoc_plan P, const double* u_dev, void* workspace, s
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     apply_variant(P, best);
+    for (auto* g : P->groups) apply_variant(g, best);
     if (chosen) *chosen = best;
   });
 }
@@ -2981,11 +3123,7 @@ qoc_status qoc_propagate(qoc_plan P, const double* u_dev, void* U_out_dev, void*
   return guarded([&] {
     QOC_REQUIRE(P && u_dev && U_out_dev && workspace, QOC_ERR_INVALID_ARG, "null argument");
     QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
-    hipStream_t st = (hipStream_t)stream;
-    if (P->prec == QOC_C128)
-      Driver<double>::propagate(P, u_dev, (double2*)U_out_dev, (char*)workspace, st);
-    else
-      Driver<float>::propagate(P, u_dev, (double2*)U_out_dev, (char*)workspace, st);
+    exec_propagate(P, u_dev, (double2*)U_out_dev, (char*)workspace, (hipStream_t)stream);
   });
 }
 
@@ -2995,11 +3133,7 @@ qoc_status qoc_fidelity_grad(qoc_plan P, const double* u_dev, const void* psi0_d
     QOC_REQUIRE(P && u_dev && psi0_dev && psif_dev && out_dev && grad_dev && workspace, QOC_ERR_INVALID_ARG,
                 "null argument");
     QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
-    hipStream_t st = (hipStream_t)stream;
-    if (P->prec == QOC_C128)
-      Driver<double>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, st);
-    else
-      Driver<float>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, st);
+    exec_run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, (char*)workspace, (hipStream_t)stream);
   });
 }
 
@@ -3008,11 +3142,7 @@ qoc_status qoc_fidelity(qoc_plan P, const double* u_dev, const void* psi0_dev, c
   return guarded([&] {
     QOC_REQUIRE(P && u_dev && psi0_dev && psif_dev && out_dev && workspace, QOC_ERR_INVALID_ARG, "null argument");
     QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
-    hipStream_t st = (hipStream_t)stream;
-    if (P->prec == QOC_C128)
-      Driver<double>::objective_only(P, u_dev, psi0_dev, psif_dev, out_dev, (char*)workspace, st);
-    else
-      Driver<float>::objective_only(P, u_dev, psi0_dev, psif_dev, out_dev, (char*)workspace, st);
+    exec_objective(P, u_dev, psi0_dev, psif_dev, out_dev, (char*)workspace, (hipStream_t)stream);
   });
 }
 
@@ -3053,12 +3183,7 @@ qoc_status qoc_fidelity_grad_noalloc(qoc_plan P, const double* u_dev, const void
                 "the plan's workspace (" + std::to_string(P->bytes) + " bytes) exceeds the library's static " +
                     "scratch of " + std::to_string((size_t)QOC_STATIC_SCRATCH_BYTES) +
                     " bytes: create the plan with max_workspace_bytes <= QOC_STATIC_SCRATCH_BYTES");
-    char* ws = static_scratch();
-    hipStream_t st = (hipStream_t)stream;
-    if (P->prec == QOC_C128)
-      Driver<double>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, ws, st);
-    else
-      Driver<float>::run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, ws, st);
+    exec_run(P, u_dev, psi0_dev, psif_dev, out_dev, grad_dev, static_scratch(), (hipStream_t)stream);
   });
 }
 
@@ -3069,6 +3194,12 @@ qoc_status qoc_plan_read_state(qoc_plan P, int problem, int which, int j, const 
     QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
     QOC_REQUIRE(problem >= 0 && problem < P->P, QOC_ERR_INVALID_ARG, "problem out of range");
     QOC_REQUIRE(which == 0 || which == 1, QOC_ERR_INVALID_ARG, "which must be 0 (state) or 1 (costate)");
+    if (!P->groups.empty()) {  // the group that ran this problem, and its index there
+      size_t g = P->groups.size() - 1;
+      while (P->grp_prob0[g] > problem) --g;
+      problem -= P->grp_prob0[g];
+      P = P->groups[g];
+    }
     const ProbDev& pb = P->probs[problem];
     QOC_REQUIRE(which == 0 ? (j >= 0 && j <= pb.N) : (j >= 1 && j <= pb.N), QOC_ERR_INVALID_ARG,
                 "slice index out of range (states 0..N, costates 1..N)");
@@ -3091,6 +3222,21 @@ qoc_status qoc_plan_set_sweep_mode(qoc_plan P, int mode) {
     QOC_REQUIRE(mode >= 0 && mode <= (QOC_SWEEP_SOLO | QOC_SWEEP_TEST_STALL_FWD | QOC_SWEEP_TEST_STALL_BWD),
                 QOC_ERR_INVALID_ARG, "unknown sweep mode bits");
     P->sweep_mode = mode;
+    for (auto* g : P->groups) g->sweep_mode = mode;
+  });
+}
+
+qoc_status qoc_plan_groups(qoc_plan P, int* count, int32_t* prob_begin, int32_t* seg_len, int32_t* nseg, int cap) {
+  return guarded([&] {
+    QOC_REQUIRE(P && count, QOC_ERR_INVALID_ARG, "null argument");
+    const int n = std::max<int>(1, (int)P->groups.size());
+    *count = n;
+    for (int g = 0; g < n && g < cap; ++g) {
+      const qoc_plan_s* G = P->groups.empty() ? P : P->groups[g];
+      if (prob_begin) prob_begin[g] = P->groups.empty() ? 0 : P->grp_prob0[g];
+      if (seg_len) seg_len[g] = G->seg_len;
+      if (nseg) nseg[g] = G->nseg;
+    }
   });
 }
 

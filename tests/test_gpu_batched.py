@@ -122,3 +122,55 @@ def test_symmetric_candidates(lib, prec):
               f"max|dg|={np.abs(g - gref).max():.2e}", flush=True)
         assert abs(out[c, 0].item() - vals["F"]) <= tf
         assert np.abs(g - gref).max() <= tg
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_problem_groups_equal_the_single_group_plan(lib, prec):
+    """A batched plan whose budget cannot hold every problem's propagators runs groups of
+    problems one after another (no recompute): results bit for bit those of the plan that
+    holds them all, for the full call, the objective-only call and the states read back; the
+    FP64 results also against the oracle."""
+    import torch
+    print(f"problem groups {prec}", flush=True)
+    rng = np.random.default_rng(41)
+    ws = []
+    for n, N in ((8, 60), (6, 25), (8, 33), (7, 50), (6, 12), (8, 41)):
+        u = rng.uniform(-1, 1, (N, 2))
+        ws.append(W.Workload(f"ring{n}", n, "dihedral", 1, W.heisenberg_ring_terms(0.6 + 0.05 * n),
+                             W.global_controls(), N, 0.04, u))
+    states = [_problem_states(rng, w.n) for w in ws]
+    systems = [lib.System(lib.Basis(w.n), w.h0, w.hk) for w in ws]
+    Ns, dts = [w.N for w in ws], [w.dt for w in ws]
+    us = [torch.tensor(w.u, device="cuda") for w in ws]
+    p0 = [torch.tensor(s[0], device="cuda") for s in states]
+    pf = [torch.tensor(s[1], device="cuda") for s in states]
+    P1 = lib.Plan.batched(systems, prec, Ns, dts, 1.0)
+    assert P1.info["problem_groups"] == 1 and P1.info["segments"] == 1
+    o1, g1 = lib.fidelity_grad_batched(P1, us, p0, pf)
+    full = P1.workspace_bytes
+    Pg, frac = None, 0.5
+    while frac > 0.01:
+        cand = lib.Plan.batched(systems, prec, Ns, dts, 1.0, int(full * frac))
+        if cand.info["problem_groups"] >= 3:
+            Pg = cand
+            break
+        frac *= 0.8
+    assert Pg is not None
+    print(f"  groups {Pg.groups()}", flush=True)
+    assert Pg.workspace_bytes <= int(full * frac)
+    og_, gg = lib.fidelity_grad_batched(Pg, us, p0, pf)
+    # out[6], the largest squaring count, is taken over the problems that share a group
+    assert torch.equal(og_[:, :6], o1[:, :6]) and torch.equal(og_[:, 7], o1[:, 7])
+    for a, b in zip(gg, g1):
+        assert torch.equal(a, b)
+    assert torch.equal(lib.fidelity_batched(Pg, us, p0, pf)[:, :6], o1[:, :6])
+    last = len(ws) - 1
+    lib.fidelity_grad_batched(Pg, us, p0, pf)
+    st_g = lib.read_state(Pg, "psi", ws[last].N, problem=last)
+    lib.fidelity_grad_batched(P1, us, p0, pf)
+    assert torch.equal(st_g, lib.read_state(P1, "psi", ws[last].N, problem=last))
+    if prec == "c128":
+        for p, w in enumerate(ws):
+            ref = _oracle(w, *states[p])
+            assert abs(og_[p, 0].item() - ref["F"]) <= 1e-12
+            assert np.abs(gg[p].cpu().numpy() - ref["grad"]).max() <= 1e-12
