@@ -120,15 +120,17 @@ def timed_steps(q, torch, plan, dev, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall, prof, out, grad
 
 
-def _product_flops(m, qs, ss, r):
+def _product_flops(m, qs, ss, r, pow_free=0):
     """Algorithmic flops of the propagator products of one block over its slices.  A
     general complex m x m product is 8 m^3; the powers Y^2..Y^r of the skew-Hermitian
     generator are (skew-)Hermitian, so only their lower triangle with the diagonal,
     4 m^2 (m + 1), is work.  Degree-12 scheme (q = 0): 2 power products, then 2 + s general
-    ones; Paterson-Stockmeyer degree q r: r - 1 powers, then q - 1 + s general."""
+    ones; Paterson-Stockmeyer degree q r: r - 1 powers, then q - 1 + s general.  The
+    pow_free powers the generator forms from the operator products (Y^2, Y^3) are no
+    products."""
     herm = 4.0 * m * m * (m + 1)
     full = 8.0 * m ** 3
-    npow = np.where(qs == 0, 2, r - 1)
+    npow = np.maximum(np.where(qs == 0, 2, r - 1) - pow_free, 0)
     ngen = np.where(qs == 0, 2 + ss, (qs - 1) + ss)
     return float((npow * herm + ngen * full).sum())
 
@@ -136,19 +138,19 @@ def _product_flops(m, qs, ss, r):
 def gemm_flops(q, plan, dev, sizes):
     """Algorithmic flops of the propagator GEMMs of one call (see _product_flops)."""
     qs, ss, _ = q.slice_stats(plan, dev["u"])
-    r = plan.info["taylor_step"]
-    tot = sum(_product_flops(m, qs[b], ss[b], r) for b, m in enumerate(sizes))
+    r, pf = plan.info["taylor_step"], plan.info["powers_from_generator"]
+    tot = sum(_product_flops(m, qs[b], ss[b], r, pf) for b, m in enumerate(sizes))
     return tot, qs, ss
 
 
 def gemm_flops_jobs(q, plan, u_flat, job_sizes):
     """gemm_flops for any plan: job_sizes lists m per (problem, block) job in plan order."""
     qs, ss, _ = q.slice_stats(plan, u_flat)
-    r = plan.info["taylor_step"]
+    r, pf = plan.info["taylor_step"], plan.info["powers_from_generator"]
     tot = 0.0
     for b, m in enumerate(job_sizes):
         valid = qs[b] >= 0
-        tot += _product_flops(m, qs[b][valid], ss[b][valid], r)
+        tot += _product_flops(m, qs[b][valid], ss[b][valid], r, pf)
     return tot
 
 
@@ -158,7 +160,7 @@ def executed_flops_jobs(q, plan, u_flat, job_sizes, job_problem=None):
     problem group (a job recomputes every segment of its group before its own last one).
     job_problem: the problem of each job (batched plans)."""
     qs, ss, _ = q.slice_stats(plan, u_flat)
-    r = plan.info["taylor_step"]
+    r, pf = plan.info["taylor_step"], plan.info["powers_from_generator"]
     groups = plan.groups()
     alg = ex = 0.0
     for b, m in enumerate(job_sizes):
@@ -167,11 +169,11 @@ def executed_flops_jobs(q, plan, u_flat, job_sizes, job_problem=None):
         valid = np.where(qs[b] >= 0)[0]
         if valid.size == 0:
             continue
-        f = _product_flops(m, qs[b][valid], ss[b][valid], r)
+        f = _product_flops(m, qs[b][valid], ss[b][valid], r, pf)
         nj = int(valid.size)
         last_start = ((nj - 1) // L) * L
         alg += f
-        ex += f + (_product_flops(m, qs[b][:last_start], ss[b][:last_start], r) if last_start > 0 else 0.0)
+        ex += f + (_product_flops(m, qs[b][:last_start], ss[b][:last_start], r, pf) if last_start > 0 else 0.0)
     return alg, ex
 
 

@@ -196,7 +196,9 @@ qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
  * grid, [10] problems P, [11] (problem, block) jobs, [12] total controls (sum N_p K_p),
  * [13] total panel length (sum D_p), [14] total propagator entries, [15] GEMM tile
  * variant in use, [16] slices per Taylor-scratch chunk, [17] largest number of work-groups
- * sharing one block's sweep (1: one work-group per block), [18] problem groups.
+ * sharing one block's sweep (1: one work-group per block), [18] problem groups, [19] powers
+ * of the exponent formed by the generator instead of products (2: Y^2 and Y^3, for systems
+ * with at most 4 controls; 0 otherwise).
  * Workspace: U and U^dag of every slice of a segment, Taylor scratch (Y..Y^r and two
  * ping-pong buffers) of one chunk of slices, states, gradient slots.  When the budget holds
  * everything, segment = chunk = N; when it holds every propagator and the scratch of at

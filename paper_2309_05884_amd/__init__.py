@@ -138,7 +138,7 @@ class Plan:
     INFO_KEYS = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
                  "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid", "problems", "jobs",
                  "total_controls", "total_panel", "total_propagator", "gemm_variant", "expm_chunk", "sweep_groups",
-                 "problem_groups"]
+                 "problem_groups", "powers_from_generator"]
     N_VARIANTS = 3
 
     def __init__(self, system: System, precision: str = "c128", N: int = 1, dt: float = 0.01,

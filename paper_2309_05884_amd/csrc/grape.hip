@@ -46,6 +46,7 @@ struct JobDev {
   double dt;
   const double* h64;     // FP64 operator planes of this block
   const void* hT;        // working-precision operator planes of this block
+  const void* pwT;       // working-precision operator products (qoc_system_s::pw*), or null
   long long ent_off;     // first entry (slice of a segment) of this job
   long long item_off;    // first propagator GEMM item of this job
   long long ubuf_off;    // propagators of the segment: per slice U and U^dag (elements of T)
@@ -143,6 +144,9 @@ struct qoc_plan_s {
   double u_bound = 0.0;
   int r = 4, qmax = 4, smax = 0;
   int t12 = 0;  // slices may use the four-product degree-12 evaluation
+  // 2 when the generator forms Y^2 and Y^3 from the operator products (no power GEMMs for
+  // them), else 0; with r = 3 it then also forms each slice's first Taylor combination
+  int pow_free = 0;
   double norm_bound = 0.0;
   int seg_len = 0, nseg = 0;
   int echunk = 0;  // slices whose Taylor scratch is resident at once (the segment is formed in chunks)
@@ -208,19 +212,20 @@ __device__ inline T* tplane(char* ws, size_t off_T, long long elem_off) {
 // offered only when t12 is set (FP32 plans: its epilogues move more data per product, which
 // the FP64 accumulator layout makes four times as costly, and its products of non-unitary
 // intermediates raise the unitarity error about threefold).
-__host__ __device__ inline void pick_degree(double nx, const double* theta, int r, int qmax, int t12, int* q_out,
-                                            int* s_out) {
+// pow_free products (Y^2, Y^3) come from the generator and cost nothing here.
+__host__ __device__ inline void pick_degree(double nx, const double* theta, int r, int qmax, int t12, int pow_free,
+                                            int* q_out, int* s_out) {
   int best_q = qmax, best_s = 0, best_cost = 1 << 30;
   for (int q = qmax; q >= 1; --q) {
     int sq = 0;
     while (sq < 62 && nx > ldexp(theta[q * r], sq)) ++sq;
-    const int cost = (r - 1) + (q - 1) + sq;
+    const int cost = (r - 1 - pow_free) + (q - 1) + sq;
     if (cost < best_cost) { best_cost = cost; best_q = q; best_s = sq; }
   }
   if (t12) {
     int s12 = 0;
     while (s12 < 62 && nx > ldexp(theta[12], s12)) ++s12;
-    if (4 + s12 < best_cost) { best_q = 0; best_s = s12; }
+    if (4 - pow_free + s12 < best_cost) { best_q = 0; best_s = s12; }
   }
   *q_out = best_q;
   *s_out = best_s;
@@ -230,23 +235,159 @@ __host__ __device__ inline void pick_degree(double nx, const double* theta, int 
 // first ping-pong buffer.
 __host__ __device__ inline int qeff(int q) { return q > 0 ? q : 1; }
 
+__constant__ double kInvFact[64];
+__constant__ double kT12c[4][4];  // the degree-12 scheme's coefficients (taylor12.h)
+
 // ===================================================================== generator + norm
 // One work-group per job and group of GEN_SG slices.  Pass 1: FP64 column sums of
 // |H_j| for every slice of the group (one wave per column, lanes over rows, each operator
 // element read once for all slices), giving the exact 1-norms and each slice's (q, s).
 // Pass 2: Y = -i dt 2^-s H_j in the working precision, again reading H once per group.
 constexpr int GEN_SG = 8;
+constexpr int kMaxPair = 15, kMaxTrip = 35;  // pair_count / triple_count at kMaxPowK
+
+// Coefficients of the operator products for the group's slices, scale sc = dt 2^-s
+// folded in: pair (a <= b) -sc^2 u_a u_b, triple (a <= b <= c) sc^3 u_a u_b u_c (u_0 = 1),
+// lexicographic order as the products; in the working precision (the combinations of the
+// products are formed in it, like the products they replace).
+template <typename T>
+__device__ inline void gen_product_coefs(int K, int ns, const double (*us)[kMaxControls + 1], const double* scale,
+                                         T (*cp)[kMaxPair], T (*ct)[kMaxTrip]) {
+  const int O = K + 1;
+  for (int t = threadIdx.x; t < GEN_SG; t += blockDim.x) {
+    const double sc = t < ns ? scale[t] : 0.0, sc2 = sc * sc, sc3 = sc2 * sc;
+    int i = 0, j = 0;
+    for (int a = 0; a < O; ++a)
+      for (int b = a; b < O; ++b) cp[t][i++] = (T)(-sc2 * us[t][a] * us[t][b]);
+    for (int a = 0; a < O; ++a)
+      for (int b = a; b < O; ++b)
+        for (int c = b; c < O; ++c) ct[t][j++] = (T)(sc3 * us[t][a] * us[t][b] * us[t][c]);
+  }
+}
+
+// Pass 2 of the generator for one element idx of a job's block and the group's ns slices
+// (chunk slots Y0 + t * ent_stride): Y = -i sc H_j with sc = dt 2^-s in slot 0; with the
+// operator products (pw != null) also Y^2 = -sc^2 sum_ab u_a u_b S_ab in slot 1 and
+// Y^3 = i sc^3 sum_abc u_a u_b u_c T_abc in slot 2, and, when gen_init, the slice's first
+// Taylor combination: B4 of the degree-12 scheme (q = 0) or the Paterson-Stockmeyer
+// start T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i (r = 3) in slot r, or, for q = 1 and
+// no squaring, T0 = U itself into the propagator storage (U and U^dag).  FP64 arithmetic,
+// rounded to T once.
+template <typename T>
+__device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, int gen_init, const T* pw,
+                                   const double (*us)[kMaxControls + 1], const T (*cp)[kMaxPair],
+                                   const T (*ct)[kMaxTrip], const double* scale, const int* qsl, const int* ssl,
+                                   T* Y0, size_t ent_stride, T* U0) {
+  const int m = jb.m, mp = jb.mp, K = jb.K;
+  const size_t plane = (size_t)mp * mp;
+  const double* H = jb.h64;
+  const int rr = (int)(idx % mp), c = (int)(idx / mp);
+  const bool in = rr < m && c < m;
+  double hr[GEN_SG], hi[GEN_SG];
+#pragma unroll
+  for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
+  if (in) {
+    for (int o = 0; o <= K; ++o) {
+      const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) {
+        hr[t] += us[t][o] * ar;
+        hi[t] += us[t][o] * ai;
+      }
+    }
+  }
+  // -i * scale * (hr + i hi) = scale * hi - i scale * hr
+#pragma unroll
+  for (int t = 0; t < GEN_SG; ++t) {
+    if (t < ns) {
+      T* Y = Y0 + (size_t)t * ent_stride;
+      Y[idx] = (T)(scale[t] * hi[t]);
+      Y[idx + plane] = (T)(-scale[t] * hr[t]);
+    }
+  }
+  if (!pw) return;
+  // Y^2 = sum cp S (cp carries -sc^2), Y^3 = i sum ct T (ct carries sc^3)
+  T sr[GEN_SG], si[GEN_SG], cr[GEN_SG], ci[GEN_SG];
+#pragma unroll
+  for (int t = 0; t < GEN_SG; ++t) sr[t] = si[t] = cr[t] = ci[t] = T(0);
+  if (in) {
+    const int np = pair_count(K), nt = triple_count(K);
+#pragma unroll 2
+    for (int i = 0; i < np; ++i) {
+      const T ar = pw[(size_t)(2 * i) * plane + idx], ai = pw[(size_t)(2 * i + 1) * plane + idx];
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) {
+        sr[t] += cp[t][i] * ar;
+        si[t] += cp[t][i] * ai;
+      }
+    }
+#pragma unroll 2
+    for (int i = 0; i < nt; ++i) {
+      const size_t o = (size_t)(2 * (np + i)) * plane + idx;
+      const T ar = pw[o], ai = pw[o + plane];
+#pragma unroll
+      for (int t = 0; t < GEN_SG; ++t) {
+        cr[t] += ct[t][i] * ar;
+        ci[t] += ct[t][i] * ai;
+      }
+    }
+  }
+  const bool diag = rr == c && rr < m;
+#pragma unroll
+  for (int t = 0; t < GEN_SG; ++t) {
+    if (t >= ns) continue;
+    const double sc = scale[t];
+    const double y1r = sc * hi[t], y1i = -sc * hr[t];
+    const double y2r = sr[t], y2i = si[t];
+    const double y3r = -(double)ci[t], y3i = cr[t];
+    T* Y = Y0 + (size_t)t * ent_stride;
+    Y[2 * plane + idx] = (T)y2r;
+    Y[3 * plane + idx] = (T)y2i;
+    Y[4 * plane + idx] = (T)y3r;
+    Y[5 * plane + idx] = (T)y3i;
+    if (!gen_init) continue;
+    const int q = qsl[t];
+    double c0, c1, c2, c3;
+    if (q == 0) {
+      c0 = kT12c[3][0];
+      c1 = kT12c[3][1];
+      c2 = kT12c[3][2];
+      c3 = kT12c[3][3];
+    } else {
+      c0 = kInvFact[(q - 1) * 3];
+      c1 = kInvFact[(q - 1) * 3 + 1];
+      c2 = kInvFact[(q - 1) * 3 + 2];
+      c3 = kInvFact[q * 3];
+    }
+    const double vr = c1 * y1r + c2 * y2r + c3 * y3r + (diag ? c0 : 0.0);
+    const double vi = c1 * y1i + c2 * y2i + c3 * y3i;
+    if (q == 1 && ssl[t] == 0) {
+      // degree 3, no squaring: T0 is the propagator
+      T* U = U0 + (size_t)t * 4 * plane;
+      U[idx] = (T)vr;
+      U[idx + plane] = (T)vi;
+      const size_t tr = (size_t)c + (size_t)rr * mp;  // U^dag[c][rr] = conj(U[rr][c])
+      U[2 * plane + tr] = (T)vr;
+      U[3 * plane + tr] = (T)(-vi);
+    } else {
+      Y[(size_t)(2 * r) * plane + idx] = (T)vr;
+      Y[(size_t)(2 * r + 1) * plane + idx] = (T)vi;
+    }
+  }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs, const double* u, int seg_j0,
                                                    int seg_len, int c0, int clen, int groups, char* ws, size_t off_T,
                                                    int* ent_s,
                                                    int* ent_q, double* ent_norm, int* flags, const double* theta,
-                                                   int r, int qmax, int t12, int smax, double norm_bound,
+                                                   int r, int qmax, int t12, int pow_free, int smax, double norm_bound,
                                                    int skip_n) {
   __shared__ double red[GEN_SG][256];
   __shared__ double us[GEN_SG][kMaxControls + 1];
+  __shared__ T cp[GEN_SG][kMaxPair], ct[GEN_SG][kMaxTrip];
   __shared__ double scale[GEN_SG];
+  __shared__ int qsl[GEN_SG], ssl[GEN_SG];
   const int J = blockIdx.x / groups, g = blockIdx.x % groups;
   if (J >= njobs) return;
   const JobDev jb = jobs[J];
@@ -312,7 +453,7 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
     if (!finite) flag |= 2;
     if (nx > norm_bound * (1.0 + 1e-12)) flag |= 1;
     int best_q, best_s;
-    pick_degree(nx, theta, r, qmax, t12, &best_q, &best_s);
+    pick_degree(nx, theta, r, qmax, t12, pow_free, &best_q, &best_s);
     if (best_s > smax) { flag |= 1; best_s = smax; }
     if (flag) atomicOr(flags, flag);
     atomicMax(flags + 1, best_s);
@@ -321,35 +462,19 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
     ent_q[e] = best_q;
     ent_norm[e] = nx;
     scale[t] = ldexp(jb.dt, -best_s);
+    qsl[t] = best_q;
+    ssl[t] = best_s;
   }
+  __syncthreads();
+  const T* pw = pow_free ? static_cast<const T*>(jb.pwT) : nullptr;
+  if (pw) gen_product_coefs<T>(K, ns, us, scale, cp, ct);
   __syncthreads();
   const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
   T* Y0 = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)(jl0 - c0) * ent_stride;
-  for (size_t idx = threadIdx.x; idx < plane; idx += blockDim.x) {
-    const int rr = (int)(idx % mp), c = (int)(idx / mp);
-    double hr[GEN_SG], hi[GEN_SG];
-#pragma unroll
-    for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
-    if (rr < m && c < m) {
-      for (int o = 0; o <= K; ++o) {
-        const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
-#pragma unroll
-        for (int t = 0; t < GEN_SG; ++t) {
-          hr[t] += us[t][o] * ar;
-          hi[t] += us[t][o] * ai;
-        }
-      }
-    }
-    // -i * scale * (hr + i hi) = scale * hi - i scale * hr
-#pragma unroll
-    for (int t = 0; t < GEN_SG; ++t) {
-      if (t < ns) {
-        T* Y = Y0 + (size_t)t * ent_stride;
-        Y[idx] = (T)(scale[t] * hi[t]);
-        Y[idx + plane] = (T)(-scale[t] * hr[t]);
-      }
-    }
-  }
+  T* U0 = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl0 * 4 * plane;
+  const int gen_init = pow_free && r == 3;
+  for (size_t idx = threadIdx.x; idx < plane; idx += blockDim.x)
+    gen_element<T>(jb, idx, ns, r, gen_init, pw, us, cp, ct, scale, qsl, ssl, Y0, ent_stride, U0);
 }
 
 // The same generator split over column ranges, for chunks with too few (job, slice group)
@@ -439,7 +564,7 @@ __global__ void __launch_bounds__(256) k_gen_norms(const JobDev* jobs, int njobs
 
 __global__ void k_gen_pick(const JobDev* jobs, int njobs, const double* u, int seg_j0, int seg_len, int c0, int clen,
                            int groups, int* ent_s, int* ent_q, double* ent_norm, int* flags, const double* theta, int r,
-                           int qmax, int t12, int smax, double norm_bound, int skip_n) {
+                           int qmax, int t12, int pow_free, int smax, double norm_bound, int skip_n) {
   const int J = blockIdx.x / groups, g = blockIdx.x % groups;
   if (J >= njobs) return;
   const JobDev jb = jobs[J];
@@ -456,7 +581,7 @@ __global__ void k_gen_pick(const JobDev* jobs, int njobs, const double* u, int s
   if (!finite) flag |= 2;
   if (nx > norm_bound * (1.0 + 1e-12)) flag |= 1;
   int best_q, best_s;
-  pick_degree(nx, theta, r, qmax, t12, &best_q, &best_s);
+  pick_degree(nx, theta, r, qmax, t12, pow_free, &best_q, &best_s);
   if (best_s > smax) { flag |= 1; best_s = smax; }
   if (flag) atomicOr(flags, flag);
   atomicMax(flags + 1, best_s);
@@ -469,9 +594,12 @@ __global__ void k_gen_pick(const JobDev* jobs, int njobs, const double* u, int s
 template <typename T>
 __global__ void __launch_bounds__(256) k_gen_form(const JobDev* jobs, int njobs, const double* u, int seg_j0,
                                                   int seg_len, int c0, int clen, int groups, int csplit, char* ws,
-                                                  size_t off_T, const int* ent_s, int r, int skip_n) {
+                                                  size_t off_T, const int* ent_s, const int* ent_q, int r,
+                                                  int pow_free, int skip_n) {
   __shared__ double us[GEN_SG][kMaxControls + 1];
+  __shared__ T cp[GEN_SG][kMaxPair], ct[GEN_SG][kMaxTrip];
   __shared__ double scale[GEN_SG];
+  __shared__ int qsl[GEN_SG], ssl[GEN_SG];
   const int J = blockIdx.x / (groups * csplit), g = (blockIdx.x / csplit) % groups, cs = blockIdx.x % csplit;
   if (J >= njobs) return;
   const JobDev jb = jobs[J];
@@ -480,46 +608,30 @@ __global__ void __launch_bounds__(256) k_gen_form(const JobDev* jobs, int njobs,
   const int len = min(job_len(jb, seg_j0, seg_len), c0 + clen);
   if (jl0 >= len) return;
   const int ns = min(GEN_SG, len - jl0);
-  const int m = jb.m, mp = jb.mp, K = jb.K;
+  const int mp = jb.mp, K = jb.K;
   const size_t plane = (size_t)mp * mp;
   const size_t ew = (plane + csplit - 1) / csplit, lo = cs * ew, hi_ = min(plane, lo + ew);
-  const double* H = jb.h64;
   gen_load_controls(jb, u, seg_j0, jl0, ns, us);
-  if ((int)threadIdx.x < ns) scale[threadIdx.x] = ldexp(jb.dt, -ent_s[jb.ent_off + jl0 + threadIdx.x]);
+  if ((int)threadIdx.x < ns) {
+    const long long e = jb.ent_off + jl0 + threadIdx.x;
+    scale[threadIdx.x] = ldexp(jb.dt, -ent_s[e]);
+    qsl[threadIdx.x] = ent_q[e];
+    ssl[threadIdx.x] = ent_s[e];
+  }
+  __syncthreads();
+  const T* pw = pow_free ? static_cast<const T*>(jb.pwT) : nullptr;
+  if (pw) gen_product_coefs<T>(K, ns, us, scale, cp, ct);
   __syncthreads();
   const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
   T* Y0 = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)(jl0 - c0) * ent_stride;
-  for (size_t idx = lo + threadIdx.x; idx < hi_; idx += blockDim.x) {
-    const int rr = (int)(idx % mp), c = (int)(idx / mp);
-    double hr[GEN_SG], hi[GEN_SG];
-#pragma unroll
-    for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
-    if (rr < m && c < m) {
-      for (int o = 0; o <= K; ++o) {
-        const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
-#pragma unroll
-        for (int t = 0; t < GEN_SG; ++t) {
-          hr[t] += us[t][o] * ar;
-          hi[t] += us[t][o] * ai;
-        }
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < GEN_SG; ++t) {
-      if (t < ns) {
-        T* Y = Y0 + (size_t)t * ent_stride;
-        Y[idx] = (T)(scale[t] * hi[t]);
-        Y[idx + plane] = (T)(-scale[t] * hr[t]);
-      }
-    }
-  }
+  T* U0 = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl0 * 4 * plane;
+  const int gen_init = pow_free && r == 3;
+  for (size_t idx = lo + threadIdx.x; idx < hi_; idx += blockDim.x)
+    gen_element<T>(jb, idx, ns, r, gen_init, pw, us, cp, ct, scale, qsl, ssl, Y0, ent_stride, U0);
 }
 
 // ===================================================================== expm GEMM steps
 enum { STEP_POWER = 0, STEP_HORNER = 1, STEP_SQUARE = 2, STEP_T12 = 3 };
-
-__constant__ double kInvFact[64];
-__constant__ double kT12c[4][4];  // the degree-12 scheme's coefficients (taylor12.h)
 
 // One product step over every entry of a chunk of the segment (persistent, XCD-grouped
 // items).  Taylor scratch of an entry (one slot per chunk slice): 0 = Y, i-1 = Y^i (i <= r),
@@ -1497,6 +1609,95 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   }
 }
 
+// ===================================================================== set-up products
+// C = A B, or C += A B, for square mp x mp complex FP64 blocks (planar, column-major), on
+// the FP64 matrix cores with the propagator GEMM's tile: the operator products of
+// ensure_powers, once per system.
+struct SetupGemm {
+  const double* A;
+  const double* B;
+  double* C;
+  long long item_off;
+  int mp, tiles_n, accumulate;
+};
+
+template <typename Shape>
+__global__ void __launch_bounds__(256, Shape::WAVES)
+    k_setup_gemm(const SetupGemm* descs, int ndesc, long long total_items) {
+  typedef typename Shape::T T;
+  __shared__ TileSmem<Shape> lds;
+  const ItemRange rg = xcd_items(total_items);
+  ItemCursor cur;
+  struct Item {
+    TileOperands<T> op;
+    T* C;
+    int accumulate;
+  };
+  auto prep = [&](long long it, Item& x) -> bool {
+    const SetupGemm g = descs[cursor_find(descs, ndesc, it, cur)];
+    const long long local = it - g.item_off;
+    const size_t plane = (size_t)g.mp * g.mp;
+    x.op.A = g.A;
+    x.op.a_ps = plane;
+    x.op.lda = g.mp;
+    x.op.B = g.B;
+    x.op.b_ps = plane;
+    x.op.ldb = g.mp;
+    x.op.M = g.mp;
+    x.op.N = g.mp;
+    x.op.K = g.mp;
+    x.op.row0 = (int)(local / g.tiles_n) * Shape::BM;
+    x.op.col0 = (int)(local % g.tiles_n) * Shape::BN;
+    x.C = g.C;
+    x.accumulate = g.accumulate;
+    return true;
+  };
+  long long it = rg.begin;
+  if (it >= rg.end) return;
+  Item x;
+  prep(it, x);
+  TilePipe pipe = tile_start<Shape>(x.op, lds);
+  for (;;) {
+    const long long nx = it + rg.step;
+    Item xn = x;
+    const bool more = nx < rg.end;
+    if (more) prep(nx, xn);
+    TileAcc<Shape> acc;
+    tile_mma<Shape>(x.op, lds, acc, pipe, more, xn.op);
+    const int mp = x.op.M;
+    const size_t plane = (size_t)mp * mp;
+#pragma unroll
+    for (int ri = 0; ri < Shape::SM; ++ri)
+#pragma unroll
+      for (int ci = 0; ci < Shape::SN; ++ci) {
+        const int rbase = acc_row_base<Shape>(x.op.row0, ri);
+        const int col = acc_col<Shape>(x.op.col0, ci);
+        if (rbase >= mp || col >= mp) continue;
+        T* c = x.C + (size_t)(rbase + acc_row_off<T>(0)) + (size_t)col * mp;
+        typename Vec4<T>::type vr = acc.re[ri][ci], vi = acc.im[ri][ci];
+        if (x.accumulate) {
+          vr += acc_load<T>(c);
+          vi += acc_load<T>(c + plane);
+        }
+        acc_store<T>(c, vr);
+        acc_store<T>(c + plane, vi);
+      }
+    if (!more) break;
+    it = nx;
+    x = xn;
+  }
+}
+
+__global__ void k_axpy_planes(const double* a, double* c, size_t n) {  // c += a
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    c[i] += a[i];
+}
+
+__global__ void k_planes_to_float(const double* a, float* c, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    c[i] = (float)a[i];
+}
+
 // Load a chunk of forward states (src = 0) or costates (src = 1) into a gradient slot.
 template <typename T>
 __global__ void k_chunk_load(const JobDev* jobs, int njobs, char* ws, size_t off_T, int src, int slot, int j0,
@@ -2055,7 +2256,8 @@ static void timed(int kind, hipStream_t st, F&& launch) {
 
 // Norms and (q, s) choice of every slice, without forming the generators (statistics).
 __global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njobs, const double* u, int Nmax,
-                                                     const double* theta, int r, int qmax, int t12, int* q_out, int* s_out,
+                                                     const double* theta, int r, int qmax, int t12, int pow_free,
+                                                     int* q_out, int* s_out,
                                                      double* n_out) {
   __shared__ double red[256];
   __shared__ double ujs[kMaxControls + 1];
@@ -2099,7 +2301,7 @@ __global__ void __launch_bounds__(256) k_slice_norms(const JobDev* jobs, int njo
   if (threadIdx.x == 0) {
     const double nx = jb.dt * red[0];
     int q, s;
-    pick_degree(nx, theta, r, qmax, t12, &q, &s);
+    pick_degree(nx, theta, r, qmax, t12, pow_free, &q, &s);
     q_out[(size_t)J * Nmax + j] = q;
     s_out[(size_t)J * Nmax + j] = s;
     n_out[(size_t)J * Nmax + j] = nx;
@@ -2248,7 +2450,8 @@ struct Driver {
         timed(PK_GENERATOR, st, [&] {
           hipLaunchKernelGGL(k_generator<T>, dim3(njobs * groups), dim3(256), 0, st, dj, njobs, u, seg_j0, L, c0,
                              clen, groups, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags,
-                             P->d_theta.as<double>(), P->r, P->qmax, P->t12, P->smax, P->norm_bound, skip_n);
+                             P->d_theta.as<double>(), P->r, P->qmax, P->t12, P->pow_free, P->smax, P->norm_bound,
+                             skip_n);
         });
       } else {
         timed(PK_GENERATOR, st, [&] {
@@ -2259,9 +2462,10 @@ struct Driver {
                              c0, clen, groups, csplit, ent_norm(P, ws), skip_n);
           hipLaunchKernelGGL(k_gen_pick, dim3((unsigned)wgs), dim3(64), 0, st, dj, njobs, u, seg_j0, L, c0, clen,
                              groups, ent_s(P, ws), ent_q(P, ws), ent_norm(P, ws), flags, P->d_theta.as<double>(),
-                             P->r, P->qmax, P->t12, P->smax, P->norm_bound, skip_n);
+                             P->r, P->qmax, P->t12, P->pow_free, P->smax, P->norm_bound, skip_n);
           hipLaunchKernelGGL(k_gen_form<T>, dim3((unsigned)(wgs * csplit)), dim3(256), 0, st, dj, njobs, u, seg_j0,
-                             L, c0, clen, groups, csplit, ws, P->off_T, ent_s(P, ws), P->r, skip_n);
+                             L, c0, clen, groups, csplit, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), P->r, P->pow_free,
+                             skip_n);
         });
       }
       auto step = [&](int mode, int s) {
@@ -2270,7 +2474,8 @@ struct Driver {
                                P->r, seg_j0, L, c0, clen, skip_n, flags);
         });
       };
-      for (int i = 2; i <= P->r; ++i) step(STEP_POWER, i);
+      // powers Y^2 .. Y^r (those the generator formed are skipped)
+      for (int i = 2 + P->pow_free; i <= P->r; ++i) step(STEP_POWER, i);
       if (P->t12) {
         step(STEP_T12, 1);
         step(STEP_T12, 2);
@@ -2548,6 +2753,109 @@ static ProblemSpec all_blocks(qoc_system_s* sys, int N, double dt) {
   return ProblemSpec{sys, N, dt, sys->blocks};
 }
 
+// The operator products of qoc_system_s::pw64 / pw32 (see there), formed once per system:
+// ordered pair products P_xy = H_x H_y (temporary), S_ab from them, then every triple
+// product as H_x S_yz summed over the representatives of its distinct orderings:
+// T_aaa = H_a S_aa; T_aac = H_a S_ac + H_c S_aa; T_acc = H_a S_cc + H_c S_ac;
+// T_abc = H_a S_bc + H_b S_ac + H_c S_ab (a < b < c).
+static void ensure_powers(qoc_system_s* S) {
+  if (S->pw_ready || S->K > kMaxPowK) return;
+  const int K = S->K, O = K + 1, npair = pair_count(K), ntrip = triple_count(K), npw = npair + ntrip;
+  int64_t elems = 0;
+  S->pw_off.clear();
+  for (auto& b : S->blocks) {
+    S->pw_off.push_back(elems);
+    elems += (int64_t)npw * 2 * b.mp * b.mp;
+  }
+  S->pw64.alloc((size_t)elems * sizeof(double));
+  S->pw32.alloc((size_t)elems * sizeof(float));
+  hipStream_t st = nullptr;
+  typedef TileShape<double, 2, 2, 2> Shape;
+  auto pair_index = [&](int a, int b) {  // position of (a <= b) in lexicographic order
+    int idx = 0;
+    for (int x = 0; x < a; ++x) idx += O - x;
+    return idx + (b - a);
+  };
+  for (size_t bi = 0; bi < S->blocks.size(); ++bi) {
+    const auto& blk = S->blocks[bi];
+    const int mp = blk.mp;
+    const size_t plane = (size_t)mp * mp;
+    const int tm = (mp + Shape::BM - 1) / Shape::BM, tn = (mp + Shape::BN - 1) / Shape::BN;
+    const double* H = S->h64.as<double>() + blk.h_off;
+    double* PW = S->pw64.as<double>() + S->pw_off[bi];
+    auto op = [&](int o) { return H + (size_t)(2 * o) * plane; };
+    auto pw = [&](int idx) { return PW + (size_t)(2 * idx) * plane; };
+    DeviceBuffer tmp((size_t)O * O * 2 * plane * sizeof(double));
+    auto pxy = [&](int x, int y) { return tmp.as<double>() + (size_t)(2 * (x * O + y)) * plane; };
+    auto run = [&](const std::vector<SetupGemm>& list) {
+      std::vector<SetupGemm> d(list);
+      long long items = 0;
+      for (auto& g : d) {
+        g.item_off = items;
+        items += (long long)tm * tn;
+      }
+      DeviceBuffer dd(d.size() * sizeof(SetupGemm));
+      QOC_HIP(hipMemcpy(dd.ptr, d.data(), d.size() * sizeof(SetupGemm), hipMemcpyHostToDevice));
+      const int grid = (int)std::min<long long>(2048, (items + 7) / 8 * 8);
+      hipLaunchKernelGGL(k_setup_gemm<Shape>, dim3(std::max(8, grid)), dim3(256), 0, st, dd.as<SetupGemm>(),
+                         (int)d.size(), items);
+      QOC_HIP(hipGetLastError());
+      QOC_HIP(hipStreamSynchronize(st));
+    };
+    // ordered pair products, then S_ab = P_ab + P_ba (a < b), S_aa = P_aa
+    std::vector<SetupGemm> g1;
+    for (int x = 0; x < O; ++x)
+      for (int y = 0; y < O; ++y) g1.push_back(SetupGemm{op(x), op(y), pxy(x, y), 0, mp, tn, 0});
+    run(g1);
+    for (int a = 0; a < O; ++a)
+      for (int b = a; b < O; ++b) {
+        QOC_HIP(hipMemcpy(pw(pair_index(a, b)), pxy(a, b), 2 * plane * sizeof(double), hipMemcpyDeviceToDevice));
+        if (b != a)
+          hipLaunchKernelGGL(k_axpy_planes, dim3(1024), dim3(256), 0, st, pxy(b, a), pw(pair_index(a, b)), 2 * plane);
+      }
+    QOC_HIP(hipGetLastError());
+    QOC_HIP(hipStreamSynchronize(st));
+    // triple products (a <= b <= c in lexicographic order), each a sum of H_x S_yz
+    std::vector<SetupGemm> g2;
+    int t = npair;
+    for (int a = 0; a < O; ++a)
+      for (int b = a; b < O; ++b)
+        for (int c = b; c < O; ++c, ++t) {
+          std::vector<std::pair<int, int>> terms;  // (x, pair index of the other two)
+          if (a == b && b == c) {
+            terms = {{a, pair_index(a, a)}};
+          } else if (a == b) {
+            terms = {{a, pair_index(a, c)}, {c, pair_index(a, a)}};
+          } else if (b == c) {
+            terms = {{a, pair_index(b, b)}, {b, pair_index(a, b)}};
+          } else {
+            terms = {{a, pair_index(b, c)}, {b, pair_index(a, c)}, {c, pair_index(a, b)}};
+          }
+          for (size_t i = 0; i < terms.size(); ++i)
+            g2.push_back(SetupGemm{op(terms[i].first), pw(terms[i].second), pw(t), 0, mp, tn, i > 0 ? 1 : 0});
+        }
+    // the accumulating products into one output must not run concurrently: one launch per
+    // term position
+    for (int pass = 0; pass < 3; ++pass) {
+      std::vector<SetupGemm> part;
+      size_t k = 0;
+      for (int a = 0; a < O; ++a)
+        for (int b = a; b < O; ++b)
+          for (int c = b; c < O; ++c) {
+            const int nterms = (a == b && b == c) ? 1 : ((a == b || b == c) ? 2 : 3);
+            if (pass < nterms) part.push_back(g2[k + pass]);
+            k += nterms;
+          }
+      if (!part.empty()) run(part);
+    }
+  }
+  hipLaunchKernelGGL(k_planes_to_float, dim3(4096), dim3(256), 0, st, S->pw64.as<double>(), S->pw32.as<float>(),
+                     (size_t)elems);
+  QOC_HIP(hipGetLastError());
+  QOC_HIP(hipStreamSynchronize(st));
+  S->pw_ready = true;
+}
+
 // Default workspace budget: 85 % of the free device memory (the rest for the caller's
 // tensors and the allocator), at most 240 GiB of the 288 GB part.
 static size_t default_budget() {
@@ -2576,6 +2884,14 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->r = f64 ? 4 : 3;
   P->qmax = f64 ? 6 : 4;  // degrees up to 24 (FP64) / 12 (FP32)
   P->t12 = f64 ? 0 : 1;
+  // Y^2 and Y^3 from the operator products when every system has them (few controls)
+  {
+    bool all = true;
+    for (auto& pr : probs) all = all && pr.sys->K <= kMaxPowK;
+    if (all)
+      for (auto& pr : probs) ensure_powers(pr.sys);
+    P->pow_free = all ? 2 : 0;
+  }
   const double unit = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
   double nb = 0.0;
   int max_mp = 0;
@@ -2597,7 +2913,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     // piecewise constant between the points theta_{qr} 2^s, so evaluate just above each
     auto choose_s = [&](double nx) {
       int q = 0, sq = 0;
-      pick_degree(nx, theta, P->r, P->qmax, P->t12, &q, &sq);
+      pick_degree(nx, theta, P->r, P->qmax, P->t12, P->pow_free, &q, &sq);
       return sq;
     };
     int smax = choose_s(nb);
@@ -2746,6 +3062,10 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       j.dt = pr.dt;
       j.h64 = pr.sys->h64.as<double>() + b.h_off;
       j.hT = f64 ? (const void*)(pr.sys->h64.as<double>() + b.h_off) : (const void*)(pr.sys->h32.as<float>() + b.h_off);
+      j.pwT = nullptr;
+      if (P->pow_free)
+        j.pwT = f64 ? (const void*)(pr.sys->pw64.as<double>() + pr.sys->pw_off[b.index])
+                    : (const void*)(pr.sys->pw32.as<float>() + pr.sys->pw_off[b.index]);
       j.state_off = state_base + b.state_off;
       j.u_off = u_off;
       j.ent_off = ent_off;
@@ -3049,10 +3369,11 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
       if (E == P || g->nseg > E->nseg) E = g;
       sweep_groups = std::max(sweep_groups, g->coop ? g->coop_w : 1);
     }
-    int64_t v[19] = {E->seg_len, E->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
+    int64_t v[20] = {E->seg_len, E->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
                      E->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U,
-                     P->variant, E->echunk, sweep_groups, (int64_t)std::max<size_t>(1, P->groups.size())};
-    for (int i = 0; i < cap && i < 19; ++i) info[i] = v[i];
+                     P->variant, E->echunk, sweep_groups, (int64_t)std::max<size_t>(1, P->groups.size()),
+                     P->pow_free};
+    for (int i = 0; i < cap && i < 20; ++i) info[i] = v[i];
   });
 }
 
@@ -3322,8 +3643,8 @@ qoc_status qoc_plan_slice_stats(qoc_plan P, const double* u_dev, int32_t* q_host
     const size_t cnt = (size_t)njobs * P->Nmax;
     DeviceBuffer q(cnt * 4), sbuf(cnt * 4), nrm(cnt * 8);
     hipLaunchKernelGGL(k_slice_norms, dim3(P->Nmax, std::min(njobs, 32768)), dim3(256), 0, st, P->d_jobs.as<JobDev>(), njobs, u_dev,
-                       P->Nmax, P->d_theta.as<double>(), P->r, P->qmax, P->t12, q.as<int>(), sbuf.as<int>(),
-                       nrm.as<double>());
+                       P->Nmax, P->d_theta.as<double>(), P->r, P->qmax, P->t12, P->pow_free, q.as<int>(),
+                       sbuf.as<int>(), nrm.as<double>());
     QOC_HIP(hipGetLastError());
     QOC_HIP(hipMemcpyAsync(q_host, q.ptr, cnt * 4, hipMemcpyDeviceToHost, st));
     QOC_HIP(hipMemcpyAsync(s_host, sbuf.ptr, cnt * 4, hipMemcpyDeviceToHost, st));

@@ -283,6 +283,7 @@ qoc_status qoc_project(qoc_basis B, const qoc_term* h0, int n_h0, const qoc_term
       blk.d = bi.d;
       blk.h_off = elems;
       blk.state_off = bi.state_off;
+      blk.index = (int)S->blocks.size();
       elems += (int64_t)2 * nops * blk.mp * blk.mp;
       S->blocks.push_back(blk);
     }

@@ -15,6 +15,11 @@ namespace qoc {
 
 // control operators per system (per-qubit x and y fields of up to 16 qubits)
 constexpr int kMaxControls = 32;
+// systems with at most this many controls get the generator's operator products (the
+// products grow as K^3: 50 per block at K = 4)
+constexpr int kMaxPowK = 4;
+__host__ __device__ inline int pair_count(int K) { return (K + 1) * (K + 2) / 2; }
+__host__ __device__ inline int triple_count(int K) { return (K + 1) * (K + 2) * (K + 3) / 6; }
 
 // ---------------------------------------------------------------------------------------
 // error plumbing
@@ -138,6 +143,7 @@ struct qoc_system_s {
   int K = 0;
   struct Block {
     int m, mp, d;
+    int index;            // position in the system's block list
     int64_t h_off;        // element offset of the block's operator planes
     int64_t state_off;    // complex offset in state panels
     std::vector<double> norm1;  // exact 1-norm of each operator block (host)
@@ -148,6 +154,16 @@ struct qoc_system_s {
   qoc::DeviceBuffer h64;  // double
   qoc::DeviceBuffer h32;  // float
   int64_t h_elems = 0;
+  // Symmetrised operator products from which the generator forms the second and third
+  // powers of a slice's exponent by linear combination (formed once, when a plan first
+  // needs them, for K <= kMaxPowK): per block, the pair products S_ab = H_a H_b + H_b H_a
+  // (a < b) and S_aa = H_a^2, (K+1)(K+2)/2 of them with (a, b) in lexicographic order, then
+  // the triple products T_abc = sum of H_x H_y H_z over the distinct orderings (x, y, z) of
+  // (a, b, c), a <= b <= c, (K+1)(K+2)(K+3)/6 of them; planes as the operators' (re, im;
+  // column-major mp x mp, zero padded), FP64 and an FP32 copy.
+  qoc::DeviceBuffer pw64, pw32;
+  std::vector<int64_t> pw_off;  // element offset of each block's products
+  bool pw_ready = false;
 };
 
 namespace qoc {
