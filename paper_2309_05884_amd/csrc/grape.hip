@@ -208,11 +208,13 @@ __device__ inline T* tplane(char* ws, size_t off_T, long long elem_off) {
 // Evaluation scheme of a slice with ||X||_1 = nx: Paterson-Stockmeyer Taylor of degree
 // q r (powers Y^2..Y^r, q-1 Horner products: r-1+q-1 products) or, q = 0, the four-product
 // degree-12 scheme (A^2, A^3 and two products); then s squarings.  The cheapest in
-// products wins, ties to the larger Paterson-Stockmeyer degree.  The degree-12 scheme is
-// offered only when t12 is set (FP32 plans: its epilogues move more data per product, which
-// the FP64 accumulator layout makes four times as costly, and its products of non-unitary
-// intermediates raise the unitarity error about threefold).
-// pow_free products (Y^2, Y^3) come from the generator and cost nothing here.
+// products wins; among Paterson-Stockmeyer degrees ties go to the larger one, and the
+// degree-12 scheme wins a tie with them (the higher degree, and every such slice shares the
+// same two launches).  The degree-12 scheme is offered only when t12 is set (FP32 plans:
+// its epilogues move more data per product, which the FP64 accumulator layout makes four
+// times as costly, and its products of non-unitary intermediates raise the unitarity error
+// about threefold).  pow_free products (Y^2, Y^3) come from the generator and cost nothing
+// here.
 __host__ __device__ inline void pick_degree(double nx, const double* theta, int r, int qmax, int t12, int pow_free,
                                             int* q_out, int* s_out) {
   int best_q = qmax, best_s = 0, best_cost = 1 << 30;
@@ -225,7 +227,7 @@ __host__ __device__ inline void pick_degree(double nx, const double* theta, int 
   if (t12) {
     int s12 = 0;
     while (s12 < 62 && nx > ldexp(theta[12], s12)) ++s12;
-    if (4 - pow_free + s12 < best_cost) { best_q = 0; best_s = s12; }
+    if (4 - pow_free + s12 <= best_cost) { best_q = 0; best_s = s12; }
   }
   *q_out = best_q;
   *s_out = best_s;
@@ -268,11 +270,13 @@ __device__ inline void gen_product_coefs(int K, int ns, const double (*us)[kMaxC
 // Pass 2 of the generator for one element idx of a job's block and the group's ns slices
 // (chunk slots Y0 + t * ent_stride): Y = -i sc H_j with sc = dt 2^-s in slot 0; with the
 // operator products (pw != null) also Y^2 = -sc^2 sum_ab u_a u_b S_ab in slot 1 and
-// Y^3 = i sc^3 sum_abc u_a u_b u_c T_abc in slot 2, and, when gen_init, the slice's first
-// Taylor combination: B4 of the degree-12 scheme (q = 0) or the Paterson-Stockmeyer
-// start T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i (r = 3) in slot r, or, for q = 1 and
-// no squaring, T0 = U itself into the propagator storage (U and U^dag).  FP64 arithmetic,
-// rounded to T once.
+// Y^3 = i sc^3 sum_abc u_a u_b u_c T_abc in slot 2.  When gen_init (FP32 plans, r = 3) the
+// slice's first Taylor combinations are formed here too: for the degree-12 scheme (q = 0)
+// B_i = sum_k c[i][k] Y^k (Y^0 = I) go to slots 0, 1, 2 (B1, B2, B3, in place of the powers,
+// which that scheme needs no more) and r (B4); for Paterson-Stockmeyer (r = 3) the start
+// T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i goes to slot r, or, for q = 1 and no
+// squaring, T0 = U itself to the propagator storage (U and U^dag).  FP64 arithmetic for Y,
+// the working precision for the product combinations (like the products they replace).
 template <typename T>
 __device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, int gen_init, const T* pw,
                                    const double (*us)[kMaxControls + 1], const T (*cp)[kMaxPair],
@@ -296,16 +300,18 @@ __device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, 
       }
     }
   }
-  // -i * scale * (hr + i hi) = scale * hi - i scale * hr
+  if (!pw) {
+    // -i * scale * (hr + i hi) = scale * hi - i scale * hr
 #pragma unroll
-  for (int t = 0; t < GEN_SG; ++t) {
-    if (t < ns) {
-      T* Y = Y0 + (size_t)t * ent_stride;
-      Y[idx] = (T)(scale[t] * hi[t]);
-      Y[idx + plane] = (T)(-scale[t] * hr[t]);
+    for (int t = 0; t < GEN_SG; ++t) {
+      if (t < ns) {
+        T* Y = Y0 + (size_t)t * ent_stride;
+        Y[idx] = (T)(scale[t] * hi[t]);
+        Y[idx + plane] = (T)(-scale[t] * hr[t]);
+      }
     }
+    return;
   }
-  if (!pw) return;
   // Y^2 = sum cp S (cp carries -sc^2), Y^3 = i sum ct T (ct carries sc^3)
   T sr[GEN_SG], si[GEN_SG], cr[GEN_SG], ci[GEN_SG];
 #pragma unroll
@@ -341,24 +347,28 @@ __device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, 
     const double y2r = sr[t], y2i = si[t];
     const double y3r = -(double)ci[t], y3i = cr[t];
     T* Y = Y0 + (size_t)t * ent_stride;
+    const int q = gen_init ? qsl[t] : 1;
+    if (gen_init && q == 0) {
+      // degree-12 scheme: B1, B2, B3 into slots 0..2, B4 into slot r
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double vr = kT12c[b][1] * y1r + kT12c[b][2] * y2r + kT12c[b][3] * y3r + (diag ? kT12c[b][0] : 0.0);
+        const double vi = kT12c[b][1] * y1i + kT12c[b][2] * y2i + kT12c[b][3] * y3i;
+        const size_t sl = b < 3 ? (size_t)b : (size_t)r;
+        Y[(2 * sl) * plane + idx] = (T)vr;
+        Y[(2 * sl + 1) * plane + idx] = (T)vi;
+      }
+      continue;
+    }
+    Y[idx] = (T)y1r;
+    Y[plane + idx] = (T)y1i;
     Y[2 * plane + idx] = (T)y2r;
     Y[3 * plane + idx] = (T)y2i;
     Y[4 * plane + idx] = (T)y3r;
     Y[5 * plane + idx] = (T)y3i;
     if (!gen_init) continue;
-    const int q = qsl[t];
-    double c0, c1, c2, c3;
-    if (q == 0) {
-      c0 = kT12c[3][0];
-      c1 = kT12c[3][1];
-      c2 = kT12c[3][2];
-      c3 = kT12c[3][3];
-    } else {
-      c0 = kInvFact[(q - 1) * 3];
-      c1 = kInvFact[(q - 1) * 3 + 1];
-      c2 = kInvFact[(q - 1) * 3 + 2];
-      c3 = kInvFact[q * 3];
-    }
+    const double c0 = kInvFact[(q - 1) * 3], c1 = kInvFact[(q - 1) * 3 + 1], c2 = kInvFact[(q - 1) * 3 + 2],
+                 c3 = kInvFact[q * 3];
     const double vr = c1 * y1r + c2 * y2r + c3 * y3r + (diag ? c0 : 0.0);
     const double vi = c1 * y1i + c2 * y2i + c3 * y3i;
     if (q == 1 && ssl[t] == 0) {
@@ -650,7 +660,7 @@ template <typename Shape>
 __global__ void __launch_bounds__(256, Shape::WAVES)
     k_expm_step(const JobDev* jobs, int njobs, long long total_items, char* ws, size_t off_T, const int* ent_s,
                 const int* ent_q, int mode, int step, int r, int seg_j0, int seg_len, int c0, int clen,
-                int skip_n, const int* flags) {
+                int skip_n, const int* flags, int gen_b) {
   typedef typename Shape::T T;
   __shared__ TileSmem<Shape> lds;
   // a Horner or squaring step no entry needs (flags[2] is the largest q, flags[1] the
@@ -804,7 +814,20 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
           for (int v = 0; v < 4; ++v)
             if (row0 + v * AccRowStep<T>::value == col && col < x.m) vr[v] += (T)coef[0];
         }
-        if (mode == STEP_T12) {
+        if (mode == STEP_T12 && gen_b) {
+          // the generator wrote B1, B2, B3 into buffers 0..2
+          if (step == 1) {
+            // A6 = B3 + B4^2 (the product); buffer 1 <- B2 + A6 (not an operand of this step)
+            vr += acc_load<T>(base + 4 * plane + at);
+            vi += acc_load<T>(base + 5 * plane + at);
+            acc_store<T>(base + 2 * plane + at, acc_load<T>(base + 2 * plane + at) + vr);
+            acc_store<T>(base + 3 * plane + at, acc_load<T>(base + 3 * plane + at) + vi);
+          } else {
+            // T12 = B1 (buffer 0) + (B2 + A6) A6
+            vr += acc_load<T>(base + at);
+            vi += acc_load<T>(base + at + plane);
+          }
+        } else if (mode == STEP_T12) {
           // sum_k c[k] P_k at this tile for P_0 = I, P_1..3 = Y, Y^2, Y^3 (buffers 0..2)
           const V4 y1r = acc_load<T>(base + at), y1i = acc_load<T>(base + at + plane);
           const V4 y2r = acc_load<T>(base + 2 * plane + at), y2i = acc_load<T>(base + 3 * plane + at);
@@ -2337,7 +2360,7 @@ static void upload_factorials() {
 // work.  Every shape accumulates each output element over k in the same order, so the
 // choice does not change any result bit.
 typedef void (*ExpmLaunch)(dim3, hipStream_t, const JobDev*, int, long long, char*, size_t, const int*,
-                           const int*, int, int, int, int, int, int, int, int, const int*);
+                           const int*, int, int, int, int, int, int, int, int, const int*, int);
 typedef void (*PanelLaunch)(dim3, hipStream_t, const JobDev*, const PanelDesc*, int, long long, char*, size_t, int,
                             int);
 typedef void (*ChainLaunch)(dim3, hipStream_t, const JobDev*, int, long long, char*, size_t, int, int, int);
@@ -2352,9 +2375,9 @@ struct GemmVariant {
 template <typename C>
 void launch_expm(dim3 g, hipStream_t st, const JobDev* j, int nj, long long items, char* ws, size_t offT,
                  const int* es, const int* eq, int mode, int step, int r, int j0, int len, int c0, int clen,
-                 int skip_n, const int* flags) {
+                 int skip_n, const int* flags, int gen_b) {
   hipLaunchKernelGGL(k_expm_step<C>, g, dim3(256), 0, st, j, nj, items, ws, offT, es, eq, mode, step, r, j0, len, c0,
-                     clen, skip_n, flags);
+                     clen, skip_n, flags, gen_b);
 }
 template <typename C>
 void launch_panel(dim3 g, hipStream_t st, const JobDev* j, const PanelDesc* d, int nd, long long items, char* ws,
@@ -2471,7 +2494,7 @@ struct Driver {
       auto step = [&](int mode, int s) {
         timed(PK_EXPM_GEMM, st, [&] {
           gemm_variant(P).expm(grid, st, dj, njobs, P->expm_items, ws, P->off_T, ent_s(P, ws), ent_q(P, ws), mode, s,
-                               P->r, seg_j0, L, c0, clen, skip_n, flags);
+                               P->r, seg_j0, L, c0, clen, skip_n, flags, P->pow_free && P->r == 3 ? 1 : 0);
         });
       };
       // powers Y^2 .. Y^r (those the generator formed are skipped)
