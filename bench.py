@@ -791,6 +791,8 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] calibration copy: {n * 4} bytes read, {n * 4} bytes written", file=sys.stderr, flush=True)
         del src, dst
+    measured_peak = {"c64": q.measure_mfma_peak("c64"), "c128": q.measure_mfma_peak("c128")}
+    print(f"[bench] measured MFMA rate (TFLOP/s): {measured_peak}", file=sys.stderr, flush=True)
     w, B, S, v0, vf, dev = build_problem(q, W, torch)
     nblocks = len(B.sizes)
     units = w.N * nblocks
@@ -893,6 +895,10 @@ def main():
                      "alg_flops_per_launch": flops32 * args.steps / gemm_n,
                      "avg_launch_ms": gemm_ms / gemm_n, "kernel_ms_per_step": gemm_ms / args.steps,
                      "executed_mfma_frac": 0.75 * achieved / MFMA_PEAK["c64"],
+                     "measured_peak": measured_peak["c64"],
+                     "measured_peak_note": "v_mfma_f32_16x16x4f32 chains on register operands over a full grid "
+                                           "(qoc_measure_mfma_peak); FP64: %.1f TFLOP/s" % measured_peak["c128"],
+                     "executed_frac_of_measured_peak": 0.75 * achieved / measured_peak["c64"],
                      "note": "algorithmic flops 8 m^3 per complex m x m product, 4 m^2 (m + 1) for the "
                              "(skew-)Hermitian powers of the generator (lower triangle; the upper is mirrored); "
                              "the kernel forms each with three real MFMA products (Gauss): 3/4 of them executed"},

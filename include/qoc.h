@@ -373,6 +373,13 @@ qoc_status qoc_lts_fidelity_grad(int n, double Bz, double c_cpl, const double* u
  * [3] forward sweep, [4] backward sweep, [5] objective, [6] gradient GEMM, [7] gradient
  * vector kernels, [8] gradient reduction, [9] other. */
 qoc_status qoc_profile_begin(int max_launches);
+/* Measured matrix-core rate of the current device for the MFMA instruction the tiles use
+ * (v_mfma_f32_16x16x4f32 for QOC_C64, v_mfma_f64_16x16x4f64 for QOC_C128): every wave of a
+ * full grid issues independent MFMAs on register operands, with no memory traffic; *tflops
+ * receives 2 * 16 * 16 * 4 flops per instruction over the time of one launch (HIP events on
+ * `stream`, after a warm-up).  The reference for the propagator GEMM's fraction of the
+ * achievable rate.  Synchronises `stream`. */
+qoc_status qoc_measure_mfma_peak(int precision, double* tflops, void* stream);
 qoc_status qoc_profile_end(double* ms, int64_t* launches, int cap);
 
 /* Per job and slice (host arrays [jobs][max N], jobs = (problem, block) pairs in order):

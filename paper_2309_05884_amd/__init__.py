@@ -20,7 +20,7 @@ from . import _capi as C
 from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "fidelity", "fidelity_batched",
-           "read_state", "check_flags", "fidelity_grad_noalloc", "STATIC_SCRATCH_BYTES", "propagate", "GrapeFidelity", "SWEEP_SOLO", "SWEEP_TEST_STALL_FWD", "SWEEP_TEST_STALL_BWD",
+           "read_state", "check_flags", "measure_mfma_peak", "fidelity_grad_noalloc", "STATIC_SCRATCH_BYTES", "propagate", "GrapeFidelity", "SWEEP_SOLO", "SWEEP_TEST_STALL_FWD", "SWEEP_TEST_STALL_BWD",
            "QocError", "library_path", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
            "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply",
            "lts_fidelity_grad", "optimize_lbfgs_lts"]
@@ -242,6 +242,13 @@ class Plan:
 
 PROFILE_KINDS = ["generator", "propagator_gemm", "gate_chain", "sweep_fwd", "sweep_bwd", "objective",
                  "gradient_gemm", "gradient_vector", "gradient_finish", "other"]
+
+
+def measure_mfma_peak(precision: str = "c64") -> float:
+    """Measured TFLOP/s of the matrix-core instruction the tiles use (qoc_measure_mfma_peak)."""
+    v = ctypes.c_double()
+    C.check(C.lib().qoc_measure_mfma_peak(C.PRECISIONS[precision], ctypes.byref(v), _stream()))
+    return float(v.value)
 
 
 def profile_begin(max_launches: int = 100000):

@@ -3320,6 +3320,25 @@ static void exec_propagate(qoc_plan_s* P, const double* u, double2* U_out, char*
     Driver<float>::propagate(P, u, U_out, ws, st);
 }
 
+// Matrix-core rate probe: every wave runs a chain of 16x16x4 MFMAs of the kind the tiles use
+// on register operands (8 independent accumulators, no memory traffic), for `iters` rounds.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mfma_peak(int iters, T* sink) {
+  typedef typename Vec4<T>::type V;
+  V acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = V{0, 0, 0, 0};
+  const T a = (T)(threadIdx.x + 1) * (T)1e-3, b = (T)(blockIdx.x + 1) * (T)1e-3;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = mfma16(a, b, acc[k]);
+  }
+  T sum = T(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sum += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+  if (sum == T(-1)) sink[0] = sum;  // never true: keeps the chain alive
+}
+
 }  // namespace qoc
 
 using namespace qoc;
@@ -3616,6 +3635,44 @@ qoc_status qoc_gate_fidelity(qoc_plan P, const void* Ka_dev, const void* Kb_dev,
                        njobs, static_cast<const double2*>(Ka_dev), static_cast<const double2*>(Kb_dev), part);
     hipLaunchKernelGGL(k_gate_finish, dim3(1), dim3(64), 0, st, dj, njobs, part, out_dev);
     QOC_HIP(hipGetLastError());
+  });
+}
+
+qoc_status qoc_measure_mfma_peak(int precision, double* tflops, void* stream) {
+  return guarded([&] {
+    QOC_REQUIRE(tflops, QOC_ERR_INVALID_ARG, "null argument");
+    QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    QOC_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    QOC_HIP(hipGetDeviceProperties(&prop, dev));
+    const void* fn = precision == QOC_C128 ? (const void*)k_mfma_peak<double> : (const void*)k_mfma_peak<float>;
+    int occ = 1;
+    QOC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, 256, 0));
+    const int grid = prop.multiProcessorCount * std::max(1, occ);
+    const int iters = 1 << 14;
+    DeviceBuffer sink(16);
+    hipEvent_t e0, e1;
+    QOC_HIP(hipEventCreate(&e0));
+    QOC_HIP(hipEventCreate(&e1));
+    auto launch = [&] {
+      if (precision == QOC_C128)
+        hipLaunchKernelGGL(k_mfma_peak<double>, dim3(grid), dim3(256), 0, st, iters, sink.as<double>());
+      else
+        hipLaunchKernelGGL(k_mfma_peak<float>, dim3(grid), dim3(256), 0, st, iters, sink.as<float>());
+    };
+    launch();  // warm-up
+    QOC_HIP(hipEventRecord(e0, st));
+    launch();
+    QOC_HIP(hipEventRecord(e1, st));
+    QOC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    QOC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // 2 * 16 * 16 * 4 flops per MFMA, 8 per round per wave, 4 waves per work-group
+    *tflops = (double)grid * 4 * 8 * iters * 2048.0 / (ms * 1e-3) / 1e12;
   });
 }
 
