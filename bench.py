@@ -222,7 +222,10 @@ def one_step(torch, run):
 
 def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, precision="c64", job_problem=None):
     """Time `steps` calls of run() after `warmup`, with the library's per-kernel events;
-    returns throughput and the propagator GEMM's fraction of the MFMA peak."""
+    returns throughput and the propagator GEMM's fraction of the MFMA peak.  The plan's
+    workspace is allocated before the timed region (set-up, not part of a step)."""
+    plan.workspace()
+    torch.cuda.synchronize()
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()

@@ -158,6 +158,7 @@ struct qoc_plan_s {
   size_t off_flags = 0, off_ent = 0, off_T = 0, off_gacc = 0, off_sync = 0, off_xchg = 0, bytes = 0;
   long long xchg_words = 0;  // per direction
   bool coop = false;      // co-operative sweeps (several work-groups per job)
+  bool coop_serial = false;  // ... whose two directions do not fit on the CUs together
   int coop_w = 1;         // largest number of work-groups of a job
   size_t coop_lds = 0;    // dynamic LDS of the co-operative sweep (bytes)
   long long expm_items = 0, panel_items = 0;
@@ -2613,7 +2614,15 @@ struct Driver {
         hipLaunchKernelGGL(k_overlap<T>, dim3(P->P), dim3(1024), 0, s, dj, dpr, ws, P->off_T, flags, out);
       });
     };
-    if (P->nseg == 1) {
+    if (P->nseg == 1 && P->coop_serial) {
+      // every propagator stays resident, but the two co-operative sweeps do not fit on the
+      // CUs together: one after the other
+      expm_segment(P, ws, u, 0, st);
+      sweep(P, ws, 0, 0, st);
+      objective(st);
+      sweep(P, ws, 1, 0, st);
+      hipLaunchKernelGGL(k_fold_flags, dim3(1), dim3(64), 0, st, flags, P->P, out);
+    } else if (P->nseg == 1) {
       // every propagator stays resident: the two sweeps are independent and run side by
       // side, the backward one on the plan's second stream (fork/join by events)
       expm_segment(P, ws, u, 0, st);
@@ -3161,7 +3170,9 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   apply_variant(P.get(), 0);
   // the sweeps keep the state and partial sums in LDS; allow the dynamic size beyond 64 KB
   const int lds = (int)(P->sweep_lds_elems * P->elem);
-  // co-operative sweeps when every work-group of both concurrent sweeps fits on its own CU
+  // co-operative sweeps when every work-group of a sweep fits on its own CU; the two
+  // directions run side by side when both sweeps' work-groups fit together, else one after
+  // the other (a plan that segments runs them one after the other anyway)
   {
     const int rb = f64 ? CoopRows<double>::value : CoopRows<float>::value;
     long long groups = 0;
@@ -3173,7 +3184,8 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       wmax = std::max(wmax, w);
       elems = std::max(elems, (size_t)2 * j.d * j.mp + (size_t)2 * 16 * j.d * rb);
     }
-    P->coop = 2 * groups <= ncu && elems * P->elem <= 160 * 1024;
+    P->coop = groups <= ncu && elems * P->elem <= 160 * 1024;
+    P->coop_serial = P->coop && 2 * groups > ncu;
     P->coop_w = wmax;
     P->coop_lds = elems * P->elem;
   }
