@@ -2785,13 +2785,14 @@ static ProblemSpec all_blocks(qoc_system_s* sys, int N, double dt) {
   return ProblemSpec{sys, N, dt, sys->blocks};
 }
 
-// The operator products of qoc_system_s::pw64 / pw32 (see there), formed once per system:
-// ordered pair products P_xy = H_x H_y (temporary), S_ab from them, then every triple
+// The operator products of qoc_system_s::pw64 / pw32 (see there), formed once per system
+// and kept in the precision a plan asks for (FP64 for complex128 plans, FP32 for complex64
+// ones): ordered pair products P_xy = H_x H_y (temporary), S_ab from them, then every triple
 // product as H_x S_yz summed over the representatives of its distinct orderings:
 // T_aaa = H_a S_aa; T_aac = H_a S_ac + H_c S_aa; T_acc = H_a S_cc + H_c S_ac;
 // T_abc = H_a S_bc + H_b S_ac + H_c S_ab (a < b < c).
-static void ensure_powers(qoc_system_s* S) {
-  if (S->pw_ready || S->K > kMaxPowK) return;
+static void ensure_powers(qoc_system_s* S, bool f64) {
+  if (S->K > kMaxPowK || (f64 ? S->pw64.ptr : S->pw32.ptr) != nullptr) return;
   const int K = S->K, O = K + 1, npair = pair_count(K), ntrip = triple_count(K), npw = npair + ntrip;
   int64_t elems = 0;
   S->pw_off.clear();
@@ -2799,8 +2800,7 @@ static void ensure_powers(qoc_system_s* S) {
     S->pw_off.push_back(elems);
     elems += (int64_t)npw * 2 * b.mp * b.mp;
   }
-  S->pw64.alloc((size_t)elems * sizeof(double));
-  S->pw32.alloc((size_t)elems * sizeof(float));
+  DeviceBuffer prod((size_t)elems * sizeof(double));
   hipStream_t st = nullptr;
   typedef TileShape<double, 2, 2, 2> Shape;
   auto pair_index = [&](int a, int b) {  // position of (a <= b) in lexicographic order
@@ -2814,7 +2814,7 @@ static void ensure_powers(qoc_system_s* S) {
     const size_t plane = (size_t)mp * mp;
     const int tm = (mp + Shape::BM - 1) / Shape::BM, tn = (mp + Shape::BN - 1) / Shape::BN;
     const double* H = S->h64.as<double>() + blk.h_off;
-    double* PW = S->pw64.as<double>() + S->pw_off[bi];
+    double* PW = prod.as<double>() + S->pw_off[bi];
     auto op = [&](int o) { return H + (size_t)(2 * o) * plane; };
     auto pw = [&](int idx) { return PW + (size_t)(2 * idx) * plane; };
     DeviceBuffer tmp((size_t)O * O * 2 * plane * sizeof(double));
@@ -2881,11 +2881,15 @@ static void ensure_powers(qoc_system_s* S) {
       if (!part.empty()) run(part);
     }
   }
-  hipLaunchKernelGGL(k_planes_to_float, dim3(4096), dim3(256), 0, st, S->pw64.as<double>(), S->pw32.as<float>(),
-                     (size_t)elems);
-  QOC_HIP(hipGetLastError());
-  QOC_HIP(hipStreamSynchronize(st));
-  S->pw_ready = true;
+  if (f64) {
+    S->pw64 = std::move(prod);
+  } else {
+    S->pw32.alloc((size_t)elems * sizeof(float));
+    hipLaunchKernelGGL(k_planes_to_float, dim3(4096), dim3(256), 0, st, prod.as<double>(), S->pw32.as<float>(),
+                       (size_t)elems);
+    QOC_HIP(hipGetLastError());
+    QOC_HIP(hipStreamSynchronize(st));
+  }
 }
 
 // Default workspace budget: 85 % of the free device memory (the rest for the caller's
@@ -2921,7 +2925,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     bool all = true;
     for (auto& pr : probs) all = all && pr.sys->K <= kMaxPowK;
     if (all)
-      for (auto& pr : probs) ensure_powers(pr.sys);
+      for (auto& pr : probs) ensure_powers(pr.sys, f64);
     P->pow_free = all ? 2 : 0;
   }
   const double unit = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);

@@ -160,10 +160,9 @@ struct qoc_system_s {
   // (a < b) and S_aa = H_a^2, (K+1)(K+2)/2 of them with (a, b) in lexicographic order, then
   // the triple products T_abc = sum of H_x H_y H_z over the distinct orderings (x, y, z) of
   // (a, b, c), a <= b <= c, (K+1)(K+2)(K+3)/6 of them; planes as the operators' (re, im;
-  // column-major mp x mp, zero padded), FP64 and an FP32 copy.
+  // column-major mp x mp, zero padded), FP64 and / or FP32 (whichever plans have needed).
   qoc::DeviceBuffer pw64, pw32;
   std::vector<int64_t> pw_off;  // element offset of each block's products
-  bool pw_ready = false;
 };
 
 namespace qoc {
