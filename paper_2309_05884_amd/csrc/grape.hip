@@ -2892,6 +2892,15 @@ static void ensure_powers(qoc_system_s* S, bool f64) {
   }
 }
 
+// The operator products of every system of a plan, when all have at most kMaxPowK controls
+// (formed before the workspace budget is taken from the free memory).
+static bool prepare_powers(const std::vector<ProblemSpec>& probs, bool f64) {
+  for (auto& pr : probs)
+    if (pr.sys->K > kMaxPowK) return false;
+  for (auto& pr : probs) ensure_powers(pr.sys, f64);
+  return true;
+}
+
 // Default workspace budget: 85 % of the free device memory (the rest for the caller's
 // tensors and the allocator), at most 240 GiB of the 288 GB part.
 static size_t default_budget() {
@@ -2921,13 +2930,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->qmax = f64 ? 6 : 4;  // degrees up to 24 (FP64) / 12 (FP32)
   P->t12 = f64 ? 0 : 1;
   // Y^2 and Y^3 from the operator products when every system has them (few controls)
-  {
-    bool all = true;
-    for (auto& pr : probs) all = all && pr.sys->K <= kMaxPowK;
-    if (all)
-      for (auto& pr : probs) ensure_powers(pr.sys, f64);
-    P->pow_free = all ? 2 : 0;
-  }
+  P->pow_free = prepare_powers(probs, f64) ? 2 : 0;
   const double unit = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
   double nb = 0.0;
   int max_mp = 0;
@@ -3217,8 +3220,12 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
 }
 
 // Bytes a group of problems needs with every propagator resident: states, gradient slots
-// for a chunk of `chunk` slices, U and U^dag of every slice, and the Taylor scratch of 8
-// slices (the layout build_plan makes, without the alignment of its regions).
+// for a chunk of `chunk` slices, U and U^dag of every slice, and the Taylor scratch of
+// kGroupChunk slices (the layout build_plan makes, without the alignment of its regions).
+// The propagators of a group are formed kGroupChunk slices per round of launches or more:
+// a group packed with the scratch of only a few slices would pay each launch's tail many
+// times over.
+constexpr int kGroupChunk = 32;
 static size_t resident_bytes(const std::vector<ProblemSpec>& probs, size_t b0, size_t b1, size_t elem, int r,
                              int nslots, int chunk) {
   size_t fixed = 0, grad = 0, props = 0, scratch = 0;
@@ -3235,7 +3242,7 @@ static size_t resident_bytes(const std::vector<ProblemSpec>& probs, size_t b0, s
       scratch += (size_t)(r + 2) * 2 * mp * mp * elem;
     }
   }
-  return fixed + grad + props + (size_t)std::min(nmax, 8) * scratch;
+  return fixed + grad + props + (size_t)std::min(nmax, kGroupChunk) * scratch;
 }
 
 // Split a batched plan whose propagators do not all fit into groups of consecutive problems
@@ -3399,6 +3406,8 @@ qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* 
     QOC_REQUIRE(P >= 1 && P <= 65535, QOC_ERR_INVALID_ARG, "P must be in 1..65535");
     std::vector<ProblemSpec> probs;
     for (int p = 0; p < P; ++p) probs.push_back(all_blocks(systems[p], N[p], dt[p]));
+    QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
+    prepare_powers(probs, precision == QOC_C128);
     const size_t budget = max_ws ? max_ws : default_budget();
     std::unique_ptr<qoc_plan_s> full(build_plan(probs, precision, u_bound, budget));
     if (full->nseg > 1 && P > 1) group_problems(full.get(), probs, precision, u_bound, budget);
