@@ -220,7 +220,8 @@ def one_step(torch, run):
     return e0.elapsed_time(e1), res
 
 
-def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, precision="c64", job_problem=None):
+def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, precision="c64", job_problem=None,
+                 launches_per_step=8192):
     """Time `steps` calls of run() after `warmup`, with the library's per-kernel events;
     returns throughput and the propagator GEMM's fraction of the MFMA peak.  The plan's
     workspace is allocated before the timed region (set-up, not part of a step)."""
@@ -229,7 +230,7 @@ def profiled_leg(q, torch, plan, run, steps, warmup, u_flat, job_sizes, units, p
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
-    q.profile_begin(steps * 8192)
+    q.profile_begin(steps * launches_per_step)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
@@ -640,7 +641,7 @@ def sym_leg(q, torch, W, C):
 
     nb = len(Bs.sizes)
     sym = profiled_leg(q, torch, Ps, run, 1, 0, uflat, list(Bs.sizes) * C, C * nb * ws.N,
-                       job_problem=[c for c in range(C) for _ in range(nb)])
+                       job_problem=[c for c in range(C) for _ in range(nb)], launches_per_step=1 << 17)
     out = res["out"]
     for c in range(C):
         q.check_flags(out[c])
@@ -744,6 +745,7 @@ def batch_leg(q, torch, W, Pn):
     torch.cuda.empty_cache()
     fp = _fp64_subset(q, torch, subset_plan, lambda P: q.fidelity_grad_batched(P, ub[:k], p0[:k], pf[:k], check=False))
     fp["subset"] = f"first {k} problems"
+    print(f"[bench] batch: planning {len(wl)} problems", file=sys.stderr, flush=True)
     Pb = q.Plan.batched(systems, "c64", [x.N for x in wl], [x.dt for x in wl], 1.0)
     Pb.set_variant(chosen)
     uflat = torch.cat([x.reshape(-1) for x in ub])
@@ -755,7 +757,11 @@ def batch_leg(q, torch, W, Pn):
         res["out"], res["grads"] = q.fidelity_grad_batched(Pb, ub, p0, pf, check=False)
 
     jp = [p for p, x in enumerate(wl) for _ in bases[x.n].sizes]
-    batch = profiled_leg(q, torch, Pb, run, 1, 0, uflat, sizes, units_b, job_problem=jp)
+    print(f"[bench] batch plan: {Pb.info['problem_groups']} problem groups, workspace {Pb.workspace_bytes / 2**30:.1f} GiB",
+          file=sys.stderr, flush=True)
+    q.set_progress(True)  # a line per finished problem group: a full-size step runs for minutes
+    batch = profiled_leg(q, torch, Pb, run, 1, 0, uflat, sizes, units_b, job_problem=jp, launches_per_step=1 << 18)
+    q.set_progress(False)
     out = res["out"]
     for p in range(len(wl)):
         q.check_flags(out[p])

@@ -191,16 +191,19 @@ qoc_status qoc_plan_create_blocks(qoc_system system, const int* blocks, int nblo
 void qoc_plan_free(qoc_plan plan);
 qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
 /* Plan facts: info[0] segment length, [1] number of segments, [2] Taylor degree step r,
- * [3] largest degree, [4] Frechet series terms, [5] Frechet sub-steps, [6] propagator
- * bytes per slice, [7] largest squaring count, [8] gradient chunk (slices), [9] GEMM
+ * [3] largest degree, [4] Frechet series terms, [5] Frechet sub-steps, [6] workspace
+ * bytes per slice (propagator slot and Taylor scratch), [7] largest squaring count, [8] gradient chunk (slices), [9] GEMM
  * grid, [10] problems P, [11] (problem, block) jobs, [12] total controls (sum N_p K_p),
  * [13] total panel length (sum D_p), [14] total propagator entries, [15] GEMM tile
  * variant in use, [16] slices per Taylor-scratch chunk, [17] largest number of work-groups
  * sharing one block's sweep (1: one work-group per block), [18] problem groups, [19] powers
  * of the exponent formed by the generator instead of products (2: Y^2 and Y^3, for systems
- * with at most 4 controls; 0 otherwise).
- * Workspace: U and U^dag of every slice of a segment, Taylor scratch (Y..Y^r and two
- * ping-pong buffers) of one chunk of slices, states, gradient slots.  When the budget holds
+ * with at most 4 controls; 0 otherwise), [20] planes per propagator slot (4: U and room for
+ * the gate product tree; 2: U alone).
+ * Workspace: U of every slice of a segment (both sweeps read it: the backward one takes
+ * U^dag lambda as dot products down U's columns), Taylor scratch (Y..Y^r and two ping-pong
+ * buffers) of one chunk of slices, states, gradient slots; each slice's slot also holds
+ * room for qoc_gate_propagate's product tree when the plan fits in one pass with it.  When the budget holds
  * everything, segment = chunk = N; when it holds every propagator and the scratch of at
  * least 8 slices, segment = N and the chunk is what the rest holds; otherwise the
  * propagators of earlier segments are recomputed during the backward sweep.
@@ -306,8 +309,9 @@ qoc_status qoc_plan_set_sweep_mode(qoc_plan plan, int mode);
  * in qoc_propagate and multiplied as a balanced tree of batched complex GEMMs on the MFMA
  * units (log2 N levels, N - 1 products per block).  K_out_dev receives, block after
  * block, column-major m x m interleaved complex128 matrices (length sum of m^2).
- * Requires every propagator of the pulse to fit the plan's workspace (one segment,
- * qoc_plan_info [1] == 1), else QOC_ERR_UNSUPPORTED; QOC_ERR_UNSUPPORTED for a batched
+ * Requires every propagator of the pulse to fit the plan's workspace twice over (one
+ * segment with room for the tree: qoc_plan_info [1] == 1 and [20] == 4), else
+ * QOC_ERR_UNSUPPORTED; QOC_ERR_UNSUPPORTED for a batched
  * plan.  Like qoc_propagate it reports no status word: qoc_plan_slice_stats or
  * qoc_fidelity_grad flag controls beyond the plan's norm bound.  Asynchronous on
  * `stream`; uses the workspace as qoc_fidelity_grad does. */
@@ -363,6 +367,14 @@ qoc_status qoc_lts_fidelity_grad(int n, double Bz, double c_cpl, const double* u
                                  int P, const void* psi0_dev, const void* psif_dev, double* out_dev,
                                  double* grad_dev, void* workspace, size_t workspace_bytes, void* stream);
 
+/* Progress lines for long batched calls (process-wide switch, off by default).  When
+ * enabled, every call on a plan with problem groups (qoc_plan_groups) queues after each
+ * group a host function on the call's stream that prints, once the group's work has
+ * finished, "[qoc] problem group g/G done (problems a..b)" to stderr.  For callers that
+ * watch a long call's liveness; it adds one host callback per group and is not meant for
+ * graph capture.  Always QOC_OK. */
+qoc_status qoc_set_progress(int enable);
+
 /* Benchmark instrumentation (process-wide, not thread-safe while enabled).
  * qoc_profile_begin pre-creates HIP events for up to max_launches kernel launches and
  * enables recording: every kernel the hot-path calls enqueue is bracketed by events on
@@ -371,7 +383,9 @@ qoc_status qoc_lts_fidelity_grad(int n, double Bz, double c_cpl, const double* u
  * [0] generator + norm, [1] propagator GEMM (powers, Horner or degree-12 steps,
  * squarings), [2] gate product tree (qoc_gate_propagate),
  * [3] forward sweep, [4] backward sweep, [5] objective, [6] gradient GEMM, [7] gradient
- * vector kernels, [8] gradient reduction, [9] other. */
+ * vector kernels, [8] gradient reduction, [9] other.  qoc_profile_end returns
+ * QOC_ERR_INVALID_ARG (after writing the partial totals) when more launches were made than
+ * max_launches covers. */
 qoc_status qoc_profile_begin(int max_launches);
 /* Measured matrix-core rate of the current device for the MFMA instruction the tiles use
  * (v_mfma_f32_16x16x4f32 for QOC_C64, v_mfma_f64_16x16x4f64 for QOC_C128): every wave of a

@@ -83,6 +83,7 @@ PROTOTYPES = {
     "qoc_measure_mfma_peak": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]),
     "qoc_plan_groups": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_int]),
+    "qoc_set_progress": (ctypes.c_int, [ctypes.c_int]),
     "qoc_profile_begin": (ctypes.c_int, [ctypes.c_int]),
     "qoc_profile_end": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
     "qoc_plan_slice_stats": (ctypes.c_int, [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),

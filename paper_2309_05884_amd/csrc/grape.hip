@@ -27,7 +27,10 @@
 // processed in segments of equal length for every job; a job whose problem has fewer
 // slices simply has less (or no) work in the later segments.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <memory>
 #include <mutex>
 
 #include "mfma_tile.h"
@@ -49,7 +52,9 @@ struct JobDev {
   const void* pwT;       // working-precision operator products (qoc_system_s::pw*), or null
   long long ent_off;     // first entry (slice of a segment) of this job
   long long item_off;    // first propagator GEMM item of this job
-  long long ubuf_off;    // propagators of the segment: per slice U and U^dag (elements of T)
+  long long ubuf_off;    // propagators of the segment: per slice U (elements of T)
+  long long uslot;       // elements per propagator slot: U (2 planes), or U and the product
+                         // tree's second half (4 planes) when the plan has room for both
   long long sbuf_off;    // Taylor scratch of one chunk: per slice Y..Y^r and two ping-pong buffers
   long long psi_off;     // forward states (elements of T), planes of mp x (N+1)d
   long long lam_off;     // costates (elements of T), planes of mp x N d
@@ -150,6 +155,7 @@ struct qoc_plan_s {
   double norm_bound = 0.0;
   int seg_len = 0, nseg = 0;
   int echunk = 0;  // slices whose Taylor scratch is resident at once (the segment is formed in chunks)
+  int uplanes = 4;  // planes per propagator slot: U (2), or U and the gate tree's second half (4)
   int R = 1, Q = 1;
   int chunk = 0;  // slices per gradient chunk
   int nslots = 0;
@@ -374,12 +380,9 @@ __device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, 
     const double vi = c1 * y1i + c2 * y2i + c3 * y3i;
     if (q == 1 && ssl[t] == 0) {
       // degree 3, no squaring: T0 is the propagator
-      T* U = U0 + (size_t)t * 4 * plane;
+      T* U = U0 + (size_t)t * jb.uslot;
       U[idx] = (T)vr;
       U[idx + plane] = (T)vi;
-      const size_t tr = (size_t)c + (size_t)rr * mp;  // U^dag[c][rr] = conj(U[rr][c])
-      U[2 * plane + tr] = (T)vr;
-      U[3 * plane + tr] = (T)(-vi);
     } else {
       Y[(size_t)(2 * r) * plane + idx] = (T)vr;
       Y[(size_t)(2 * r + 1) * plane + idx] = (T)vi;
@@ -482,7 +485,7 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
   __syncthreads();
   const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
   T* Y0 = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)(jl0 - c0) * ent_stride;
-  T* U0 = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl0 * 4 * plane;
+  T* U0 = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl0 * jb.uslot;
   const int gen_init = pow_free && r == 3;
   for (size_t idx = threadIdx.x; idx < plane; idx += blockDim.x)
     gen_element<T>(jb, idx, ns, r, gen_init, pw, us, cp, ct, scale, qsl, ssl, Y0, ent_stride, U0);
@@ -635,7 +638,7 @@ __global__ void __launch_bounds__(256) k_gen_form(const JobDev* jobs, int njobs,
   __syncthreads();
   const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
   T* Y0 = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)(jl0 - c0) * ent_stride;
-  T* U0 = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl0 * 4 * plane;
+  T* U0 = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl0 * jb.uslot;
   const int gen_init = pow_free && r == 3;
   for (size_t idx = lo + threadIdx.x; idx < hi_; idx += blockDim.x)
     gen_element<T>(jb, idx, ns, r, gen_init, pw, us, cp, ct, scale, qsl, ssl, Y0, ent_stride, U0);
@@ -647,13 +650,13 @@ enum { STEP_POWER = 0, STEP_HORNER = 1, STEP_SQUARE = 2, STEP_T12 = 3 };
 // One product step over every entry of a chunk of the segment (persistent, XCD-grouped
 // items).  Taylor scratch of an entry (one slot per chunk slice): 0 = Y, i-1 = Y^i (i <= r),
 // r and r+1 = ping-pong T.  The last power step also forms the Horner start T0; the last
-// product of an entry writes U and U^dag into the segment's propagator storage.
+// product of an entry writes U into the segment's propagator storage.
 // One tile product of the propagator formation: operands, where the result goes.
 template <typename T>
 struct ExpmItem {
   TileOperands<T> op;
   T* base;   // Taylor scratch of the entry's chunk slot
-  T* ubase;  // U, then U^dag, of the entry
+  T* ubase;  // U of the entry
   int m, ic, se, qe;
 };
 
@@ -710,7 +713,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     const int mp = jb.mp;
     const size_t plane = (size_t)mp * mp;
     x.base = tplane<T>(ws, off_T, jb.sbuf_off) + (size_t)jc * (size_t)(r + 2) * 2 * plane;
-    x.ubase = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * 4 * plane;
+    x.ubase = tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * jb.uslot;
     x.m = jb.m;
     x.ic = ic;
     x.se = se;
@@ -900,25 +903,6 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
           for (int v = 0; v < 4; ++v)
             if (row0 + v * AccRowStep<T>::value == col && col < x.m) tr[v] += (T)coef[0];
           put(init_final ? ubase : base + (size_t)r * 2 * plane, tr, ti, mr, mi);
-          if (init_final) {
-            T* D = ubase + 2 * plane;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              T* dr = D + (size_t)col + (size_t)(row0 + v * AccRowStep<T>::value) * mp;
-              dr[0] = tr[v];
-              dr[plane] = -ti[v];
-            }
-          }
-        }
-        if (final_op) {
-          // conjugate transpose for the backward sweep: Udag[col][row] = conj(U[row][col])
-          T* D = ubase + 2 * plane;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            T* dr = D + (size_t)col + (size_t)(row0 + v * AccRowStep<T>::value) * mp;
-            dr[0] = vr[v];
-            dr[plane] = -vi[v];
-          }
         }
       }
     if (!more) break;
@@ -930,7 +914,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
 template <typename T>
 __device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int jl, int dagger) {
   const size_t plane = (size_t)jb.mp * jb.mp;
-  return tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * 4 * plane + (dagger ? 2 * plane : 0);
+  return tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * jb.uslot + (dagger ? 2 * plane : 0);
 }
 
 // ===================================================================== state set-up
@@ -998,11 +982,11 @@ __global__ void k_export_state(const JobDev* jobs, int job_begin, int job_end, c
 
 // ===================================================================== sweeps
 // Sweep through one segment, one work-group (16 waves) per job, the state in LDS.
-// DIR 0: psi_{j+1} = U_j psi_j from the forward store; DIR 1: lambda_j = U_j^dag
-// lambda_{j+1} with the conjugate transpose written by the last product of each slice,
-// so both directions stream their matrix column by column.  A lane owns two adjacent
-// rows (8- or 16-byte loads), a wave 128 rows and one of G k-ranges; loads are unrolled
-// so that many bytes are in flight per lane; partial sums meet in LDS.
+// DIR 0: psi_{j+1} = U_j psi_j, streaming U column by column: a lane owns 16 bytes of
+// consecutive rows, a wave 64 such row vectors and one of G k-ranges; loads are unrolled
+// so that many bytes are in flight per lane; partial sums meet in LDS.  DIR 1 (lambda_j =
+// U_j^dag lambda_{j+1}) reads the same stored U as dot products down its columns
+// (sweep_solo_bwd and the *_bwd variants below): only U is kept per slice.
 template <typename T> struct SweepUnroll { static constexpr int value = 8; };
 template <> struct SweepUnroll<double> { static constexpr int value = 4; };
 
@@ -1139,13 +1123,132 @@ __device__ void sweep_solo(const JobDev& jb, char* ws, size_t off_T, const int* 
   }
 }
 
+// ---- backward sweeps from the forward store.  Row i of U^dag is the conjugate of column i
+// of U, contiguous in memory, so each entry of lambda_j = U_j^dag lambda_{j+1} is a dot
+// product down one column.  KL lanes share a row; each takes RPL consecutive entries of
+// the column (one 16-byte load per plane) per pass of KL * RPL entries, and the KL partial
+// sums meet by butterfly shuffles.  Entries at or beyond m are masked (the state is zero
+// there and the padding of U is never read into a sum).
+template <typename T, int KL, int UNR>
+__device__ inline void dag_row_acc(const T* col, size_t plane, int m, int k0, const T* sre, const T* sim, int mp,
+                                   int d, T (&a)[2][2]) {
+  typedef typename Vec16<T>::type TV;
+  constexpr int RPL = Vec16<T>::n, STEP = KL * RPL;
+  for (int kb = k0; kb < m; kb += STEP * UNR) {
+    TV ur[UNR] = {}, ui[UNR] = {};
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) {
+      const int k = kb + q * STEP;
+      if (k < m) {
+        ur[q] = *reinterpret_cast<const TV*>(col + k);
+        ui[q] = *reinterpret_cast<const TV*>(col + k + plane);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < UNR; ++q) {
+      const int k = kb + q * STEP;
+      if (k >= m) break;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c >= d) break;
+        const TV pr = *reinterpret_cast<const TV*>(sre + c * mp + k);
+        const TV pi = *reinterpret_cast<const TV*>(sim + c * mp + k);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          const bool in = k + e < m;
+          const T xr = in ? ur[q][e] : T(0), xi = in ? ui[q][e] : T(0);
+          // conj(x) p = (xr pr + xi pi) + i (xr pi - xi pr)
+          a[c][0] += xr * pr[e] + xi * pi[e];
+          a[c][1] += xr * pi[e] - xi * pr[e];
+        }
+      }
+    }
+  }
+}
+
+// sum over each group of KL consecutive lanes (every lane of the group ends with the total)
+template <int KL, typename T>
+__device__ inline void lane_group_sum(T (&a)[2][2]) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      T v = a[c][h];
+#pragma unroll
+      for (int sh = 1; sh < KL; sh <<= 1) v += __shfl_xor(v, sh);
+      a[c][h] = v;
+    }
+}
+
+// One work-group sweeps one job backwards through the segment: the 16 waves take the rows
+// RW = RPL at a time; the state and the next one alternate between two LDS buffers, so a
+// slice costs one barrier.
+template <typename T>
+__device__ void sweep_solo_bwd(const JobDev& jb, char* ws, size_t off_T, int seg_j0, int seg_len) {
+  constexpr int RPL = Vec16<T>::n, RW = RPL, KL = 64 / RW;
+  extern __shared__ __attribute__((aligned(16))) char smem_raw[];
+  const int len = job_len(jb, seg_j0, seg_len);
+  if (len <= 0) return;
+  const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
+  T* cre = reinterpret_cast<T*>(smem_raw);  // state [d][mp], then the next state
+  T* cim = cre + (size_t)d * mp;
+  T* nre = cim + (size_t)d * mp;
+  T* nim = nre + (size_t)d * mp;
+  T* S = tplane<T>(ws, off_T, jb.lam_off);
+  const size_t ps = (size_t)mp * N * d;
+  const size_t plane = (size_t)mp * mp;
+  {
+    const int col_in = seg_j0 + len - 1;
+    for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
+      const int c = idx / mp, i = idx % mp;
+      const size_t g = ((size_t)col_in * d + c) * mp + i;
+      cre[idx] = S[g];
+      cim[idx] = S[g + ps];
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int rr = lane / KL, kl = lane % KL;
+  for (int it = 0; it < len; ++it) {
+    const int jl = len - 1 - it;
+    const T* U = entry_U<T>(jb, ws, off_T, jl, 0);
+    const int col_out = seg_j0 + jl - 1;
+    for (int rg = wave; rg * RW < mp; rg += nw) {
+      const int i = rg * RW + rr;  // < mp (a multiple of 16)
+      T a[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+      if (i < m) dag_row_acc<T, KL, 4>(U + (size_t)i * mp, plane, m, kl * RPL, cre, cim, mp, d, a);
+      lane_group_sum<KL>(a);
+      if (kl == 0)
+        for (int c = 0; c < d; ++c) {
+          nre[c * mp + i] = a[c][0];
+          nim[c * mp + i] = a[c][1];
+          if (col_out >= 0) {
+            const size_t g = ((size_t)col_out * d + c) * mp + i;
+            S[g] = a[c][0];
+            S[g + ps] = a[c][1];
+          }
+        }
+    }
+    __syncthreads();
+    T* t = cre;
+    cre = nre;
+    nre = t;
+    t = cim;
+    cim = nim;
+    nim = t;
+  }
+}
+
 template <typename T, int DIR>
 __global__ void __launch_bounds__(1024) k_sweep(const JobDev* jobs, int njobs, char* ws, size_t off_T,
                                                 const int* ent_s, const int* ent_q, int r, int seg_j0, int seg_len) {
   const int J = blockIdx.x;
   if (J >= njobs) return;
   const JobDev jb = jobs[J];
-  sweep_solo<T, DIR>(jb, ws, off_T, ent_s, ent_q, r, seg_j0, seg_len);
+  if constexpr (DIR == 1)
+    sweep_solo_bwd<T>(jb, ws, off_T, seg_j0, seg_len);
+  else
+    sweep_solo<T, DIR>(jb, ws, off_T, ent_s, ent_q, r, seg_j0, seg_len);
 }
 
 // ---- co-operative sweep: the rows of a job are split over W = ceil(mp / RB) work-groups
@@ -1346,6 +1449,160 @@ __device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j
   }
 }
 
+// The backward sweep of a job whose rows fit one work-group: wave w takes rows 4w .. 4w+3,
+// 16 lanes per row cover the column (16 RPL = RB entries); the next slice's column segment
+// is loaded while the current one is applied, and the state alternates between two LDS
+// buffers, so a slice costs one barrier.
+template <typename T>
+__device__ void sweep_single_bwd(const JobDev& jb, char* ws, size_t off_T, int seg_j0, int len, char* smem_raw) {
+  typedef typename Vec16<T>::type TV;
+  constexpr int RPL = Vec16<T>::n, KL = 16;
+  const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
+  T* st = reinterpret_cast<T*>(smem_raw);  // [buffer][re, im][d][mp]
+  T* S = tplane<T>(ws, off_T, jb.lam_off);
+  const size_t ps = (size_t)mp * N * d;
+  const size_t plane = (size_t)mp * mp;
+  const size_t dm = (size_t)d * mp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rr = lane / KL, kl = lane % KL;
+  const int i = 4 * wave + rr, k = kl * RPL;  // 4 waves per 16 rows cover mp (launch width)
+  const bool act = i < m && k < m;
+  {
+    const int col_in = seg_j0 + len - 1;
+    for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
+      const int c = idx / mp, ii = idx % mp;
+      const size_t g = ((size_t)col_in * d + c) * mp + ii;
+      st[idx] = S[g];
+      st[dm + idx] = S[g + ps];
+    }
+  }
+  TV ur = {}, ui = {};
+  if (act) {
+    const T* U = entry_U<T>(jb, ws, off_T, len - 1, 0) + (size_t)i * mp + k;
+    ur = *reinterpret_cast<const TV*>(U);
+    ui = *reinterpret_cast<const TV*>(U + plane);
+  }
+  __syncthreads();
+  for (int it = 0; it < len; ++it) {
+    const int jl = len - 1 - it;
+    TV nr = {}, ni = {};
+    if (act && it + 1 < len) {
+      const T* U = entry_U<T>(jb, ws, off_T, jl - 1, 0) + (size_t)i * mp + k;
+      nr = *reinterpret_cast<const TV*>(U);
+      ni = *reinterpret_cast<const TV*>(U + plane);
+    }
+    const T* cre = st + (size_t)(it & 1) * 2 * dm;
+    const T* cim = cre + dm;
+    T* nre = st + (size_t)((it + 1) & 1) * 2 * dm;
+    T* nim = nre + dm;
+    T a[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c >= d) break;
+        const TV pr = *reinterpret_cast<const TV*>(cre + c * mp + k);
+        const TV pi = *reinterpret_cast<const TV*>(cim + c * mp + k);
+#pragma unroll
+        for (int e = 0; e < RPL; ++e) {
+          const bool in = k + e < m;
+          const T xr = in ? ur[e] : T(0), xi = in ? ui[e] : T(0);
+          a[c][0] += xr * pr[e] + xi * pi[e];
+          a[c][1] += xr * pi[e] - xi * pr[e];
+        }
+      }
+    }
+    lane_group_sum<KL>(a);
+    const int col_out = seg_j0 + jl - 1;
+    if (kl == 0 && i < mp)
+      for (int c = 0; c < d; ++c) {
+        nre[c * mp + i] = a[c][0];
+        nim[c * mp + i] = a[c][1];
+        if (col_out >= 0) {
+          const size_t g = ((size_t)col_out * d + c) * mp + i;
+          S[g] = a[c][0];
+          S[g + ps] = a[c][1];
+        }
+      }
+    __syncthreads();
+    ur = nr;
+    ui = ni;
+  }
+}
+
+// The backward co-operative sweep's slices (after the groups agreed to go): rows of this
+// group r0 .. r0 + RB - 1, wave w rows r0 + RW w .. + RW - 1 with KL = 64 / RW lanes each;
+// the hand-off is the forward sweep's (tagged words by slice parity).  One LDS state
+// buffer: a barrier after each slice keeps the next slice's state read behind every
+// wave's use of the current one.
+template <typename T>
+__device__ void sweep_coop_bwd(const JobDev& jb, char* ws, size_t off_T, int seg_j0, int len,
+                               unsigned long long* X, int* flags, unsigned tag_skew, char* smem_raw) {
+  typedef XchgVal<T> XV;
+  constexpr int RPL = Vec16<T>::n, RB = CoopRows<T>::value, RW = RPL, KL = 64 / RW;
+  __shared__ int abort_now;
+  const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
+  T* sre = reinterpret_cast<T*>(smem_raw);  // state [d][mp]
+  T* sim = sre + (size_t)d * mp;
+  T* S = tplane<T>(ws, off_T, jb.lam_off);
+  const size_t ps = (size_t)mp * N * d;
+  const size_t plane = (size_t)mp * mp;
+  const size_t xplane = (size_t)d * mp * XV::W;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rr = lane / KL, kl = lane % KL;
+  const int i = blockIdx.x * RB + wave * RW + rr;
+  {
+    const int col_in = seg_j0 + len - 1;
+    for (int idx = threadIdx.x; idx < mp * d; idx += blockDim.x) {
+      const int c = idx / mp, ii = idx % mp;
+      const size_t g = ((size_t)col_in * d + c) * mp + ii;
+      sre[idx] = S[g];
+      sim[idx] = S[g + ps];
+    }
+    if (threadIdx.x == 0) abort_now = 0;
+    __syncthreads();
+  }
+  for (int it = 0; it < len; ++it) {
+    const int jl = len - 1 - it;
+    if (it > 0) {
+      // the state after slice it - 1, published by every group with tag it
+      const unsigned long long* Xp = X + (size_t)((it - 1) & 1) * 2 * xplane;
+      bool ok = true;
+      for (int idx = threadIdx.x; idx < mp * d && ok; idx += blockDim.x) {
+        T vr = T(0), vi = T(0);
+        ok = XV::get(Xp + (size_t)idx * XV::W, (unsigned)it + tag_skew, vr) &&
+             XV::get(Xp + xplane + (size_t)idx * XV::W, (unsigned)it + tag_skew, vi);
+        sre[idx] = vr;
+        sim[idx] = vi;
+      }
+      if (!ok) {
+        abort_now = 1;
+        __hip_atomic_fetch_or(flags, kFlagSweepAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __syncthreads();
+      if (abort_now) return;
+    }
+    const T* U = entry_U<T>(jb, ws, off_T, jl, 0);
+    T a[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
+    if (i < m) dag_row_acc<T, KL, 4>(U + (size_t)i * mp, plane, m, kl * RPL, sre, sim, mp, d, a);
+    lane_group_sum<KL>(a);
+    const int col_out = seg_j0 + jl - 1;
+    if (kl == 0 && i < mp)
+      for (int c = 0; c < d; ++c) {
+        if (it + 1 < len) {
+          unsigned long long* Xo = X + (size_t)(it & 1) * 2 * xplane + ((size_t)c * mp + i) * XV::W;
+          XV::put(Xo, a[c][0], (unsigned)(it + 1));
+          XV::put(Xo + xplane, a[c][1], (unsigned)(it + 1));
+        }
+        if (col_out >= 0) {
+          const size_t g = ((size_t)col_out * d + c) * mp + i;
+          S[g] = a[c][0];
+          S[g + ps] = a[c][1];
+        }
+      }
+    __syncthreads();
+  }
+}
+
 // mode (host test switches, 0 in normal use): bit 0 -- group 0 runs every multi-group job
 // alone without waiting for the others (sweep_solo); bit 1 -- the groups wait for hand-off
 // tags that are never written, so every bounded wait times out and the sweep gives up with
@@ -1368,18 +1625,28 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
   const int W = (mp + RB - 1) / RB;
   if ((int)blockIdx.x >= W) return;
   if (W == 1) {
-    sweep_single<T, DIR>(jb, ws, off_T, seg_j0, len, smem_raw);
+    if constexpr (DIR == 1)
+      sweep_single_bwd<T>(jb, ws, off_T, seg_j0, len, smem_raw);
+    else
+      sweep_single<T, DIR>(jb, ws, off_T, seg_j0, len, smem_raw);
     return;
   }
   int* ctl = ctl_all + 4 * J;
   const int decision = coop_decide(ctl, W, flags, mode & 1);
   if (decision == kCoopSolo) {
-    sweep_solo<T, DIR>(jb, ws, off_T, ent_s, ent_q, r, seg_j0, seg_len);
+    if constexpr (DIR == 1)
+      sweep_solo_bwd<T>(jb, ws, off_T, seg_j0, seg_len);
+    else
+      sweep_solo<T, DIR>(jb, ws, off_T, ent_s, ent_q, r, seg_j0, seg_len);
     return;
   }
   if (decision != kCoopGo) return;
   // tags run 1 .. len - 1 < 2^24 (N <= 2^24): the skewed tag is never written
   const unsigned tag_skew = (mode & 2) ? (1u << 30) : 0u;
+  if (DIR == 1) {
+    sweep_coop_bwd<T>(jb, ws, off_T, seg_j0, len, xchg_all + jb.xchg_off, flags, tag_skew, smem_raw);
+    return;
+  }
   T* sre = reinterpret_cast<T*>(smem_raw);  // state [d][mp]
   T* sim = sre + (size_t)d * mp;
   T* pre = sim + (size_t)d * mp;             // wave partials [16][d][RB]
@@ -2031,8 +2298,8 @@ __global__ void k_grad_finish(const JobDev* jobs, const ProbDev* probs, const ch
 // The time-ordered product K = U_{N-1} ... U_1 U_0 of every block (the unitary a pulse
 // implements, Sec. III B), as a balanced tree of batched complex GEMMs: at each level,
 // factor pair p (slots 2p and 2p+1 of half `src` of the propagator store: half 0 holds U,
-// half 1 U^dag, which this path does not need) becomes U_{2p+1} U_{2p} in slot p of the
-// other half, and an odd last factor is carried over.  The level's items are laid out as
+// half 1 is room the plan keeps for this tree when it fits) becomes U_{2p+1} U_{2p} in slot
+// p of the other half, and an odd last factor is carried over.  The level's items are laid out as
 // the propagator GEMM's (echunk pair slots x tiles per job); a launch covers pairs
 // c0 .. c0 + echunk - 1.  Reads and writes of one level touch different halves.
 template <typename Shape>
@@ -2059,10 +2326,10 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     const int mp = jb.mp;
     const size_t plane = (size_t)mp * mp;
     T* ub = tplane<T>(ws, off_T, jb.ubuf_off);
-    x.op.A = ub + (size_t)(2 * p + 1) * 4 * plane + (size_t)src * 2 * plane;
+    x.op.A = ub + (size_t)(2 * p + 1) * jb.uslot + (size_t)src * 2 * plane;
     x.op.a_ps = plane;
     x.op.lda = mp;
-    x.op.B = ub + (size_t)(2 * p) * 4 * plane + (size_t)src * 2 * plane;
+    x.op.B = ub + (size_t)(2 * p) * jb.uslot + (size_t)src * 2 * plane;
     x.op.b_ps = plane;
     x.op.ldb = mp;
     x.op.M = mp;
@@ -2070,7 +2337,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     x.op.K = mp;
     x.op.row0 = ti * Shape::BM;
     x.op.col0 = tj * Shape::BN;
-    x.C = ub + (size_t)p * 4 * plane + (size_t)(1 - src) * 2 * plane;
+    x.C = ub + (size_t)p * jb.uslot + (size_t)(1 - src) * 2 * plane;
     return true;
   };
   long long it = rg.begin;
@@ -2111,8 +2378,8 @@ __global__ void k_chain_carry(const JobDev* jobs, int njobs, char* ws, size_t of
     const JobDev jb = jobs[J];
     const size_t plane = (size_t)jb.mp * jb.mp;
     T* ub = tplane<T>(ws, off_T, jb.ubuf_off);
-    const T* a = ub + (size_t)from * 4 * plane + (size_t)src * 2 * plane;
-    T* b = ub + (size_t)to * 4 * plane + (size_t)(1 - src) * 2 * plane;
+    const T* a = ub + (size_t)from * jb.uslot + (size_t)src * 2 * plane;
+    T* b = ub + (size_t)to * jb.uslot + (size_t)(1 - src) * 2 * plane;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * plane; i += (size_t)gridDim.x * blockDim.x)
       b[i] = a[i];
   }
@@ -2258,6 +2525,7 @@ struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
+  size_t dropped = 0;  // launches made while the pool was exhausted (not timed)
   struct Rec { int kind; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::mutex mu;
@@ -2273,6 +2541,7 @@ static void timed(int kind, hipStream_t st, F&& launch) {
     QOC_HIP(hipEventRecord(b, st));
     g_prof.recs.push_back({kind, a, b});
   } else {
+    if (g_prof.on) ++g_prof.dropped;
     launch();
   }
   QOC_HIP(hipGetLastError());
@@ -2892,12 +3161,32 @@ static void ensure_powers(qoc_system_s* S, bool f64) {
   }
 }
 
-// The operator products of every system of a plan, when all have at most kMaxPowK controls
-// (formed before the workspace budget is taken from the free memory).
+// Whether a plan's generator forms Y^2 and Y^3 from operator products: every system has at
+// most kMaxPowK controls, and the products still missing fit in an eighth of the free device
+// memory (a large batch of distinct Hamiltonians keeps that memory for its propagators, whose
+// recomputation would cost more than the two power products per slice).  Forms the missing
+// products when it says yes; call it before the workspace budget is read from the free memory.
 static bool prepare_powers(const std::vector<ProblemSpec>& probs, bool f64) {
   for (auto& pr : probs)
     if (pr.sys->K > kMaxPowK) return false;
-  for (auto& pr : probs) ensure_powers(pr.sys, f64);
+  std::vector<qoc_system_s*> missing;
+  size_t bytes = 0;
+  for (auto& pr : probs) {
+    qoc_system_s* S = pr.sys;
+    if ((f64 ? S->pw64.ptr : S->pw32.ptr) != nullptr ||
+        std::find(missing.begin(), missing.end(), S) != missing.end())
+      continue;
+    missing.push_back(S);
+    size_t planes = 0;
+    for (auto& b : S->blocks) planes += (size_t)b.mp * b.mp;
+    bytes += (size_t)(pair_count(S->K) + triple_count(S->K)) * 2 * planes * (f64 ? sizeof(double) : sizeof(float));
+  }
+  if (!missing.empty()) {
+    size_t free_b = 0, total_b = 0;
+    QOC_HIP(hipMemGetInfo(&free_b, &total_b));
+    if (bytes > free_b / 8) return false;
+    for (auto* S : missing) ensure_powers(S, f64);
+  }
   return true;
 }
 
@@ -2909,7 +3198,12 @@ static size_t default_budget() {
   return std::min<size_t>((size_t)240 << 30, free_b / 20 * 17);
 }
 
-static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precision, double u_bound, size_t max_ws) {
+// pow_mode: -1 decides whether the generator uses operator products (prepare_powers); 0 / 1
+// take a decision made for the whole batch (1: the products exist).  parent (a problem
+// group's plan): the batch plan whose numerical choices the group takes over -- products,
+// Frechet sub-steps and terms, gradient route -- so that grouping changes no result.
+static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precision, double u_bound, size_t max_ws,
+                              int pow_mode = -1, const qoc_plan_s* parent = nullptr) {
   QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
   QOC_REQUIRE(std::isfinite(u_bound) && u_bound >= 0.0, QOC_ERR_INVALID_ARG, "u_bound must be finite and >= 0");
   QOC_REQUIRE(!probs.empty(), QOC_ERR_INVALID_ARG, "no problems");
@@ -2930,7 +3224,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->qmax = f64 ? 6 : 4;  // degrees up to 24 (FP64) / 12 (FP32)
   P->t12 = f64 ? 0 : 1;
   // Y^2 and Y^3 from the operator products when every system has them (few controls)
-  P->pow_free = prepare_powers(probs, f64) ? 2 : 0;
+  P->pow_free = parent ? parent->pow_free : (pow_mode < 0 ? prepare_powers(probs, f64) : pow_mode > 0) ? 2 : 0;
   const double unit = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
   double nb = 0.0;
   int max_mp = 0;
@@ -2991,6 +3285,11 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
     P->Q = bestQ;
   }
   P->small_grad = max_mp <= kSmallGradMaxWidth && P->R * P->Q <= kSmallGradMaxRQ;
+  if (parent) {  // the parent's bound covers this subset: its choices hold here too
+    P->R = parent->R;
+    P->Q = parent->Q;
+    P->small_grad = parent->small_grad;
+  }
   QOC_REQUIRE(max_mp <= 4096, QOC_ERR_UNSUPPORTED, "blocks larger than 4096 are not supported by the sweep kernels");
   P->max_mp = max_mp;
   size_t lds_elems = 0;
@@ -3002,70 +3301,84 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   const int K = P->Kmax;
   const int nslots = K + 4 + P->R * P->Q;
   P->nslots = nslots;
-  // per-slice bytes: U and U^dag kept for the segment, Taylor scratch (Y..Y^r, two
-  // ping-pong buffers) for one chunk; fixed state bytes
-  size_t per_slice = 0, per_scratch = 0, fixed = 0;
+  // per-slice bytes: U kept for the segment (uplanes planes: U alone, or U and room for
+  // the gate product tree), Taylor scratch (Y..Y^r, two ping-pong buffers) for one chunk;
+  // fixed state bytes
+  size_t per_plane = 0, per_scratch = 0, fixed = 0;
   for (auto& pr : probs)
     for (auto& b : pr.blocks) {
-      per_slice += (size_t)2 * 2 * b.mp * b.mp * P->elem;
+      per_plane += (size_t)b.mp * b.mp * P->elem;
       per_scratch += (size_t)(P->r + 2) * 2 * b.mp * b.mp * P->elem;
       fixed += (size_t)2 * b.mp * ((size_t)(pr.N + 1) * b.d + (size_t)pr.N * b.d) * P->elem;
     }
-  int chunk = std::min(P->Nmax, 2048);
-  auto grad_bytes = [&](int ch) {
-    size_t g = 0;
-    for (auto& pr : probs)
-      for (auto& b : pr.blocks) {
-        const int cc = (ch * b.d + 15) / 16 * 16;
-        g += (size_t)nslots * 2 * b.mp * cc * P->elem + (size_t)cc * K * 16;
-      }
-    return g;
-  };
   const size_t budget = max_ws ? max_ws : default_budget();
-  while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice + per_scratch > budget) chunk /= 2;
-  // A smaller gradient chunk (down to 16 slices: more, narrower gradient launches, the same
-  // work) is preferred when it lets every propagator stay resident (no recompute in the
-  // backward sweep).  When the propagators must be segmented anyway, the gradient slots
-  // take at most an eighth of the budget, so that the segments stay long: each segment
-  // costs a round of launches and every segment but the last is formed twice.
-  const long long ec_min = std::min(P->Nmax, 8);
-  auto resident = [&](int ch) {
-    return fixed + grad_bytes(ch) + (size_t)P->Nmax * per_slice + (size_t)ec_min * per_scratch <= budget;
-  };
-  if (!resident(chunk)) {
-    int ch = chunk;
-    while (ch > 16 && !resident(ch)) ch /= 2;
-    if (resident(ch)) {
-      chunk = ch;
-    } else {
-      while (chunk > 16 && grad_bytes(chunk) > budget / 8) chunk /= 2;
+  // The segment length, Taylor chunk and gradient chunk for uplanes planes per slice; true
+  // when everything is resident and formed in one pass.
+  auto plan_memory = [&](int uplanes) {
+    const size_t per_slice = (size_t)uplanes * per_plane;
+    int chunk = std::min(P->Nmax, 2048);
+    auto grad_bytes = [&](int ch) {
+      size_t g = 0;
+      for (auto& pr : probs)
+        for (auto& b : pr.blocks) {
+          const int cc = (ch * b.d + 15) / 16 * 16;
+          g += (size_t)nslots * 2 * b.mp * cc * P->elem + (size_t)cc * K * 16;
+        }
+      return g;
+    };
+    while (chunk > 16 && fixed + grad_bytes(chunk) + per_slice + per_scratch > budget) chunk /= 2;
+    // A smaller gradient chunk (down to 16 slices: more, narrower gradient launches, the same
+    // work) is preferred when it lets every propagator stay resident (no recompute in the
+    // backward sweep).  When the propagators must be segmented anyway, the gradient slots
+    // take at most an eighth of the budget, so that the segments stay long: each segment
+    // costs a round of launches and every segment but the last is formed twice.
+    const long long ec_min = std::min(P->Nmax, 8);
+    auto resident = [&](int ch) {
+      return fixed + grad_bytes(ch) + (size_t)P->Nmax * per_slice + (size_t)ec_min * per_scratch <= budget;
+    };
+    if (!resident(chunk)) {
+      int ch = chunk;
+      while (ch > 16 && !resident(ch)) ch /= 2;
+      if (resident(ch)) {
+        chunk = ch;
+      } else {
+        while (chunk > 16 && grad_bytes(chunk) > budget / 8) chunk /= 2;
+      }
     }
-  }
-  P->chunk = chunk;
-  const size_t need = fixed + grad_bytes(chunk);
-  const size_t avail = budget > need ? budget - need : 0;
-  if ((size_t)P->Nmax * (per_slice + per_scratch) <= avail) {
-    // everything resident: one segment formed in one pass
-    P->seg_len = P->echunk = P->Nmax;
-  } else if ((size_t)P->Nmax * per_slice + (size_t)ec_min * per_scratch <= avail) {
-    // every propagator resident (no recompute in the backward sweep); the rest holds the
-    // Taylor scratch of as many slices as fit
-    P->seg_len = P->Nmax;
-    P->echunk = (int)std::min<long long>(P->Nmax, (long long)((avail - (size_t)P->Nmax * per_slice) /
-                                                              std::max<size_t>(per_scratch, 1)));
-  } else {
-    // Taylor scratch for a chunk of slices (at most an eighth of the budget, at least 8 slices
-    // when they fit), U and U^dag of as many slices as the rest holds
-    long long ec = (long long)(avail / 8 / std::max<size_t>(per_scratch, 1));
-    ec = std::max<long long>(1, std::min<long long>(ec, P->Nmax));
-    if (ec < 8) ec = std::max<long long>(1, std::min<long long>(8, (long long)(avail / 2 / std::max<size_t>(per_scratch, 1))));
-    const size_t left = avail > (size_t)ec * per_scratch ? avail - (size_t)ec * per_scratch : 0;
-    const long long seg = (long long)(left / std::max<size_t>(per_slice, 1));
-    QOC_REQUIRE(seg >= 1, QOC_ERR_OUT_OF_MEMORY, "workspace budget below one slice of propagators");
-    P->seg_len = (int)std::min<long long>(seg, P->Nmax);
-    P->echunk = (int)std::min<long long>(ec, P->seg_len);
-  }
-  P->nseg = (P->Nmax + P->seg_len - 1) / P->seg_len;
+    P->chunk = chunk;
+    const size_t need = fixed + grad_bytes(chunk);
+    const size_t avail = budget > need ? budget - need : 0;
+    if ((size_t)P->Nmax * (per_slice + per_scratch) <= avail) {
+      // everything resident: one segment formed in one pass
+      P->seg_len = P->echunk = P->Nmax;
+    } else if ((size_t)P->Nmax * per_slice + (size_t)ec_min * per_scratch <= avail) {
+      // every propagator resident (no recompute in the backward sweep); the rest holds the
+      // Taylor scratch of as many slices as fit
+      P->seg_len = P->Nmax;
+      P->echunk = (int)std::min<long long>(P->Nmax, (long long)((avail - (size_t)P->Nmax * per_slice) /
+                                                                std::max<size_t>(per_scratch, 1)));
+    } else {
+      // Taylor scratch for a chunk of slices (at most an eighth of the budget, at least 8 slices
+      // when they fit), U of as many slices as the rest holds
+      long long ec = (long long)(avail / 8 / std::max<size_t>(per_scratch, 1));
+      ec = std::max<long long>(1, std::min<long long>(ec, P->Nmax));
+      if (ec < 8) ec = std::max<long long>(1, std::min<long long>(8, (long long)(avail / 2 / std::max<size_t>(per_scratch, 1))));
+      const size_t left = avail > (size_t)ec * per_scratch ? avail - (size_t)ec * per_scratch : 0;
+      const long long seg = (long long)(left / std::max<size_t>(per_slice, 1));
+      if (seg < 1 && uplanes > 2) return false;  // the U-only layout may still fit
+      QOC_REQUIRE(seg >= 1, QOC_ERR_OUT_OF_MEMORY, "workspace budget below one slice of propagators");
+      P->seg_len = (int)std::min<long long>(seg, P->Nmax);
+      P->echunk = (int)std::min<long long>(ec, P->seg_len);
+    }
+    P->nseg = (P->Nmax + P->seg_len - 1) / P->seg_len;
+    return P->nseg == 1 && P->echunk == P->Nmax;
+  };
+  // Room for the gate product tree's second half only where it costs nothing: when the
+  // plan is resident and formed in one pass with it; otherwise U alone, so that longer
+  // segments (or every slice) fit.
+  P->uplanes = plan_memory(4) ? 4 : 2;
+  if (P->uplanes == 2) plan_memory(2);
+  const int chunk = P->chunk;
   // layout
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -3110,7 +3423,8 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       j.ent_off = ent_off;
       ent_off += P->seg_len;
       j.ubuf_off = tel;
-      tel += (long long)P->seg_len * 2 * 2 * b.mp * b.mp;
+      j.uslot = (long long)P->uplanes * b.mp * b.mp;
+      tel += (long long)P->seg_len * j.uslot;
       j.sbuf_off = tel;
       tel += (long long)P->echunk * (P->r + 2) * 2 * b.mp * b.mp;
       j.psi_off = tel;
@@ -3220,7 +3534,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
 }
 
 // Bytes a group of problems needs with every propagator resident: states, gradient slots
-// for a chunk of `chunk` slices, U and U^dag of every slice, and the Taylor scratch of
+// for a chunk of `chunk` slices, U of every slice, and the Taylor scratch of
 // kGroupChunk slices (the layout build_plan makes, without the alignment of its regions).
 // The propagators of a group are formed kGroupChunk slices per round of launches or more:
 // a group packed with the scratch of only a few slices would pay each launch's tail many
@@ -3238,7 +3552,7 @@ static size_t resident_bytes(const std::vector<ProblemSpec>& probs, size_t b0, s
       fixed += 2 * mp * ((size_t)(pr.N + 1) * b.d + (size_t)pr.N * b.d) * elem;
       const size_t cc = (size_t)(std::min(chunk, nmax) * b.d + 15) / 16 * 16;
       grad += (size_t)nslots * 2 * mp * cc * elem + cc * pr.sys->K * 16;
-      props += (size_t)pr.N * 4 * mp * mp * elem;
+      props += (size_t)pr.N * 2 * mp * mp * elem;
       scratch += (size_t)(r + 2) * 2 * mp * mp * elem;
     }
   }
@@ -3266,7 +3580,7 @@ static void group_problems(qoc_plan_s* full, const std::vector<ProblemSpec>& pro
     const auto [b0, b1] = todo.front();
     todo.erase(todo.begin());
     std::vector<ProblemSpec> sub(probs.begin() + b0, probs.begin() + b1);
-    std::unique_ptr<qoc_plan_s> g(build_plan(sub, precision, u_bound, budget));
+    std::unique_ptr<qoc_plan_s> g(build_plan(sub, precision, u_bound, budget, -1, full));
     if (g->nseg > 1 && b1 - b0 > 1) {
       const size_t mid = b0 + (b1 - b0) / 2;
       todo.insert(todo.begin(), {{b0, mid}, {mid, b1}});
@@ -3296,6 +3610,26 @@ static GroupOffsets group_offsets(const qoc_plan_s* P, size_t g) {
   return {pb.u_off, jb.state_off, 8LL * p0, jb.uout_off};
 }
 
+// Opt-in progress lines (qoc_set_progress): after each problem group of a grouped call a
+// host function queued on the stream reports, once the group's work has finished, which
+// problems it covered.
+static std::atomic<int> g_progress{0};
+struct ProgressNote {
+  int g, G, p0, p1;
+};
+static void progress_note_cb(void* p) {
+  std::unique_ptr<ProgressNote> n(static_cast<ProgressNote*>(p));
+  std::fprintf(stderr, "[qoc] problem group %d/%d done (problems %d..%d)\n", n->g + 1, n->G, n->p0, n->p1 - 1);
+  std::fflush(stderr);
+}
+static void note_group_done(const qoc_plan_s* P, size_t g, hipStream_t st) {
+  if (!g_progress.load(std::memory_order_relaxed)) return;
+  const int p1 = g + 1 < P->groups.size() ? P->grp_prob0[g + 1] : P->P;
+  std::unique_ptr<ProgressNote> n(new ProgressNote{(int)g, (int)P->groups.size(), P->grp_prob0[g], p1});
+  QOC_HIP(hipLaunchHostFunc(st, progress_note_cb, n.get()));
+  n.release();  // the host function owns it now
+}
+
 // The hot-path calls on a plan, group by group when the plan has problem groups.
 static void exec_run(qoc_plan_s* P, const double* u, const void* psi0, const void* psif, double* out, double* grad,
                      char* ws, hipStream_t st) {
@@ -3304,6 +3638,7 @@ static void exec_run(qoc_plan_s* P, const double* u, const void* psi0, const voi
       const GroupOffsets o = group_offsets(P, g);
       exec_run(P->groups[g], u + o.u, static_cast<const double2*>(psi0) + o.D, static_cast<const double2*>(psif) + o.D,
                out + o.out, grad + o.u, ws, st);
+      note_group_done(P, g, st);
     }
     return;
   }
@@ -3320,6 +3655,7 @@ static void exec_objective(qoc_plan_s* P, const double* u, const void* psi0, con
       const GroupOffsets o = group_offsets(P, g);
       exec_objective(P->groups[g], u + o.u, static_cast<const double2*>(psi0) + o.D,
                      static_cast<const double2*>(psif) + o.D, out + o.out, ws, st);
+      note_group_done(P, g, st);
     }
     return;
   }
@@ -3334,6 +3670,7 @@ static void exec_propagate(qoc_plan_s* P, const double* u, double2* U_out, char*
     for (size_t g = 0; g < P->groups.size(); ++g) {
       const GroupOffsets o = group_offsets(P, g);
       exec_propagate(P->groups[g], u + o.u, U_out + o.U, ws, st);
+      note_group_done(P, g, st);
     }
     return;
   }
@@ -3407,9 +3744,9 @@ qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* 
     std::vector<ProblemSpec> probs;
     for (int p = 0; p < P; ++p) probs.push_back(all_blocks(systems[p], N[p], dt[p]));
     QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
-    prepare_powers(probs, precision == QOC_C128);
+    const bool pw = prepare_powers(probs, precision == QOC_C128);
     const size_t budget = max_ws ? max_ws : default_budget();
-    std::unique_ptr<qoc_plan_s> full(build_plan(probs, precision, u_bound, budget));
+    std::unique_ptr<qoc_plan_s> full(build_plan(probs, precision, u_bound, budget, pw ? 1 : 0));
     if (full->nseg > 1 && P > 1) group_problems(full.get(), probs, precision, u_bound, budget);
     *out = full.release();
   });
@@ -3428,7 +3765,7 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
   return guarded([&] {
     QOC_REQUIRE(P && info, QOC_ERR_INVALID_ARG, "null argument");
     size_t per_slice = 0;
-    for (auto& j : P->jobs) per_slice += (size_t)(2 + P->r + 2) * 2 * j.mp * j.mp * P->elem;
+    for (auto& j : P->jobs) per_slice += (size_t)(P->uplanes + (P->r + 2) * 2) * j.mp * j.mp * P->elem;
     // a plan with problem groups reports the execution of the group with the most segments
     const qoc_plan_s* E = P;
     int sweep_groups = P->coop ? P->coop_w : 1;
@@ -3436,11 +3773,11 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
       if (E == P || g->nseg > E->nseg) E = g;
       sweep_groups = std::max(sweep_groups, g->coop ? g->coop_w : 1);
     }
-    int64_t v[20] = {E->seg_len, E->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
+    int64_t v[21] = {E->seg_len, E->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
                      E->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U,
                      P->variant, E->echunk, sweep_groups, (int64_t)std::max<size_t>(1, P->groups.size()),
-                     P->pow_free};
-    for (int i = 0; i < cap && i < 20; ++i) info[i] = v[i];
+                     P->pow_free, E->uplanes};
+    for (int i = 0; i < cap && i < 21; ++i) info[i] = v[i];
   });
 }
 
@@ -3634,8 +3971,9 @@ qoc_status qoc_gate_propagate(qoc_plan P, const double* u_dev, void* K_out_dev, 
     QOC_REQUIRE(P && u_dev && K_out_dev && workspace, QOC_ERR_INVALID_ARG, "null argument");
     QOC_REQUIRE(ws_bytes >= P->bytes, QOC_ERR_OUT_OF_MEMORY, "workspace smaller than the plan requires");
     QOC_REQUIRE(P->P == 1, QOC_ERR_UNSUPPORTED, "gate propagation takes a one-problem plan");
-    QOC_REQUIRE(P->nseg == 1, QOC_ERR_UNSUPPORTED,
-                "gate propagation needs every propagator of the pulse resident (one segment)");
+    QOC_REQUIRE(P->nseg == 1 && P->uplanes == 4, QOC_ERR_UNSUPPORTED,
+                "gate propagation needs every propagator of the pulse resident twice over (one segment with room "
+                "for the product tree)");
     hipStream_t st = (hipStream_t)stream;
     if (P->prec == QOC_C128)
       Driver<double>::gate(P, u_dev, static_cast<double2*>(K_out_dev), (char*)workspace, st);
@@ -3701,6 +4039,11 @@ qoc_status qoc_measure_mfma_peak(int precision, double* tflops, void* stream) {
   });
 }
 
+qoc_status qoc_set_progress(int enable) {
+  g_progress.store(enable ? 1 : 0, std::memory_order_relaxed);
+  return QOC_OK;
+}
+
 qoc_status qoc_profile_begin(int max_launches) {
   return guarded([&] {
     QOC_REQUIRE(max_launches >= 0 && max_launches <= (1 << 22), QOC_ERR_INVALID_ARG, "max_launches out of range");
@@ -3712,6 +4055,7 @@ qoc_status qoc_profile_begin(int max_launches) {
       g_prof.pool.push_back(e);
     }
     g_prof.used = 0;
+    g_prof.dropped = 0;
     g_prof.recs.clear();
     g_prof.on = true;
   });
@@ -3734,8 +4078,12 @@ qoc_status qoc_profile_end(double* ms, int64_t* launches, int cap) {
       if (ms) ms[i] = acc[i];
       if (launches) launches[i] = cnt[i];
     }
+    const size_t dropped = g_prof.dropped;
     g_prof.recs.clear();
     g_prof.used = 0;
+    g_prof.dropped = 0;
+    QOC_REQUIRE(dropped == 0, QOC_ERR_INVALID_ARG,
+                "more launches than qoc_profile_begin's max_launches: the totals would be partial");
   });
 }
 

@@ -74,11 +74,15 @@ def test_gate_rejects_segmented_plans(lib):
     B, S = _system(lib, n, h0, hk)
     P = lib.Plan(S, "c128", N, dt, 1.0)
     Pseg = None
-    for frac in (0.7, 0.5, 0.35, 0.25, 0.15):  # budgets that hold only part of the pulse's propagators
+    assert P.info["propagator_planes"] == 4
+    Pone = None  # one segment, but no room for the tree's second half
+    for frac in (0.9, 0.8, 0.7, 0.6, 0.5, 0.35, 0.25, 0.15, 0.1, 0.07, 0.05):  # budgets below the full plan
         try:
             cand = lib.Plan(S, "c128", N, dt, 1.0, max_workspace_bytes=int(P.workspace_bytes * frac))
         except QocError:
             break
+        if cand.info["segments"] == 1 and cand.info["propagator_planes"] == 2 and Pone is None:
+            Pone = cand
         if cand.info["segments"] > 1:
             Pseg = cand
             break
@@ -86,6 +90,9 @@ def test_gate_rejects_segmented_plans(lib):
     u = torch.zeros((N, 2), dtype=torch.float64, device="cuda")
     with pytest.raises(QocError, match="UNSUPPORTED"):
         lib.gate_propagate(Pseg, u)
+    assert Pone is not None
+    with pytest.raises(QocError, match="UNSUPPORTED"):
+        lib.gate_propagate(Pone, u)
 
 
 def test_ring12_block_at_full_size_equals_the_time_ordered_product(lib):

@@ -180,15 +180,17 @@ def test_workspace_budgets_bitwise_equal(lib):
     ob = oracle_blocks(6, w.h0, w.hk)
     psi0, psif = all_states(ob, np.random.default_rng(6))
     out1, g1, P1 = _device(lib, 6, "dihedral", 1, w.h0, w.hk, w.u, w.dt, psi0, psif, "c64")
-    assert P1.info["segments"] == 1 and P1.info["expm_chunk"] == 48
+    assert P1.info["segments"] == 1 and P1.info["expm_chunk"] == 48 and P1.info["propagator_planes"] == 4
     full = P1.workspace_bytes
     seen = set()
-    for frac in (0.9, 0.75, 0.5, 0.35):
+    for frac in (0.9, 0.75, 0.5, 0.35, 0.25, 0.18, 0.12, 0.08):
         o, g, P = _device(lib, 6, "dihedral", 1, w.h0, w.hk, w.u, w.dt, psi0, psif, "c64", max_ws=int(full * frac))
         info = P.info
         seen.add((info["segments"] > 1, info["expm_chunk"] < info["segment"]))
-        print(f"  budget {frac}: segments {info['segments']} segment {info['segment']} chunk {info['expm_chunk']}",
-              flush=True)
+        print(f"  budget {frac}: segments {info['segments']} segment {info['segment']} chunk {info['expm_chunk']} "
+              f"planes {info['propagator_planes']}", flush=True)
         assert np.array_equal(o[:6], out1[:6]) and np.array_equal(g, g1)
+        if info["segments"] > 1:
+            break
     assert (False, True) in seen or (True, True) in seen
     assert any(seg for seg, _ in seen)

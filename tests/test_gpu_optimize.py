@@ -117,7 +117,7 @@ def test_optimiser_on_a_segmented_plan_takes_the_same_steps(lib):
     h0, hk, b0, p0, pf, u0 = _problem(24)
     P = _gpu_plan(lib, h0, hk, "c128", 3.0)
     Pseg = None
-    for frac in (0.6, 0.45, 0.3, 0.2):
+    for frac in (0.6, 0.45, 0.3, 0.2, 0.14, 0.1, 0.07, 0.05):
         B = lib.Basis(N_QUBITS, "dihedral", 1)
         S = lib.System(B, h0, hk)
         cand = lib.Plan(S, "c128", N, DT, 3.0, max_workspace_bytes=int(P.workspace_bytes * frac), blocks=[0])
