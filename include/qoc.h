@@ -199,7 +199,8 @@ qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
  * sharing one block's sweep (1: one work-group per block), [18] problem groups, [19] powers
  * of the exponent formed by the generator instead of products (2: Y^2 and Y^3, for systems
  * with at most 4 controls; 0 otherwise), [20] planes per propagator slot (4: U and room for
- * the gate product tree; 2: U alone).
+ * the gate product tree; 2: U alone), [21] 1 when operator products are formed per call in
+ * the workspace (qoc_set_products_policy).
  * Workspace: U of every slice of a segment (both sweeps read it: the backward one takes
  * U^dag lambda as dot products down U's columns), Taylor scratch (Y..Y^r and two ping-pong
  * buffers) of one chunk of slices, states, gradient slots; each slice's slot also holds
@@ -366,6 +367,16 @@ qoc_status qoc_lts_grad_workspace_size(int n, int N, int P, size_t* bytes);
 qoc_status qoc_lts_fidelity_grad(int n, double Bz, double c_cpl, const double* u_dev, int N, double dt,
                                  int P, const void* psi0_dev, const void* psif_dev, double* out_dev,
                                  double* grad_dev, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Where plans created from now on take the operator products of systems with at most 4
+ * controls (process-wide, host call).  0 (default): a plan forms the products its systems
+ * lack and keeps them with the systems when they fit an eighth of the free device memory;
+ * otherwise (a large batch of distinct Hamiltonians) the products of the systems without
+ * them are formed at the start of every hot-path call into the plan's workspace (counted in
+ * qoc_plan_workspace_size), in the plan's precision, group by group for plans with problem
+ * groups.  1: always the workspace form for systems that keep no products (for tests of
+ * that form).  QOC_ERR_INVALID_ARG for another value. */
+qoc_status qoc_set_products_policy(int policy);
 
 /* Progress lines for long batched calls (process-wide switch, off by default).  When
  * enabled, every call on a plan with problem groups (qoc_plan_groups) queues after each

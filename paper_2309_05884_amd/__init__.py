@@ -21,7 +21,7 @@ from ._capi import QocError
 
 __all__ = ["Basis", "System", "Plan", "fidelity_grad", "fidelity_grad_batched", "fidelity", "fidelity_batched",
            "read_state", "check_flags", "measure_mfma_peak", "fidelity_grad_noalloc", "STATIC_SCRATCH_BYTES", "propagate", "GrapeFidelity", "SWEEP_SOLO", "SWEEP_TEST_STALL_FWD", "SWEEP_TEST_STALL_BWD",
-           "QocError", "library_path", "set_progress", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
+           "QocError", "library_path", "set_progress", "set_products_policy", "profile_begin", "profile_end", "slice_stats", "CapturedStep",
            "optimize_lbfgs", "gate_propagate", "gate_fidelity", "lts_apply",
            "lts_fidelity_grad", "optimize_lbfgs_lts"]
 
@@ -138,7 +138,8 @@ class Plan:
     INFO_KEYS = ["segment", "segments", "taylor_step", "max_degree", "series_terms", "substeps",
                  "bytes_per_slice", "max_squarings", "grad_chunk", "gemm_grid", "problems", "jobs",
                  "total_controls", "total_panel", "total_propagator", "gemm_variant", "expm_chunk", "sweep_groups",
-                 "problem_groups", "powers_from_generator", "propagator_planes"]
+                 "problem_groups", "powers_from_generator", "propagator_planes",
+                 "products_in_workspace"]
     N_VARIANTS = 3
 
     def __init__(self, system: System, precision: str = "c128", N: int = 1, dt: float = 0.01,
@@ -249,6 +250,11 @@ def measure_mfma_peak(precision: str = "c64") -> float:
     v = ctypes.c_double()
     C.check(C.lib().qoc_measure_mfma_peak(C.PRECISIONS[precision], ctypes.byref(v), _stream()))
     return float(v.value)
+
+
+def set_products_policy(policy: int = 0):
+    """Where new plans keep operator products: 0 automatic, 1 always in the workspace (qoc_set_products_policy)."""
+    C.check(C.lib().qoc_set_products_policy(int(policy)))
 
 
 def set_progress(enable: bool = True):

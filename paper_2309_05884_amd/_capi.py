@@ -84,6 +84,7 @@ PROTOTYPES = {
     "qoc_plan_groups": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_int]),
     "qoc_set_progress": (ctypes.c_int, [ctypes.c_int]),
+    "qoc_set_products_policy": (ctypes.c_int, [ctypes.c_int]),
     "qoc_profile_begin": (ctypes.c_int, [ctypes.c_int]),
     "qoc_profile_end": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
     "qoc_plan_slice_stats": (ctypes.c_int, [vp, vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),

@@ -10,10 +10,11 @@
 //   Y = X_j / 2^s_j;  T = T_p(Y) by Paterson-Stockmeyer (powers Y^2..Y^r, then q_j-1
 //   Horner products in Y^r);  U_j = T^(2^s_j).
 // All products are complex GEMMs on the matrix cores (FP64 or FP32 MFMA).
-// Sweeps: psi_{j+1} = U_j psi_j (forward), lambda_j = U_j^dag lambda_{j+1} (backward),
-// sequential in j; a block's rows are split over ceil(m / 64) (FP32) or ceil(m / 32)
-// (FP64) work-groups that hand the new state to each other after every slice, and a
-// block that fits one work-group keeps its state in LDS.  Objective o = <psi_f|psi_N>
+// Sweeps: psi_{j+1} = U_j psi_j (forward), lambda_j = U_j^dag lambda_{j+1} (backward,
+// as dot products down the columns of the same stored U), sequential in j; a block's rows
+// are split over ceil(m / 64) (FP32) or ceil(m / 32) (FP64) work-groups that hand the new
+// state to each other after every slice, and a block that fits one work-group keeps its
+// state in LDS.  Objective o = <psi_f|psi_N>
 // in FP64.
 // Gradient: do/du[j,k] = <lambda_{j+1}| L(X_j, -i dt H_k) |psi_j>, with L the Frechet
 // derivative of exp, through the vector series
@@ -32,6 +33,7 @@
 #include <cstdio>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 
 #include "mfma_tile.h"
 #include "qoc_internal.h"
@@ -50,6 +52,7 @@ struct JobDev {
   const double* h64;     // FP64 operator planes of this block
   const void* hT;        // working-precision operator planes of this block
   const void* pwT;       // working-precision operator products (qoc_system_s::pw*), or null
+  long long pw_off;      // ... or their workspace copy (elements of T; -1: none)
   long long ent_off;     // first entry (slice of a segment) of this job
   long long item_off;    // first propagator GEMM item of this job
   long long ubuf_off;    // propagators of the segment: per slice U (elements of T)
@@ -136,6 +139,12 @@ __device__ inline int find_desc(const PanelDesc* d, int n, long long key) {
   return lo;
 }
 
+// the operator products of job jb's block: the system's own, or the workspace copy
+template <typename T>
+__device__ inline const T* job_products(const JobDev& jb, char* ws, size_t off_T) {
+  return jb.pw_off >= 0 ? reinterpret_cast<const T*>(ws + off_T) + jb.pw_off : static_cast<const T*>(jb.pwT);
+}
+
 // slices of job J inside the segment starting at seg_j0 (<= 0: none)
 __device__ inline int job_len(const JobDev& jb, int seg_j0, int seg_len) { return min(seg_len, jb.N - seg_j0); }
 
@@ -152,6 +161,14 @@ struct qoc_plan_s {
   // 2 when the generator forms Y^2 and Y^3 from the operator products (no power GEMMs for
   // them), else 0; with r = 3 it then also forms each slice's first Taylor combination
   int pow_free = 0;
+  // Products of systems that do not keep their own (too large for the free memory) live in
+  // the workspace and are formed at the start of every call: five passes of set-up GEMMs
+  // (product_descs), descriptors on the device, pass p = [pw_pass_begin[p], [p + 1]).
+  int pw_mode = 0;  // prepare_powers' decision
+  bool pw_ws = false;
+  qoc::DeviceBuffer d_pwgemm;
+  int pw_pass_begin[6] = {0, 0, 0, 0, 0, 0};
+  long long pw_pass_items[5] = {0, 0, 0, 0, 0};
   double norm_bound = 0.0;
   int seg_len = 0, nseg = 0;
   int echunk = 0;  // slices whose Taylor scratch is resident at once (the segment is formed in chunks)
@@ -282,7 +299,7 @@ __device__ inline void gen_product_coefs(int K, int ns, const double (*us)[kMaxC
 // B_i = sum_k c[i][k] Y^k (Y^0 = I) go to slots 0, 1, 2 (B1, B2, B3, in place of the powers,
 // which that scheme needs no more) and r (B4); for Paterson-Stockmeyer (r = 3) the start
 // T0 = c_{qr} Y^r + sum_{i<r} c_{(q-1)r+i} Y^i goes to slot r, or, for q = 1 and no
-// squaring, T0 = U itself to the propagator storage (U and U^dag).  FP64 arithmetic for Y,
+// squaring, T0 = U itself to the propagator storage.  FP64 arithmetic for Y,
 // the working precision for the product combinations (like the products they replace).
 template <typename T>
 __device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, int gen_init, const T* pw,
@@ -480,7 +497,7 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
     ssl[t] = best_s;
   }
   __syncthreads();
-  const T* pw = pow_free ? static_cast<const T*>(jb.pwT) : nullptr;
+  const T* pw = pow_free ? job_products<T>(jb, ws, off_T) : nullptr;
   if (pw) gen_product_coefs<T>(K, ns, us, scale, cp, ct);
   __syncthreads();
   const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
@@ -633,7 +650,7 @@ __global__ void __launch_bounds__(256) k_gen_form(const JobDev* jobs, int njobs,
     ssl[threadIdx.x] = ent_s[e];
   }
   __syncthreads();
-  const T* pw = pow_free ? static_cast<const T*>(jb.pwT) : nullptr;
+  const T* pw = pow_free ? job_products<T>(jb, ws, off_T) : nullptr;
   if (pw) gen_product_coefs<T>(K, ns, us, scale, cp, ct);
   __syncthreads();
   const size_t ent_stride = (size_t)(r + 2) * 2 * plane;
@@ -1900,21 +1917,35 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   }
 }
 
-// ===================================================================== set-up products
-// C = A B, or C += A B, for square mp x mp complex FP64 blocks (planar, column-major), on
-// the FP64 matrix cores with the propagator GEMM's tile: the operator products of
-// ensure_powers, once per system.
-struct SetupGemm {
-  const double* A;
-  const double* B;
-  double* C;
+// ===================================================================== operator products
+// C = A B, or C += A B, for square mp x mp complex blocks (planar, column-major), on the
+// matrix cores with the propagator GEMM's tile: the operator products, once per system
+// (ensure_powers, FP64) or at the start of each call into the workspace
+// (Driver::form_products, the working precision).  An operand whose bit is set in `rel`
+// (1 A, 2 B, 4 C) holds a byte offset from the kernel's `base` (the workspace) instead of
+// an address.
+template <typename T>
+struct SetupGemmT {
+  const T* A;
+  const T* B;
+  T* C;
   long long item_off;
-  int mp, tiles_n, accumulate;
+  int mp, tiles_n, accumulate, rel;
 };
+
+// The set-up GEMM tile that forms workspace products in a plan's precision.
+template <typename T> struct ProductShape;
+template <> struct ProductShape<float> { typedef TileShape<float, 2, 2, 2> type; };
+template <> struct ProductShape<double> { typedef TileShape<double, 2, 2, 2> type; };
+
+template <typename T>
+__device__ inline T* rel_ptr(const T* p, int is_rel, char* base) {
+  return is_rel ? reinterpret_cast<T*>(base + reinterpret_cast<uintptr_t>(p)) : const_cast<T*>(p);
+}
 
 template <typename Shape>
 __global__ void __launch_bounds__(256, Shape::WAVES)
-    k_setup_gemm(const SetupGemm* descs, int ndesc, long long total_items) {
+    k_setup_gemm(const SetupGemmT<typename Shape::T>* descs, int ndesc, long long total_items, char* base) {
   typedef typename Shape::T T;
   __shared__ TileSmem<Shape> lds;
   const ItemRange rg = xcd_items(total_items);
@@ -1925,13 +1956,13 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     int accumulate;
   };
   auto prep = [&](long long it, Item& x) -> bool {
-    const SetupGemm g = descs[cursor_find(descs, ndesc, it, cur)];
+    const SetupGemmT<T> g = descs[cursor_find(descs, ndesc, it, cur)];
     const long long local = it - g.item_off;
     const size_t plane = (size_t)g.mp * g.mp;
-    x.op.A = g.A;
+    x.op.A = rel_ptr(g.A, g.rel & 1, base);
     x.op.a_ps = plane;
     x.op.lda = g.mp;
-    x.op.B = g.B;
+    x.op.B = rel_ptr(g.B, g.rel & 2, base);
     x.op.b_ps = plane;
     x.op.ldb = g.mp;
     x.op.M = g.mp;
@@ -1939,7 +1970,7 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
     x.op.K = g.mp;
     x.op.row0 = (int)(local / g.tiles_n) * Shape::BM;
     x.op.col0 = (int)(local % g.tiles_n) * Shape::BN;
-    x.C = g.C;
+    x.C = rel_ptr(g.C, g.rel & 4, base);
     x.accumulate = g.accumulate;
     return true;
   };
@@ -1979,9 +2010,52 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   }
 }
 
-__global__ void k_axpy_planes(const double* a, double* c, size_t n) {  // c += a
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    c[i] += a[i];
+// The product launches of one block (operators H, products PW; either may be a workspace
+// byte offset, flagged in rel_h / rel_pw), appended to the five passes, which run in order:
+// pass 0 S_ab = H_a H_b (a <= b, lexicographic), pass 1 S_ab += H_b H_a (a < b), passes
+// 2..4 the first, second and third term of each triple product, a sum of H_x S_yz over the
+// representatives of its distinct orderings: T_aaa = H_a S_aa; T_aac = H_a S_ac + H_c S_aa;
+// T_acc = H_a S_cc + H_c S_ac; T_abc = H_a S_bc + H_b S_ac + H_c S_ab (a < b < c).  Item
+// offsets run on within each pass.
+template <typename T>
+static void product_descs(const T* H, int rel_h, T* PW, int rel_pw, int K, int mp, int bm, int bn,
+                          std::vector<SetupGemmT<T>> (&pass)[5], long long (&items)[5]) {
+  const int O = K + 1;
+  const size_t plane = (size_t)mp * mp;
+  const int tm = (mp + bm - 1) / bm, tn = (mp + bn - 1) / bn;
+  auto op = [&](int o) { return H + (size_t)(2 * o) * plane; };
+  auto pw = [&](int idx) { return PW + (size_t)(2 * idx) * plane; };
+  auto pair_index = [&](int a, int b) {  // position of (a <= b) in lexicographic order
+    int idx = 0;
+    for (int x = 0; x < a; ++x) idx += O - x;
+    return idx + (b - a);
+  };
+  auto add = [&](int p, const T* A, int ra, const T* B, int rb, T* C, int acc) {
+    pass[p].push_back(SetupGemmT<T>{A, B, C, items[p], mp, tn, acc, (ra ? 1 : 0) | (rb ? 2 : 0) | (rel_pw ? 4 : 0)});
+    items[p] += (long long)tm * tn;
+  };
+  for (int a = 0; a < O; ++a)
+    for (int b = a; b < O; ++b) {
+      add(0, op(a), rel_h, op(b), rel_h, pw(pair_index(a, b)), 0);
+      if (b != a) add(1, op(b), rel_h, op(a), rel_h, pw(pair_index(a, b)), 1);
+    }
+  int t = pair_count(K);
+  for (int a = 0; a < O; ++a)
+    for (int b = a; b < O; ++b)
+      for (int c = b; c < O; ++c, ++t) {
+        std::vector<std::pair<int, int>> terms;  // (x, pair index of the other two)
+        if (a == b && b == c) {
+          terms = {{a, pair_index(a, a)}};
+        } else if (a == b) {
+          terms = {{a, pair_index(a, c)}, {c, pair_index(a, a)}};
+        } else if (b == c) {
+          terms = {{a, pair_index(b, b)}, {b, pair_index(a, b)}};
+        } else {
+          terms = {{a, pair_index(b, c)}, {b, pair_index(a, c)}, {c, pair_index(a, b)}};
+        }
+        for (size_t i = 0; i < terms.size(); ++i)
+          add(2 + (int)i, op(terms[i].first), rel_h, pw(terms[i].second), rel_pw, pw(t), i > 0 ? 1 : 0);
+      }
 }
 
 __global__ void k_planes_to_float(const double* a, float* c, size_t n) {
@@ -2719,6 +2793,23 @@ struct Driver {
   }
   static size_t sweep_lds(const qoc_plan_s* P) { return P->sweep_lds_elems * sizeof(T); }
 
+  // The workspace copies of the operator products (systems that keep none), at the start of
+  // every call that forms propagators: five passes of set-up GEMMs (product_descs).
+  static void form_products(qoc_plan_s* P, char* ws, hipStream_t st) {
+    if (!P->pw_ws) return;
+    typedef typename ProductShape<T>::type Shape;
+    const SetupGemmT<T>* d = P->d_pwgemm.as<SetupGemmT<T>>();
+    for (int p = 0; p < 5; ++p) {
+      const int n = P->pw_pass_begin[p + 1] - P->pw_pass_begin[p];
+      const long long items = P->pw_pass_items[p];
+      if (n == 0) continue;
+      const unsigned grid = (unsigned)std::max<long long>(8, std::min<long long>(P->grid_gemm, (items + 7) / 8 * 8));
+      timed(PK_GENERATOR, st, [&] {
+        hipLaunchKernelGGL(k_setup_gemm<Shape>, dim3(grid), dim3(256), 0, st, d + P->pw_pass_begin[p], n, items, ws);
+      });
+    }
+  }
+
   // Propagators of the segment starting at seg_j0.  skip_n > 0 (backward recompute): jobs
   // with N <= skip_n are left alone -- their last segment is this one, whose propagators
   // no later segment overwrote.
@@ -2728,8 +2819,8 @@ struct Driver {
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     const int L = P->seg_len;
     const dim3 grid(P->grid_gemm);
-    // the segment in chunks of echunk slices: Taylor scratch for one chunk, U and U^dag of
-    // every slice kept
+    // the segment in chunks of echunk slices: Taylor scratch for one chunk, U of every
+    // slice kept
     for (int c0 = 0; c0 < L; c0 += P->echunk) {
       const int clen = std::min(P->echunk, L - c0);
       const int groups = (clen + GEN_SG - 1) / GEN_SG;
@@ -2819,6 +2910,7 @@ struct Driver {
   static void tune_pass(qoc_plan_s* P, const double* u, char* ws, hipStream_t st) {
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);
+    form_products(P, ws, st);
     expm_segment(P, ws, u, 0, st);
     gemm_variant(P).panel(dim3(P->grid_gemm), st, P->d_jobs.as<JobDev>(), P->d_panels.as<PanelDesc>(),
                           (int)P->panels.size(), P->panel_items, ws, P->off_T, P->Kmax + 1, 0);
@@ -2830,6 +2922,7 @@ struct Driver {
     const JobDev* dj = P->d_jobs.as<JobDev>();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);
+    form_products(P, ws, st);
     expm_segment(P, ws, u, 0, st);
     int cnt = P->Nmax, src = 0;
     while (cnt > 1) {
@@ -2856,6 +2949,7 @@ struct Driver {
     const int njobs = (int)P->jobs.size();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);
+    form_products(P, ws, st);
     for (int sg = 0; sg < P->nseg; ++sg) {
       const int j0 = sg * P->seg_len;
       expm_segment(P, ws, u, j0, st);
@@ -2874,6 +2968,7 @@ struct Driver {
     const ProbDev* dpr = P->d_probs.as<ProbDev>();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);  // status ints only
+    form_products(P, ws, st);
     timed(PK_OTHER, st, [&] {
       hipLaunchKernelGGL(k_states_in<T>, dim3(std::max(1, std::min(64, 8192 / njobs)), std::min(njobs, 32768)), dim3(256), 0, st, dj, njobs, (const double2*)psi0,
                          (const double2*)psif, ws, P->off_T, flags);
@@ -2932,6 +3027,7 @@ struct Driver {
     const ProbDev* dpr = P->d_probs.as<ProbDev>();
     int* flags = reinterpret_cast<int*>(ws + P->off_flags);
     hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, st, flags, 16);
+    form_products(P, ws, st);
     timed(PK_OTHER, st, [&] {
       hipLaunchKernelGGL(k_states_in<T>, dim3(std::max(1, std::min(64, 8192 / njobs)), std::min(njobs, 32768)),
                          dim3(256), 0, st, dj, njobs, (const double2*)psi0, (const double2*)psif, ws, P->off_T, flags);
@@ -3055,14 +3151,11 @@ static ProblemSpec all_blocks(qoc_system_s* sys, int N, double dt) {
 }
 
 // The operator products of qoc_system_s::pw64 / pw32 (see there), formed once per system
-// and kept in the precision a plan asks for (FP64 for complex128 plans, FP32 for complex64
-// ones): ordered pair products P_xy = H_x H_y (temporary), S_ab from them, then every triple
-// product as H_x S_yz summed over the representatives of its distinct orderings:
-// T_aaa = H_a S_aa; T_aac = H_a S_ac + H_c S_aa; T_acc = H_a S_cc + H_c S_ac;
-// T_abc = H_a S_bc + H_b S_ac + H_c S_ab (a < b < c).
+// on the FP64 matrix cores (product_descs' five passes over all blocks) and kept in the
+// precision a plan asks for (FP64 for complex128 plans, FP32 for complex64 ones).
 static void ensure_powers(qoc_system_s* S, bool f64) {
   if (S->K > kMaxPowK || (f64 ? S->pw64.ptr : S->pw32.ptr) != nullptr) return;
-  const int K = S->K, O = K + 1, npair = pair_count(K), ntrip = triple_count(K), npw = npair + ntrip;
+  const int K = S->K, npw = pair_count(K) + triple_count(K);
   int64_t elems = 0;
   S->pw_off.clear();
   for (auto& b : S->blocks) {
@@ -3072,83 +3165,22 @@ static void ensure_powers(qoc_system_s* S, bool f64) {
   DeviceBuffer prod((size_t)elems * sizeof(double));
   hipStream_t st = nullptr;
   typedef TileShape<double, 2, 2, 2> Shape;
-  auto pair_index = [&](int a, int b) {  // position of (a <= b) in lexicographic order
-    int idx = 0;
-    for (int x = 0; x < a; ++x) idx += O - x;
-    return idx + (b - a);
-  };
+  std::vector<SetupGemmT<double>> pass[5];
+  long long items[5] = {0, 0, 0, 0, 0};
   for (size_t bi = 0; bi < S->blocks.size(); ++bi) {
     const auto& blk = S->blocks[bi];
-    const int mp = blk.mp;
-    const size_t plane = (size_t)mp * mp;
-    const int tm = (mp + Shape::BM - 1) / Shape::BM, tn = (mp + Shape::BN - 1) / Shape::BN;
-    const double* H = S->h64.as<double>() + blk.h_off;
-    double* PW = prod.as<double>() + S->pw_off[bi];
-    auto op = [&](int o) { return H + (size_t)(2 * o) * plane; };
-    auto pw = [&](int idx) { return PW + (size_t)(2 * idx) * plane; };
-    DeviceBuffer tmp((size_t)O * O * 2 * plane * sizeof(double));
-    auto pxy = [&](int x, int y) { return tmp.as<double>() + (size_t)(2 * (x * O + y)) * plane; };
-    auto run = [&](const std::vector<SetupGemm>& list) {
-      std::vector<SetupGemm> d(list);
-      long long items = 0;
-      for (auto& g : d) {
-        g.item_off = items;
-        items += (long long)tm * tn;
-      }
-      DeviceBuffer dd(d.size() * sizeof(SetupGemm));
-      QOC_HIP(hipMemcpy(dd.ptr, d.data(), d.size() * sizeof(SetupGemm), hipMemcpyHostToDevice));
-      const int grid = (int)std::min<long long>(2048, (items + 7) / 8 * 8);
-      hipLaunchKernelGGL(k_setup_gemm<Shape>, dim3(std::max(8, grid)), dim3(256), 0, st, dd.as<SetupGemm>(),
-                         (int)d.size(), items);
-      QOC_HIP(hipGetLastError());
-      QOC_HIP(hipStreamSynchronize(st));
-    };
-    // ordered pair products, then S_ab = P_ab + P_ba (a < b), S_aa = P_aa
-    std::vector<SetupGemm> g1;
-    for (int x = 0; x < O; ++x)
-      for (int y = 0; y < O; ++y) g1.push_back(SetupGemm{op(x), op(y), pxy(x, y), 0, mp, tn, 0});
-    run(g1);
-    for (int a = 0; a < O; ++a)
-      for (int b = a; b < O; ++b) {
-        QOC_HIP(hipMemcpy(pw(pair_index(a, b)), pxy(a, b), 2 * plane * sizeof(double), hipMemcpyDeviceToDevice));
-        if (b != a)
-          hipLaunchKernelGGL(k_axpy_planes, dim3(1024), dim3(256), 0, st, pxy(b, a), pw(pair_index(a, b)), 2 * plane);
-      }
+    product_descs<double>(S->h64.as<double>() + blk.h_off, 0, prod.as<double>() + S->pw_off[bi], 0, K, blk.mp,
+                          Shape::BM, Shape::BN, pass, items);
+  }
+  for (int p = 0; p < 5; ++p) {
+    if (pass[p].empty()) continue;
+    DeviceBuffer dd(pass[p].size() * sizeof(SetupGemmT<double>));
+    QOC_HIP(hipMemcpy(dd.ptr, pass[p].data(), pass[p].size() * sizeof(SetupGemmT<double>), hipMemcpyHostToDevice));
+    const int grid = (int)std::min<long long>(2048, (items[p] + 7) / 8 * 8);
+    hipLaunchKernelGGL(k_setup_gemm<Shape>, dim3(std::max(8, grid)), dim3(256), 0, st, dd.as<SetupGemmT<double>>(),
+                       (int)pass[p].size(), items[p], nullptr);
     QOC_HIP(hipGetLastError());
     QOC_HIP(hipStreamSynchronize(st));
-    // triple products (a <= b <= c in lexicographic order), each a sum of H_x S_yz
-    std::vector<SetupGemm> g2;
-    int t = npair;
-    for (int a = 0; a < O; ++a)
-      for (int b = a; b < O; ++b)
-        for (int c = b; c < O; ++c, ++t) {
-          std::vector<std::pair<int, int>> terms;  // (x, pair index of the other two)
-          if (a == b && b == c) {
-            terms = {{a, pair_index(a, a)}};
-          } else if (a == b) {
-            terms = {{a, pair_index(a, c)}, {c, pair_index(a, a)}};
-          } else if (b == c) {
-            terms = {{a, pair_index(b, b)}, {b, pair_index(a, b)}};
-          } else {
-            terms = {{a, pair_index(b, c)}, {b, pair_index(a, c)}, {c, pair_index(a, b)}};
-          }
-          for (size_t i = 0; i < terms.size(); ++i)
-            g2.push_back(SetupGemm{op(terms[i].first), pw(terms[i].second), pw(t), 0, mp, tn, i > 0 ? 1 : 0});
-        }
-    // the accumulating products into one output must not run concurrently: one launch per
-    // term position
-    for (int pass = 0; pass < 3; ++pass) {
-      std::vector<SetupGemm> part;
-      size_t k = 0;
-      for (int a = 0; a < O; ++a)
-        for (int b = a; b < O; ++b)
-          for (int c = b; c < O; ++c) {
-            const int nterms = (a == b && b == c) ? 1 : ((a == b || b == c) ? 2 : 3);
-            if (pass < nterms) part.push_back(g2[k + pass]);
-            k += nterms;
-          }
-      if (!part.empty()) run(part);
-    }
   }
   if (f64) {
     S->pw64 = std::move(prod);
@@ -3161,14 +3193,18 @@ static void ensure_powers(qoc_system_s* S, bool f64) {
   }
 }
 
-// Whether a plan's generator forms Y^2 and Y^3 from operator products: every system has at
-// most kMaxPowK controls, and the products still missing fit in an eighth of the free device
-// memory (a large batch of distinct Hamiltonians keeps that memory for its propagators, whose
-// recomputation would cost more than the two power products per slice).  Forms the missing
-// products when it says yes; call it before the workspace budget is read from the free memory.
-static bool prepare_powers(const std::vector<ProblemSpec>& probs, bool f64) {
+// How a plan's generator gets Y^2 and Y^3: 0 by power products (some system has more than
+// kMaxPowK controls); 1 from operator products kept with every system; 2 from products formed
+// at the start of every call in the workspace for the systems that keep none.  The products
+// still missing are formed and kept with their systems when they fit an eighth of the free
+// device memory: a large batch of distinct Hamiltonians (the 256-ring batch: 97 GB of
+// products) keeps that memory for its propagators and forms each problem group's products
+// per call instead (a few per cent of the call's products).  Call it before the workspace
+// budget is read from the free memory.
+static std::atomic<int> g_products_policy{0};  // qoc_set_products_policy
+static int prepare_powers(const std::vector<ProblemSpec>& probs, bool f64) {
   for (auto& pr : probs)
-    if (pr.sys->K > kMaxPowK) return false;
+    if (pr.sys->K > kMaxPowK) return 0;
   std::vector<qoc_system_s*> missing;
   size_t bytes = 0;
   for (auto& pr : probs) {
@@ -3181,13 +3217,19 @@ static bool prepare_powers(const std::vector<ProblemSpec>& probs, bool f64) {
     for (auto& b : S->blocks) planes += (size_t)b.mp * b.mp;
     bytes += (size_t)(pair_count(S->K) + triple_count(S->K)) * 2 * planes * (f64 ? sizeof(double) : sizeof(float));
   }
-  if (!missing.empty()) {
-    size_t free_b = 0, total_b = 0;
-    QOC_HIP(hipMemGetInfo(&free_b, &total_b));
-    if (bytes > free_b / 8) return false;
+  if (missing.empty()) return 1;
+  size_t free_b = 0, total_b = 0;
+  QOC_HIP(hipMemGetInfo(&free_b, &total_b));
+  if (g_products_policy.load() == 0 && bytes <= free_b / 8) {
     for (auto* S : missing) ensure_powers(S, f64);
+    return 1;
   }
-  return true;
+  return 2;
+}
+
+// whether system S keeps operator products in the plan's precision
+static bool keeps_products(const qoc_system_s* S, bool f64) {
+  return (f64 ? S->pw64.ptr : S->pw32.ptr) != nullptr;
 }
 
 // Default workspace budget: 85 % of the free device memory (the rest for the caller's
@@ -3198,10 +3240,38 @@ static size_t default_budget() {
   return std::min<size_t>((size_t)240 << 30, free_b / 20 * 17);
 }
 
-// pow_mode: -1 decides whether the generator uses operator products (prepare_powers); 0 / 1
-// take a decision made for the whole batch (1: the products exist).  parent (a problem
-// group's plan): the batch plan whose numerical choices the group takes over -- products,
-// Frechet sub-steps and terms, gradient route -- so that grouping changes no result.
+// Device descriptors of the workspace products (Driver::form_products): every (system,
+// block) key's five passes, the passes concatenated.  The products' addresses are workspace
+// byte offsets (off_T + element offset); the operators are the systems' own planes.
+template <typename T>
+static void upload_product_descs(qoc_plan_s* P, const std::vector<std::pair<const qoc_system_s*, int>>& keys,
+                                 const std::vector<long long>& off) {
+  typedef typename ProductShape<T>::type Shape;
+  std::vector<SetupGemmT<T>> pass[5];
+  long long items[5] = {0, 0, 0, 0, 0};
+  for (size_t k = 0; k < keys.size(); ++k) {
+    const qoc_system_s* S = keys[k].first;
+    const auto& b = S->blocks[keys[k].second];
+    const T* H = std::is_same<T, double>::value ? reinterpret_cast<const T*>(S->h64.as<double>() + b.h_off)
+                                                : reinterpret_cast<const T*>(S->h32.as<float>() + b.h_off);
+    T* PW = reinterpret_cast<T*>((uintptr_t)(P->off_T + (size_t)off[k] * sizeof(T)));
+    product_descs<T>(H, 0, PW, 1, S->K, b.mp, Shape::BM, Shape::BN, pass, items);
+  }
+  std::vector<SetupGemmT<T>> all;
+  for (int p = 0; p < 5; ++p) {
+    P->pw_pass_begin[p] = (int)all.size();
+    P->pw_pass_items[p] = items[p];
+    all.insert(all.end(), pass[p].begin(), pass[p].end());
+  }
+  P->pw_pass_begin[5] = (int)all.size();
+  P->d_pwgemm.alloc(all.size() * sizeof(SetupGemmT<T>));
+  QOC_HIP(hipMemcpy(P->d_pwgemm.ptr, all.data(), all.size() * sizeof(SetupGemmT<T>), hipMemcpyHostToDevice));
+}
+
+// pow_mode: -1 decides how the generator gets its powers (prepare_powers); 0 / 1 / 2 take a
+// decision made for the whole batch.  parent (a problem group's plan): the batch plan whose
+// numerical choices the group takes over -- products, Frechet sub-steps and terms, gradient
+// route -- so that grouping changes no result.
 static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precision, double u_bound, size_t max_ws,
                               int pow_mode = -1, const qoc_plan_s* parent = nullptr) {
   QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
@@ -3224,7 +3294,9 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->qmax = f64 ? 6 : 4;  // degrees up to 24 (FP64) / 12 (FP32)
   P->t12 = f64 ? 0 : 1;
   // Y^2 and Y^3 from the operator products when every system has them (few controls)
-  P->pow_free = parent ? parent->pow_free : (pow_mode < 0 ? prepare_powers(probs, f64) : pow_mode > 0) ? 2 : 0;
+  const int pmode = parent ? parent->pw_mode : (pow_mode < 0 ? prepare_powers(probs, f64) : pow_mode);
+  P->pw_mode = pmode;
+  P->pow_free = pmode > 0 ? 2 : 0;
   const double unit = f64 ? std::ldexp(1.0, -53) : std::ldexp(1.0, -24);
   double nb = 0.0;
   int max_mp = 0;
@@ -3311,6 +3383,22 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       per_scratch += (size_t)(P->r + 2) * 2 * b.mp * b.mp * P->elem;
       fixed += (size_t)2 * b.mp * ((size_t)(pr.N + 1) * b.d + (size_t)pr.N * b.d) * P->elem;
     }
+  // operator products held in the workspace: one copy per (system, block) whose system keeps
+  // none, in first-use order
+  std::vector<std::pair<const qoc_system_s*, int>> pw_keys;
+  if (P->pow_free)
+    for (auto& pr : probs) {
+      if (keeps_products(pr.sys, f64)) continue;
+      const int npw = pair_count(pr.sys->K) + triple_count(pr.sys->K);
+      for (auto& b : pr.blocks) {
+        const std::pair<const qoc_system_s*, int> key{pr.sys, b.index};
+        if (std::find(pw_keys.begin(), pw_keys.end(), key) != pw_keys.end()) continue;
+        pw_keys.push_back(key);
+        fixed += (size_t)npw * 2 * b.mp * b.mp * P->elem;
+      }
+    }
+  P->pw_ws = !pw_keys.empty();
+  std::vector<long long> pw_key_off(pw_keys.size(), -1);
   const size_t budget = max_ws ? max_ws : default_budget();
   // The segment length, Taylor chunk and gradient chunk for uplanes planes per slice; true
   // when everything is resident and formed in one pass.
@@ -3366,8 +3454,12 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       const size_t left = avail > (size_t)ec * per_scratch ? avail - (size_t)ec * per_scratch : 0;
       const long long seg = (long long)(left / std::max<size_t>(per_slice, 1));
       if (seg < 1 && uplanes > 2) return false;  // the U-only layout may still fit
-      QOC_REQUIRE(seg >= 1, QOC_ERR_OUT_OF_MEMORY, "workspace budget below one slice of propagators");
-      P->seg_len = (int)std::min<long long>(seg, P->Nmax);
+      // a batch plan that does not fit at all is split into problem groups (its own layout
+      // is then never used); a single problem must fit one slice
+      QOC_REQUIRE(seg >= 1 || (probs.size() > 1 && !parent), QOC_ERR_OUT_OF_MEMORY,
+                  "workspace budget below one slice of propagators");
+      const long long seg_ok = std::max<long long>(seg, 1);
+      P->seg_len = (int)std::min<long long>(seg_ok, P->Nmax);
       P->echunk = (int)std::min<long long>(ec, P->seg_len);
     }
     P->nseg = (P->Nmax + P->seg_len - 1) / P->seg_len;
@@ -3415,9 +3507,19 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       j.h64 = pr.sys->h64.as<double>() + b.h_off;
       j.hT = f64 ? (const void*)(pr.sys->h64.as<double>() + b.h_off) : (const void*)(pr.sys->h32.as<float>() + b.h_off);
       j.pwT = nullptr;
-      if (P->pow_free)
+      j.pw_off = -1;
+      if (P->pow_free && keeps_products(pr.sys, f64)) {
         j.pwT = f64 ? (const void*)(pr.sys->pw64.as<double>() + pr.sys->pw_off[b.index])
                     : (const void*)(pr.sys->pw32.as<float>() + pr.sys->pw_off[b.index]);
+      } else if (P->pow_free) {
+        const size_t kidx = std::find(pw_keys.begin(), pw_keys.end(),
+                                      std::pair<const qoc_system_s*, int>{pr.sys, b.index}) - pw_keys.begin();
+        if (pw_key_off[kidx] < 0) {
+          pw_key_off[kidx] = tel;
+          tel += (long long)(pair_count(pr.sys->K) + triple_count(pr.sys->K)) * 2 * b.mp * b.mp;
+        }
+        j.pw_off = pw_key_off[kidx];
+      }
       j.state_off = state_base + b.state_off;
       j.u_off = u_off;
       j.ent_off = ent_off;
@@ -3456,6 +3558,12 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->total_U = uout;
   P->max_cc = max_cc;
   P->off_T = take((size_t)tel * P->elem);
+  if (P->pw_ws) {
+    if (f64)
+      upload_product_descs<double>(P.get(), pw_keys, pw_key_off);
+    else
+      upload_product_descs<float>(P.get(), pw_keys, pw_key_off);
+  }
   P->off_gacc = take((size_t)std::max<long long>(gacc, 1) * 16);
   P->off_sync = take((size_t)2 * 4 * sizeof(int) * P->jobs.size());  // co-operative sweep control words
   P->xchg_words = xw;
@@ -3541,7 +3649,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
 // times over.
 constexpr int kGroupChunk = 32;
 static size_t resident_bytes(const std::vector<ProblemSpec>& probs, size_t b0, size_t b1, size_t elem, int r,
-                             int nslots, int chunk) {
+                             int nslots, int chunk, bool ws_products) {
   size_t fixed = 0, grad = 0, props = 0, scratch = 0;
   int nmax = 0;
   for (size_t p = b0; p < b1; ++p) nmax = std::max(nmax, probs[p].N);
@@ -3553,6 +3661,8 @@ static size_t resident_bytes(const std::vector<ProblemSpec>& probs, size_t b0, s
       const size_t cc = (size_t)(std::min(chunk, nmax) * b.d + 15) / 16 * 16;
       grad += (size_t)nslots * 2 * mp * cc * elem + cc * pr.sys->K * 16;
       props += (size_t)pr.N * 2 * mp * mp * elem;
+      if (ws_products && !keeps_products(pr.sys, elem == 8))
+        fixed += (size_t)(pair_count(pr.sys->K) + triple_count(pr.sys->K)) * 2 * mp * mp * elem;
       scratch += (size_t)(r + 2) * 2 * mp * mp * elem;
     }
   }
@@ -3570,7 +3680,8 @@ static void group_problems(qoc_plan_s* full, const std::vector<ProblemSpec>& pro
   for (size_t b0 = 0; b0 < probs.size();) {
     size_t b1 = b0 + 1;
     while (b1 < probs.size() &&
-           resident_bytes(probs, b0, b1 + 1, full->elem, full->r, nslots, std::min(full->Nmax, 2048)) <= limit)
+           resident_bytes(probs, b0, b1 + 1, full->elem, full->r, nslots, std::min(full->Nmax, 2048), full->pw_mode == 2) <=
+               limit)
       ++b1;
     todo.push_back({b0, b1});
     b0 = b1;
@@ -3744,10 +3855,10 @@ qoc_status qoc_plan_create_batched(const qoc_system* systems, int P, const int* 
     std::vector<ProblemSpec> probs;
     for (int p = 0; p < P; ++p) probs.push_back(all_blocks(systems[p], N[p], dt[p]));
     QOC_REQUIRE(precision == QOC_C128 || precision == QOC_C64, QOC_ERR_INVALID_ARG, "unknown precision");
-    const bool pw = prepare_powers(probs, precision == QOC_C128);
+    const int pmode = prepare_powers(probs, precision == QOC_C128);
     const size_t budget = max_ws ? max_ws : default_budget();
-    std::unique_ptr<qoc_plan_s> full(build_plan(probs, precision, u_bound, budget, pw ? 1 : 0));
-    if (full->nseg > 1 && P > 1) group_problems(full.get(), probs, precision, u_bound, budget);
+    std::unique_ptr<qoc_plan_s> full(build_plan(probs, precision, u_bound, budget, pmode));
+    if ((full->nseg > 1 || full->bytes > budget) && P > 1) group_problems(full.get(), probs, precision, u_bound, budget);
     *out = full.release();
   });
 }
@@ -3773,11 +3884,11 @@ qoc_status qoc_plan_info(qoc_plan P, int64_t* info, int cap) {
       if (E == P || g->nseg > E->nseg) E = g;
       sweep_groups = std::max(sweep_groups, g->coop ? g->coop_w : 1);
     }
-    int64_t v[21] = {E->seg_len, E->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
+    int64_t v[22] = {E->seg_len, E->nseg, P->r, (int64_t)P->qmax * P->r, P->Q, P->R, (int64_t)per_slice, P->smax,
                      E->chunk, P->grid_gemm, P->P, (int64_t)P->jobs.size(), P->total_u, P->total_D, P->total_U,
                      P->variant, E->echunk, sweep_groups, (int64_t)std::max<size_t>(1, P->groups.size()),
-                     P->pow_free, E->uplanes};
-    for (int i = 0; i < cap && i < 21; ++i) info[i] = v[i];
+                     P->pow_free, E->uplanes, P->pw_mode == 2 ? 1 : 0};
+    for (int i = 0; i < cap && i < 22; ++i) info[i] = v[i];
   });
 }
 
@@ -4036,6 +4147,13 @@ qoc_status qoc_measure_mfma_peak(int precision, double* tflops, void* stream) {
     (void)hipEventDestroy(e1);
     // 2 * 16 * 16 * 4 flops per MFMA, 8 per round per wave, 4 waves per work-group
     *tflops = (double)grid * 4 * 8 * iters * 2048.0 / (ms * 1e-3) / 1e12;
+  });
+}
+
+qoc_status qoc_set_products_policy(int policy) {
+  return guarded([&] {
+    QOC_REQUIRE(policy == 0 || policy == 1, QOC_ERR_INVALID_ARG, "policy must be 0 or 1");
+    g_products_policy.store(policy);
   });
 }
 

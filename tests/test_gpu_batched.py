@@ -174,3 +174,64 @@ def test_problem_groups_equal_the_single_group_plan(lib, prec):
             ref = _oracle(w, *states[p])
             assert abs(og_[p, 0].item() - ref["F"]) <= 1e-12
             assert np.abs(gg[p].cpu().numpy() - ref["grad"]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_products_formed_in_the_workspace(lib, prec):
+    """Operator products formed at the start of every call in the workspace (the form a batch
+    of distinct Hamiltonians too large to keep them takes): complex128 results bit for bit
+    those of the plan whose systems keep their products (both formed by the same FP64 set-up
+    products), complex64 ones (products formed in FP32) against the FP64 oracle; and the same
+    form with problem groups, each group forming its own, bit for bit the one-group plan."""
+    import torch
+    print(f"workspace products {prec}", flush=True)
+    rng = np.random.default_rng(43)
+    ws = []
+    for n, N in ((8, 30), (6, 21), (7, 26), (8, 17)):
+        u = rng.uniform(-1, 1, (N, 2))
+        ws.append(W.Workload(f"ring{n}", n, "dihedral", 1, W.heisenberg_ring_terms(0.55 + 0.05 * n),
+                             W.global_controls(), N, 0.04, u))
+    states = [_problem_states(rng, w.n) for w in ws]
+    Ns, dts = [w.N for w in ws], [w.dt for w in ws]
+    us = [torch.tensor(w.u, device="cuda") for w in ws]
+    p0 = [torch.tensor(s[0], device="cuda") for s in states]
+    pf = [torch.tensor(s[1], device="cuda") for s in states]
+    sys_kept = [lib.System(lib.Basis(w.n), w.h0, w.hk) for w in ws]
+    Pk = lib.Plan.batched(sys_kept, prec, Ns, dts, 1.0)
+    assert Pk.info["products_in_workspace"] == 0 and Pk.info["powers_from_generator"] == 2
+    ok, gk = lib.fidelity_grad_batched(Pk, us, p0, pf)
+    lib.set_products_policy(1)
+    try:
+        sys_ws = [lib.System(lib.Basis(w.n), w.h0, w.hk) for w in ws]
+        Pw = lib.Plan.batched(sys_ws, prec, Ns, dts, 1.0)
+        full = Pw.workspace_bytes
+        Pg, frac = None, 0.5
+        while frac > 0.01:
+            cand = lib.Plan.batched(sys_ws, prec, Ns, dts, 1.0, int(full * frac))
+            if cand.info["problem_groups"] >= 3:
+                Pg = cand
+                break
+            frac *= 0.8
+    finally:
+        lib.set_products_policy(0)
+    assert Pw.info["products_in_workspace"] == 1 and Pw.info["powers_from_generator"] == 2
+    assert Pw.workspace_bytes > Pk.workspace_bytes
+    ow, gw = lib.fidelity_grad_batched(Pw, us, p0, pf)
+    assert int(ow[:, 7].abs().max().item()) == 0
+    assert Pg is not None and Pg.info["products_in_workspace"] == 1
+    print(f"  groups {Pg.groups()}", flush=True)
+    og_, gg = lib.fidelity_grad_batched(Pg, us, p0, pf)
+    assert torch.equal(og_[:, :6], ow[:, :6])
+    for a, b in zip(gg, gw):
+        assert torch.equal(a, b)
+    if prec == "c128":
+        assert torch.equal(ow[:, :6], ok[:, :6])
+        for a, b in zip(gw, gk):
+            assert torch.equal(a, b)
+    for p, w in enumerate(ws):
+        ref = _oracle(w, *states[p])
+        g = gw[p].cpu().numpy()
+        tf = 1e-12 if prec == "c128" else 1e-6
+        tg = 1e-12 if prec == "c128" else fp32_grad_tol(np.abs(ref["grad"]).max())
+        assert abs(ow[p, 0].item() - ref["F"]) <= tf
+        assert np.abs(g - ref["grad"]).max() <= tg
