@@ -139,6 +139,17 @@ __device__ inline int find_desc(const PanelDesc* d, int n, long long key) {
   return lo;
 }
 
+// A pointer known to address device (global) memory: loads and stores through it take the
+// global path instead of the flat one (whose completion the LDS wait counter also tracks).
+template <typename T>
+__device__ inline T* global_ptr(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ inline const T* global_ptr(const T* p) {
+  return (const T*)(const __attribute__((address_space(1))) T*)p;
+}
+
 // the operator products of job jb's block: the system's own, or the workspace copy
 template <typename T>
 __device__ inline const T* job_products(const JobDev& jb, char* ws, size_t off_T) {
@@ -316,7 +327,8 @@ __device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, 
   for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
   if (in) {
     for (int o = 0; o <= K; ++o) {
-      const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
+      const double ar = ld_global<double>(H + (size_t)(2 * o) * plane + idx);
+      const double ai = ld_global<double>(H + (size_t)(2 * o + 1) * plane + idx);
 #pragma unroll
       for (int t = 0; t < GEN_SG; ++t) {
         hr[t] += us[t][o] * ar;
@@ -344,7 +356,8 @@ __device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, 
     const int np = pair_count(K), nt = triple_count(K);
 #pragma unroll 2
     for (int i = 0; i < np; ++i) {
-      const T ar = pw[(size_t)(2 * i) * plane + idx], ai = pw[(size_t)(2 * i + 1) * plane + idx];
+      const T ar = ld_global<T>(pw + (size_t)(2 * i) * plane + idx);
+      const T ai = ld_global<T>(pw + (size_t)(2 * i + 1) * plane + idx);
 #pragma unroll
       for (int t = 0; t < GEN_SG; ++t) {
         sr[t] += cp[t][i] * ar;
@@ -354,7 +367,7 @@ __device__ inline void gen_element(const JobDev& jb, size_t idx, int ns, int r, 
 #pragma unroll 2
     for (int i = 0; i < nt; ++i) {
       const size_t o = (size_t)(2 * (np + i)) * plane + idx;
-      const T ar = pw[o], ai = pw[o + plane];
+      const T ar = ld_global<T>(pw + o), ai = ld_global<T>(pw + o + plane);
 #pragma unroll
       for (int t = 0; t < GEN_SG; ++t) {
         cr[t] += ct[t][i] * ar;
@@ -452,7 +465,8 @@ __global__ void __launch_bounds__(256) k_generator(const JobDev* jobs, int njobs
 #pragma unroll
       for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
       for (int o = 0; o <= K; ++o) {
-        const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
+        const double ar = ld_global<double>(H + (size_t)(2 * o) * plane + idx);
+        const double ai = ld_global<double>(H + (size_t)(2 * o + 1) * plane + idx);
 #pragma unroll
         for (int t = 0; t < GEN_SG; ++t) {
           hr[t] += us[t][o] * ar;
@@ -566,7 +580,8 @@ __global__ void __launch_bounds__(256) k_gen_norms(const JobDev* jobs, int njobs
 #pragma unroll
       for (int t = 0; t < GEN_SG; ++t) hr[t] = hi[t] = 0.0;
       for (int o = 0; o <= K; ++o) {
-        const double ar = H[(size_t)(2 * o) * plane + idx], ai = H[(size_t)(2 * o + 1) * plane + idx];
+        const double ar = ld_global<double>(H + (size_t)(2 * o) * plane + idx);
+        const double ai = ld_global<double>(H + (size_t)(2 * o + 1) * plane + idx);
 #pragma unroll
         for (int t = 0; t < GEN_SG; ++t) {
           hr[t] += us[t][o] * ar;
@@ -1940,7 +1955,8 @@ template <> struct ProductShape<double> { typedef TileShape<double, 2, 2, 2> typ
 
 template <typename T>
 __device__ inline T* rel_ptr(const T* p, int is_rel, char* base) {
-  return is_rel ? reinterpret_cast<T*>(base + reinterpret_cast<uintptr_t>(p)) : const_cast<T*>(p);
+  T* q = is_rel ? reinterpret_cast<T*>(base + reinterpret_cast<uintptr_t>(p)) : const_cast<T*>(p);
+  return global_ptr(q);
 }
 
 template <typename Shape>
@@ -2210,7 +2226,7 @@ __device__ inline double2 small_hv(const T* H, size_t hplane, int mp, int m, int
                                    const T* vi) {
   T ar = T(0), ai = T(0);
   if (row < m) {
-    const T* hr = H + (size_t)(2 * o) * hplane + row;
+    const T* hr = H + (size_t)(2 * o) * hplane + row;  // global or LDS (staged)
     const T* hi = H + (size_t)(2 * o + 1) * hplane + row;
     for (int c = 0; c < m; ++c) {
       const T xr = hr[(size_t)c * mp], xi = hi[(size_t)c * mp], yr = vr[c], yi = vi[c];

@@ -610,15 +610,23 @@ template <> struct AccRowStep<double> { static constexpr int value = 4; };
 template <typename T>
 __device__ inline typename Vec4<T>::type acc_load(const T* p);
 template <>
-__device__ inline f4v acc_load<float>(const float* p) { return *reinterpret_cast<const f4v*>(p); }
+__device__ inline f4v acc_load<float>(const float* p) { return ld_global<f4v>(p); }
 template <>
-__device__ inline d4v acc_load<double>(const double* p) { return d4v{p[0], p[4], p[8], p[12]}; }
+__device__ inline d4v acc_load<double>(const double* p) {
+  return d4v{ld_global<double>(p), ld_global<double>(p + 4), ld_global<double>(p + 8), ld_global<double>(p + 12)};
+}
 template <typename T>
 __device__ inline void acc_store(T* p, typename Vec4<T>::type v);
 template <>
-__device__ inline void acc_store<float>(float* p, f4v v) { *reinterpret_cast<f4v*>(p) = v; }
+__device__ inline void acc_store<float>(float* p, f4v v) { *(__attribute__((address_space(1))) f4v*)p = v; }
 template <>
-__device__ inline void acc_store<double>(double* p, d4v v) { p[0] = v[0]; p[4] = v[1]; p[8] = v[2]; p[12] = v[3]; }
+__device__ inline void acc_store<double>(double* p, d4v v) {
+  __attribute__((address_space(1))) double* g = (__attribute__((address_space(1))) double*)p;
+  g[0] = v[0];
+  g[4] = v[1];
+  g[8] = v[2];
+  g[12] = v[3];
+}
 
 template <typename C>
 __device__ inline int acc_col(int col0, int ci) {
