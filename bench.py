@@ -67,8 +67,9 @@ def parse():
                     help="S_128 candidate pulses timed in one batched plan (0: skip; 1024 = the full workload)")
     ap.add_argument("--ring14-slices", type=int, default=4000,
                     help="slices of the 14-qubit staggered-control ring timed (0: skip; 4000 = the full pulse)")
-    ap.add_argument("--batch-problems", type=int, default=32,
-                    help="problems of the 256-ring batched workload timed in one plan (0: skip; 256 = all)")
+    ap.add_argument("--batch-problems", type=int, default=256,
+                    help="problems of the 256-ring batched workload timed in one plan (0: skip; 256 = all, "
+                         "about 3 minutes per step)")
     ap.add_argument("--dense-slices", type=int, default=16,
                     help="slices of the same pulse timed on the dense 4096-dim space (0: skip)")
     ap.add_argument("--paper-comparison", type=int, default=14, metavar="NMAX",
@@ -843,16 +844,22 @@ def main():
         del Pd, Sd, Bd
         torch.cuda.empty_cache()
 
-    sym = sym_leg(q, torch, W, args.sym_candidates) if args.sym_candidates > 0 else None
+    def leg(name, fn, *a):
+        t0 = time.time()
+        r = fn(*a)
+        print(f"[bench] {name} leg: {time.time() - t0:.1f} s wall", file=sys.stderr, flush=True)
+        return r
+
+    sym = leg("S_128 candidates", sym_leg, q, torch, W, args.sym_candidates) if args.sym_candidates > 0 else None
     comparison = None
     if args.paper_comparison > 0:
-        comparison = paper_comparison(q, torch, W, args.paper_comparison)
+        comparison = leg("paper comparison", paper_comparison, q, torch, W, args.paper_comparison)
         torch.cuda.empty_cache()
-    optimizer = optimizer_leg(q, torch, W) if args.optimizer else None
-    lts = lts_leg(q, torch) if args.lts else None
+    optimizer = leg("optimizer", optimizer_leg, q, torch, W) if args.optimizer else None
+    lts = leg("Trotterised", lts_leg, q, torch) if args.lts else None
 
-    ring14 = ring14_leg(q, torch, W, args.ring14_slices) if args.ring14_slices > 0 else None
-    batch = batch_leg(q, torch, W, args.batch_problems) if args.batch_problems > 0 else None
+    ring14 = leg("ring-14", ring14_leg, q, torch, W, args.ring14_slices) if args.ring14_slices > 0 else None
+    batch = leg("ring batch", batch_leg, q, torch, W, args.batch_problems) if args.batch_problems > 0 else None
 
     gemm_ms, gemm_n = prof32["propagator_gemm"]
     achieved = flops32 * args.steps / (gemm_ms * 1e-3) / 1e12

@@ -204,7 +204,7 @@ qoc_status qoc_plan_workspace_size(qoc_plan plan, size_t* bytes);
  * Workspace: U of every slice of a segment (both sweeps read it: the backward one takes
  * U^dag lambda as dot products down U's columns), Taylor scratch (Y..Y^r and two ping-pong
  * buffers) of one chunk of slices, states, gradient slots; each slice's slot also holds
- * room for qoc_gate_propagate's product tree when the plan fits in one pass with it.  When the budget holds
+ * room for qoc_gate_propagate's product tree when every propagator still fits with it.  When the budget holds
  * everything, segment = chunk = N; when it holds every propagator and the scratch of at
  * least 8 slices, segment = N and the chunk is what the rest holds; otherwise the
  * propagators of earlier segments are recomputed during the backward sweep.

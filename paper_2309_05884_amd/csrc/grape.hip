@@ -3417,7 +3417,7 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   std::vector<long long> pw_key_off(pw_keys.size(), -1);
   const size_t budget = max_ws ? max_ws : default_budget();
   // The segment length, Taylor chunk and gradient chunk for uplanes planes per slice; true
-  // when everything is resident and formed in one pass.
+  // when every propagator is resident (one segment).
   auto plan_memory = [&](int uplanes) {
     const size_t per_slice = (size_t)uplanes * per_plane;
     int chunk = std::min(P->Nmax, 2048);
@@ -3479,11 +3479,11 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
       P->echunk = (int)std::min<long long>(ec, P->seg_len);
     }
     P->nseg = (P->Nmax + P->seg_len - 1) / P->seg_len;
-    return P->nseg == 1 && P->echunk == P->Nmax;
+    return P->nseg == 1;
   };
-  // Room for the gate product tree's second half only where it costs nothing: when the
-  // plan is resident and formed in one pass with it; otherwise U alone, so that longer
-  // segments (or every slice) fit.
+  // Room for the gate product tree's second half whenever every propagator stays resident
+  // with it (the gate path needs one segment); otherwise U alone, so that longer segments
+  // (or every slice) fit.
   P->uplanes = plan_memory(4) ? 4 : 2;
   if (P->uplanes == 2) plan_memory(2);
   const int chunk = P->chunk;
