@@ -58,10 +58,10 @@ def test_ring14_full_pulse_fd_and_invariants(lib):
     * central differences (h = 1e-4) of F on 32 seeded (slice, control) pairs spread over the
       pulse, through the slice-local identity o(u + h e_jk) = <lambda_{j+1}|U_j(u')|psi_j>
       (only slice j changes), against the gradient;
-    * the complex64 plan of the same pulse: |dF| <= 1e-6 and gradient within 2e-5 max|g| of
+    * the complex64 plan of the same pulse: |dF| <= 1e-6 and gradient within fp32_grad_tol of
       the complex128 one."""
     import torch
-    from tests._common import read_golden
+    from tests._common import fp32_grad_tol, read_golden
     print("ring14 full pulse, complex128", flush=True)
     w = W.config4(seed=0, variant="all")
     rng = w.notes["rng"]
@@ -114,4 +114,7 @@ def test_ring14_full_pulse_fd_and_invariants(lib):
     dF = abs(out32[0].item() - out[0].item())
     dg = np.abs(grad32.cpu().numpy() - g).max()
     print(f"  |dF| {dF:.2e} max|dg| {dg:.2e} ({dg / np.abs(g).max():.2e} of max|g|)", flush=True)
-    assert dF <= 1e-6 and dg <= 2e-5 * np.abs(g).max()
+    # F ~ 3e-6 after the 4000 slices: max|g| (2.5e-6) is small against the costates' rounding
+    # scale 2 |o| dt ||H_k|| u32 sqrt(N) ~ 2e-9, so the absolute floor of fp32_grad_tol binds
+    # (measured 1.9e-10)
+    assert dF <= 1e-6 and dg <= fp32_grad_tol(np.abs(g).max())

@@ -106,3 +106,44 @@ def test_ring14_two_site_group_vs_oracle(lib, prec):
     else:
         assert abs(F - vals["F"]) <= 1e-6
         assert np.abs(g - gref).max() <= fp32_grad_tol(np.abs(gref).max())
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_ring14_segmented_vs_oracle(lib, prec):
+    """The 14-qubit two-site-group workload's first 64 slices on a plan whose workspace budget
+    forces at least three segments (the 1300-2340-wide blocks swept co-operatively across
+    segment boundaries, earlier segments recomputed in the backward sweep) against stored
+    oracle values, and bit for bit the one-segment plan (complex128 blocks sweep one work-group
+    each)."""
+    import torch
+    from tests._common import plan_with_segments
+    print(f"ring14 segmented {prec}", flush=True)
+    w = W.config4(seed=0, variant="all")
+    rng = w.notes["rng"]
+    B = lib.Basis(14, "dihedral", 2)
+    S = lib.System(B, w.h0, w.hk)
+    vf = torch.tensor(W.gaussian_panel(rng, B.dim), device="cuda")
+    v0 = torch.tensor(W.gaussian_panel(rng, B.dim), device="cuda")
+    vals, gref = read_golden("ring14_T2R_allblocks_N64.txt")
+    N = gref.shape[0]
+    u = torch.tensor(w.u[:N], device="cuda")
+    P1 = lib.Plan(S, prec, N, w.dt, 2.0)
+    assert P1.info["segments"] == 1
+    o1, g1 = lib.fidelity_grad(P1, u, v0, vf)
+    del P1
+    torch.cuda.empty_cache()
+    P = plan_with_segments(lib, S, prec, N, w.dt, 2.0, 3)
+    print(f"  plan {P.info}", flush=True)
+    # complex64: the co-operative sweep (64-row groups); complex128 blocks need more 32-row
+    # groups than the CUs hold, so they sweep one work-group per block
+    assert P.info["sweep_groups"] > 1 if prec == "c64" else P.info["sweep_groups"] == 1
+    out, grad = lib.fidelity_grad(P, u, v0, vf)
+    assert torch.equal(out[:6], o1[:6]) and torch.equal(grad, g1)
+    g = grad.cpu().numpy()
+    print(f"  |dF| = {abs(out[0].item() - vals['F']):.2e}  max|dg| = {np.abs(g - gref).max():.2e}", flush=True)
+    if prec == "c128":
+        assert abs(out[0].item() - vals["F"]) <= 1e-12
+        assert np.abs(g - gref).max() <= 1e-12
+    else:
+        assert abs(out[0].item() - vals["F"]) <= 1e-6
+        assert np.abs(g - gref).max() <= fp32_grad_tol(np.abs(gref).max())
