@@ -2092,11 +2092,10 @@ __global__ void k_chunk_load(const JobDev* jobs, int njobs, char* ws, size_t off
   const size_t vplane = (size_t)mp * jb.cc;
   const T* S = tplane<T>(ws, off_T, src == 0 ? jb.psi_off : jb.lam_off);
   const size_t sps = (size_t)mp * (src == 0 ? (size_t)(N + 1) * d : (size_t)N * d);
-  const long long total = (long long)mp * jb.cc;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int col = (int)(idx / mp), i = (int)(idx % mp);
-    const int jj = col / d, c = col % d;
+  const int total = mp * jb.cc;  // < 2^31 (mp <= 4096, cc <= 2 * 2048 + 15)
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const int col = idx / mp, i = idx - col * mp;
+    const int jj = d == 1 ? col : col >> 1, c = d == 1 ? 0 : col & 1;  // d is 1 or 2
     T vr = T(0), vi = T(0);
     if (jj < nsl) {
       const size_t gs = ((size_t)(j0 + jj) * d + c) * mp + i;
@@ -2121,12 +2120,11 @@ __global__ void k_series_combine(const JobDev* jobs, int njobs, char* ws, size_t
   const double* uj = u + jb.u_off;
   T* g = tplane<T>(ws, off_T, jb.gbase_off);
   const size_t vplane = (size_t)mp * jb.cc;
-  const long long total = (long long)mp * jb.cc;
+  const int total = mp * jb.cc;  // < 2^31 (mp <= 4096, cc <= 2 * 2048 + 15)
   const T cf = (T)(sign_over * jb.dt / R);
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (long long)gridDim.x * blockDim.x) {
-    const int col = (int)(idx / mp);
-    const int jj = col / d;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const int col = idx / mp;
+    const int jj = d == 1 ? col : col >> 1;  // d is 1 or 2
     T sr = g[idx], si = g[idx + vplane];  // Z_0
     if (jj < nsl) {
       for (int k = 1; k <= K; ++k) {
@@ -3382,8 +3380,11 @@ static qoc_plan_s* build_plan(const std::vector<ProblemSpec>& probs, int precisi
   P->max_mp = max_mp;
   size_t lds_elems = 0;
   for (auto& pr : probs)
-    for (auto& b : pr.blocks)
+    for (auto& b : pr.blocks) {
+      // copies: the dimension of a ring group's irrep (1 or 2; one for S_n blocks)
+      QOC_REQUIRE(b.d == 1 || b.d == 2, QOC_ERR_UNSUPPORTED, "blocks with more than two copies");
       lds_elems = std::max(lds_elems, (size_t)2 * b.d * b.mp * (1 + sweep_kgroups(b.mp, (int)P->elem)));
+    }
   P->sweep_lds_elems = lds_elems;
   QOC_REQUIRE(lds_elems * P->elem <= 160 * 1024, QOC_ERR_UNSUPPORTED, "block panel too large for the LDS-resident sweep");
   const int K = P->Kmax;
