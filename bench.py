@@ -31,17 +31,16 @@ if ROOT not in sys.path:
 MFMA_PEAK = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix TFLOP/s, MI355X
 
 # HBM-side bytes of k_expm_step<float> on this workload, from two rocprofv3 --pmc runs
-# (FETCH_SIZE, then WRITE_SIZE; mean KiB per dispatch over each tile variant's last 8
-# dispatches of `bench.py --steps 1 --warmup 1 --fp64-steps 0 --no-cpu-baseline
+# (FETCH_SIZE, then WRITE_SIZE; mean KiB per dispatch over the 6 dispatches of the timed
+# step, in the tile variant the autotuner chose, of `bench.py --steps 1 --warmup 1 --fp64-steps 0 --no-cpu-baseline
 # --copy-calibration 256 --sym-candidates 0 --ring14-slices 0 --batch-problems 0
 # --dense-slices 0 --paper-comparison 0 --optimizer 0 --gate 0 --lts 0`), each scaled by
 # what the same counter reads for the 256 MiB
 # calibration copy (FETCH_SIZE reads half of the bytes copied: x2.0; WRITE_SIZE all of
 # them: x1.0).  Valid only for the kernel sources they were taken with (sha1 of
 # mfma_tile.h + grape.hip).
-TRAFFIC = {"sources_sha1": "4a811cb297e287d05a6934d579339bf3be25d755", "fetch_scale": 2.0, "write_scale": 1.0,
-           "kib": {"fp32 128x64": (11787138.4, 6446834.2), "fp32 64x64": (14336225.4, 6460062.7),
-                   "fp32 64x128": (12721752.3, 6045069.4)}}
+TRAFFIC = {"sources_sha1": "b946e2078f00719a299b8d4a65a8de0502eb82c0", "fetch_scale": 2.0, "write_scale": 1.0,
+           "kib": {"fp32 64x128": (9302180.8, 3149684.7)}}
 
 
 def kernel_sources_sha1():
