@@ -2151,12 +2151,12 @@ __global__ void k_series_combine(const JobDev* jobs, int njobs, char* ws, size_t
 
 // G[col][k] += sum_{i < nb} w_{i,t} <b_i | Z_k>, FP64; one wave per (job, column).  The
 // weights are real, so this is <sum_i w_i b_i | Z_k>: one pass over the rows forms the
-// combined bank vector and its products with up to KG controls at a time.
-template <typename T>
+// combined bank vector and its products with up to KG controls at a time (KG = 2 for plans
+// with at most two controls: fewer registers, more resident waves; the same sums).
+template <typename T, int KG>
 __global__ void __launch_bounds__(256) k_series_dot(const JobDev* jobs, int njobs, char* ws, size_t off_T,
                                                     size_t off_gacc, int bank_slot, int nb, const double* w,
                                                     int zero_first, int j0) {
-  constexpr int KG = 8;
   for (int J = blockIdx.y; J < njobs; J += gridDim.y) {
   const JobDev jb = jobs[J];
   if (jb.N - j0 <= 0) continue;
@@ -3129,8 +3129,13 @@ struct Driver {
           gemm(cur);
           const double* wt = P->d_w.as<double>() + (size_t)t * Q;
           timed(PK_GRAD_VECTOR, st, [&] {
-            hipLaunchKernelGGL(k_series_dot<T>, dim3(std::max(1, std::min((P->max_cc + 3) / 4, 8192 / njobs)), std::min(njobs, 32768)), dim3(256), 0, st, dj, njobs, ws,
-                               P->off_T, P->off_gacc, bank, Q - t, wt, first_dot ? 1 : 0, j0);
+            const dim3 dg(std::max(1, std::min((P->max_cc + 3) / 4, 8192 / njobs)), std::min(njobs, 32768));
+            if (P->Kmax <= 2)
+              hipLaunchKernelGGL((k_series_dot<T, 2>), dg, dim3(256), 0, st, dj, njobs, ws, P->off_T, P->off_gacc,
+                                 bank, Q - t, wt, first_dot ? 1 : 0, j0);
+            else
+              hipLaunchKernelGGL((k_series_dot<T, 8>), dg, dim3(256), 0, st, dj, njobs, ws, P->off_T, P->off_gacc,
+                                 bank, Q - t, wt, first_dot ? 1 : 0, j0);
           });
           first_dot = false;
           if (t + 1 < Q || need_next_state) {
