@@ -39,8 +39,8 @@ MFMA_PEAK = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix TFLOP/s, MI
 # calibration copy (FETCH_SIZE reads half of the bytes copied: x2.0; WRITE_SIZE all of
 # them: x1.0).  Valid only for the kernel sources they were taken with (sha1 of
 # mfma_tile.h + grape.hip).
-TRAFFIC = {"sources_sha1": "b946e2078f00719a299b8d4a65a8de0502eb82c0", "fetch_scale": 2.0, "write_scale": 1.0,
-           "kib": {"fp32 64x128": (9302180.8, 3149684.7)}}
+TRAFFIC = {"sources_sha1": "e2b51476ac01d4eab3ac0cfe79b29306d61a382a", "fetch_scale": 2.0, "write_scale": 1.0,
+           "kib": {"fp32 64x128": (9297436.2, 3155288.3)}}
 
 
 def kernel_sources_sha1():
