@@ -124,6 +124,43 @@ def test_symmetric_candidates(lib, prec):
         assert np.abs(g - gref).max() <= tg
 
 
+def test_progress_lines_per_problem_group(lib, capfd):
+    """qoc_set_progress: one stderr line per finished problem group, from the call's stream."""
+    import torch
+    print("progress lines", flush=True)
+    rng = np.random.default_rng(47)
+    ws = []
+    for n, N in ((8, 40), (6, 20), (8, 30), (7, 25)):
+        u = rng.uniform(-1, 1, (N, 2))
+        ws.append(W.Workload(f"ring{n}", n, "dihedral", 1, W.heisenberg_ring_terms(0.9), W.global_controls(), N,
+                             0.04, u))
+    states = [_problem_states(rng, w.n) for w in ws]
+    systems = [lib.System(lib.Basis(w.n), w.h0, w.hk) for w in ws]
+    Ns, dts = [w.N for w in ws], [w.dt for w in ws]
+    full = lib.Plan.batched(systems, "c64", Ns, dts, 1.0).workspace_bytes
+    Pg, frac = None, 0.5
+    while frac > 0.01:
+        cand = lib.Plan.batched(systems, "c64", Ns, dts, 1.0, int(full * frac))
+        if cand.info["problem_groups"] >= 2:
+            Pg = cand
+            break
+        frac *= 0.8
+    assert Pg is not None
+    G = Pg.info["problem_groups"]
+    capfd.readouterr()
+    lib.set_progress(True)
+    try:
+        lib.fidelity_grad_batched(Pg, [torch.tensor(w.u, device="cuda") for w in ws],
+                                  [torch.tensor(s[0], device="cuda") for s in states],
+                                  [torch.tensor(s[1], device="cuda") for s in states])
+        torch.cuda.synchronize()
+    finally:
+        lib.set_progress(False)
+    err = capfd.readouterr().err
+    lines = [l for l in err.splitlines() if l.startswith("[qoc] problem group")]
+    assert len(lines) == G and lines[-1].startswith(f"[qoc] problem group {G}/{G} done")
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_problem_groups_equal_the_single_group_plan(lib, prec):
     """A batched plan whose budget cannot hold every problem's propagators runs groups of
