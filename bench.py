@@ -30,17 +30,17 @@ if ROOT not in sys.path:
 
 MFMA_PEAK = {"c64": 157.3, "c128": 78.6}  # dense FP32 / FP64 matrix TFLOP/s, MI355X
 
-# HBM-side bytes of k_expm_step<float> on this workload, from two rocprofv3 --pmc runs
-# (FETCH_SIZE, then WRITE_SIZE; mean KiB per dispatch over the 6 dispatches of the timed
-# step, in the tile variant the autotuner chose, of `bench.py --steps 1 --warmup 1 --fp64-steps 0 --no-cpu-baseline
-# --copy-calibration 256 --sym-candidates 0 --ring14-slices 0 --batch-problems 0
-# --dense-slices 0 --paper-comparison 0 --optimizer 0 --gate 0 --lts 0`), each scaled by
-# what the same counter reads for the 256 MiB
-# calibration copy (FETCH_SIZE reads half of the bytes copied: x2.0; WRITE_SIZE all of
-# them: x1.0).  Valid only for the kernel sources they were taken with (sha1 of
-# mfma_tile.h + grape.hip).
-TRAFFIC = {"sources_sha1": "e2b51476ac01d4eab3ac0cfe79b29306d61a382a", "fetch_scale": 2.0, "write_scale": 1.0,
-           "kib": {"fp32 64x128": (9297436.2, 3155288.3)}}
+# HBM-side bytes of k_expm_step<float> on this workload, from two rocprofv3 --pmc runs per
+# tile variant (FETCH_SIZE, then WRITE_SIZE; mean KiB per dispatch over the 6 dispatches of
+# the timed step of `bench.py --steps 1 --warmup 1 --fp64-steps 0 --no-cpu-baseline
+# --copy-calibration 256 --gemm-variant32 V --sym-candidates 0 --ring14-slices 0
+# --batch-problems 0 --dense-slices 0 --paper-comparison 0 --optimizer 0 --gate 0 --lts 0`
+# for the two variants the autotuner picks between here), each scaled by what the same
+# counter reads for the 256 MiB calibration copy (FETCH_SIZE reads half of the bytes
+# copied: x2.0; WRITE_SIZE all of them: x1.0).  Valid only for the kernel sources they
+# were taken with (sha1 of mfma_tile.h + grape.hip).
+TRAFFIC = {"sources_sha1": "34a790a897730ad0fdbee64710992256ab0ee41c", "fetch_scale": 2.0, "write_scale": 1.0,
+           "kib": {"fp32 64x128": (9242093.9, 3144451.2), "fp32 128x64": (8404172.6, 3535608.6)}}
 
 
 def kernel_sources_sha1():
@@ -81,6 +81,9 @@ def parse():
                     help="also run the Trotterised per-qubit-control legs (1) or skip them (0)")
     ap.add_argument("--optimizer", type=int, default=1,
                     help="also run the L-BFGS GRAPE optimiser legs (1) or skip them (0)")
+    ap.add_argument("--gemm-variant32", type=int, default=-1, metavar="V",
+                    help="run the headline FP32 plan in tile variant V instead of the autotuner's choice (for "
+                         "hardware-counter runs of one variant; -1: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
@@ -808,7 +811,11 @@ def main():
     print(f"[bench] blocks {B.sizes} copies {B.copies}", file=sys.stderr, flush=True)
 
     P32 = q.Plan(S, "c64", w.N, w.dt, 2.0)
-    tune32 = P32.autotune(dev["u"])
+    if args.gemm_variant32 >= 0:
+        P32.set_variant(args.gemm_variant32)
+        tune32 = (args.gemm_variant32, [])
+    else:
+        tune32 = P32.autotune(dev["u"])
     print(f"[bench] c64 plan {P32.info} workspace {P32.workspace_bytes / 2**30:.1f} GiB; GEMM variant "
           f"{P32.variant_name} (autotune ms {tune32[1]})", file=sys.stderr, flush=True)
     ms32, wall32, prof32, out32, grad32 = timed_steps(q, torch, P32, dev, args.steps, args.warmup)

@@ -1334,27 +1334,42 @@ __device__ inline int coop_decide(int* ctl, int W, int* flags, int force_solo) {
 __device__ inline void xchg_put(unsigned long long* p, unsigned bits, unsigned tag) {
   __hip_atomic_store(p, ((unsigned long long)tag << 32) | bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// spins (bounded) until the word carries tag; false on time-out
-__device__ inline bool xchg_get(const unsigned long long* p, unsigned tag, unsigned& bits) {
+// spins (bounded) until each of the N words carries tag; false on time-out.  Every load is
+// issued before any tag is checked, so one round trip covers all N words.
+template <int N>
+__device__ inline bool xchg_get_n(const unsigned long long* const (&p)[N], unsigned tag, unsigned (&bits)[N]) {
+  unsigned long long w[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) w[i] = __hip_atomic_load(p[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   long s = 0;
   for (;;) {
-    const unsigned long long w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((unsigned)(w >> 32) == tag) {
-      bits = (unsigned)w;
+    bool all = true;
+#pragma unroll
+    for (int i = 0; i < N; ++i) all = all && (unsigned)(w[i] >> 32) == tag;
+    if (all) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) bits[i] = (unsigned)w[i];
       return true;
     }
     if (++s >= kStepSpins) return false;
     __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if ((unsigned)(w[i] >> 32) != tag) w[i] = __hip_atomic_load(p[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 template <typename T> struct XchgVal;
 template <> struct XchgVal<float> {
   static constexpr int W = 1;
   __device__ static void put(unsigned long long* p, float v, unsigned tag) { xchg_put(p, __float_as_uint(v), tag); }
-  __device__ static bool get(const unsigned long long* p, unsigned tag, float& v) {
-    unsigned b;
-    if (!xchg_get(p, tag, b)) return false;
-    v = __uint_as_float(b);
+  // the values at a and b (the two planes of one state entry)
+  __device__ static bool get_pair(const unsigned long long* a, const unsigned long long* b, unsigned tag, float& va,
+                                  float& vb) {
+    const unsigned long long* const p[2] = {a, b};
+    unsigned w[2];
+    if (!xchg_get_n<2>(p, tag, w)) return false;
+    va = __uint_as_float(w[0]);
+    vb = __uint_as_float(w[1]);
     return true;
   }
 };
@@ -1365,10 +1380,13 @@ template <> struct XchgVal<double> {
     xchg_put(p, (unsigned)b, tag);
     xchg_put(p + 1, (unsigned)(b >> 32), tag);
   }
-  __device__ static bool get(const unsigned long long* p, unsigned tag, double& v) {
-    unsigned lo, hi;
-    if (!xchg_get(p, tag, lo) || !xchg_get(p + 1, tag, hi)) return false;
-    v = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  __device__ static bool get_pair(const unsigned long long* a, const unsigned long long* b, unsigned tag, double& va,
+                                  double& vb) {
+    const unsigned long long* const p[4] = {a, a + 1, b, b + 1};
+    unsigned w[4];
+    if (!xchg_get_n<4>(p, tag, w)) return false;
+    va = __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
+    vb = __longlong_as_double((long long)(((unsigned long long)w[3] << 32) | w[2]));
     return true;
   }
 };
@@ -1601,8 +1619,8 @@ __device__ void sweep_coop_bwd(const JobDev& jb, char* ws, size_t off_T, int seg
       bool ok = true;
       for (int idx = threadIdx.x; idx < mp * d && ok; idx += blockDim.x) {
         T vr = T(0), vi = T(0);
-        ok = XV::get(Xp + (size_t)idx * XV::W, (unsigned)it + tag_skew, vr) &&
-             XV::get(Xp + xplane + (size_t)idx * XV::W, (unsigned)it + tag_skew, vi);
+        ok = XV::get_pair(Xp + (size_t)idx * XV::W, Xp + xplane + (size_t)idx * XV::W, (unsigned)it + tag_skew, vr,
+                          vi);
         sre[idx] = vr;
         sim[idx] = vi;
       }
@@ -1716,8 +1734,8 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
       bool ok = true;
       for (int idx = threadIdx.x; idx < mp * d && ok; idx += blockDim.x) {
         T vr = T(0), vi = T(0);
-        ok = XV::get(Xp + (size_t)idx * XV::W, (unsigned)it + tag_skew, vr) &&
-             XV::get(Xp + xplane + (size_t)idx * XV::W, (unsigned)it + tag_skew, vi);
+        ok = XV::get_pair(Xp + (size_t)idx * XV::W, Xp + xplane + (size_t)idx * XV::W, (unsigned)it + tag_skew, vr,
+                          vi);
         sre[idx] = vr;
         sim[idx] = vi;
       }
@@ -2838,12 +2856,13 @@ struct Driver {
     for (int c0 = 0; c0 < L; c0 += P->echunk) {
       const int clen = std::min(P->echunk, L - c0);
       const int groups = (clen + GEN_SG - 1) / GEN_SG;
-      // too few (job, slice group) work-groups to fill the GPU, each reading large operator
-      // planes: split each over columns
-      const long long wgs = (long long)njobs * groups;
-      const int csplit = wgs >= P->ncu || P->max_mp < 64 ? 1
-                                       : (int)std::min<long long>((2LL * P->ncu + wgs - 1) / wgs,
-                                                                  std::max(1, P->max_mp / 16));
+      // too few (job, slice group) work-groups to keep every CU busy with several (and to
+      // even out blocks of different sizes), each reading large operator planes: split each
+      // over column ranges
+      const long long wgs = (long long)njobs * groups, target = 16LL * P->ncu;
+      const int csplit = wgs >= target || P->max_mp < 64
+                             ? 1
+                             : (int)std::min<long long>((target + wgs - 1) / wgs, std::max(1, P->max_mp / 16));
       if (csplit == 1) {
         timed(PK_GENERATOR, st, [&] {
           hipLaunchKernelGGL(k_generator<T>, dim3(njobs * groups), dim3(256), 0, st, dj, njobs, u, seg_j0, L, c0,
