@@ -17,5 +17,6 @@ def test_bench_help_lists_legs():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0
-    for flag in ("--steps", "--warmup", "--fp64-steps", "--dense-slices", "--sym-candidates", "--copy-calibration"):
+    for flag in ("--steps", "--warmup", "--fp64-steps", "--dense-slices", "--sym-candidates", "--copy-calibration",
+                 "--gemm-variant32"):
         assert flag in r.stdout
