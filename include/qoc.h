@@ -304,6 +304,15 @@ qoc_status qoc_plan_read_state(qoc_plan plan, int problem, int which, int j, con
 enum { QOC_SWEEP_SOLO = 1, QOC_SWEEP_TEST_STALL_FWD = 2, QOC_SWEEP_TEST_STALL_BWD = 4 };
 qoc_status qoc_plan_set_sweep_mode(qoc_plan plan, int mode);
 
+/* Generator switch, for tests (0 in normal use).  The slice generator (Eq. (3)'s exponent
+ * and, with operator products, its powers and first Taylor combinations) runs one
+ * work-group per (block, group of 8 slices), split over column ranges when there are fewer
+ * than 16 such pairs per compute unit.  ranges = 0 keeps that rule; ranges >= 1 runs every
+ * call over exactly min(ranges, max(1, widest padded block / 16)) ranges (1: unsplit).
+ * Each element is formed by the same arithmetic either way, so results are unchanged bit
+ * for bit.  QOC_ERR_INVALID_ARG for a null plan or ranges < 0.  Host call. */
+qoc_status qoc_plan_set_generator_split(qoc_plan plan, int ranges);
+
 /* Gate propagation: the unitary a pulse implements, K = U_{N-1} ... U_1 U_0 (Eq. (3)'s
  * slice propagators in time order), for every block of a one-problem plan; Sec. III B
  * compares two such products by the gate fidelity below.  The propagators are formed as

@@ -229,6 +229,11 @@ class Plan:
         """Co-operative sweep switches (SWEEP_SOLO, SWEEP_TEST_STALL_FWD / _BWD bits; 0 = normal)."""
         C.check(C.lib().qoc_plan_set_sweep_mode(self._h, int(mode)))
 
+    def set_generator_split(self, ranges: int):
+        """Generator column ranges (qoc_plan_set_generator_split): 0 = automatic, k >= 1 = k
+        ranges (capped by the widest block); results are the same bit for bit."""
+        C.check(C.lib().qoc_plan_set_generator_split(self._h, int(ranges)))
+
     def workspace(self):
         torch = _torch()
         if self._ws is None:

@@ -80,6 +80,7 @@ PROTOTYPES = {
     "qoc_plan_read_state": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp,
                                            vp]),
     "qoc_plan_set_sweep_mode": (ctypes.c_int, [vp, ctypes.c_int]),
+    "qoc_plan_set_generator_split": (ctypes.c_int, [vp, ctypes.c_int]),
     "qoc_measure_mfma_peak": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp]),
     "qoc_plan_groups": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_int]),

@@ -210,6 +210,7 @@ struct qoc_plan_s {
   int grid_gemm = 512;
   int variant = 0;        // GEMM tile variant (index into the precision's table)
   int sweep_mode = 0;     // QOC_SWEEP_* bits (qoc_plan_set_sweep_mode)
+  int gen_split = 0;      // generator column ranges (0: automatic; qoc_plan_set_generator_split)
   int ncu = 256;
   hipStream_t st2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -2860,7 +2861,8 @@ struct Driver {
       // even out blocks of different sizes), each reading large operator planes: split each
       // over column ranges
       const long long wgs = (long long)njobs * groups, target = 16LL * P->ncu;
-      const int csplit = wgs >= target || P->max_mp < 64
+      const int csplit = P->gen_split > 0 ? std::min(P->gen_split, std::max(1, P->max_mp / 16))
+                         : wgs >= target || P->max_mp < 64
                              ? 1
                              : (int)std::min<long long>((target + wgs - 1) / wgs, std::max(1, P->max_mp / 16));
       if (csplit == 1) {
@@ -4100,6 +4102,15 @@ qoc_status qoc_plan_set_sweep_mode(qoc_plan P, int mode) {
                 QOC_ERR_INVALID_ARG, "unknown sweep mode bits");
     P->sweep_mode = mode;
     for (auto* g : P->groups) g->sweep_mode = mode;
+  });
+}
+
+qoc_status qoc_plan_set_generator_split(qoc_plan P, int ranges) {
+  return guarded([&] {
+    QOC_REQUIRE(P, QOC_ERR_INVALID_ARG, "null plan");
+    QOC_REQUIRE(ranges >= 0, QOC_ERR_INVALID_ARG, "negative number of column ranges");
+    P->gen_split = ranges;
+    for (auto* g : P->groups) g->gen_split = ranges;
   });
 }
 

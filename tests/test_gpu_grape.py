@@ -67,6 +67,41 @@ def test_all_blocks_full_coupling(lib, prec):
 
 
 @pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_generator_split_is_bitwise_neutral(lib, prec):
+    """The slice generator over its automatic number of column ranges, one range and three
+    (qoc_plan_set_generator_split) gives the same objective and gradient bit for bit; the
+    automatic one against the oracle."""
+    import torch
+    print(f"generator split {prec}", flush=True)
+    n, N, dt = 10, 240, 0.02
+    h0, hk = W.heisenberg_ring_terms(1.0), W.global_controls()
+    rng = np.random.default_rng(31)
+    u = rng.uniform(-1.0, 1.0, (N, 2))
+    ob = oracle_blocks(n, h0, hk)
+    assert max(b["H0"].shape[0] for b in ob) >= 64  # wide enough for the split to apply
+    psi0, psif = all_states(ob, rng)
+    B = lib.Basis(n, "dihedral", 1)
+    P = lib.Plan(lib.System(B, h0, hk), prec, N, dt, 1.0)
+    args = (torch.tensor(u, device="cuda"), torch.tensor(flat_from_panels(psi0), device="cuda"),
+            torch.tensor(flat_from_panels(psif), device="cuda"))
+    res = []
+    for k in (0, 1, 3):
+        P.set_generator_split(k)
+        out, grad = lib.fidelity_grad(P, *args)
+        torch.cuda.synchronize()
+        res.append((out.cpu().numpy().copy(), grad.cpu().numpy().copy()))
+    for out, grad in res[1:]:
+        assert np.array_equal(out[:6], res[0][0][:6])
+        assert np.array_equal(grad, res[0][1])
+    ref = og.fidelity_grad(ob, u, dt, psi0, psif)
+    tf, tg = _tol(prec, ref["grad"])
+    assert abs(res[0][0][0] - ref["F"]) <= tf
+    assert np.abs(res[0][1] - ref["grad"]).max() <= tg
+    with pytest.raises(lib.QocError):
+        P.set_generator_split(-1)
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_two_site_group_four_controls(lib, prec):
     """The staggered-control workload (K = 4) under the two-site rotation group."""
     print(f"two-site group {prec}", flush=True)
