@@ -944,10 +944,10 @@ __global__ void __launch_bounds__(256, Shape::WAVES)
   }
 }
 
+// U of slice jl of the segment (the sweeps read U itself in both directions)
 template <typename T>
-__device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int jl, int dagger) {
-  const size_t plane = (size_t)jb.mp * jb.mp;
-  return tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * jb.uslot + (dagger ? 2 * plane : 0);
+__device__ inline const T* entry_U(const JobDev& jb, char* ws, size_t off_T, int jl) {
+  return tplane<T>(ws, off_T, jb.ubuf_off) + (size_t)jl * jb.uslot;
 }
 
 // ===================================================================== state set-up
@@ -1036,6 +1036,7 @@ __host__ __device__ inline int sweep_kgroups(int mp, int elem) {
 template <typename T, int DIR>
 __device__ void sweep_solo(const JobDev& jb, char* ws, size_t off_T, const int* ent_s, const int* ent_q, int r,
                            int seg_j0, int seg_len) {
+  static_assert(DIR == 0, "the backward one-group sweep is sweep_solo_bwd");
   typedef typename Vec16<T>::type TV;
   typedef typename Vec4<T>::type T4;
   constexpr int UNR = SweepUnroll<T>::value, RPL = Vec16<T>::n;
@@ -1065,7 +1066,7 @@ __device__ void sweep_solo(const JobDev& jb, char* ws, size_t off_T, const int* 
   const size_t plane = (size_t)mp * mp;
   for (int it = 0; it < len; ++it) {
     const int jl = DIR == 0 ? it : len - 1 - it;
-    const T* U = entry_U<T>(jb, ws, off_T, jl, DIR);
+    const T* U = entry_U<T>(jb, ws, off_T, jl);
     for (int task = wave; task < R * G; task += 16) {
       const int rg = task % R, kg = task / R;
       const int i0 = rg * RG + RPL * lane;  // rows i0 .. i0 + RPL - 1 (mp is a multiple of 16)
@@ -1244,7 +1245,7 @@ __device__ void sweep_solo_bwd(const JobDev& jb, char* ws, size_t off_T, int seg
   const int rr = lane / KL, kl = lane % KL;
   for (int it = 0; it < len; ++it) {
     const int jl = len - 1 - it;
-    const T* U = entry_U<T>(jb, ws, off_T, jl, 0);
+    const T* U = entry_U<T>(jb, ws, off_T, jl);
     const int col_out = seg_j0 + jl - 1;
     for (int rg = wave; rg * RW < mp; rg += nw) {
       const int i = rg * RW + rr;  // < mp (a multiple of 16)
@@ -1400,6 +1401,7 @@ template <> struct XchgVal<double> {
 // needs (4 columns per wave), so the barriers span fewer waves.
 template <typename T, int DIR>
 __device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j0, int len, char* smem_raw) {
+  static_assert(DIR == 0, "the backward one-group sweep is sweep_single_bwd");
   typedef typename Vec16<T>::type TV;
   constexpr int RPL = Vec16<T>::n, RB = CoopRows<T>::value;
   const int m = jb.m, mp = jb.mp, d = jb.d, N = jb.N;
@@ -1426,7 +1428,7 @@ __device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j
   }
   TV ur = {}, ui = {};
   if (act) {
-    const T* U = entry_U<T>(jb, ws, off_T, DIR == 0 ? 0 : len - 1, DIR) + row + (size_t)k * mp;
+    const T* U = entry_U<T>(jb, ws, off_T, DIR == 0 ? 0 : len - 1) + row + (size_t)k * mp;
     ur = *reinterpret_cast<const TV*>(U);
     ui = *reinterpret_cast<const TV*>(U + plane);
   }
@@ -1435,7 +1437,7 @@ __device__ void sweep_single(const JobDev& jb, char* ws, size_t off_T, int seg_j
     const int jl = DIR == 0 ? it : len - 1 - it;
     TV nr = {}, ni = {};
     if (act && it + 1 < len) {
-      const T* U = entry_U<T>(jb, ws, off_T, DIR == 0 ? jl + 1 : jl - 1, DIR) + row + (size_t)k * mp;
+      const T* U = entry_U<T>(jb, ws, off_T, DIR == 0 ? jl + 1 : jl - 1) + row + (size_t)k * mp;
       nr = *reinterpret_cast<const TV*>(U);
       ni = *reinterpret_cast<const TV*>(U + plane);
     }
@@ -1529,7 +1531,7 @@ __device__ void sweep_single_bwd(const JobDev& jb, char* ws, size_t off_T, int s
   }
   TV ur = {}, ui = {};
   if (act) {
-    const T* U = entry_U<T>(jb, ws, off_T, len - 1, 0) + (size_t)i * mp + k;
+    const T* U = entry_U<T>(jb, ws, off_T, len - 1) + (size_t)i * mp + k;
     ur = *reinterpret_cast<const TV*>(U);
     ui = *reinterpret_cast<const TV*>(U + plane);
   }
@@ -1538,7 +1540,7 @@ __device__ void sweep_single_bwd(const JobDev& jb, char* ws, size_t off_T, int s
     const int jl = len - 1 - it;
     TV nr = {}, ni = {};
     if (act && it + 1 < len) {
-      const T* U = entry_U<T>(jb, ws, off_T, jl - 1, 0) + (size_t)i * mp + k;
+      const T* U = entry_U<T>(jb, ws, off_T, jl - 1) + (size_t)i * mp + k;
       nr = *reinterpret_cast<const TV*>(U);
       ni = *reinterpret_cast<const TV*>(U + plane);
     }
@@ -1632,7 +1634,7 @@ __device__ void sweep_coop_bwd(const JobDev& jb, char* ws, size_t off_T, int seg
       __syncthreads();
       if (abort_now) return;
     }
-    const T* U = entry_U<T>(jb, ws, off_T, jl, 0);
+    const T* U = entry_U<T>(jb, ws, off_T, jl);
     T a[2][2] = {{T(0), T(0)}, {T(0), T(0)}};
     if (i < m) dag_row_acc<T, KL, 4>(U + (size_t)i * mp, plane, m, kl * RPL, sre, sim, mp, d, a);
     lane_group_sum<KL>(a);
@@ -1747,7 +1749,7 @@ __global__ void __launch_bounds__(1024) k_sweep_coop(const JobDev* jobs, int njo
       __syncthreads();
       if (abort_now) return;
     }
-    const T* U = entry_U<T>(jb, ws, off_T, jl, DIR);
+    const T* U = entry_U<T>(jb, ws, off_T, jl);
     T a[2][2][RPL];  // [copy][re, im][row]
 #pragma unroll
     for (int c = 0; c < 2; ++c)
@@ -2590,7 +2592,7 @@ __global__ void k_export_U(const JobDev* jobs, int njobs, char* ws, size_t off_T
   const JobDev jb = jobs[J];
   const int jl = (int)(e - jb.ent_off);
   if (jl >= job_len(jb, seg_j0, seg_len)) continue;
-  const T* U = entry_U<T>(jb, ws, off_T, jl, 0);
+  const T* U = entry_U<T>(jb, ws, off_T, jl);
   const size_t plane = (size_t)jb.mp * jb.mp;
   double2* dst = out + jb.uout_off + (size_t)(seg_j0 + jl) * jb.m * jb.m;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < (long long)jb.m * jb.m;
